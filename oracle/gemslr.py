@@ -1,0 +1,175 @@
+"""GeMSLR setup (Alg. 1) and preconditioner apply M^{-1} (Alg. 2).
+
+Level structure (Sec. 2.4): A_l = [[B_l, F_l], [E_l, C_l]] with A_0 = P^T A P
+and A_{l+1} = C_l.  With the composed permutation of partition.py every C_l
+is the tail of the permuted vector, so level l acts on the index range
+[start_l, n) and splits it into B_l = [start_l, start_{l+1}) and
+C_l = [start_{l+1}, n).
+
+Setup (Alg. 1): ILU of every B_l, then the rank-k terms W_l, R_l built
+bottom-up (l = L-1 ... 0) because G_hat_l needs C_l^{-1}, which is the apply
+of the levels below l (Sec. 4.2).  The last separator C_{L-1} is kept only
+on its diagonal blocks (block Jacobi) and factored the same way (Sec. 4.3);
+it is stored here as level L with no interface (s = 0).
+
+Apply (Alg. 2) with zero inner GMRES iterations at level 0 and a low-rank
+term at every level, the last one included:
+    z1 = U_l^{-1} L_l^{-1} b1
+    z2 = b2 - E_l z1
+    u2 = W_l [(I - R_l)^{-1} - I] W_l^H z2
+    y2 = M_{l+1}^{-1} (u2 + z2)        (C_last^{-1} below the last level)
+    y1 = z1 - U_l^{-1} L_l^{-1} F_l y2
+"""
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+from scipy.sparse.linalg import spsolve_triangular
+
+from . import ilu as ilu_mod
+from . import lowrank
+
+
+@dataclass
+class Level:
+    start: int
+    d: int
+    s: int
+    blocks: np.ndarray      # block boundaries relative to start, nb+1 entries
+    Lf: sp.csr_matrix       # strictly lower ILU factor (unit diagonal implied)
+    Uf: sp.csr_matrix       # upper ILU factor including the diagonal
+    E: sp.csr_matrix        # s x d
+    F: sp.csr_matrix        # d x s
+    W: np.ndarray = None    # s x k
+    R: np.ndarray = None    # k x k
+    H: np.ndarray = None    # k x k, (I - R)^{-1} - I
+    info: dict = None
+
+
+@dataclass
+class Setup:
+    n: int
+    perm: np.ndarray
+    levels: list            # L+1 entries; the last is C_last with s = 0
+    Ap: sp.csr_matrix       # P^T A P
+    real: bool
+
+    @property
+    def nlevels(self):
+        return len(self.levels) - 1
+
+
+def csr(rowptr, col, val, n):
+    a = sp.csr_matrix((val, col, rowptr), shape=(n, n))
+    a.sort_indices()
+    return a
+
+
+def _block_diag_part(B, blocks):
+    """Keep only the entries of B inside its diagonal blocks."""
+    B = B.tocoo()
+    lab = np.zeros(B.shape[0], dtype=np.int64)
+    for i in range(len(blocks) - 1):
+        lab[blocks[i]:blocks[i + 1]] = i
+    keep = lab[B.row] == lab[B.col]
+    return sp.csr_matrix((B.data[keep], (B.row[keep], B.col[keep])),
+                         shape=B.shape)
+
+
+def trisolve(lv, b):
+    """U^{-1} L^{-1} b for one level (b may hold several columns)."""
+    if lv.d == 0:
+        return b.copy()
+    I = sp.identity(lv.d, dtype=lv.Lf.dtype, format="csr")
+    y = spsolve_triangular((lv.Lf + I).tocsr(), b, lower=True)
+    return spsolve_triangular(lv.Uf, y, lower=False)
+
+
+def apply_level(st, l, b):
+    """M_l^{-1} b on the index range of level l (Alg. 2)."""
+    lv = st.levels[l]
+    if l == st.nlevels:
+        return trisolve(lv, b)
+    b1, b2 = b[:lv.d], b[lv.d:]
+    z1 = trisolve(lv, b1)
+    z2 = b2 - lv.E @ z1
+    if lv.W is not None and lv.W.shape[1] > 0:
+        u2 = lv.W @ (lv.H @ (lv.W.conj().T @ z2))
+    else:
+        u2 = np.zeros_like(z2)
+    y2 = apply_level(st, l + 1, u2 + z2)
+    y1 = z1 - trisolve(lv, lv.F @ y2)
+    return np.concatenate([y1, y2], axis=0)
+
+
+def apply(st, x):
+    """y = M^{-1} x in the original ordering."""
+    q = apply_level(st, 0, x[st.perm])
+    y = np.empty_like(q)
+    y[st.perm] = q
+    return y
+
+
+def apply_permuted(st, xp):
+    return apply_level(st, 0, xp)
+
+
+def ghat_matvec(st, l, v):
+    """G_hat_l v = E_l U_l^{-1} L_l^{-1} F_l C_l^{-1} v (Sec. 2.3; E_l, not
+    its transpose -- the transpose in the multilevel formula does not
+    conform)."""
+    lv = st.levels[l]
+    c = apply_level(st, l + 1, v)
+    return lv.E @ trisolve(lv, lv.F @ c)
+
+
+def setup(rowptr, col, val, part, ilu="ilut", drop_tol=1e-3, lfil=10,
+          rank=32, seed=0, lowrank_last_level=True, dense_max=2000,
+          arnoldi_tol=1e-2, max_cycles=20):
+    n = len(rowptr) - 1
+    A = csr(rowptr, col, val, n)
+    real = not np.iscomplexobj(val)
+    perm = part.perm
+    Ap = A[perm][:, perm].tocsr()
+    Ap.sort_indices()
+    ls = part.level_start
+    L = part.nlevels
+    levels = []
+    for l in range(L + 1):
+        a = ls[l]
+        b = ls[l + 1] if l < L else n
+        B = Ap[a:b, a:b]
+        blocks = part.blocks[l] - a
+        if l == L:
+            B = _block_diag_part(B, blocks)
+            E = sp.csr_matrix((0, b - a), dtype=Ap.dtype)
+            F = sp.csr_matrix((b - a, 0), dtype=Ap.dtype)
+        else:
+            E = Ap[b:, a:b].tocsr()
+            F = Ap[a:b, b:].tocsr()
+        Lf, Uf = ilu_mod.factor(B, ilu, drop_tol, lfil)
+        levels.append(Level(int(a), int(b - a), int(n - b), blocks, Lf, Uf,
+                            E, F))
+    st = Setup(n, perm, levels, Ap, real)
+    # low-rank terms, bottom-up
+    for l in range(L - 1, -1, -1):
+        lv = levels[l]
+        k = min(rank, lv.s)
+        if l == L - 1 and not lowrank_last_level:
+            k = 0
+        dt = np.float64 if real else np.complex128
+        if k == 0:
+            lv.W = np.zeros((lv.s, 0), dtype=dt)
+            lv.R = np.zeros((0, 0), dtype=dt)
+            lv.info = {"mode": "none"}
+        elif lv.s <= dense_max:
+            G = ghat_matvec(st, l, np.eye(lv.s, dtype=dt))
+            lv.W, lv.R = lowrank.dense_lowrank(G, k, real)
+            lv.info = {"mode": "dense"}
+        else:
+            lv.W, lv.R, lv.info = lowrank.krylov_schur(
+                lambda v: ghat_matvec(st, l, v), lv.s, k, real,
+                seed=seed + l, tol=arnoldi_tol, max_cycles=max_cycles)
+            lv.info["mode"] = "krylov-schur"
+        lv.H = lowrank.finish(lv.W, lv.R)
+    return st
