@@ -1,0 +1,266 @@
+/*
+ * gemslr.h -- C ABI of the MI355X GeMSLR preconditioner library (libgemslr.so)
+ *
+ * GeMSLR is the multilevel Schur-complement low-rank preconditioner of
+ * Xu, Kalantzis, Li and Saad, "parGeMSLR: A Parallel Multilevel Schur
+ * Complement Low-Rank Preconditioning and Solution Package for General Sparse
+ * Matrices" (arXiv 2205.03224).  The library builds the preconditioner on the
+ * host and one GPU (Alg. 1), applies M^{-1} on the GPU (Alg. 2) and runs
+ * right-preconditioned flexible GMRES around it (Sec. 4.1, Sec. 5).
+ *
+ * Conventions for every entry point:
+ *  - Return value: GS_OK (0) on success, > 0 for a usable but incomplete
+ *    result, < 0 for an error.  No C++ exception crosses this boundary; the
+ *    message of the last error of a context is available from gs_last_error.
+ *  - Pointers documented as "host" are read during the call only and stay
+ *    owned by the caller.  Pointers documented as "device" are caller-owned
+ *    device memory (e.g. torch tensors) on the context's device; the library
+ *    never frees them.
+ *  - Values of type GS_C128 are interleaved (re, im) float64 pairs.
+ *  - Sparse matrices are CSR: rowptr (int64, n+1, rowptr[0] = 0),
+ *    col (int32, sorted strictly ascending inside each row), values.
+ *  - Device work is queued on the context's HIP stream; functions that hand
+ *    a result to the host (solve, the setup routines) synchronise it.
+ */
+#ifndef GEMSLR_H
+#define GEMSLR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+enum {
+  GS_OK = 0,
+  GS_NOT_CONVERGED = 1, /* solve stopped at maxit; best iterate returned      */
+  GS_EINVAL = -1,       /* invalid argument or malformed CSR                    */
+  GS_EZEROPIVOT = -2,   /* zero or non-finite pivot in an incomplete LU          */
+  GS_ESINGULAR = -3,    /* |1 - theta| < 1e-12 for a Ritz value: I - R singular  */
+  GS_EDEVICE = -4,      /* HIP runtime error                                     */
+  GS_ESTATE = -5,       /* call out of order (e.g. apply before setup)           */
+  GS_ENOMEM = -6        /* device or host allocation failed                      */
+};
+
+enum { GS_F64 = 0, GS_C128 = 1 };                  /* value type of A, b, x  */
+enum { GS_PREC_F64 = 0, GS_PREC_F32 = 1, GS_PREC_BF16 = 2 }; /* apply storage */
+enum { GS_ILUT = 0, GS_ILU0 = 1 };
+
+/* ---------------------------------------------------------------- options */
+typedef struct {
+  int ilu_kind;           /* GS_ILUT (dual threshold, Saad 1994) or GS_ILU0   */
+  int lfil;               /* ILUT: max entries kept per row in L and in U,
+                             diagonal excluded                        [10]    */
+  int fgmres_restart;     /* FGMRES cycle length m (Sec. 5)           [50]    */
+  int maxit;              /* total FGMRES iteration cap (Sec. 5)      [1000]  */
+  double arnoldi_tol;     /* Ritz residual / |theta| accepted: two digits
+                             of accuracy (Sec. 5)                     [1e-2]  */
+  int arnoldi_max_cycles; /* thick-restart cycles per level           [20]    */
+  int lowrank_last_level; /* 1: low-rank term also at level L-1       [1]     */
+  int precision;          /* GS_PREC_*: storage of L, U, E, F, W in the apply;
+                             F32/BF16 solve in float32           [GS_PREC_F64] */
+  int grid_ndim;          /* >0: A is a grid operator with lexicographic
+                             numbering x + N0*y + N0*N1*z                 [0]  */
+  int32_t grid_dims[3];   /* points per axis for the geometric separator     */
+  uint64_t seed;          /* Arnoldi start vectors (SplitMix64)        [0]    */
+  int nthreads;           /* host threads for the factorisation (0 = all)     */
+} gs_opts;
+
+/* Fill *opts with the defaults shown in brackets above. */
+void gs_opts_default(gs_opts* opts);
+
+/* ---------------------------------------------------------------- info */
+#define GS_MAX_LEVELS 8
+typedef struct {
+  int its;                  /* FGMRES iterations of the last solve           */
+  double relres;            /* true ||b - A x|| / ||b|| at exit (float64)     */
+  int converged;            /* 1 if relres <= tol                             */
+  int nlevels;              /* L: levels with a Schur complement              */
+  int64_t d[GS_MAX_LEVELS + 1];      /* rows of B_l (index L: C_last)          */
+  int64_t s[GS_MAX_LEVELS + 1];      /* rows of C_l                           */
+  int64_t nblocks[GS_MAX_LEVELS + 1];
+  int32_t k[GS_MAX_LEVELS + 1];      /* rank kept at level l                  */
+  int32_t depth_l[GS_MAX_LEVELS + 1];/* max wavefront depth of L over blocks  */
+  int32_t depth_u[GS_MAX_LEVELS + 1];/* same for U                            */
+  int32_t arnoldi_cycles[GS_MAX_LEVELS + 1];
+  int32_t arnoldi_matvecs[GS_MAX_LEVELS + 1];
+  int32_t arnoldi_converged[GS_MAX_LEVELS + 1];
+  int64_t nnz_lu;           /* sum of nnz(L)+nnz(U) incl. diagonals, all levels */
+  int64_t nnz_ef;           /* sum of nnz(E_l)+nnz(F_l)                       */
+  int64_t nnz_a;            /* nnz(A)                                         */
+  double fill;              /* nnz_lu / nnz_a (Sec. 5 "fill")                 */
+  double fill_lowrank;      /* (nnz_lu + sum s_l k_l + k_l^2) / nnz_a         */
+  double apply_bytes;       /* compulsory HBM bytes of one apply (see DESIGN) */
+  double t_partition, t_factor, t_layout, t_lowrank, t_solve; /* seconds     */
+} gs_info;
+
+/* ---------------------------------------------------------------- context */
+typedef struct gs_ctx gs_ctx;
+
+/* Create a context on HIP device `device` that queues its work on `stream`
+ * (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL = the
+ * device's null stream).  device < 0 creates a host-only context that can
+ * run the host stages (partition, factorisation) but not apply/solve.
+ * Errors: GS_EINVAL (ctx NULL), GS_EDEVICE. */
+int gs_create(gs_ctx** ctx, int device, void* stream);
+
+/* Release every resource the context owns.  NULL is ignored. */
+void gs_destroy(gs_ctx* ctx);
+
+/* Message of the context's last error ("" if none); valid until the next
+ * call on the context.  ctx NULL returns the last gs_create error. */
+const char* gs_last_error(const gs_ctx* ctx);
+
+/* ---------------------------------------------------------------- setup */
+/* Build M^{-1} for the n x n matrix A (Alg. 1, Sec. 4.2):
+ *  - reorder A with a multilevel p-way vertex separator (Alg. 3, Sec. 3)
+ *    into `levels` levels of `nparts` parts (fewer when the separator is too
+ *    small to split, Sec. 3.2); this build takes the geometric separator of
+ *    a grid graph, so opts->grid_ndim/grid_dims are required;
+ *  - incomplete LU of every diagonal block of B_l (ILUT(drop_tol, lfil) or
+ *    ILU(0)), and block-Jacobi ILU of the last separator (Sec. 4.3);
+ *  - rank-`rank` Schur-complement correction W_l, R_l at every level,
+ *    bottom-up, by thick-restart Arnoldi on G_l = E_l U_l^{-1} L_l^{-1} F_l
+ *    C_l^{-1} with cycle length 2*rank (Sec. 2.3, Sec. 4.2), run on the GPU.
+ * A (host CSR, dtype GS_F64 or GS_C128) is copied; the caller keeps it.
+ * Errors: GS_EINVAL (malformed CSR, missing diagonal, n <= 0, rank < 0,
+ * nparts not a dim-th power, no grid), GS_EZEROPIVOT, GS_ESINGULAR,
+ * GS_EDEVICE, GS_ENOMEM.  A previous setup of the context is released. */
+int gs_setup(gs_ctx* ctx, int64_t n, const int64_t* rowptr,
+             const int32_t* col, const void* val, int dtype, int levels,
+             int nparts, int rank, double drop_tol, const gs_opts* opts);
+
+/* One level of an explicitly given preconditioner, in permuted numbering.
+ * Level l acts on the index range [start_l, n) of the permuted vector:
+ * B_l = [start_l, start_l + d) and C_l = [start_l + d, n), s = n - start_l - d
+ * (Sec. 2.4; the per-level permutations compose into one).  The final entry
+ * (C_last, Sec. 4.3) has s = 0 and no E, F, W, H.  All pointers are host,
+ * values of the context's dtype. */
+typedef struct {
+  int64_t d;                    /* rows of B_l                                  */
+  int64_t nblocks;              /* diagonal blocks of B_l                       */
+  const int64_t* block_ptr;     /* nblocks+1 row offsets in [0, d]              */
+  const int64_t* l_rowptr; const int32_t* l_col; const void* l_val;
+                                /* strictly lower ILU factor (unit diagonal
+                                   implied), d x d, level-local columns         */
+  const int64_t* u_rowptr; const int32_t* u_col; const void* u_val;
+                                /* upper ILU factor with diagonal, d x d        */
+  const int64_t* e_rowptr; const int32_t* e_col; const void* e_val;
+                                /* E_l: s x d (rows in C_l, columns in B_l)     */
+  const int64_t* f_rowptr; const int32_t* f_col; const void* f_val;
+                                /* F_l: d x s (rows in B_l, columns in C_l)     */
+  int32_t k;                    /* rank of the correction                      */
+  const void* w;                /* W_l: s x k, column-major                     */
+  const void* h;                /* H_l = (I - R_l)^{-1} - I: k x k, column-major */
+} gs_level_data;
+
+/* Install an explicitly given preconditioner (same M^{-1} as an external
+ * setup, e.g. for checking the apply against an independent
+ * implementation).  A is the unpermuted matrix (used by gs_solve); perm[i]
+ * is the original index of permuted position i; levels has nlevels+1
+ * entries whose d sum to n.  Copies everything.  Errors: GS_EINVAL,
+ * GS_EDEVICE, GS_ENOMEM. */
+int gs_setup_explicit(gs_ctx* ctx, int64_t n, const int64_t* rowptr,
+                      const int32_t* col, const void* val, int dtype,
+                      const int64_t* perm, int nlevels,
+                      const gs_level_data* levels, const gs_opts* opts);
+
+/* Change the storage precision of the installed preconditioner (GS_PREC_*):
+ * the factors, E, F and W are re-uploaded from the host copy.  FGMRES,
+ * residuals and orthogonalisation stay float64.  Real dtype only for
+ * F32/BF16.  Errors: GS_ESTATE, GS_EINVAL, GS_EDEVICE. */
+int gs_set_precision(gs_ctx* ctx, int precision);
+
+/* ---------------------------------------------------------------- apply */
+/* y = M^{-1} x (Alg. 2 with no inner iteration at level 0).  x, y: device,
+ * n values of the context's dtype, original (unpermuted) ordering; they must
+ * not alias.  Asynchronous on the context's stream.
+ * Errors: GS_ESTATE (no setup), GS_EINVAL (NULL or aliasing), GS_EDEVICE. */
+int gs_apply(gs_ctx* ctx, const void* x, void* y);
+
+/* Same as gs_apply for `nrhs` vectors stored one after another
+ * (x + j*n, y + j*n).  Errors as gs_apply. */
+int gs_apply_many(gs_ctx* ctx, int nrhs, const void* x, void* y);
+
+/* ---------------------------------------------------------------- measurement */
+/* Run `reps` applies of x (as gs_apply) with a HIP event pair recorded on the
+ * context's stream around every kernel launch.  On return *nsteps holds the
+ * launches per apply (<= cap) and, for launch i in launch order, step_ms[i] is
+ * its mean duration in ms and step_bytes[i] its compulsory HBM bytes (every
+ * stored array read once, every vector entry read or written once per touch).
+ * Labels: gs_apply_step_label.  For measurement only; synchronises.
+ * Errors: GS_ESTATE, GS_EINVAL (also cap too small), GS_EDEVICE. */
+int gs_apply_profile(gs_ctx* ctx, const void* x, void* y, int reps, double* step_ms,
+                     double* step_bytes, int cap, int* nsteps);
+/* Label of launch i of the last gs_apply_profile ("" if out of range). */
+const char* gs_apply_step_label(const gs_ctx* ctx, int i);
+
+/* Event probe: after this call every launch of kernel class `kind`
+ * (0 = block triangular solves of level 0, 1 = those of the other levels,
+ * 2 = interface step, 3 = low-rank update, 4 = permutations; -1 = off) made by
+ * later gs_apply / gs_solve calls is bracketed by a HIP event pair on the
+ * context's stream, up to max_launches launches.  gs_probe_read synchronises
+ * and returns the probed launch count, their summed duration (ms) and summed
+ * compulsory bytes since the previous read.  Errors: GS_ESTATE, GS_EINVAL. */
+int gs_probe_enable(gs_ctx* ctx, int kind, int max_launches);
+int gs_probe_read(gs_ctx* ctx, int64_t* launches, double* total_ms, double* total_bytes);
+
+/* ---------------------------------------------------------------- solve */
+/* Solve A x = b by right-preconditioned FGMRES(m) with M^{-1} applied every
+ * iteration (Sec. 4.1, Sec. 5).  b, x: device, n values, original ordering;
+ * x holds the initial guess on entry and the iterate on exit.  Stops when the
+ * float64 true residual ||b - A x|| / ||b|| <= tol.  Synchronises the stream.
+ * Returns GS_OK, or GS_NOT_CONVERGED after opts.maxit iterations with the
+ * best iterate in x.  info may be NULL.  Errors: GS_ESTATE, GS_EINVAL,
+ * GS_EDEVICE. */
+int gs_solve(gs_ctx* ctx, const void* b, void* x, double tol, gs_info* info);
+
+/* Copy the setup statistics (sizes, ranks, depths, fill, timings). */
+int gs_get_info(const gs_ctx* ctx, gs_info* info);
+
+/* ---------------------------------------------------------------- host stages */
+/* Multilevel geometric vertex-separator reordering of a grid operator
+ * (Alg. 3, Sec. 3.2).  Host only; usable without a device.
+ *  perm:       out, n entries, perm[new] = old
+ *  level_start:out, levels+2 entries: start of B_0..B_{L-1}, C_last, n
+ *  nlevels:    out, L
+ *  block_ptr:  out, global block boundaries of all L+1 segments, each
+ *              segment's list [b_0, ..., b_nb] stored one after another
+ *  block_count:out, L+1 entries: blocks per segment
+ *  block_cap:  capacity of block_ptr (n + levels + 2 always suffices)
+ * Errors: GS_EINVAL. */
+int gs_partition_grid(int ndim, const int32_t* dims, int nparts, int levels,
+                      int64_t n, const int64_t* rowptr, const int32_t* col,
+                      int64_t* perm, int64_t* level_start, int* nlevels,
+                      int64_t* block_ptr, int64_t* block_count,
+                      int64_t block_cap);
+
+/* Incomplete LU of one square host CSR matrix (ILUT(tau, lfil) or ILU(0),
+ * row-wise IKJ).  Host only.  L (strictly lower, unit diagonal implied) and U
+ * (upper with diagonal) are written to caller arrays of capacity l_cap and
+ * u_cap entries (rowptr arrays need n+1).  Errors: GS_EINVAL (also when a
+ * capacity is too small), GS_EZEROPIVOT. */
+int gs_ilu(int64_t n, const int64_t* rowptr, const int32_t* col,
+           const void* val, int dtype, int kind, double tau, int lfil,
+           int64_t* l_rowptr, int32_t* l_col, void* l_val, int64_t l_cap,
+           int64_t* u_rowptr, int32_t* u_col, void* u_val, int64_t u_cap);
+
+/* Copy out the installed preconditioner's level `l` (0..L) as host arrays
+ * (the format of gs_level_data; caller supplies arrays of the sizes
+ * reported by gs_get_level_sizes).  For checkpointing and inspection.
+ * sizes[0..7] = d, s, nblocks, nnz(L), nnz(U), nnz(E), nnz(F), k. */
+int gs_get_level_sizes(const gs_ctx* ctx, int l, int64_t* sizes);
+int gs_get_level(const gs_ctx* ctx, int l, int64_t* block_ptr,
+                 int64_t* l_rowptr, int32_t* l_col, void* l_val,
+                 int64_t* u_rowptr, int32_t* u_col, void* u_val,
+                 int64_t* e_rowptr, int32_t* e_col, void* e_val,
+                 int64_t* f_rowptr, int32_t* f_col, void* f_val,
+                 void* w, void* h);
+/* perm: n entries (perm[new] = old). */
+int gs_get_perm(const gs_ctx* ctx, int64_t* perm);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GEMSLR_H */

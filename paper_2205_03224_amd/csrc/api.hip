@@ -1,0 +1,949 @@
+// Context, low-rank setup on the GPU (thick-restart Arnoldi), FGMRES and the
+// C ABI declared in include/gemslr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "device.h"
+#include "engine.h"
+
+using gs::cplx;
+using gs::Error;
+
+struct gs_ctx {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int dtype = GS_F64;
+  int precision = GS_PREC_F64;
+  bool ready = false;
+  gs_opts opts{};
+  std::unique_ptr<gs::HostSetup<double>> hd;
+  std::unique_ptr<gs::HostSetup<cplx>> hz;
+  std::unique_ptr<gs::Engine> eng;
+  // solve data: permuted A on the device and FGMRES work space
+  std::unique_ptr<gs::DevMem> amem;
+  int32_t* a_rp = nullptr;
+  int32_t* a_ci = nullptr;
+  void* a_v = nullptr;
+  int32_t* perm = nullptr;
+  std::unique_ptr<gs::DevMem> wmem;
+  int w_m = -1;
+  void* pin = nullptr;  // pinned staging for small device->host reads
+  size_t pin_bytes = 0;
+  gs_info info{};
+  std::vector<std::string> step_labels;  // of the last gs_apply_profile
+};
+
+static std::string g_create_error;
+
+namespace gs {
+
+#define HIPCHK(x) hipcheck((x), #x)
+
+template <class T> struct DevOf;
+template <> struct DevOf<double> { using type = double; };
+template <> struct DevOf<cplx> { using type = dcplx; };
+
+static void* pinned(gs_ctx* c, size_t bytes) {
+  if (bytes > c->pin_bytes) {
+    if (c->pin) (void)hipHostFree(c->pin);
+    c->pin = nullptr;
+    HIPCHK(hipHostMalloc(&c->pin, bytes, hipHostMallocDefault));
+    c->pin_bytes = bytes;
+  }
+  return c->pin;
+}
+
+template <class T> static HostSetup<T>& host(gs_ctx* c);
+template <> HostSetup<double>& host<double>(gs_ctx* c) { return *c->hd; }
+template <> HostSetup<cplx>& host<cplx>(gs_ctx* c) { return *c->hz; }
+
+// ------------------------------------------------------------ small helpers
+template <class DT> static DT from_host(double v);
+template <> double from_host<double>(double v) { return v; }
+template <> dcplx from_host<dcplx>(double v) { return mk(v, 0.0); }
+
+// CGS with one re-orthogonalisation pass: w <- w - V (V^H w), twice; the
+// coefficients of both passes are added into hacc (if not null).
+template <class DT>
+static void cgs2(const DT* V, int64_t ld, int ncol, DT* w, int64_t n, DT* partial, DT* h,
+                 DT* hacc, hipStream_t st) {
+  if (hacc) launch_fill<DT>(hacc, from_host<DT>(0.0), ncol, st);
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_multidot<DT>(V, ld, ncol, w, n, partial, h, st);
+    launch_gemv_sub<DT>(V, ld, ncol, h, w, n, hacc, st);
+  }
+}
+
+// ------------------------------------------------------------ low-rank setup
+// Thick-restart (Krylov-Schur) Arnoldi on Ĝ_l on the GPU (Sec. 2.3, Sec. 4.2):
+// cycle length m = 2k, Ritz pairs accepted when |b^H y| <= tol |theta|.
+// Orthogonalisation and the basis are float64 / complex128 whatever the
+// storage precision of the factors used inside Ĝ_l.
+template <class T>
+static void lowrank_level(gs_ctx* c, int l, int kreq) {
+  using DT = typename DevOf<T>::type;
+  const bool real = std::is_same<T, double>::value;
+  HostSetup<T>& S = host<T>(c);
+  HostLevel<T>& h = S.lv[l];
+  const hipStream_t st = c->stream;
+  const int64_t s = h.s;
+  const int k = (int)std::min<int64_t>(kreq, s);
+  if (k <= 0) return;
+  int m = (int)std::min<int64_t>(2 * (int64_t)k, s);
+  if (m <= k) m = (int)std::min<int64_t>(k + 1, s);
+  DevMem mem;
+  DT* V = mem.alloc<DT>((size_t)s * (m + 1));
+  DT* w = mem.alloc<DT>(s);
+  DT* tmp = mem.alloc<DT>((size_t)s * (m + 1));
+  DT* hd = mem.alloc<DT>(m + 1);
+  DT* hacc = mem.alloc<DT>(m + 1);
+  DT* part = mem.alloc<DT>((size_t)256 * (m + 1));
+  double* npart = mem.alloc<double>(256);
+  double* nrm = mem.alloc<double>(2);
+  DT* Gd = mem.alloc<DT>((size_t)m * m);
+  std::vector<DT> hv(s);
+  std::vector<double> v0(s);
+  auto upload_start = [&](uint64_t sd, DT* dst) {
+    start_vector(sd, s, v0.data());
+    for (int64_t i = 0; i < s; ++i) hv[i] = from_host<DT>(v0[i]);
+    HIPCHK(hipMemcpyAsync(dst, hv.data(), s * sizeof(DT), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  };
+  const uint64_t seed = c->opts.seed + (uint64_t)l;
+  upload_start(seed, V);
+  launch_norm<DT>(V, s, npart, nrm, st);
+  launch_scale_inv<DT>(V, nrm, V, s, st);
+
+  std::vector<cplx> Sm((size_t)(m + 1) * m, cplx(0));  // Krylov decomposition G V = V S
+  auto Sat = [&](int i, int j) -> cplx& { return Sm[(size_t)j * (m + 1) + i]; };
+  const size_t stage_bytes = (m + 1) * sizeof(DT) + 2 * sizeof(double);
+  int j0 = 0, nmv = 0;
+  const int maxcyc = std::max(1, c->opts.arnoldi_max_cycles);
+  for (int cycle = 0; cycle < maxcyc; ++cycle) {
+    for (int j = j0; j < m; ++j) {
+      c->eng->ghat(l, V + (size_t)j * s, w);
+      ++nmv;
+      launch_norm<DT>(w, s, npart, nrm + 1, st);
+      cgs2<DT>(V, s, j + 1, w, s, part, hd, hacc, st);
+      launch_norm<DT>(w, s, npart, nrm, st);
+      char* pb = (char*)pinned(c, stage_bytes);
+      HIPCHK(hipMemcpyAsync(pb, hacc, (j + 1) * sizeof(DT), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(pb + (m + 1) * sizeof(DT), nrm, 2 * sizeof(double),
+                            hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      const DT* hh = (const DT*)pb;
+      const double* nn = (const double*)(pb + (m + 1) * sizeof(DT));
+      for (int i = 0; i <= j; ++i) {
+        cplx v;
+        std::memcpy((void*)&v, &hh[i], sizeof(DT));
+        if (real) v = cplx(((const double*)hh)[i], 0.0);
+        Sat(i, j) = v;
+      }
+      const double beta = nn[0], wn = nn[1];
+      DT* vnext = V + (size_t)(j + 1) * s;
+      if (beta > 1e-12 * wn) {
+        Sat(j + 1, j) = beta;
+        launch_scale_inv<DT>(w, nrm, vnext, s, st);
+      } else {
+        Sat(j + 1, j) = 0.0;
+        if (j + 1 < m) {
+          upload_start(c->opts.seed + (uint64_t)l + 0x5DEECE66DULL * (uint64_t)nmv, vnext);
+          cgs2<DT>(V, s, j + 1, vnext, s, part, hd, nullptr, st);
+          launch_norm<DT>(vnext, s, npart, nrm, st);
+          launch_scale_inv<DT>(vnext, nrm, vnext, s, st);
+        } else {
+          launch_fill<DT>(vnext, from_host<DT>(0.0), s, st);
+        }
+      }
+    }
+    // Schur form of the m x m Rayleigh matrix, wanted values first
+    std::vector<cplx> Tm((size_t)m * m), Q;
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) Tm[(size_t)j * m + i] = Sat(i, j);
+    const std::vector<cplx> Sorig = Tm;
+    schur_complex(m, Tm, Q);
+    std::vector<cplx> theta(m);
+    for (int i = 0; i < m; ++i) theta[i] = Tm[(size_t)i * m + i];
+    std::vector<int> sel = select_wanted(theta, k, real);
+    schur_reorder(m, Tm, Q, sel);
+    int kk = 0;
+    for (int x : sel) kk += x;
+    std::vector<cplx> thk(kk);
+    for (int i = 0; i < kk; ++i) thk[i] = Tm[(size_t)i * m + i];
+    // residuals of the wanted Ritz pairs: |b Q_k y_i|
+    std::vector<cplx> Tk((size_t)kk * kk), Y;
+    for (int j = 0; j < kk; ++j)
+      for (int i = 0; i < kk; ++i) Tk[(size_t)j * kk + i] = Tm[(size_t)j * m + i];
+    triu_eigvecs(kk, Tk, Y);
+    std::vector<cplx> bq(kk, 0.0);
+    for (int j = 0; j < kk; ++j)
+      for (int i = 0; i < m; ++i) bq[j] += Sat(m, i) * Q[(size_t)j * m + i];
+    bool conv = true;
+    for (int i = 0; i < kk; ++i) {
+      cplx r = 0;
+      for (int j = 0; j < kk; ++j) r += bq[j] * Y[(size_t)i * kk + j];
+      if (std::abs(r) > c->opts.arnoldi_tol * std::abs(thk[i])) conv = false;
+    }
+    // basis G (m x kk) and R = G^H S G
+    std::vector<T> G((size_t)m * kk), R((size_t)kk * kk);
+    if (real) {
+      // real orthonormal basis of the conjugate-closed invariant subspace:
+      // pivoted Gram-Schmidt on [Re Q_k, Im Q_k]
+      std::vector<std::vector<double>> X;
+      for (int j = 0; j < kk; ++j) {
+        std::vector<double> re(m), im(m);
+        for (int i = 0; i < m; ++i) { re[i] = Q[(size_t)j * m + i].real(); im[i] = Q[(size_t)j * m + i].imag(); }
+        X.push_back(re);
+        X.push_back(im);
+      }
+      double first = -1;
+      for (int q = 0; q < kk; ++q) {
+        int best = -1;
+        double bn = -1;
+        for (size_t x = 0; x < X.size(); ++x) {
+          double nn2 = 0;
+          for (double e : X[x]) nn2 += e * e;
+          if (nn2 > bn) { bn = nn2; best = (int)x; }
+        }
+        bn = std::sqrt(bn);
+        if (first < 0) first = bn;
+        if (bn <= 1e-8 * first) throw Error(GS_EINVAL, "wanted Ritz set is not closed under conjugation");
+        std::vector<double> qv = X[best];
+        for (double& e : qv) e /= bn;
+        X.erase(X.begin() + best);
+        for (int pass = 0; pass < 2; ++pass)
+          for (auto& x : X) {
+            double d = 0;
+            for (int i = 0; i < m; ++i) d += qv[i] * x[i];
+            for (int i = 0; i < m; ++i) x[i] -= d * qv[i];
+          }
+        for (int i = 0; i < m; ++i) ((double*)G.data())[(size_t)q * m + i] = qv[i];
+      }
+      for (int b = 0; b < kk; ++b)
+        for (int a = 0; a < kk; ++a) {
+          double acc = 0;
+          for (int i = 0; i < m; ++i) {
+            double sg = 0;
+            for (int j = 0; j < m; ++j) sg += Sorig[(size_t)j * m + i].real() * ((double*)G.data())[(size_t)b * m + j];
+            acc += ((double*)G.data())[(size_t)a * m + i] * sg;
+          }
+          ((double*)R.data())[(size_t)b * kk + a] = acc;
+        }
+    } else {
+      for (int j = 0; j < kk; ++j)
+        for (int i = 0; i < m; ++i) std::memcpy((void*)&G[(size_t)j * m + i], &Q[(size_t)j * m + i], sizeof(cplx));
+      for (int j = 0; j < kk; ++j)
+        for (int i = 0; i < kk; ++i) std::memcpy((void*)&R[(size_t)j * kk + i], &Tm[(size_t)j * m + i], sizeof(cplx));
+    }
+    HIPCHK(hipMemcpyAsync(Gd, G.data(), G.size() * sizeof(DT), hipMemcpyHostToDevice, st));
+    const bool last = conv || cycle == maxcyc - 1 || kk >= m;
+    if (last) {
+      launch_gemm_small<DT>(V, s, m, Gd, kk, tmp, s, s, st);
+      h.W.resize((size_t)s * kk);
+      HIPCHK(hipMemcpyAsync(h.W.data(), tmp, h.W.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      h.k = kk;
+      h.H = correction_matrix<T>(kk, R, thk);
+      h.arnoldi_cycles = cycle + 1;
+      h.arnoldi_matvecs = nmv;
+      h.arnoldi_converged = conv ? 1 : 0;
+      c->eng->set_lowrank(l, kk, h.W.data(), h.H.data());
+      return;
+    }
+    // thick restart: V[:, :kk] = V_m G, V[:, kk] = v_{m+1}
+    launch_gemm_small<DT>(V, s, m, Gd, kk, tmp, s, s, st);
+    launch_copy<DT>(tmp, V, (int64_t)s * kk, st);
+    launch_copy<DT>(V + (size_t)m * s, V + (size_t)kk * s, s, st);
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<cplx> bg(kk, 0.0);
+    for (int j = 0; j < kk; ++j)
+      for (int i = 0; i < m; ++i) {
+        cplx gij;
+        if (real) gij = cplx(((double*)G.data())[(size_t)j * m + i], 0);
+        else std::memcpy((void*)&gij, &G[(size_t)j * m + i], sizeof(cplx));
+        bg[j] += Sat(m, i) * gij;
+      }
+    std::fill(Sm.begin(), Sm.end(), cplx(0));
+    for (int j = 0; j < kk; ++j)
+      for (int i = 0; i < kk; ++i) {
+        cplx r;
+        if (real) r = cplx(((double*)R.data())[(size_t)j * kk + i], 0);
+        else std::memcpy((void*)&r, &R[(size_t)j * kk + i], sizeof(cplx));
+        Sat(i, j) = r;
+      }
+    for (int j = 0; j < kk; ++j) Sat(kk, j) = bg[j];
+    j0 = kk;
+  }
+}
+
+// ------------------------------------------------------------ FGMRES
+template <class T>
+static int fgmres(gs_ctx* c, const void* b_user, void* x_user, double tol, gs_info* info) {
+  using DT = typename DevOf<T>::type;
+  const hipStream_t st = c->stream;
+  const int64_t n = host<T>(c).n;
+  const int m = std::max(1, c->opts.fgmres_restart);
+  const int maxit = std::max(1, c->opts.maxit);
+  const double t0 = now_s();
+  if (c->w_m != m || !c->wmem) {
+    c->wmem.reset();
+    c->wmem = std::make_unique<DevMem>();
+    c->w_m = m;
+  }
+  DevMem& M = *c->wmem;
+  if (M.ptrs.empty()) {
+    M.alloc<DT>((size_t)n * (m + 1));  // V
+    M.alloc<DT>((size_t)n * m);        // Z
+    M.alloc<DT>(n);                    // w
+    M.alloc<DT>(n);                    // r
+    M.alloc<DT>(n);                    // xp
+    M.alloc<DT>(n);                    // bp
+    M.alloc<DT>(m + 1);                // h
+    M.alloc<DT>(m + 1);                // hacc
+    M.alloc<DT>((size_t)256 * (m + 1));// partial
+    M.alloc<double>(256);              // norm partials
+    M.alloc<double>(4);                // norms
+  }
+  DT* V = (DT*)M.ptrs[0];
+  DT* Z = (DT*)M.ptrs[1];
+  DT* w = (DT*)M.ptrs[2];
+  DT* r = (DT*)M.ptrs[3];
+  DT* xp = (DT*)M.ptrs[4];
+  DT* bp = (DT*)M.ptrs[5];
+  DT* hd = (DT*)M.ptrs[6];
+  DT* hacc = (DT*)M.ptrs[7];
+  DT* part = (DT*)M.ptrs[8];
+  double* npart = (double*)M.ptrs[9];
+  double* nrm = (double*)M.ptrs[10];
+  launch_permute<DT>((const DT*)b_user, c->perm, bp, n, false, st);
+  launch_permute<DT>((const DT*)x_user, c->perm, xp, n, false, st);
+  const DT* Av = (const DT*)c->a_v;
+  auto read_norm = [&]() {
+    double* pb = (double*)pinned(c, 64);
+    HIPCHK(hipMemcpyAsync(pb, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return pb[0];
+  };
+  launch_norm<DT>(bp, n, npart, nrm, st);
+  const double nb = read_norm();
+  int its = 0;
+  double relres = 0;
+  bool converged = false;
+  std::vector<T> Hh((size_t)(m + 1) * m), g(m + 1), sn(m), y(m);
+  std::vector<double> cs(m);
+  auto H_ = [&](int i, int j) -> T& { return Hh[(size_t)j * (m + 1) + i]; };
+  if (nb == 0) {
+    launch_fill<DT>(xp, from_host<DT>(0.0), n, st);
+    converged = true;
+  }
+  while (!converged) {
+    launch_residual<DT>(c->a_rp, c->a_ci, Av, xp, bp, r, n, st);
+    launch_norm<DT>(r, n, npart, nrm, st);
+    const double beta = read_norm();
+    relres = beta / nb;
+    if (relres <= tol) { converged = true; break; }
+    if (its >= maxit) break;
+    launch_scale_inv<DT>(r, nrm, V, n, st);
+    std::fill(Hh.begin(), Hh.end(), T(0));
+    std::fill(g.begin(), g.end(), T(0));
+    g[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      c->eng->apply(V + (size_t)j * n, Z + (size_t)j * n, true);
+      launch_spmv<DT>(c->a_rp, c->a_ci, Av, Z + (size_t)j * n, w, n, st);
+      cgs2<DT>(V, n, j + 1, w, n, part, hd, hacc, st);
+      launch_norm<DT>(w, n, npart, nrm, st);
+      launch_scale_inv<DT>(w, nrm, V + (size_t)(j + 1) * n, n, st);
+      char* pb = (char*)pinned(c, (m + 2) * sizeof(DT) + 16);
+      HIPCHK(hipMemcpyAsync(pb, hacc, (j + 1) * sizeof(DT), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(pb + (m + 1) * sizeof(DT), nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int i = 0; i <= j; ++i) std::memcpy((void*)&H_(i, j), pb + i * sizeof(DT), sizeof(DT));
+      double hn;
+      std::memcpy(&hn, pb + (m + 1) * sizeof(DT), sizeof(double));
+      H_(j + 1, j) = hn;
+      for (int i = 0; i < j; ++i) {
+        T t1 = cs[i] * H_(i, j) + sn[i] * H_(i + 1, j);
+        T t2 = -conjv(sn[i]) * H_(i, j) + cs[i] * H_(i + 1, j);
+        H_(i, j) = t1;
+        H_(i + 1, j) = t2;
+      }
+      // Givens rotation G = [[c, s], [-conj s, c]], c real, zeroing H(j+1, j)
+      const T a = H_(j, j), bb = H_(j + 1, j);
+      double cc;
+      T ss, rr;
+      if (absval(bb) == 0) { cc = 1; ss = T(0); rr = a; }
+      else if (absval(a) == 0) { cc = 0; ss = conjv(bb) / absval(bb); rr = T(absval(bb)); }
+      else {
+        const double tt = std::hypot(absval(a), absval(bb));
+        const T ph = a / absval(a);
+        cc = absval(a) / tt;
+        ss = ph * conjv(bb) / tt;
+        rr = ph * tt;
+      }
+      cs[j] = cc;
+      sn[j] = ss;
+      H_(j, j) = rr;
+      H_(j + 1, j) = T(0);
+      g[j + 1] = -conjv(ss) * g[j];
+      g[j] = cc * g[j];
+      ++its;
+      jend = j + 1;
+      if (absval(g[j + 1]) <= tol * nb || its >= maxit || hn == 0) break;
+    }
+    for (int i = jend - 1; i >= 0; --i) {
+      T sacc = g[i];
+      for (int q = i + 1; q < jend; ++q) sacc -= H_(i, q) * y[q];
+      y[i] = sacc / H_(i, i);
+    }
+    HIPCHK(hipMemcpyAsync(hd, y.data(), jend * sizeof(DT), hipMemcpyHostToDevice, st));
+    launch_gemv_add<DT>(Z, n, jend, hd, xp, n, st);
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  launch_permute<DT>(xp, c->perm, (DT*)x_user, n, true, st);
+  HIPCHK(hipStreamSynchronize(st));
+  c->info.its = its;
+  c->info.relres = relres;
+  c->info.converged = converged ? 1 : 0;
+  c->info.t_solve = now_s() - t0;
+  if (info) *info = c->info;
+  return converged ? GS_OK : GS_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------------ setup helpers
+template <class T>
+static void finish_setup(gs_ctx* c) {
+  HostSetup<T>& S = host<T>(c);
+  using DT = typename DevOf<T>::type;
+  // permuted A for the solver
+  c->amem = std::make_unique<DevMem>();
+  const CSR<T>& Ap = S.Ap;
+  std::vector<int32_t> rp(Ap.rp.begin(), Ap.rp.end());
+  std::vector<int32_t> p32(S.perm.begin(), S.perm.end());
+  c->a_rp = c->amem->alloc<int32_t>(rp.size());
+  c->a_ci = c->amem->alloc<int32_t>(Ap.ci.size());
+  c->a_v = c->amem->alloc<DT>(Ap.v.size());
+  c->perm = c->amem->alloc<int32_t>(p32.size());
+  HIPCHK(hipMemcpyAsync(c->a_rp, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->a_ci, Ap.ci.data(), Ap.ci.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->a_v, Ap.v.data(), Ap.v.size() * sizeof(DT), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->perm, p32.data(), p32.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->wmem.reset();
+  c->w_m = -1;
+  // statistics
+  gs_info& I = c->info;
+  I.nlevels = S.L();
+  I.nnz_lu = 0;
+  I.nnz_ef = 0;
+  I.nnz_a = S.A.nnz();
+  double lr = 0;
+  for (int l = 0; l <= S.L() && l <= GS_MAX_LEVELS; ++l) {
+    const HostLevel<T>& h = S.lv[l];
+    I.d[l] = h.d;
+    I.s[l] = h.s;
+    I.nblocks[l] = (int64_t)h.blocks.size() - 1;
+    I.k[l] = h.k;
+    I.arnoldi_cycles[l] = h.arnoldi_cycles;
+    I.arnoldi_matvecs[l] = h.arnoldi_matvecs;
+    I.arnoldi_converged[l] = h.arnoldi_converged;
+    I.nnz_lu += h.L.nnz() + h.U.nnz();
+    I.nnz_ef += h.E.nnz() + h.F.nnz();
+    lr += (double)h.s * h.k + (double)h.k * h.k;
+  }
+  I.fill = (double)I.nnz_lu / (double)std::max<int64_t>(1, I.nnz_a);
+  I.fill_lowrank = ((double)I.nnz_lu + lr) / (double)std::max<int64_t>(1, I.nnz_a);
+  c->eng->stats(&I, 0);
+  I.apply_bytes = c->eng->bytes_per_apply();
+  c->ready = true;
+}
+
+template <class T>
+static void copy_csr(int64_t nr, int64_t nc, const int64_t* rp, const int32_t* ci, const void* v,
+                     CSR<T>& out) {
+  out = CSR<T>();
+  out.nrows = nr;
+  out.ncols = nc;
+  out.rp.assign(rp, rp + nr + 1);
+  const int64_t nnz = rp[nr];
+  out.ci.assign(ci, ci + nnz);
+  out.v.resize(nnz);
+  if (nnz) std::memcpy((void*)out.v.data(), v, nnz * sizeof(T));
+}
+
+template <class T>
+static void setup_native(gs_ctx* c, int64_t n, const int64_t* rp, const int32_t* ci,
+                         const void* val, int levels, int nparts, int rank, double drop_tol) {
+  auto S = std::make_unique<HostSetup<T>>();
+  copy_csr<T>(n, n, rp, ci, val, S->A);
+  double t0 = now_s();
+  if (c->opts.grid_ndim <= 0)
+    throw Error(GS_EINVAL, "the geometric separator needs opts.grid_ndim / grid_dims");
+  Partition part = partition_grid(c->opts.grid_ndim, c->opts.grid_dims, nparts, levels, n, rp, ci);
+  if (part.L > GS_MAX_LEVELS) throw Error(GS_EINVAL, "too many levels");
+  double t1 = now_s();
+  extract_levels<T>(S->A, part, *S);
+  factor_levels<T>(*S, c->opts.ilu_kind, drop_tol, c->opts.lfil, c->opts.nthreads);
+  double t2 = now_s();
+  if (std::is_same<T, double>::value) c->hd.reset((HostSetup<double>*)S.release());
+  else c->hz.reset((HostSetup<cplx>*)S.release());
+  c->eng = make_engine(host<T>(c), c->precision, c->stream);
+  double t3 = now_s();
+  HostSetup<T>& H = host<T>(c);
+  for (int l = H.L() - 1; l >= 0; --l) {
+    if (l == H.L() - 1 && !c->opts.lowrank_last_level) continue;
+    lowrank_level<T>(c, l, rank);
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double t4 = now_s();
+  c->info = gs_info{};
+  c->info.t_partition = t1 - t0;
+  c->info.t_factor = t2 - t1;
+  c->info.t_layout = t3 - t2;
+  c->info.t_lowrank = t4 - t3;
+  finish_setup<T>(c);
+}
+
+template <class T>
+static void setup_explicit(gs_ctx* c, int64_t n, const int64_t* rp, const int32_t* ci,
+                           const void* val, const int64_t* perm, int nlevels,
+                           const gs_level_data* L) {
+  auto S = std::make_unique<HostSetup<T>>();
+  copy_csr<T>(n, n, rp, ci, val, S->A);
+  S->n = n;
+  S->perm.assign(perm, perm + n);
+  {
+    std::vector<char> seen(n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      if (perm[i] < 0 || perm[i] >= n || seen[perm[i]]) throw Error(GS_EINVAL, "perm is not a permutation");
+      seen[perm[i]] = 1;
+    }
+  }
+  S->Ap = permute(S->A, S->perm);
+  if (nlevels < 0 || nlevels > GS_MAX_LEVELS) throw Error(GS_EINVAL, "bad nlevels");
+  int64_t start = 0;
+  S->lv.resize(nlevels + 1);
+  for (int l = 0; l <= nlevels; ++l) {
+    const gs_level_data& a = L[l];
+    HostLevel<T>& h = S->lv[l];
+    h.start = start;
+    h.d = a.d;
+    h.s = n - start - a.d;
+    if (a.d < 0 || h.s < 0) throw Error(GS_EINVAL, "level sizes exceed n");
+    if (l == nlevels && h.s != 0) throw Error(GS_EINVAL, "level sizes do not add up to n");
+    if (a.nblocks < 0 || !a.block_ptr) throw Error(GS_EINVAL, "missing block_ptr");
+    h.blocks.assign(a.block_ptr, a.block_ptr + a.nblocks + 1);
+    if (h.blocks.front() != 0 || h.blocks.back() != a.d) throw Error(GS_EINVAL, "block_ptr must span [0, d]");
+    for (size_t b = 0; b + 1 < h.blocks.size(); ++b)
+      if (h.blocks[b + 1] < h.blocks[b]) throw Error(GS_EINVAL, "block_ptr not monotone");
+    if (a.d > 0) {
+      validate_csr(a.d, a.u_rowptr, a.u_col, true);
+      if (a.l_rowptr[a.d] > 0) validate_csr(a.d, a.l_rowptr, a.l_col, false);
+    }
+    copy_csr<T>(a.d, a.d, a.l_rowptr, a.l_col, a.l_val, h.L);
+    copy_csr<T>(a.d, a.d, a.u_rowptr, a.u_col, a.u_val, h.U);
+    if (h.s > 0) {
+      copy_csr<T>(h.s, a.d, a.e_rowptr, a.e_col, a.e_val, h.E);
+      copy_csr<T>(a.d, h.s, a.f_rowptr, a.f_col, a.f_val, h.F);
+      for (int32_t x : h.E.ci) if (x < 0 || x >= a.d) throw Error(GS_EINVAL, "E column out of range");
+      for (int32_t x : h.F.ci) if (x < 0 || x >= h.s) throw Error(GS_EINVAL, "F column out of range");
+      h.k = a.k;
+      if (a.k < 0 || a.k > h.s) throw Error(GS_EINVAL, "bad rank");
+      if (a.k > 0) {
+        h.W.resize((size_t)h.s * a.k);
+        h.H.resize((size_t)a.k * a.k);
+        std::memcpy((void*)h.W.data(), a.w, h.W.size() * sizeof(T));
+        std::memcpy((void*)h.H.data(), a.h, h.H.size() * sizeof(T));
+      }
+    } else {
+      h.E.nrows = 0; h.E.ncols = a.d;
+      h.F.nrows = a.d; h.F.ncols = 0;
+      h.F.rp.assign(a.d + 1, 0);
+    }
+    start += a.d;
+  }
+  if (std::is_same<T, double>::value) c->hd.reset((HostSetup<double>*)S.release());
+  else c->hz.reset((HostSetup<cplx>*)S.release());
+  c->eng = make_engine(host<T>(c), c->precision, c->stream);
+  c->info = gs_info{};
+  finish_setup<T>(c);
+}
+
+}  // namespace gs
+
+// ====================================================================== C ABI
+using namespace gs;
+
+#define GS_GUARD(ctx, ...)                                   \
+  try {                                                      \
+    __VA_ARGS__;                                             \
+  } catch (const Error& e) {                                 \
+    if (ctx) (ctx)->err = e.what();                          \
+    return e.code;                                           \
+  } catch (const std::bad_alloc&) {                          \
+    if (ctx) (ctx)->err = "host allocation failed";          \
+    return GS_ENOMEM;                                        \
+  } catch (const std::exception& e) {                        \
+    if (ctx) (ctx)->err = e.what();                          \
+    return GS_EINVAL;                                        \
+  }
+
+template <class T>
+static int ilu_host(int64_t n, const int64_t* rowptr, const int32_t* col, const void* val,
+                    int kind, double tau, int lfil, int64_t* lrp, int32_t* lci, void* lv,
+                    int64_t lcap, int64_t* urp, int32_t* uci, void* uv, int64_t ucap) {
+  CSR<T> B, L, U;
+  copy_csr<T>(n, n, rowptr, col, val, B);
+  if (kind == GS_ILU0) ilu0(B, L, U);
+  else if (kind == GS_ILUT) ilut(B, tau, lfil, L, U);
+  else throw Error(GS_EINVAL, "unknown ILU kind");
+  if (L.nnz() > lcap || U.nnz() > ucap) throw Error(GS_EINVAL, "output capacity too small");
+  std::copy(L.rp.begin(), L.rp.end(), lrp);
+  std::copy(U.rp.begin(), U.rp.end(), urp);
+  std::copy(L.ci.begin(), L.ci.end(), lci);
+  std::copy(U.ci.begin(), U.ci.end(), uci);
+  std::memcpy(lv, (const void*)L.v.data(), L.v.size() * sizeof(T));
+  std::memcpy(uv, (const void*)U.v.data(), U.v.size() * sizeof(T));
+  return GS_OK;
+}
+
+template <class T>
+static void level_sizes(const HostSetup<T>& S, int l, int64_t* z) {
+  if (l < 0 || l > S.L()) throw Error(GS_EINVAL, "level out of range");
+  const HostLevel<T>& h = S.lv[l];
+  z[0] = h.d;
+  z[1] = h.s;
+  z[2] = (int64_t)h.blocks.size() - 1;
+  z[3] = h.L.nnz();
+  z[4] = h.U.nnz();
+  z[5] = h.E.nnz();
+  z[6] = h.F.nnz();
+  z[7] = h.k;
+}
+
+template <class T>
+static void level_copy(const HostSetup<T>& S, int l, int64_t* bp, int64_t* lrp, int32_t* lci,
+                       void* lv, int64_t* urp, int32_t* uci, void* uv, int64_t* erp, int32_t* eci,
+                       void* ev, int64_t* frp, int32_t* fci, void* fv, void* w, void* h) {
+  if (l < 0 || l > S.L()) throw Error(GS_EINVAL, "level out of range");
+  const HostLevel<T>& x = S.lv[l];
+  auto cp = [](const CSR<T>& m, int64_t* rp, int32_t* ci, void* v) {
+    if (rp) std::copy(m.rp.begin(), m.rp.end(), rp);
+    if (ci) std::copy(m.ci.begin(), m.ci.end(), ci);
+    if (v) std::memcpy(v, (const void*)m.v.data(), m.v.size() * sizeof(T));
+  };
+  if (bp) std::copy(x.blocks.begin(), x.blocks.end(), bp);
+  cp(x.L, lrp, lci, lv);
+  cp(x.U, urp, uci, uv);
+  if (x.s > 0) {
+    cp(x.E, erp, eci, ev);
+    cp(x.F, frp, fci, fv);
+  }
+  if (w && !x.W.empty()) std::memcpy(w, (const void*)x.W.data(), x.W.size() * sizeof(T));
+  if (h && !x.H.empty()) std::memcpy(h, (const void*)x.H.data(), x.H.size() * sizeof(T));
+}
+
+extern "C" {
+
+void gs_opts_default(gs_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->ilu_kind = GS_ILUT;
+  o->lfil = 10;
+  o->fgmres_restart = 50;
+  o->maxit = 1000;
+  o->arnoldi_tol = 1e-2;
+  o->arnoldi_max_cycles = 20;
+  o->lowrank_last_level = 1;
+  o->precision = GS_PREC_F64;
+  o->grid_ndim = 0;
+  o->seed = 0;
+  o->nthreads = 0;
+}
+
+int gs_create(gs_ctx** ctx, int device, void* stream) {
+  if (!ctx) return GS_EINVAL;
+  *ctx = nullptr;
+  auto c = std::make_unique<gs_ctx>();
+  gs_opts_default(&c->opts);
+  c->device = device;
+  if (device >= 0) {
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) {
+      g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+      return GS_EDEVICE;
+    }
+    c->stream = (hipStream_t)stream;
+  }
+  *ctx = c.release();
+  return GS_OK;
+}
+
+void gs_destroy(gs_ctx* c) {
+  if (!c) return;
+  if (c->device >= 0) {
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    c->eng.reset();
+    c->amem.reset();
+    c->wmem.reset();
+    if (c->pin) (void)hipHostFree(c->pin);
+  }
+  delete c;
+}
+
+const char* gs_last_error(const gs_ctx* c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+static int need_device(gs_ctx* c) {
+  if (!c) return GS_EINVAL;
+  if (c->device < 0) {
+    c->err = "host-only context";
+    return GS_ESTATE;
+  }
+  hipcheck(hipSetDevice(c->device), "hipSetDevice");
+  return GS_OK;
+}
+
+int gs_setup(gs_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col, const void* val,
+             int dtype, int levels, int nparts, int rank, double drop_tol, const gs_opts* opts) {
+  if (!c) return GS_EINVAL;
+  GS_GUARD(c, {
+    int r = need_device(c);
+    if (r) return r;
+    if (opts) c->opts = *opts;
+    if (dtype != GS_F64 && dtype != GS_C128) throw Error(GS_EINVAL, "dtype must be GS_F64 or GS_C128");
+    if (rank < 0 || levels < 1 || nparts < 1) throw Error(GS_EINVAL, "bad levels/nparts/rank");
+    if (!val) throw Error(GS_EINVAL, "NULL values");
+    validate_csr(n, rowptr, col, true);
+    c->ready = false;
+    c->eng.reset();
+    c->hd.reset();
+    c->hz.reset();
+    c->dtype = dtype;
+    c->precision = c->opts.precision;
+    if (dtype == GS_F64) setup_native<double>(c, n, rowptr, col, val, levels, nparts, rank, drop_tol);
+    else setup_native<cplx>(c, n, rowptr, col, val, levels, nparts, rank, drop_tol);
+    return GS_OK;
+  });
+}
+
+int gs_setup_explicit(gs_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col,
+                      const void* val, int dtype, const int64_t* perm, int nlevels,
+                      const gs_level_data* levels, const gs_opts* opts) {
+  if (!c) return GS_EINVAL;
+  GS_GUARD(c, {
+    int r = need_device(c);
+    if (r) return r;
+    if (opts) c->opts = *opts;
+    if (dtype != GS_F64 && dtype != GS_C128) throw Error(GS_EINVAL, "dtype must be GS_F64 or GS_C128");
+    if (!perm || !levels || !val) throw Error(GS_EINVAL, "NULL argument");
+    validate_csr(n, rowptr, col, false);
+    c->ready = false;
+    c->eng.reset();
+    c->hd.reset();
+    c->hz.reset();
+    c->dtype = dtype;
+    c->precision = c->opts.precision;
+    if (dtype == GS_F64) setup_explicit<double>(c, n, rowptr, col, val, perm, nlevels, levels);
+    else setup_explicit<cplx>(c, n, rowptr, col, val, perm, nlevels, levels);
+    return GS_OK;
+  });
+}
+
+int gs_set_precision(gs_ctx* c, int precision) {
+  if (!c) return GS_EINVAL;
+  GS_GUARD(c, {
+    int r = need_device(c);
+    if (r) return r;
+    if (!c->ready) throw Error(GS_ESTATE, "no setup");
+    if (precision == c->precision) return GS_OK;
+    c->eng.reset();
+    if (c->dtype == GS_F64) c->eng = make_engine(*c->hd, precision, c->stream);
+    else c->eng = make_engine(*c->hz, precision, c->stream);
+    c->precision = precision;
+    c->eng->stats(&c->info, 0);
+    c->info.apply_bytes = c->eng->bytes_per_apply();
+    return GS_OK;
+  });
+}
+
+int gs_apply(gs_ctx* c, const void* x, void* y) { return gs_apply_many(c, 1, x, y); }
+
+int gs_apply_many(gs_ctx* c, int nrhs, const void* x, void* y) {
+  if (!c) return GS_EINVAL;
+  GS_GUARD(c, {
+    int r = need_device(c);
+    if (r) return r;
+    if (!c->ready) throw Error(GS_ESTATE, "apply before setup");
+    if (!x || !y || nrhs < 0) throw Error(GS_EINVAL, "NULL vector");
+    const int64_t n = c->dtype == GS_F64 ? c->hd->n : c->hz->n;
+    const size_t vb = c->dtype == GS_F64 ? 8 : 16;
+    const char* xb = (const char*)x;
+    char* yb = (char*)y;
+    const size_t bytes = (size_t)n * vb * (size_t)nrhs;
+    if (xb < yb + bytes && yb < xb + bytes) throw Error(GS_EINVAL, "x and y alias");
+    for (int j = 0; j < nrhs; ++j) c->eng->apply(xb + (size_t)j * n * vb, yb + (size_t)j * n * vb, false);
+    hipcheck(hipGetLastError(), "kernel launch");
+    return GS_OK;
+  });
+}
+
+int gs_apply_profile(gs_ctx* c, const void* x, void* y, int reps, double* step_ms,
+                     double* step_bytes, int cap, int* nsteps) {
+  if (!c) return GS_EINVAL;
+  GS_GUARD(c, {
+    int r = need_device(c);
+    if (r) return r;
+    if (!c->ready) throw Error(GS_ESTATE, "apply before setup");
+    if (!x || !y || !step_ms || !step_bytes || !nsteps || reps < 1) throw Error(GS_EINVAL, "bad argument");
+    std::vector<double> ms, by;
+    std::vector<std::string> lab;
+    const int ns = c->eng->profile(x, y, reps, ms, by, lab);
+    if (ns > cap) throw Error(GS_EINVAL, "cap smaller than the number of launches");
+    std::copy(ms.begin(), ms.end(), step_ms);
+    std::copy(by.begin(), by.end(), step_bytes);
+    c->step_labels = lab;
+    *nsteps = ns;
+    return GS_OK;
+  });
+}
+
+const char* gs_apply_step_label(const gs_ctx* c, int i) {
+  if (!c || i < 0 || i >= (int)c->step_labels.size()) return "";
+  return c->step_labels[i].c_str();
+}
+
+int gs_probe_enable(gs_ctx* c, int kind, int max_launches) {
+  if (!c) return GS_EINVAL;
+  GS_GUARD(c, {
+    int r = need_device(c);
+    if (r) return r;
+    if (!c->ready) throw Error(GS_ESTATE, "no setup");
+    if (max_launches < 0) throw Error(GS_EINVAL, "max_launches < 0");
+    c->eng->probe_enable(kind, max_launches);
+    return GS_OK;
+  });
+}
+
+int gs_probe_read(gs_ctx* c, int64_t* launches, double* total_ms, double* total_bytes) {
+  if (!c || !launches || !total_ms || !total_bytes) return GS_EINVAL;
+  GS_GUARD(c, {
+    int r = need_device(c);
+    if (r) return r;
+    if (!c->ready) throw Error(GS_ESTATE, "no setup");
+    c->eng->probe_read(launches, total_ms, total_bytes);
+    return GS_OK;
+  });
+}
+
+int gs_solve(gs_ctx* c, const void* b, void* x, double tol, gs_info* info) {
+  if (!c) return GS_EINVAL;
+  GS_GUARD(c, {
+    int r = need_device(c);
+    if (r) return r;
+    if (!c->ready) throw Error(GS_ESTATE, "solve before setup");
+    if (!b || !x) throw Error(GS_EINVAL, "NULL vector");
+    if (!(tol > 0)) throw Error(GS_EINVAL, "tol must be positive");
+    if (c->dtype == GS_F64) return fgmres<double>(c, b, x, tol, info);
+    return fgmres<cplx>(c, b, x, tol, info);
+  });
+}
+
+int gs_get_info(const gs_ctx* c, gs_info* info) {
+  if (!c || !info) return GS_EINVAL;
+  if (!c->ready) return GS_ESTATE;
+  *info = c->info;
+  return GS_OK;
+}
+
+int gs_partition_grid(int ndim, const int32_t* dims, int nparts, int levels, int64_t n,
+                      const int64_t* rowptr, const int32_t* col, int64_t* perm,
+                      int64_t* level_start, int* nlevels, int64_t* block_ptr,
+                      int64_t* block_count, int64_t block_cap) {
+  gs_ctx* none = nullptr;
+  GS_GUARD(none, {
+    if (!perm || !level_start || !nlevels || !block_ptr || !block_count)
+      throw Error(GS_EINVAL, "NULL output");
+    validate_csr(n, rowptr, col, false);
+    Partition p = partition_grid(ndim, dims, nparts, levels, n, rowptr, col);
+    int64_t need = 0;
+    for (auto& b : p.blocks) need += (int64_t)b.size();
+    if (need > block_cap) throw Error(GS_EINVAL, "block_cap too small");
+    std::copy(p.perm.begin(), p.perm.end(), perm);
+    std::copy(p.level_start.begin(), p.level_start.end(), level_start);
+    *nlevels = p.L;
+    int64_t pos = 0;
+    for (size_t l = 0; l < p.blocks.size(); ++l) {
+      block_count[l] = (int64_t)p.blocks[l].size() - 1;
+      for (int64_t x : p.blocks[l]) block_ptr[pos++] = x;
+    }
+    return GS_OK;
+  });
+}
+
+int gs_ilu(int64_t n, const int64_t* rowptr, const int32_t* col, const void* val, int dtype,
+           int kind, double tau, int lfil, int64_t* l_rowptr, int32_t* l_col, void* l_val,
+           int64_t l_cap, int64_t* u_rowptr, int32_t* u_col, void* u_val, int64_t u_cap) {
+  gs_ctx* none = nullptr;
+  GS_GUARD(none, {
+    if (!val || !l_rowptr || !l_col || !l_val || !u_rowptr || !u_col || !u_val)
+      throw Error(GS_EINVAL, "NULL argument");
+    validate_csr(n, rowptr, col, false);
+    if (dtype == GS_F64)
+      return ilu_host<double>(n, rowptr, col, val, kind, tau, lfil, l_rowptr, l_col, l_val, l_cap,
+                              u_rowptr, u_col, u_val, u_cap);
+    if (dtype == GS_C128)
+      return ilu_host<cplx>(n, rowptr, col, val, kind, tau, lfil, l_rowptr, l_col, l_val, l_cap,
+                            u_rowptr, u_col, u_val, u_cap);
+    throw Error(GS_EINVAL, "bad dtype");
+  });
+}
+
+int gs_get_level_sizes(const gs_ctx* c, int l, int64_t* sizes) {
+  if (!c || !sizes) return GS_EINVAL;
+  if (!c->ready) return GS_ESTATE;
+  gs_ctx* cc = const_cast<gs_ctx*>(c);
+  GS_GUARD(cc, {
+    if (c->dtype == GS_F64) level_sizes(*c->hd, l, sizes);
+    else level_sizes(*c->hz, l, sizes);
+    return GS_OK;
+  });
+}
+
+int gs_get_level(const gs_ctx* c, int l, int64_t* block_ptr, int64_t* l_rowptr, int32_t* l_col,
+                 void* l_val, int64_t* u_rowptr, int32_t* u_col, void* u_val, int64_t* e_rowptr,
+                 int32_t* e_col, void* e_val, int64_t* f_rowptr, int32_t* f_col, void* f_val,
+                 void* w, void* h) {
+  if (!c) return GS_EINVAL;
+  if (!c->ready) return GS_ESTATE;
+  gs_ctx* cc = const_cast<gs_ctx*>(c);
+  GS_GUARD(cc, {
+    if (c->dtype == GS_F64)
+      level_copy(*c->hd, l, block_ptr, l_rowptr, l_col, l_val, u_rowptr, u_col, u_val, e_rowptr,
+                 e_col, e_val, f_rowptr, f_col, f_val, w, h);
+    else
+      level_copy(*c->hz, l, block_ptr, l_rowptr, l_col, l_val, u_rowptr, u_col, u_val, e_rowptr,
+                 e_col, e_val, f_rowptr, f_col, f_val, w, h);
+    return GS_OK;
+  });
+}
+
+int gs_get_perm(const gs_ctx* c, int64_t* perm) {
+  if (!c || !perm) return GS_EINVAL;
+  if (!c->ready) return GS_ESTATE;
+  const std::vector<int64_t>& p = c->dtype == GS_F64 ? c->hd->perm : c->hz->perm;
+  std::copy(p.begin(), p.end(), perm);
+  return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// Device-side types, kernel argument blocks and launcher declarations of
+// libgemslr.  Shared by the kernels (kernels.hip) and the host orchestration
+// (gemslr.hip); not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+// ------------------------------------------------------------ scalar types
+struct dcplx {
+  double x, y;
+};
+__host__ __device__ inline dcplx mk(double a, double b) { dcplx r; r.x = a; r.y = b; return r; }
+__host__ __device__ inline dcplx operator+(dcplx a, dcplx b) { return mk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline dcplx operator-(dcplx a, dcplx b) { return mk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline dcplx operator-(dcplx a) { return mk(-a.x, -a.y); }
+__host__ __device__ inline dcplx operator*(dcplx a, dcplx b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline dcplx operator*(dcplx a, double s) { return mk(a.x * s, a.y * s); }
+__host__ __device__ inline dcplx& operator+=(dcplx& a, dcplx b) { a = a + b; return a; }
+__host__ __device__ inline dcplx& operator-=(dcplx& a, dcplx b) { a = a - b; return a; }
+__host__ __device__ inline dcplx& operator*=(dcplx& a, dcplx b) { a = a * b; return a; }
+__host__ __device__ inline dcplx conj(dcplx a) { return mk(a.x, -a.y); }
+__host__ __device__ inline double conj(double a) { return a; }
+__host__ __device__ inline float conj(float a) { return a; }
+__host__ __device__ inline double norm2(dcplx a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline double norm2(double a) { return a * a; }
+__host__ __device__ inline float norm2(float a) { return a * a; }
+
+// bfloat16 storage (upper half of a float32, round-to-nearest-even on the
+// host when packing)
+struct bf16 {
+  uint16_t u;
+};
+
+// conversions between storage, compute and vector types
+__device__ inline double cvt_d(double a) { return a; }
+__device__ inline double cvt_d(float a) { return (double)a; }
+__device__ inline float cvt_f(float a) { return a; }
+__device__ inline float cvt_f(double a) { return (float)a; }
+__device__ inline float cvt_f(bf16 a) { return __uint_as_float(((uint32_t)a.u) << 16); }
+
+template <class To, class From> struct Cvt;
+template <> struct Cvt<double, double> { __device__ static double f(double a) { return a; } };
+template <> struct Cvt<float, float> { __device__ static float f(float a) { return a; } };
+template <> struct Cvt<float, double> { __device__ static float f(double a) { return (float)a; } };
+template <> struct Cvt<double, float> { __device__ static double f(float a) { return (double)a; } };
+template <> struct Cvt<float, bf16> { __device__ static float f(bf16 a) { return __uint_as_float(((uint32_t)a.u) << 16); } };
+template <> struct Cvt<dcplx, dcplx> { __device__ static dcplx f(dcplx a) { return a; } };
+template <class To, class From> __device__ inline To cvt(From a) { return Cvt<To, From>::f(a); }
+
+// Precision traits: V = stored factor/E/F/W value, C = compute, X = element
+// of the working vector, D = stored inverse diagonal, O = element of the
+// user-facing vectors (float64 or complex128).
+struct PF64  { using V = double; using C = double; using X = double; using D = double; using O = double; };
+struct PC128 { using V = dcplx;  using C = dcplx;  using X = dcplx;  using D = dcplx;  using O = dcplx; };
+struct PF32  { using V = float;  using C = float;  using X = float;  using D = float;  using O = double; };
+struct PBF16 { using V = bf16;   using C = float;  using X = float;  using D = float;  using O = double; };
+
+// ------------------------------------------------------------ layouts
+// One triangle (L or U) of one level, all diagonal blocks, in the
+// level-scheduled "stage" layout: each block's rows are grouped by
+// wavefront level, each level cut into stages of at most 64 rows; inside a
+// stage rows are sorted by entry count (descending) and the entries are
+// stored slot-major (the j-th entry of every row that has one, then the
+// (j+1)-th ...), so the 64 lanes of a wave read consecutive addresses.
+template <class P>
+struct TriDev {
+  const int32_t* blk_stage;  // nb+1: stage range of each block
+  const int32_t* stage_row;  // nstages+1: row-slot offsets
+  const int32_t* stage_ent;  // nstages+1: entry offsets
+  const uint32_t* rowinfo;   // per row slot: block-local row | count << 16
+  const typename P::D* dinv; // per row slot, U only: 1/u_ii
+  const typename P::V* val;  // entries
+  const uint16_t* col;       // block-local column of each entry
+};
+
+template <class P>
+struct CsrDev {
+  const int32_t* rp;
+  const int32_t* ci;
+  const typename P::V* v;
+};
+
+enum { TRI_DOWN = 0, TRI_UP = 1 };
+
+template <class P>
+struct TriArgs {
+  TriDev<P> lo, up;
+  const int32_t* blk_row;    // nb+1 block row starts (level-local)
+  typename P::X* t;          // working vector at this level's start
+  int64_t d;                 // rows of B_l
+  CsrDev<P> F;               // UP mode: F_l (rows of B_l, cols of C_l)
+  typename P::X* xg;         // scratch (d entries) when blocks exceed LDS
+  int32_t nb;
+};
+
+template <class P>
+struct IfArgs {
+  CsrDev<P> E;               // s x d
+  typename P::X* t;          // working vector at this level's start
+  int64_t d, s;
+  int32_t k;
+  const typename P::V* W;    // s x k column-major
+  const typename P::C* H;    // k x k column-major, compute type
+  typename P::C* partial;    // gridDim x k partial sums of W^H z2
+  typename P::C* tprime;     // k: H (W^H z2)
+  uint32_t* counter;         // zero between launches
+};
+
+// ------------------------------------------------------------ launchers
+template <class P> void launch_trisolve(const TriArgs<P>& a, int mode, int maxslot,
+                                        int max_block_rows, hipStream_t st);
+template <class P> void launch_interface(const IfArgs<P>& a, hipStream_t st);
+template <class P> void launch_lowrank_update(typename P::X* tc, int64_t s, int k,
+                                              const typename P::V* W,
+                                              const typename P::C* tprime, hipStream_t st);
+template <class P> void launch_gather(const typename P::O* x, const int32_t* perm,
+                                      typename P::X* t, int64_t n, hipStream_t st);
+template <class P> void launch_scatter(const typename P::X* t, const int32_t* perm,
+                                       typename P::O* y, int64_t n, hipStream_t st);
+
+// float64 / complex128 vector kernels for FGMRES and Arnoldi
+template <class T> void launch_spmv(const int32_t* rp, const int32_t* ci, const T* v,
+                                    const T* x, T* y, int64_t n, hipStream_t st);
+// y = b - A x
+template <class T> void launch_residual(const int32_t* rp, const int32_t* ci, const T* v,
+                                        const T* x, const T* b, T* y, int64_t n, hipStream_t st);
+// h[c] = sum_i conj(V[i + c ld]) w[i], c < ncol (partials then a fixed-order sum)
+template <class T> void launch_multidot(const T* V, int64_t ld, int ncol, const T* w,
+                                        int64_t n, T* partial, T* h, hipStream_t st);
+// w -= V h (ncol columns); if hacc != null also hacc += h
+template <class T> void launch_gemv_sub(const T* V, int64_t ld, int ncol, const T* h,
+                                        T* w, int64_t n, T* hacc, hipStream_t st);
+// out[0] = ||w||_2 (partials then fixed-order sum)
+template <class T> void launch_norm(const T* w, int64_t n, double* partial, double* out,
+                                   hipStream_t st);
+// y = x / (*nrm)  (or zero when *nrm == 0)
+template <class T> void launch_scale_inv(const T* x, const double* nrm, T* y, int64_t n,
+                                         hipStream_t st);
+// x += Z y (ncol columns)
+template <class T> void launch_gemv_add(const T* Z, int64_t ld, int ncol, const T* y,
+                                        T* x, int64_t n, hipStream_t st);
+// Y = V G with V n x m (ld), G m x k column-major (host-computed), Y n x k (ldy)
+template <class T> void launch_gemm_small(const T* V, int64_t ld, int m, const T* G, int k,
+                                          T* Y, int64_t ldy, int64_t n, hipStream_t st);
+template <class T> void launch_fill(T* x, T v, int64_t n, hipStream_t st);
+// y[i] = x[perm[i]] (gather into reordered numbering) / y[perm[i]] = x[i]
+template <class T> void launch_permute(const T* x, const int32_t* perm, T* y, int64_t n,
+                                       bool scatter, hipStream_t st);
+template <class T> void launch_copy(const T* x, T* y, int64_t n, hipStream_t st);
+
+}  // namespace gs

@@ -1,0 +1,68 @@
+// Host-side engine interface of libgemslr (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+void hipcheck(hipError_t e, const char* what);
+double now_s();
+
+// Device allocations owned by one object, released together.
+struct DevMem {
+  std::vector<void*> ptrs;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem();
+  void* raw(size_t bytes);
+  template <class U> U* alloc(size_t n) { return (U*)raw(n * sizeof(U)); }
+};
+
+// Level-scheduled stage layout of one triangle of one level (host copy).
+template <class T>
+struct TriHost {
+  std::vector<int32_t> blk_stage{0}, stage_row{0}, stage_ent{0};
+  std::vector<uint32_t> rowinfo;
+  std::vector<T> dinv, val;
+  std::vector<uint16_t> col;
+  int maxslot = 0, depth = 0;
+};
+template <class T>
+TriHost<T> build_tri(const CSR<T>& M, const std::vector<int64_t>& blocks, bool upper);
+
+// The preconditioner on the device in one storage precision.  Vectors at
+// this interface hold float64 (real) or complex128 values.
+struct Engine {
+  virtual ~Engine() = default;
+  // y = M^{-1} x; permuted: x, y already in the reordered numbering
+  virtual void apply(const void* x, void* y, bool permuted) = 0;
+  // out = Ĝ_l v (s_l entries each)
+  virtual void ghat(int l, const void* v, void* out) = 0;
+  // install W_l (s_l x k) and H_l (k x k), host arrays of the value type
+  virtual void set_lowrank(int l, int k, const void* W, const void* H) = 0;
+  virtual void stats(gs_info* info, int vb_vec) = 0;
+  virtual double bytes_per_apply() const = 0;
+  // One apply per rep with HIP events around every launch; returns the number
+  // of launches and, per launch, mean ms, compulsory bytes and a label.
+  virtual int profile(const void* x, void* y, int reps, std::vector<double>& ms,
+                      std::vector<double>& bytes, std::vector<std::string>& labels) = 0;
+  // Bracket every later launch of kernel class `kind` with HIP events (up to
+  // max_launches); probe_read synchronises and returns count, ms and bytes.
+  virtual void probe_enable(int kind, int max_launches) = 0;
+  virtual void probe_read(int64_t* launches, double* ms, double* bytes) = 0;
+};
+
+// kernel classes for the measurement probe
+enum { KIND_TRI0 = 0, KIND_TRI = 1, KIND_INTERFACE = 2, KIND_LOWRANK = 3, KIND_PERM = 4 };
+
+std::unique_ptr<Engine> make_engine(const HostSetup<double>& S, int precision, hipStream_t st);
+std::unique_ptr<Engine> make_engine(const HostSetup<cplx>& S, int precision, hipStream_t st);
+
+}  // namespace gs

@@ -1,0 +1,520 @@
+// Host orchestration of libgemslr: the level-scheduled device layout, the
+// preconditioner apply (Alg. 2), the Ĝ_l matrix-vector product used by the
+// low-rank setup (Sec. 4.2), thick-restart Arnoldi on the GPU, FGMRES, and
+// the C ABI of include/gemslr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+
+#include "device.h"
+#include "engine.h"
+
+namespace gs {
+
+// ====================================================================== util
+
+void hipcheck(hipError_t e, const char* what) {
+  if (e != hipSuccess)
+    throw Error(e == hipErrorOutOfMemory ? GS_ENOMEM : GS_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(x) hipcheck((x), #x)
+
+DevMem::~DevMem() {
+  for (void* p : ptrs) (void)hipFree(p);
+}
+void* DevMem::raw(size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) throw Error(GS_ENOMEM, "hipMalloc failed: " + std::string(hipGetErrorString(e)));
+  ptrs.push_back(p);
+  return p;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// storage conversions host value -> device storage
+template <class V, class T> V to_store(const T& x);
+template <> double to_store<double, double>(const double& x) { return x; }
+template <> float to_store<float, double>(const double& x) { return (float)x; }
+template <> bf16 to_store<bf16, double>(const double& x) {
+  float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  bf16 b;
+  b.u = (uint16_t)(u >> 16);
+  return b;
+}
+template <> dcplx to_store<dcplx, cplx>(const cplx& x) { return mk(x.real(), x.imag()); }
+
+template <class V, class T>
+std::vector<V> convert(const std::vector<T>& h) {
+  std::vector<V> out(h.size());
+  for (size_t i = 0; i < h.size(); ++i) out[i] = to_store<V, T>(h[i]);
+  return out;
+}
+
+// ====================================================================== layout
+
+template <class T>
+TriHost<T> build_tri(const CSR<T>& M, const std::vector<int64_t>& blocks, bool upper) {
+  TriHost<T> h;
+  std::vector<int> lev;
+  std::vector<std::vector<int64_t>> bylev;
+  std::vector<int64_t> rows;
+  for (size_t b = 0; b + 1 < blocks.size(); ++b) {
+    const int64_t r0 = blocks[b], r1 = blocks[b + 1], nr = r1 - r0;
+    if (nr > 65535) throw Error(GS_EINVAL, "diagonal block larger than 65535 rows");
+    lev.assign(nr, 0);
+    int depth = 0;
+    auto visit = [&](int64_t i) {
+      int lv = 0;
+      for (int64_t p = M.rp[i]; p < M.rp[i + 1]; ++p) {
+        const int64_t c = M.ci[p];
+        if (c < r0 || c >= r1) throw Error(GS_EINVAL, "factor entry outside its diagonal block");
+        if (upper ? c > i : c < i) lv = std::max(lv, lev[c - r0] + 1);
+      }
+      lev[i - r0] = lv;
+      depth = std::max(depth, lv + 1);
+    };
+    if (!upper) for (int64_t i = r0; i < r1; ++i) visit(i);
+    else for (int64_t i = r1 - 1; i >= r0; --i) visit(i);
+    h.depth = std::max(h.depth, depth);
+    bylev.assign(depth, {});
+    for (int64_t i = r0; i < r1; ++i) bylev[lev[i - r0]].push_back(i);
+    auto offd_count = [&](int64_t i) {
+      int c = 0;
+      for (int64_t p = M.rp[i]; p < M.rp[i + 1]; ++p)
+        if (upper ? M.ci[p] > i : M.ci[p] < i) ++c;
+      return c;
+    };
+    for (auto& rl : bylev) {
+      std::stable_sort(rl.begin(), rl.end(), [&](int64_t x, int64_t y) {
+        return offd_count(x) > offd_count(y);
+      });
+      for (size_t c0 = 0; c0 < rl.size(); c0 += 64) {
+        const size_t c1 = std::min(rl.size(), c0 + 64);
+        int maxnz = 0;
+        std::vector<std::vector<std::pair<int32_t, T>>> ent(c1 - c0);
+        for (size_t q = c0; q < c1; ++q) {
+          const int64_t i = rl[q];
+          T diag = T(0);
+          bool hasdiag = false;
+          for (int64_t p = M.rp[i]; p < M.rp[i + 1]; ++p) {
+            const int64_t c = M.ci[p];
+            if (c == i) { diag = M.v[p]; hasdiag = true; }
+            else if (upper ? c > i : c < i) ent[q - c0].push_back({(int32_t)(c - r0), M.v[p]});
+          }
+          const int nz = (int)ent[q - c0].size();
+          if (nz > 65535) throw Error(GS_EINVAL, "row too long");
+          maxnz = std::max(maxnz, nz);
+          h.rowinfo.push_back((uint32_t)(i - r0) | ((uint32_t)nz << 16));
+          if (upper) {
+            if (!hasdiag || absval(diag) == 0.0)
+              throw Error(GS_EZEROPIVOT, "U factor has a zero or missing diagonal");
+            h.dinv.push_back(T(1) / diag);
+          }
+        }
+        h.maxslot = std::max(h.maxslot, maxnz);
+        for (int j = 0; j < maxnz; ++j)
+          for (size_t q = 0; q < ent.size(); ++q)
+            if ((int)ent[q].size() > j) {
+              h.val.push_back(ent[q][j].second);
+              h.col.push_back((uint16_t)ent[q][j].first);
+            }
+        h.stage_row.push_back((int32_t)h.rowinfo.size());
+        if (h.val.size() > (size_t)INT32_MAX) throw Error(GS_EINVAL, "factor too large");
+        h.stage_ent.push_back((int32_t)h.val.size());
+      }
+    }
+    h.blk_stage.push_back((int32_t)h.stage_row.size() - 1);
+  }
+  return h;
+}
+
+// ====================================================================== engine
+
+template <class P, class T>
+struct EngineT final : Engine {
+  using V = typename P::V;
+  using C = typename P::C;
+  using X = typename P::X;
+  using D = typename P::D;
+  using O = typename P::O;
+
+  struct Lev {
+    int64_t start = 0, d = 0, s = 0;
+    int nb = 0, maxslot = 0, max_block_rows = 0, k = 0;
+    int32_t* blk_row = nullptr;
+    TriDev<P> lo{}, up{};
+    CsrDev<P> E{}, F{};
+    V* W = nullptr;
+    C* H = nullptr;
+    C* partial = nullptr;
+    C* tprime = nullptr;
+    uint32_t* counter = nullptr;
+    int kcap = 0;
+    int64_t nnz_lu = 0, nnz_e = 0, nnz_f = 0, nstages = 0;
+    int depth_l = 0, depth_u = 0;
+  };
+
+  hipStream_t st;
+  DevMem mem;
+  int64_t n = 0;
+  // measurement hooks (see Engine::profile / probe_enable)
+  bool profiling = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<std::string> prof_label;
+  std::vector<double> prof_bytes;
+  std::vector<int> prof_kind;
+  size_t prof_i = 0;
+  int probe_kind = -1;
+  std::vector<hipEvent_t> probe_ev;
+  int64_t probe_n = 0;
+  double probe_bytes_sum = 0;
+  int32_t* perm_d = nullptr;
+  X* t = nullptr;
+  C* xg = nullptr;
+  std::vector<Lev> lv;
+
+  template <class U> U* upload(const std::vector<U>& h) {
+    U* d = mem.alloc<U>(h.size());
+    if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(U), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return d;
+  }
+
+  TriDev<P> upload_tri(const TriHost<T>& h, bool upper) {
+    TriDev<P> d;
+    d.blk_stage = upload(h.blk_stage);
+    d.stage_row = upload(h.stage_row);
+    d.stage_ent = upload(h.stage_ent);
+    d.rowinfo = upload(h.rowinfo);
+    d.dinv = upper ? upload(convert<D, T>(h.dinv)) : nullptr;
+    d.val = upload(convert<V, T>(h.val));
+    d.col = upload(h.col);
+    return d;
+  }
+
+  CsrDev<P> upload_csr(const CSR<T>& m) {
+    CsrDev<P> d;
+    std::vector<int32_t> rp(m.rp.begin(), m.rp.end());
+    d.rp = upload(rp);
+    d.ci = upload(m.ci);
+    d.v = upload(convert<V, T>(m.v));
+    return d;
+  }
+
+  EngineT(const HostSetup<T>& S, hipStream_t stream) : st(stream) {
+    n = S.n;
+    std::vector<int32_t> p32(S.perm.begin(), S.perm.end());
+    perm_d = upload(p32);
+    t = mem.alloc<X>(n);
+    int64_t maxd = 1;
+    lv.resize(S.lv.size());
+    for (size_t l = 0; l < S.lv.size(); ++l) {
+      const HostLevel<T>& h = S.lv[l];
+      Lev& L = lv[l];
+      L.start = h.start;
+      L.d = h.d;
+      L.s = h.s;
+      L.nb = (int)h.blocks.size() - 1;
+      std::vector<int32_t> br(h.blocks.begin(), h.blocks.end());
+      for (int b = 0; b < L.nb; ++b)
+        L.max_block_rows = std::max<int>(L.max_block_rows, (int)(h.blocks[b + 1] - h.blocks[b]));
+      L.blk_row = upload(br);
+      TriHost<T> tl = build_tri(h.L, h.blocks, false);
+      TriHost<T> tu = build_tri(h.U, h.blocks, true);
+      L.maxslot = std::max(tl.maxslot, tu.maxslot);
+      L.depth_l = tl.depth;
+      L.depth_u = tu.depth;
+      L.nstages = (int64_t)(tl.stage_row.size() + tu.stage_row.size()) - 2;
+      L.lo = upload_tri(tl, false);
+      L.up = upload_tri(tu, true);
+      L.nnz_lu = h.L.nnz() + h.U.nnz();
+      if (h.s > 0) {
+        L.E = upload_csr(h.E);
+        L.F = upload_csr(h.F);
+        L.nnz_e = h.E.nnz();
+        L.nnz_f = h.F.nnz();
+      } else {
+        std::vector<int32_t> zr(h.d + 1, 0);
+        L.F.rp = upload(zr);
+      }
+      maxd = std::max(maxd, h.d);
+      if (h.k > 0) set_lowrank_host((int)l, h.k, h.W, h.H);
+    }
+    xg = mem.alloc<C>(maxd);
+  }
+
+  void set_lowrank_host(int l, int k, const std::vector<T>& W, const std::vector<T>& H) {
+    Lev& L = lv[l];
+    if (k > L.kcap) {
+      const int nblk = (int)((L.s + 255) / 256);
+      L.partial = mem.alloc<C>((size_t)nblk * k);
+      L.tprime = mem.alloc<C>(k);
+      L.counter = mem.alloc<uint32_t>(1);
+      HIPCHK(hipMemsetAsync(L.counter, 0, sizeof(uint32_t), st));
+      L.kcap = k;
+    }
+    L.W = upload(convert<V, T>(W));
+    std::vector<C> hc(H.size());
+    for (size_t i = 0; i < H.size(); ++i) hc[i] = to_compute(H[i]);
+    L.H = upload(hc);
+    L.k = k;
+  }
+  static C to_compute(const T& x);
+
+  void set_lowrank(int l, int k, const void* W, const void* H) override {
+    const T* w = (const T*)W;
+    const T* h = (const T*)H;
+    set_lowrank_host(l, k, std::vector<T>(w, w + (size_t)lv[l].s * k),
+                     std::vector<T>(h, h + (size_t)k * k));
+  }
+
+  TriArgs<P> tri_args(int l) {
+    Lev& L = lv[l];
+    TriArgs<P> a;
+    a.lo = L.lo;
+    a.up = L.up;
+    a.blk_row = L.blk_row;
+    a.t = t + L.start;
+    a.d = L.d;
+    a.F = L.F;
+    a.xg = reinterpret_cast<X*>(xg);
+    a.nb = L.nb;
+    return a;
+  }
+
+  hipEvent_t ev_at(size_t i) {
+    while (prof_ev.size() <= i) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      prof_ev.push_back(e);
+    }
+    return prof_ev[i];
+  }
+  // Run one kernel launch; under measurement, bracket it with HIP events on
+  // the engine's stream.
+  template <class F>
+  void step(const std::string& label, int kind, double bytes, F&& fn) {
+    if (profiling) {
+      HIPCHK(hipEventRecord(ev_at(2 * prof_i), st));
+      fn();
+      HIPCHK(hipEventRecord(ev_at(2 * prof_i + 1), st));
+      if (prof_label.size() <= prof_i) {
+        prof_label.push_back(label);
+        prof_bytes.push_back(bytes);
+        prof_kind.push_back(kind);
+      }
+      ++prof_i;
+    } else if (kind == probe_kind && 2 * probe_n + 1 < (int64_t)probe_ev.size()) {
+      HIPCHK(hipEventRecord(probe_ev[2 * probe_n], st));
+      fn();
+      HIPCHK(hipEventRecord(probe_ev[2 * probe_n + 1], st));
+      probe_bytes_sum += bytes;
+      ++probe_n;
+    } else {
+      fn();
+    }
+  }
+
+  // ---- compulsory HBM bytes of each launch (every stored array read once,
+  // every vector entry read or written once per touch)
+  double tri_bytes(int l, int mode) const {
+    const Lev& L = lv[l];
+    const double vb = sizeof(V), xb = sizeof(X), db = sizeof(D);
+    double b = (double)(L.nnz_lu - L.d) * (vb + 2)   // factor value + 16-bit column
+               + 2.0 * L.d * 4 + L.d * db              // row info (L and U), 1/u_ii
+               + 8.0 * L.nstages + 12.0 * (L.nb + 1)   // stage and block tables
+               + 2.0 * L.d * xb;                       // right-hand side in, result out
+    if (mode == TRI_UP)
+      b += (double)L.nnz_f * (vb + 4) + (double)(L.d + 1) * 4  // F_l
+           + (double)L.nnz_f * xb + (double)L.d * xb;           // y2 gathers, z1 read
+    return b;
+  }
+  double if_bytes(int l, int k) const {
+    const Lev& L = lv[l];
+    const double vb = sizeof(V), xb = sizeof(X);
+    return (double)L.nnz_e * (vb + 4) + (double)(L.s + 1) * 4 + (double)L.nnz_e * xb +
+           2.0 * L.s * xb + (double)L.s * k * vb;
+  }
+  double upd_bytes(int l, int k) const {
+    const Lev& L = lv[l];
+    return (double)L.s * k * sizeof(V) + 2.0 * L.s * sizeof(X);
+  }
+  double perm_bytes(int64_t m) const { return (double)m * (4 + sizeof(O) + sizeof(X)); }
+
+  void interface(int l, int k) {
+    Lev& L = lv[l];
+    IfArgs<P> a;
+    a.E = L.E;
+    a.t = t + L.start;
+    a.d = L.d;
+    a.s = L.s;
+    a.k = k;
+    a.W = L.W;
+    a.H = L.H;
+    a.partial = L.partial;
+    a.tprime = L.tprime;
+    a.counter = L.counter;
+    step("interface L" + std::to_string(l), KIND_INTERFACE, if_bytes(l, k),
+         [&] { launch_interface<P>(a, st); });
+    if (k > 0)
+      step("lowrank_update L" + std::to_string(l), KIND_LOWRANK, upd_bytes(l, k),
+           [&] { launch_lowrank_update<P>(t + L.start + L.d, L.s, k, L.W, L.tprime, st); });
+  }
+
+  void down(int l) {
+    if (lv[l].nb > 0)
+      step("trisolve_down L" + std::to_string(l), l == 0 ? KIND_TRI0 : KIND_TRI,
+           tri_bytes(l, TRI_DOWN), [&] {
+             launch_trisolve<P>(tri_args(l), TRI_DOWN, lv[l].maxslot, lv[l].max_block_rows, st);
+           });
+    if (l + 1 < (int)lv.size()) interface(l, lv[l].k);
+  }
+  void up(int l) {
+    if (lv[l].nb > 0)
+      step("trisolve_up L" + std::to_string(l), l == 0 ? KIND_TRI0 : KIND_TRI,
+           tri_bytes(l, TRI_UP), [&] {
+             launch_trisolve<P>(tri_args(l), TRI_UP, lv[l].maxslot, lv[l].max_block_rows, st);
+           });
+  }
+  void run_from(int l0) {
+    const int L = (int)lv.size() - 1;
+    for (int l = l0; l <= L; ++l) down(l);
+    for (int l = L - 1; l >= l0; --l) up(l);
+  }
+
+  void apply(const void* x, void* y, bool permuted) override {
+    step("gather", KIND_PERM, perm_bytes(n),
+         [&] { launch_gather<P>((const O*)x, permuted ? nullptr : perm_d, t, n, st); });
+    run_from(0);
+    step("scatter", KIND_PERM, perm_bytes(n),
+         [&] { launch_scatter<P>(t, permuted ? nullptr : perm_d, (O*)y, n, st); });
+  }
+
+  int profile(const void* x, void* y, int reps, std::vector<double>& ms,
+              std::vector<double>& bytes, std::vector<std::string>& labels) override {
+    profiling = true;
+    std::vector<double> acc;
+    for (int r = 0; r < reps; ++r) {
+      prof_i = 0;
+      apply(x, y, false);
+      HIPCHK(hipStreamSynchronize(st));
+      acc.resize(prof_i, 0.0);
+      for (size_t i = 0; i < prof_i; ++i) {
+        float e = 0;
+        HIPCHK(hipEventElapsedTime(&e, prof_ev[2 * i], prof_ev[2 * i + 1]));
+        acc[i] += e;
+      }
+    }
+    profiling = false;
+    ms.assign(acc.size(), 0.0);
+    for (size_t i = 0; i < acc.size(); ++i) ms[i] = acc[i] / std::max(1, reps);
+    bytes.assign(prof_bytes.begin(), prof_bytes.begin() + acc.size());
+    labels.assign(prof_label.begin(), prof_label.begin() + acc.size());
+    return (int)acc.size();
+  }
+
+  void probe_enable(int kind, int max_launches) override {
+    for (hipEvent_t e : probe_ev) (void)hipEventDestroy(e);
+    probe_ev.clear();
+    probe_kind = kind;
+    probe_n = 0;
+    probe_bytes_sum = 0;
+    for (int i = 0; i < 2 * std::max(0, max_launches) + 1 && kind >= 0; ++i) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      probe_ev.push_back(e);
+    }
+  }
+  void probe_read(int64_t* launches, double* ms, double* bytes) override {
+    HIPCHK(hipStreamSynchronize(st));
+    double tot = 0;
+    for (int64_t i = 0; i < probe_n; ++i) {
+      float e = 0;
+      HIPCHK(hipEventElapsedTime(&e, probe_ev[2 * i], probe_ev[2 * i + 1]));
+      tot += e;
+    }
+    *launches = probe_n;
+    *ms = tot;
+    *bytes = probe_bytes_sum;
+    probe_n = 0;
+    probe_bytes_sum = 0;
+  }
+
+  ~EngineT() override {
+    (void)hipStreamSynchronize(st);
+    for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : probe_ev) (void)hipEventDestroy(e);
+  }
+
+  void ghat(int l, const void* v, void* out) override {
+    Lev& L = lv[l];
+    X* tc = t + L.start + L.d;
+    launch_gather<P>((const O*)v, nullptr, tc, L.s, st);
+    run_from(l + 1);
+    launch_fill<X>(t + L.start, zero_x(), L.d, st);
+    up(l);
+    launch_fill<X>(tc, zero_x(), L.s, st);
+    interface(l, 0);
+    launch_scatter<P>(tc, nullptr, (O*)out, L.s, st);
+  }
+  static X zero_x();
+
+  void stats(gs_info* info, int vb_vec) override {
+    (void)vb_vec;
+    for (size_t l = 0; l < lv.size() && l <= GS_MAX_LEVELS; ++l) {
+      info->depth_l[l] = lv[l].depth_l;
+      info->depth_u[l] = lv[l].depth_u;
+    }
+  }
+
+  // Compulsory HBM traffic of one whole apply: the sum over its launches.
+  double bytes_per_apply() const override {
+    double b = 2 * perm_bytes(n);
+    const int L = (int)lv.size() - 1;
+    for (int l = 0; l <= L; ++l) {
+      if (lv[l].nb > 0) b += tri_bytes(l, TRI_DOWN);
+      if (l < L) {
+        b += if_bytes(l, lv[l].k);
+        if (lv[l].k > 0) b += upd_bytes(l, lv[l].k);
+        if (lv[l].nb > 0) b += tri_bytes(l, TRI_UP);
+      }
+    }
+    return b;
+  }
+};
+
+template <> double EngineT<PF64, double>::to_compute(const double& x) { return x; }
+template <> float EngineT<PF32, double>::to_compute(const double& x) { return (float)x; }
+template <> float EngineT<PBF16, double>::to_compute(const double& x) { return (float)x; }
+template <> dcplx EngineT<PC128, cplx>::to_compute(const cplx& x) { return mk(x.real(), x.imag()); }
+template <> double EngineT<PF64, double>::zero_x() { return 0.0; }
+template <> float EngineT<PF32, double>::zero_x() { return 0.0f; }
+template <> float EngineT<PBF16, double>::zero_x() { return 0.0f; }
+template <> dcplx EngineT<PC128, cplx>::zero_x() { return mk(0, 0); }
+
+std::unique_ptr<Engine> make_engine(const HostSetup<double>& S, int precision, hipStream_t st) {
+  if (precision == GS_PREC_F64) return std::make_unique<EngineT<PF64, double>>(S, st);
+  if (precision == GS_PREC_F32) return std::make_unique<EngineT<PF32, double>>(S, st);
+  if (precision == GS_PREC_BF16) return std::make_unique<EngineT<PBF16, double>>(S, st);
+  throw Error(GS_EINVAL, "unknown precision");
+}
+std::unique_ptr<Engine> make_engine(const HostSetup<cplx>& S, int precision, hipStream_t st) {
+  if (precision != GS_PREC_F64) throw Error(GS_EINVAL, "complex data supports GS_PREC_F64 only");
+  return std::make_unique<EngineT<PC128, cplx>>(S, st);
+}
+
+}  // namespace gs

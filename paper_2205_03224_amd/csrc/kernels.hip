@@ -1,0 +1,601 @@
+// HIP kernels of libgemslr for gfx950 (CDNA4, 64-wide wavefronts).
+//
+// The preconditioner apply (Alg. 2) is a chain of bandwidth-bound sparse
+// steps; every kernel below streams its operands once, with the 64 lanes of
+// a wavefront reading consecutive addresses.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int kWave = 64;
+
+template <class T> __device__ inline T zero();
+template <> __device__ inline double zero<double>() { return 0.0; }
+template <> __device__ inline float zero<float>() { return 0.0f; }
+template <> __device__ inline dcplx zero<dcplx>() { return mk(0.0, 0.0); }
+
+__device__ inline double shfl_xor(double v, int m) { return __shfl_xor(v, m, kWave); }
+__device__ inline float shfl_xor(float v, int m) { return __shfl_xor(v, m, kWave); }
+__device__ inline dcplx shfl_xor(dcplx v, int m) {
+  return mk(__shfl_xor(v.x, m, kWave), __shfl_xor(v.y, m, kWave));
+}
+
+// Sum over the 64 lanes of a wavefront (butterfly; every lane gets the sum).
+template <class T> __device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor(v, m);
+  return v;
+}
+
+}  // namespace
+
+// ======================================================================
+// Batched block triangular solve: one wavefront per diagonal block.
+//
+// For block b the wavefront loads its right-hand side into LDS, runs the
+// forward sweep with L (unit diagonal) and the backward sweep with U over
+// the level-scheduled stages, and writes the result.  Rows of one stage are
+// independent, so each lane owns one row; stages follow each other in
+// dependency order and only LDS carries values between them, in program
+// order of the single wavefront (no barrier needed).  The factor entries of
+// the next stage are fetched into registers while the current stage
+// computes, so HBM latency overlaps the dependent LDS chain.
+//
+// MODE TRI_DOWN: rhs = t[rows], result stored to t[rows]           (z1)
+// MODE TRI_UP:   rhs = F_l y2 (y2 = t[d ...]), t[rows] -= result   (y1)
+// ======================================================================
+
+template <class P, int MS>
+struct StageRegs {
+  typename P::C v[MS > 0 ? MS : 1];
+  uint16_t c[MS > 0 ? MS : 1];
+  uint32_t info;
+  typename P::C dinv;
+};
+
+template <class P, int MS, bool ISU>
+__device__ __forceinline__ void stage_load(const TriDev<P>& tri, int s, int lane,
+                                           StageRegs<P, MS>& r) {
+  using C = typename P::C;
+  const int r0 = tri.stage_row[s];
+  const int nrs = tri.stage_row[s + 1] - r0;
+  int e = tri.stage_ent[s];
+  const bool act = lane < nrs;
+  r.info = act ? tri.rowinfo[r0 + lane] : 0u;
+  const int nz = (int)(r.info >> 16);
+  const int maxnz = __builtin_amdgcn_readfirstlane(nz);
+#pragma unroll
+  for (int j = 0; j < MS; ++j) {
+    if (j < maxnz) {
+      const unsigned long long m = __ballot(nz > j);
+      if (nz > j) {
+        r.v[j] = cvt<C>(tri.val[e + lane]);
+        r.c[j] = tri.col[e + lane];
+      }
+      e += __popcll(m);
+    }
+  }
+  if (ISU) r.dinv = act ? cvt<C>(tri.dinv[r0 + lane]) : zero<C>();
+}
+
+template <class P, int MS, bool ISU>
+__device__ __forceinline__ void stage_compute(const StageRegs<P, MS>& r,
+                                              typename P::C* x) {
+  using C = typename P::C;
+  const int nz = (int)(r.info >> 16);
+  const int row = (int)(r.info & 0xffffu);
+  C acc = x[row];
+#pragma unroll
+  for (int j = 0; j < MS; ++j)
+    if (j < nz) acc -= r.v[j] * x[r.c[j]];
+  if (ISU) acc *= r.dinv;
+  x[row] = acc;
+}
+
+// generic path for rows longer than the register budget: entries are read
+// as they are used
+template <class P, bool ISU>
+__device__ void sweep_generic(const TriDev<P>& tri, int s0, int s1, int lane,
+                              typename P::C* x, bool sync) {
+  using C = typename P::C;
+  for (int s = s0; s < s1; ++s) {
+    const int r0 = tri.stage_row[s];
+    const int nrs = tri.stage_row[s + 1] - r0;
+    int e = tri.stage_ent[s];
+    const bool act = lane < nrs;
+    const uint32_t info = act ? tri.rowinfo[r0 + lane] : 0u;
+    const int nz = (int)(info >> 16);
+    const int maxnz = __builtin_amdgcn_readfirstlane(nz);
+    C acc = act ? x[info & 0xffffu] : zero<C>();
+    for (int j = 0; j < maxnz; ++j) {
+      const unsigned long long m = __ballot(nz > j);
+      if (nz > j) acc -= cvt<C>(tri.val[e + lane]) * x[tri.col[e + lane]];
+      e += __popcll(m);
+    }
+    if (act) {
+      if (ISU) acc *= cvt<C>(tri.dinv[r0 + lane]);
+      x[info & 0xffffu] = acc;
+    }
+    if (sync) __syncthreads();
+  }
+}
+
+template <class P, int MS, bool ISU>
+__device__ __forceinline__ void sweep(const TriDev<P>& tri, int s0, int s1, int lane,
+                                      typename P::C* x, bool sync) {
+  if (MS == 0) {
+    sweep_generic<P, ISU>(tri, s0, s1, lane, x, sync);
+    return;
+  }
+  if (s0 >= s1) return;
+  StageRegs<P, MS> A, B;
+  stage_load<P, MS, ISU>(tri, s0, lane, A);
+  for (int s = s0; s < s1; s += 2) {
+    if (s + 1 < s1) stage_load<P, MS, ISU>(tri, s + 1, lane, B);
+    if (lane < tri.stage_row[s + 1] - tri.stage_row[s]) stage_compute<P, MS, ISU>(A, x);
+    if (sync) __syncthreads();
+    if (s + 1 >= s1) break;
+    if (s + 2 < s1) stage_load<P, MS, ISU>(tri, s + 2, lane, A);
+    if (lane < tri.stage_row[s + 2] - tri.stage_row[s + 1]) stage_compute<P, MS, ISU>(B, x);
+    if (sync) __syncthreads();
+  }
+}
+
+template <class P, int MS, bool XLDS, int MODE>
+__global__ __launch_bounds__(64) void k_trisolve(TriArgs<P> a) {
+  using C = typename P::C;
+  using X = typename P::X;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int r0 = a.blk_row[b];
+  const int nr = a.blk_row[b + 1] - r0;
+  C* x = XLDS ? reinterpret_cast<C*>(smem_raw) : reinterpret_cast<C*>(a.xg) + r0;
+  // right-hand side
+  for (int i = lane; i < nr; i += kWave) {
+    C r;
+    if (MODE == TRI_DOWN) {
+      r = cvt<C>(a.t[r0 + i]);
+    } else {
+      r = zero<C>();
+      const int p0 = a.F.rp[r0 + i], p1 = a.F.rp[r0 + i + 1];
+      for (int p = p0; p < p1; ++p) r += cvt<C>(a.F.v[p]) * cvt<C>(a.t[a.d + a.F.ci[p]]);
+    }
+    x[i] = r;
+  }
+  if (!XLDS) __syncthreads();
+  sweep<P, MS, false>(a.lo, a.lo.blk_stage[b], a.lo.blk_stage[b + 1], lane, x, !XLDS);
+  sweep<P, MS, true>(a.up, a.up.blk_stage[b], a.up.blk_stage[b + 1], lane, x, !XLDS);
+  for (int i = lane; i < nr; i += kWave) {
+    if (MODE == TRI_DOWN) a.t[r0 + i] = cvt<X>(x[i]);
+    else a.t[r0 + i] = cvt<X>(cvt<C>(a.t[r0 + i]) - x[i]);
+  }
+}
+
+template <class P, int MS, int MODE>
+static void launch_tri_ms(const TriArgs<P>& a, int max_block_rows, hipStream_t st) {
+  using C = typename P::C;
+  const size_t lds = (size_t)max_block_rows * sizeof(C);
+  if (lds <= 65536) {
+    hipLaunchKernelGGL((k_trisolve<P, MS, true, MODE>), dim3(a.nb), dim3(kWave), lds, st, a);
+  } else {
+    hipLaunchKernelGGL((k_trisolve<P, MS, false, MODE>), dim3(a.nb), dim3(kWave), 0, st, a);
+  }
+}
+
+template <class P, int MODE>
+static void launch_tri_mode(const TriArgs<P>& a, int maxslot, int mbr, hipStream_t st) {
+  if (maxslot <= 4) launch_tri_ms<P, 4, MODE>(a, mbr, st);
+  else if (maxslot <= 8) launch_tri_ms<P, 8, MODE>(a, mbr, st);
+  else if (maxslot <= 12) launch_tri_ms<P, 12, MODE>(a, mbr, st);
+  else if (maxslot <= 16) launch_tri_ms<P, 16, MODE>(a, mbr, st);
+  else launch_tri_ms<P, 0, MODE>(a, mbr, st);
+}
+
+template <class P>
+void launch_trisolve(const TriArgs<P>& a, int mode, int maxslot, int max_block_rows,
+                     hipStream_t st) {
+  if (a.nb <= 0) return;
+  if (mode == TRI_DOWN) launch_tri_mode<P, TRI_DOWN>(a, maxslot, max_block_rows, st);
+  else launch_tri_mode<P, TRI_UP>(a, maxslot, max_block_rows, st);
+}
+
+// ======================================================================
+// Interface step of one level: z2 = b2 - E_l z1 written in place, and the
+// projection W^H z2 of the low-rank term: every workgroup leaves its
+// partial sums, the last workgroup to finish adds them in workgroup order
+// (deterministic) and applies H = (I - R)^{-1} - I, giving t' = H W^H z2.
+// ======================================================================
+constexpr int kIfThreads = 256;
+
+template <class P>
+__global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
+  using C = typename P::C;
+  using X = typename P::X;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* red = reinterpret_cast<C*>(smem_raw);            // 4 x k
+  __shared__ int is_last;
+  const int tid = threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * kIfThreads + tid;
+  const bool act = j < a.s;
+  C z = zero<C>();
+  if (act) {
+    C acc = cvt<C>(a.t[a.d + j]);
+    const int p0 = a.E.rp[j], p1 = a.E.rp[j + 1];
+    for (int p = p0; p < p1; ++p) acc -= cvt<C>(a.E.v[p]) * cvt<C>(a.t[a.E.ci[p]]);
+    a.t[a.d + j] = cvt<X>(acc);
+    z = acc;
+  }
+  if (a.k == 0) return;
+  const int wave = tid / kWave, lane = tid % kWave;
+  for (int c = 0; c < a.k; ++c) {
+    C w = act ? cvt<C>(a.W[j + (int64_t)c * a.s]) : zero<C>();
+    C pr = wave_sum(conj(w) * z);
+    if (lane == 0) red[wave * a.k + c] = pr;
+  }
+  __syncthreads();
+  for (int c = tid; c < a.k; c += kIfThreads) {
+    C s = red[c];
+    for (int w = 1; w < kIfThreads / kWave; ++w) s += red[w * a.k + c];
+    a.partial[(int64_t)blockIdx.x * a.k + c] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned prev = atomicAdd(a.counter, 1u);
+    is_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  C* tv = red;  // reuse: k entries
+  for (int c = tid; c < a.k; c += kIfThreads) {
+    C s = zero<C>();
+    for (unsigned bb = 0; bb < gridDim.x; ++bb) s += a.partial[(int64_t)bb * a.k + c];
+    tv[c] = s;
+  }
+  __syncthreads();
+  for (int r = tid; r < a.k; r += kIfThreads) {
+    C s = zero<C>();
+    for (int c = 0; c < a.k; ++c) s += a.H[r + c * a.k] * tv[c];
+    a.tprime[r] = s;
+  }
+  if (tid == 0) *a.counter = 0u;
+}
+
+template <class P>
+void launch_interface(const IfArgs<P>& a, hipStream_t st) {
+  if (a.s <= 0) return;
+  using C = typename P::C;
+  const int nblk = (int)((a.s + kIfThreads - 1) / kIfThreads);
+  const size_t lds = (size_t)(kIfThreads / kWave) * (a.k > 0 ? a.k : 1) * sizeof(C);
+  hipLaunchKernelGGL(k_interface<P>, dim3(nblk), dim3(kIfThreads), lds, st, a);
+}
+
+// t_C += W t'
+template <class P>
+__global__ __launch_bounds__(256) void k_lowrank_update(typename P::X* tc, int64_t s, int k,
+                                                        const typename P::V* W,
+                                                        const typename P::C* tprime) {
+  using C = typename P::C;
+  using X = typename P::X;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tp = reinterpret_cast<C*>(smem_raw);
+  for (int c = threadIdx.x; c < k; c += blockDim.x) tp[c] = tprime[c];
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= s) return;
+  C acc = cvt<C>(tc[j]);
+  for (int c = 0; c < k; ++c) acc += cvt<C>(W[j + (int64_t)c * s]) * tp[c];
+  tc[j] = cvt<X>(acc);
+}
+
+template <class P>
+void launch_lowrank_update(typename P::X* tc, int64_t s, int k, const typename P::V* W,
+                           const typename P::C* tprime, hipStream_t st) {
+  if (s <= 0 || k <= 0) return;
+  const int nblk = (int)((s + 255) / 256);
+  hipLaunchKernelGGL(k_lowrank_update<P>, dim3(nblk), dim3(256),
+                     (size_t)k * sizeof(typename P::C), st, tc, s, k, W, tprime);
+}
+
+// ---------------------------------------------------------------- perm
+template <class P>
+__global__ void k_gather(const typename P::O* x, const int32_t* perm, typename P::X* t,
+                         int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t src = perm ? perm[i] : i;
+  t[i] = cvt<typename P::X>(x[src]);
+}
+template <class P>
+__global__ void k_scatter(const typename P::X* t, const int32_t* perm, typename P::O* y,
+                          int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t dst = perm ? perm[i] : i;
+  y[dst] = cvt<typename P::O>(t[i]);
+}
+template <class P>
+void launch_gather(const typename P::O* x, const int32_t* perm, typename P::X* t, int64_t n,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_gather<P>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, perm,
+                     t, n);
+}
+template <class P>
+void launch_scatter(const typename P::X* t, const int32_t* perm, typename P::O* y, int64_t n,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter<P>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t,
+                     perm, y, n);
+}
+
+// ======================================================================
+// float64 / complex128 vector kernels (FGMRES, Arnoldi)
+// ======================================================================
+template <class T>
+__global__ void k_spmv(const int32_t* rp, const int32_t* ci, const T* v, const T* x, T* y,
+                       int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T acc = zero<T>();
+  for (int p = rp[i]; p < rp[i + 1]; ++p) acc += v[p] * x[ci[p]];
+  y[i] = acc;
+}
+template <class T>
+void launch_spmv(const int32_t* rp, const int32_t* ci, const T* v, const T* x, T* y, int64_t n,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_spmv<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rp, ci, v,
+                     x, y, n);
+}
+
+template <class T>
+__global__ void k_residual(const int32_t* rp, const int32_t* ci, const T* v, const T* x,
+                           const T* b, T* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T acc = b[i];
+  for (int p = rp[i]; p < rp[i + 1]; ++p) acc -= v[p] * x[ci[p]];
+  y[i] = acc;
+}
+template <class T>
+void launch_residual(const int32_t* rp, const int32_t* ci, const T* v, const T* x, const T* b,
+                     T* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rp, ci,
+                     v, x, b, y, n);
+}
+
+constexpr int kDotChunk = 8;     // columns per workgroup row of the grid
+constexpr int kDotBlocks = 256;  // workgroups along the rows
+
+template <class T>
+__global__ __launch_bounds__(256) void k_multidot(const T* V, int64_t ld, int ncol,
+                                                  const T* w, int64_t n, T* partial) {
+  __shared__ T red[4][kDotChunk];
+  const int c0 = blockIdx.y * kDotChunk;
+  const int nc = min(kDotChunk, ncol - c0);
+  T acc[kDotChunk];
+#pragma unroll
+  for (int c = 0; c < kDotChunk; ++c) acc[c] = zero<T>();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T wi = w[i];
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c)
+      if (c < nc) acc[c] += conj(V[i + (int64_t)(c0 + c) * ld]) * wi;
+  }
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int c = 0; c < kDotChunk; ++c) {
+    T s = wave_sum(acc[c]);
+    if (lane == 0) red[wave][c] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < nc) {
+    T s = red[0][threadIdx.x];
+    for (int w2 = 1; w2 < 4; ++w2) s += red[w2][threadIdx.x];
+    partial[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+  }
+}
+template <class T>
+__global__ void k_sum_partials(const T* partial, int nparts, int ncol, T* h) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  T s = zero<T>();
+  for (int b = 0; b < nparts; ++b) s += partial[(int64_t)c * nparts + b];
+  h[c] = s;
+}
+template <class T>
+void launch_multidot(const T* V, int64_t ld, int ncol, const T* w, int64_t n, T* partial, T* h,
+                     hipStream_t st) {
+  if (ncol <= 0) return;
+  const int nb = (int)std::min<int64_t>(kDotBlocks, (n + 255) / 256);
+  dim3 grid(nb, (ncol + kDotChunk - 1) / kDotChunk);
+  hipLaunchKernelGGL(k_multidot<T>, grid, dim3(256), 0, st, V, ld, ncol, w, n, partial);
+  hipLaunchKernelGGL(k_sum_partials<T>, dim3((ncol + 63) / 64), dim3(64), 0, st, partial, nb,
+                     ncol, h);
+}
+
+template <class T>
+__global__ void k_gemv_sub(const T* V, int64_t ld, int ncol, const T* h, T* w, int64_t n,
+                           T* hacc) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* hs = reinterpret_cast<T*>(smem_raw);
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) hs[c] = h[c];
+  __syncthreads();
+  if (hacc && blockIdx.x == 0)
+    for (int c = threadIdx.x; c < ncol; c += blockDim.x) hacc[c] += hs[c];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T acc = w[i];
+  for (int c = 0; c < ncol; ++c) acc -= V[i + (int64_t)c * ld] * hs[c];
+  w[i] = acc;
+}
+template <class T>
+void launch_gemv_sub(const T* V, int64_t ld, int ncol, const T* h, T* w, int64_t n, T* hacc,
+                     hipStream_t st) {
+  if (ncol <= 0) return;
+  hipLaunchKernelGGL(k_gemv_sub<T>, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                     (size_t)ncol * sizeof(T), st, V, ld, ncol, h, w, n, hacc);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_norm_part(const T* w, int64_t n, double* partial) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += norm2(w[i]);
+  acc = wave_sum(acc);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) red[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+__global__ void k_norm_final(const double* partial, int nparts, double* out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += partial[b];
+  out[0] = sqrt(s);
+}
+template <class T>
+void launch_norm(const T* w, int64_t n, double* partial, double* out, hipStream_t st) {
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (n + 255) / 256));
+  hipLaunchKernelGGL(k_norm_part<T>, dim3(nb), dim3(256), 0, st, w, n, partial);
+  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, partial, nb, out);
+}
+
+template <class T>
+__global__ void k_scale_inv(const T* x, const double* nrm, T* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = nrm[0];
+  y[i] = s > 0.0 ? x[i] * (1.0 / s) : zero<T>();
+}
+template <class T>
+void launch_scale_inv(const T* x, const double* nrm, T* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_inv<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, nrm,
+                     y, n);
+}
+
+template <class T>
+__global__ void k_gemv_add(const T* Z, int64_t ld, int ncol, const T* y, T* x, int64_t n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* ys = reinterpret_cast<T*>(smem_raw);
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) ys[c] = y[c];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T acc = x[i];
+  for (int c = 0; c < ncol; ++c) acc += Z[i + (int64_t)c * ld] * ys[c];
+  x[i] = acc;
+}
+template <class T>
+void launch_gemv_add(const T* Z, int64_t ld, int ncol, const T* y, T* x, int64_t n,
+                     hipStream_t st) {
+  if (ncol <= 0) return;
+  hipLaunchKernelGGL(k_gemv_add<T>, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                     (size_t)ncol * sizeof(T), st, Z, ld, ncol, y, x, n);
+}
+
+// Y (n x k) = V (n x m) G (m x k); G staged through LDS in column chunks
+template <class T>
+__global__ void k_gemm_small(const T* V, int64_t ld, int m, const T* G, int k, T* Y,
+                             int64_t ldy, int64_t n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* gs = reinterpret_cast<T*>(smem_raw);
+  const int c = blockIdx.y;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) gs[i] = G[(int64_t)c * m + i];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  T acc = zero<T>();
+  for (int i = 0; i < m; ++i) acc += V[r + (int64_t)i * ld] * gs[i];
+  Y[r + (int64_t)c * ldy] = acc;
+}
+template <class T>
+void launch_gemm_small(const T* V, int64_t ld, int m, const T* G, int k, T* Y, int64_t ldy,
+                       int64_t n, hipStream_t st) {
+  if (k <= 0 || m <= 0) return;
+  dim3 grid((unsigned)((n + 255) / 256), k);
+  hipLaunchKernelGGL(k_gemm_small<T>, grid, dim3(256), (size_t)m * sizeof(T), st, V, ld, m, G, k,
+                     Y, ldy, n);
+}
+
+template <class T>
+__global__ void k_fill(T* x, T v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+template <class T>
+void launch_fill(T* x, T v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, v, n);
+}
+template <class T>
+__global__ void k_copy(const T* x, T* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+template <class T>
+void launch_copy(const T* x, T* y, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, n);
+}
+
+template <class T>
+__global__ void k_permute(const T* x, const int32_t* perm, T* y, int64_t n, int scatter) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (scatter) y[perm[i]] = x[i];
+  else y[i] = x[perm[i]];
+}
+template <class T>
+void launch_permute(const T* x, const int32_t* perm, T* y, int64_t n, bool scatter,
+                    hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_permute<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, perm,
+                     y, n, scatter ? 1 : 0);
+}
+
+// ---------------------------------------------------------------- instances
+#define GS_PREC_INSTANCES(P)                                                                   \
+  template void launch_trisolve<P>(const TriArgs<P>&, int, int, int, hipStream_t);             \
+  template void launch_interface<P>(const IfArgs<P>&, hipStream_t);                            \
+  template void launch_lowrank_update<P>(P::X*, int64_t, int, const P::V*, const P::C*,        \
+                                         hipStream_t);                                         \
+  template void launch_gather<P>(const P::O*, const int32_t*, P::X*, int64_t, hipStream_t);    \
+  template void launch_scatter<P>(const P::X*, const int32_t*, P::O*, int64_t, hipStream_t);
+GS_PREC_INSTANCES(PF64)
+GS_PREC_INSTANCES(PC128)
+GS_PREC_INSTANCES(PF32)
+GS_PREC_INSTANCES(PBF16)
+
+#define GS_VEC_INSTANCES(T)                                                                    \
+  template void launch_spmv<T>(const int32_t*, const int32_t*, const T*, const T*, T*,         \
+                               int64_t, hipStream_t);                                          \
+  template void launch_residual<T>(const int32_t*, const int32_t*, const T*, const T*,         \
+                                   const T*, T*, int64_t, hipStream_t);                        \
+  template void launch_multidot<T>(const T*, int64_t, int, const T*, int64_t, T*, T*,          \
+                                   hipStream_t);                                               \
+  template void launch_gemv_sub<T>(const T*, int64_t, int, const T*, T*, int64_t, T*,          \
+                                   hipStream_t);                                               \
+  template void launch_norm<T>(const T*, int64_t, double*, double*, hipStream_t);              \
+  template void launch_scale_inv<T>(const T*, const double*, T*, int64_t, hipStream_t);        \
+  template void launch_gemv_add<T>(const T*, int64_t, int, const T*, T*, int64_t,              \
+                                   hipStream_t);                                               \
+  template void launch_gemm_small<T>(const T*, int64_t, int, const T*, int, T*, int64_t,       \
+                                     int64_t, hipStream_t);                                    \
+  template void launch_fill<T>(T*, T, int64_t, hipStream_t);                                   \
+  template void launch_copy<T>(const T*, T*, int64_t, hipStream_t);                          \
+  template void launch_permute<T>(const T*, const int32_t*, T*, int64_t, bool, hipStream_t);
+GS_VEC_INSTANCES(double)
+GS_VEC_INSTANCES(dcplx)
+template void launch_fill<float>(float*, float, int64_t, hipStream_t);
+
+}  // namespace gs

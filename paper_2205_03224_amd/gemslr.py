@@ -1,0 +1,372 @@
+"""ctypes binding of libgemslr (include/gemslr.h): argument marshalling only.
+
+Every computation runs in the shared library; this module converts numpy
+arrays and torch tensors into the pointers and sizes of the C ABI and turns
+status codes into exceptions.  It raises if the library has not been built:
+there is no fallback path.
+"""
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgemslr.so")
+
+GS_OK, GS_NOT_CONVERGED = 0, 1
+GS_EINVAL, GS_EZEROPIVOT, GS_ESINGULAR, GS_EDEVICE, GS_ESTATE, GS_ENOMEM = \
+    -1, -2, -3, -4, -5, -6
+GS_F64, GS_C128 = 0, 1
+GS_PREC_F64, GS_PREC_F32, GS_PREC_BF16 = 0, 1, 2
+GS_ILUT, GS_ILU0 = 0, 1
+GS_MAX_LEVELS = 8
+
+PRECISIONS = {"f64": GS_PREC_F64, "f32": GS_PREC_F32, "bf16": GS_PREC_BF16}
+ILU_KINDS = {"ilut": GS_ILUT, "ilu0": GS_ILU0}
+
+
+class GemslrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gemslr error {code}: {msg}")
+        self.code = code
+
+
+class GsOpts(ct.Structure):
+    _fields_ = [("ilu_kind", ct.c_int), ("lfil", ct.c_int),
+                ("fgmres_restart", ct.c_int), ("maxit", ct.c_int),
+                ("arnoldi_tol", ct.c_double), ("arnoldi_max_cycles", ct.c_int),
+                ("lowrank_last_level", ct.c_int), ("precision", ct.c_int),
+                ("grid_ndim", ct.c_int), ("grid_dims", ct.c_int32 * 3),
+                ("seed", ct.c_uint64), ("nthreads", ct.c_int)]
+
+
+_L1 = GS_MAX_LEVELS + 1
+
+
+class GsInfo(ct.Structure):
+    _fields_ = [("its", ct.c_int), ("relres", ct.c_double), ("converged", ct.c_int),
+                ("nlevels", ct.c_int), ("d", ct.c_int64 * _L1), ("s", ct.c_int64 * _L1),
+                ("nblocks", ct.c_int64 * _L1), ("k", ct.c_int32 * _L1),
+                ("depth_l", ct.c_int32 * _L1), ("depth_u", ct.c_int32 * _L1),
+                ("arnoldi_cycles", ct.c_int32 * _L1),
+                ("arnoldi_matvecs", ct.c_int32 * _L1),
+                ("arnoldi_converged", ct.c_int32 * _L1),
+                ("nnz_lu", ct.c_int64), ("nnz_ef", ct.c_int64), ("nnz_a", ct.c_int64),
+                ("fill", ct.c_double), ("fill_lowrank", ct.c_double),
+                ("apply_bytes", ct.c_double), ("t_partition", ct.c_double),
+                ("t_factor", ct.c_double), ("t_layout", ct.c_double),
+                ("t_lowrank", ct.c_double), ("t_solve", ct.c_double)]
+
+    def as_dict(self):
+        L = self.nlevels
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            if isinstance(v, ct.Array):
+                v = list(v)[:L + 1]
+            out[name] = v
+        return out
+
+
+_p = ct.c_void_p
+_i64p = ct.POINTER(ct.c_int64)
+_i32p = ct.POINTER(ct.c_int32)
+
+
+class GsLevelData(ct.Structure):
+    _fields_ = [("d", ct.c_int64), ("nblocks", ct.c_int64), ("block_ptr", _p),
+                ("l_rowptr", _p), ("l_col", _p), ("l_val", _p),
+                ("u_rowptr", _p), ("u_col", _p), ("u_val", _p),
+                ("e_rowptr", _p), ("e_col", _p), ("e_val", _p),
+                ("f_rowptr", _p), ("f_col", _p), ("f_val", _p),
+                ("k", ct.c_int32), ("w", _p), ("h", _p)]
+
+
+_lib = None
+
+# (name, restype, argtypes) for every symbol of include/gemslr.h
+SIGNATURES = [
+    ("gs_opts_default", None, [ct.POINTER(GsOpts)]),
+    ("gs_create", ct.c_int, [ct.POINTER(_p), ct.c_int, _p]),
+    ("gs_destroy", None, [_p]),
+    ("gs_last_error", ct.c_char_p, [_p]),
+    ("gs_setup", ct.c_int, [_p, ct.c_int64, _p, _p, _p, ct.c_int, ct.c_int, ct.c_int,
+                            ct.c_int, ct.c_double, ct.POINTER(GsOpts)]),
+    ("gs_setup_explicit", ct.c_int, [_p, ct.c_int64, _p, _p, _p, ct.c_int, _p, ct.c_int,
+                                     ct.POINTER(GsLevelData), ct.POINTER(GsOpts)]),
+    ("gs_set_precision", ct.c_int, [_p, ct.c_int]),
+    ("gs_apply", ct.c_int, [_p, _p, _p]),
+    ("gs_apply_many", ct.c_int, [_p, ct.c_int, _p, _p]),
+    ("gs_apply_profile", ct.c_int, [_p, _p, _p, ct.c_int, _p, _p, ct.c_int,
+                                    ct.POINTER(ct.c_int)]),
+    ("gs_apply_step_label", ct.c_char_p, [_p, ct.c_int]),
+    ("gs_probe_enable", ct.c_int, [_p, ct.c_int, ct.c_int]),
+    ("gs_probe_read", ct.c_int, [_p, _i64p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]),
+    ("gs_solve", ct.c_int, [_p, _p, _p, ct.c_double, ct.POINTER(GsInfo)]),
+    ("gs_get_info", ct.c_int, [_p, ct.POINTER(GsInfo)]),
+    ("gs_partition_grid", ct.c_int, [ct.c_int, _p, ct.c_int, ct.c_int, ct.c_int64, _p, _p,
+                                     _p, _p, ct.POINTER(ct.c_int), _p, _p, ct.c_int64]),
+    ("gs_ilu", ct.c_int, [ct.c_int64, _p, _p, _p, ct.c_int, ct.c_int, ct.c_double, ct.c_int,
+                          _p, _p, _p, ct.c_int64, _p, _p, _p, ct.c_int64]),
+    ("gs_get_level_sizes", ct.c_int, [_p, ct.c_int, _p]),
+    ("gs_get_level", ct.c_int, [_p, ct.c_int] + [_p] * 15),
+    ("gs_get_perm", ct.c_int, [_p, _p]),
+]
+
+
+def lib():
+    """Load libgemslr.so (built by paper_2205_03224_amd.build); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2205_03224_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return ct.c_void_p(a.data_ptr())
+    return ct.c_void_p(a.ctypes.data)
+
+
+def _i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _vals(a, dtype=None):
+    a = np.asarray(a)
+    if dtype is None:
+        dtype = np.complex128 if np.iscomplexobj(a) else np.float64
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def opts(**kw):
+    o = GsOpts()
+    lib().gs_opts_default(ct.byref(o))
+    for k, v in kw.items():
+        if k == "grid_dims":
+            dims = list(v)
+            o.grid_ndim = len(dims)
+            for i, dv in enumerate(dims):
+                o.grid_dims[i] = int(dv)
+        elif k == "precision":
+            o.precision = PRECISIONS.get(v, v)
+        elif k in ("ilu", "ilu_kind"):
+            o.ilu_kind = ILU_KINDS.get(v, v)
+        else:
+            setattr(o, k, v)
+    return o
+
+
+class Context:
+    """One preconditioner on one GPU (gs_create ... gs_destroy)."""
+
+    def __init__(self, device=0, stream=None):
+        if stream is None and device >= 0:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = ct.c_void_p()
+        rc = lib().gs_create(ct.byref(h), device, ct.c_void_p(stream or 0))
+        if rc != GS_OK:
+            raise GemslrError(rc, lib().gs_last_error(None).decode())
+        self._h = h
+        self._keep = []
+        self.dtype = None
+        self.n = None
+
+    def _check(self, rc, ok=(GS_OK,)):
+        if rc not in ok:
+            raise GemslrError(rc, lib().gs_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- setup
+    def setup(self, rowptr, col, val, levels, nparts, rank, drop_tol, **kw):
+        rp, ci, v = _i64(rowptr), _i32(col), _vals(val)
+        self.dtype = GS_C128 if np.iscomplexobj(v) else GS_F64
+        self.n = len(rp) - 1
+        o = opts(**kw)
+        self._check(lib().gs_setup(self._h, self.n, _ptr(rp), _ptr(ci), _ptr(v), self.dtype,
+                                   levels, nparts, rank, drop_tol, ct.byref(o)))
+        return self
+
+    def setup_explicit(self, rowptr, col, val, perm, levels, **kw):
+        """levels: list of dicts with keys d, block_ptr, L, U, E, F, W, H where
+        L/U/E/F are (rowptr, col, val) triples (E, F, W, H omitted on the last
+        level)."""
+        rp, ci, v = _i64(rowptr), _i32(col), _vals(val)
+        cplx = np.iscomplexobj(v)
+        vt = np.complex128 if cplx else np.float64
+        self.dtype = GS_C128 if cplx else GS_F64
+        self.n = len(rp) - 1
+        keep = []
+        arr = (GsLevelData * len(levels))()
+        for i, lv in enumerate(levels):
+            x = arr[i]
+            x.d = int(lv["d"])
+            bp = _i64(lv["block_ptr"])
+            keep.append(bp)
+            x.nblocks = len(bp) - 1
+            x.block_ptr = _ptr(bp)
+            for name in ("L", "U", "E", "F"):
+                m = lv.get(name)
+                if m is None:
+                    continue
+                mr, mc, mv = _i64(m[0]), _i32(m[1]), _vals(m[2], vt)
+                keep += [mr, mc, mv]
+                pre = name.lower()
+                setattr(x, pre + "_rowptr", _ptr(mr))
+                setattr(x, pre + "_col", _ptr(mc))
+                setattr(x, pre + "_val", _ptr(mv))
+            W = lv.get("W")
+            if W is not None and W.shape[1] > 0:
+                Wf = np.asfortranarray(W, dtype=vt)
+                Hf = np.asfortranarray(lv["H"], dtype=vt)
+                keep += [Wf, Hf]
+                x.k = W.shape[1]
+                x.w = ct.c_void_p(Wf.ctypes.data)
+                x.h = ct.c_void_p(Hf.ctypes.data)
+            else:
+                x.k = 0
+        p = _i64(perm)
+        o = opts(**kw)
+        self._check(lib().gs_setup_explicit(self._h, self.n, _ptr(rp), _ptr(ci), _ptr(v),
+                                            self.dtype, _ptr(p), len(levels) - 1, arr,
+                                            ct.byref(o)))
+        return self
+
+    def set_precision(self, precision):
+        self._check(lib().gs_set_precision(self._h, PRECISIONS.get(precision, precision)))
+
+    # ---------------------------------------------------------------- apply / solve
+    def apply(self, x, y):
+        self._check(lib().gs_apply(self._h, _ptr(x), _ptr(y)))
+
+    def apply_many(self, nrhs, x, y):
+        self._check(lib().gs_apply_many(self._h, nrhs, _ptr(x), _ptr(y)))
+
+    def apply_profile(self, x, y, reps=10, cap=256):
+        ms = np.zeros(cap)
+        by = np.zeros(cap)
+        ns = ct.c_int()
+        self._check(lib().gs_apply_profile(self._h, _ptr(x), _ptr(y), reps, _ptr(ms), _ptr(by),
+                                           cap, ct.byref(ns)))
+        k = ns.value
+        labels = [lib().gs_apply_step_label(self._h, i).decode() for i in range(k)]
+        return [{"label": labels[i], "ms": float(ms[i]), "bytes": float(by[i])}
+                for i in range(k)]
+
+    def probe_enable(self, kind, max_launches):
+        self._check(lib().gs_probe_enable(self._h, kind, max_launches))
+
+    def probe_read(self):
+        n = ct.c_int64()
+        ms = ct.c_double()
+        by = ct.c_double()
+        self._check(lib().gs_probe_read(self._h, ct.byref(n), ct.byref(ms), ct.byref(by)))
+        return n.value, ms.value, by.value
+
+    def solve(self, b, x, tol):
+        info = GsInfo()
+        rc = self._check(lib().gs_solve(self._h, _ptr(b), _ptr(x), tol, ct.byref(info)),
+                         ok=(GS_OK, GS_NOT_CONVERGED))
+        d = info.as_dict()
+        d["status"] = rc
+        return d
+
+    def info(self):
+        info = GsInfo()
+        self._check(lib().gs_get_info(self._h, ct.byref(info)))
+        return info.as_dict()
+
+    def perm(self):
+        p = np.zeros(self.n, dtype=np.int64)
+        self._check(lib().gs_get_perm(self._h, _ptr(p)))
+        return p
+
+    def level(self, l):
+        z = np.zeros(8, dtype=np.int64)
+        self._check(lib().gs_get_level_sizes(self._h, l, _ptr(z)))
+        d, s, nb, nl, nu, ne, nf, k = (int(v) for v in z)
+        vt = np.complex128 if self.dtype == GS_C128 else np.float64
+        out = {"d": d, "s": s, "k": k, "block_ptr": np.zeros(nb + 1, np.int64)}
+        mats = {}
+        for name, rows, nnz in (("L", d, nl), ("U", d, nu), ("E", s, ne), ("F", d, nf)):
+            mats[name] = (np.zeros(rows + 1, np.int64), np.zeros(nnz, np.int32),
+                          np.zeros(nnz, vt))
+        W = np.zeros((s, k), dtype=vt, order="F")
+        H = np.zeros((k, k), dtype=vt, order="F")
+        args = [_ptr(out["block_ptr"])]
+        for name in ("L", "U", "E", "F"):
+            args += [_ptr(a) for a in mats[name]]
+        args += [ct.c_void_p(W.ctypes.data), ct.c_void_p(H.ctypes.data)]
+        self._check(lib().gs_get_level(self._h, l, *args))
+        out.update(mats)
+        out["W"], out["H"] = W, H
+        return out
+
+
+# ---------------------------------------------------------------- host stages
+def partition_grid(dims, nparts, levels, rowptr, col):
+    rp, ci = _i64(rowptr), _i32(col)
+    n = len(rp) - 1
+    d = _i32(dims)
+    perm = np.zeros(n, np.int64)
+    ls = np.zeros(levels + 2, np.int64)
+    nl = ct.c_int()
+    cap = n + levels + 2
+    bp = np.zeros(cap, np.int64)
+    bc = np.zeros(levels + 1, np.int64)
+    rc = lib().gs_partition_grid(len(d), _ptr(d), nparts, levels, n, _ptr(rp), _ptr(ci),
+                                 _ptr(perm), _ptr(ls), ct.byref(nl), _ptr(bp), _ptr(bc), cap)
+    if rc != GS_OK:
+        raise GemslrError(rc, lib().gs_last_error(None).decode())
+    L = nl.value
+    blocks, pos = [], 0
+    for l in range(L + 1):
+        cnt = int(bc[l]) + 1
+        blocks.append(bp[pos:pos + cnt].copy())
+        pos += cnt
+    return perm, ls[:L + 2].copy(), L, blocks
+
+
+def ilu(rowptr, col, val, kind="ilut", tau=0.0, lfil=10):
+    rp, ci, v = _i64(rowptr), _i32(col), _vals(val)
+    n = len(rp) - 1
+    dt = GS_C128 if np.iscomplexobj(v) else GS_F64
+    k = ILU_KINDS.get(kind, kind)
+    cap = int(rp[-1]) + n * (2 * min(int(lfil), n) + 2) if k == GS_ILUT else int(rp[-1]) + n
+    cap = min(cap, n * n + 1)
+    out = []
+    for _ in range(2):
+        out.append((np.zeros(n + 1, np.int64), np.zeros(cap, np.int32), np.zeros(cap, v.dtype)))
+    (lr, lc, lv), (ur, uc, uv) = out
+    rc = lib().gs_ilu(n, _ptr(rp), _ptr(ci), _ptr(v), dt, k, float(tau), int(min(lfil, 2**31 - 1)),
+                      _ptr(lr), _ptr(lc), _ptr(lv), cap, _ptr(ur), _ptr(uc), _ptr(uv), cap)
+    if rc != GS_OK:
+        raise GemslrError(rc, lib().gs_last_error(None).decode())
+    nl, nu = int(lr[-1]), int(ur[-1])
+    return (lr, lc[:nl].copy(), lv[:nl].copy()), (ur, uc[:nu].copy(), uv[:nu].copy())
