@@ -65,6 +65,10 @@ typedef struct {
   int32_t grid_dims[3];   /* points per axis for the geometric separator     */
   uint64_t seed;          /* Arnoldi start vectors (SplitMix64)        [0]    */
   int nthreads;           /* host threads for the factorisation (0 = all)     */
+  int defer_lowrank;      /* 1: gs_setup stops after the factorisation; the
+                             rank-k terms are built later by gs_lowrank  [0]  */
+  int block_max_iters;    /* gs_lowrank: block iterations from a starting
+                             basis before falling back to Arnoldi        [8]  */
 } gs_opts;
 
 /* Fill *opts with the defaults shown in brackets above. */
@@ -86,6 +90,9 @@ typedef struct {
   int32_t arnoldi_cycles[GS_MAX_LEVELS + 1];
   int32_t arnoldi_matvecs[GS_MAX_LEVELS + 1];
   int32_t arnoldi_converged[GS_MAX_LEVELS + 1];
+  int32_t lowrank_method[GS_MAX_LEVELS + 1]; /* 0 Arnoldi, 1 block iteration
+                                                from a given basis, 2 block
+                                                iteration then Arnoldi fallback */
   int64_t nnz_lu;           /* sum of nnz(L)+nnz(U) incl. diagonals, all levels */
   int64_t nnz_ef;           /* sum of nnz(E_l)+nnz(F_l)                       */
   int64_t nnz_a;            /* nnz(A)                                         */
@@ -182,6 +189,58 @@ int gs_apply(gs_ctx* ctx, const void* x, void* y);
 /* Same as gs_apply for `nrhs` vectors stored one after another
  * (x + j*n, y + j*n).  Errors as gs_apply. */
 int gs_apply_many(gs_ctx* ctx, int nrhs, const void* x, void* y);
+
+/* ---------------------------------------------------------------- learned start */
+/* Per-node features of the interface unknowns C_l of level l (0 <= l < L), for
+ * a network that predicts starting bases of the low-rank terms.  Host only
+ * (after a setup).  X: host, s_l x ncols row-major float32 (cols_cap >= 38);
+ * *ncols receives the feature count.  Features of node j (grid operators):
+ * normalised coordinates (3), sin/cos(m pi coordinate), m = 1..4, per axis
+ * (24), per-axis "coordinate on a cut" flags (3), log(|a_jj| / mean |a_ii|)
+ * and its mean over grid neighbours (2), per-axis convection proxy
+ * (a_{j,+axis} - a_{j,-axis}) / |a_jj| (3), sum |E_l(j,:)| / |a_jj| and
+ * sum |F_l(:,j)| / |a_jj| (2), level / L (1).
+ * Errors: GS_ESTATE, GS_EINVAL. */
+int gs_features(const gs_ctx* ctx, int level, float* X, int64_t rows_cap, int cols_cap,
+                int* ncols);
+
+/* Build (or rebuild) the rank-`rank` terms of every level bottom-up on the
+ * GPU (Sec. 4.2).  warm: NULL, or L device pointers (entries may be NULL);
+ * warm[l] is a float32 s_l x rank row-major starting basis for level l (the
+ * future-work "block" setup of Sec. 6): the level then runs a block
+ * Rayleigh-Ritz iteration -- Ritz pairs of span(V), expansion by the block
+ * residual G V - V (V^H G V), restart to the wanted k -- accepted when every
+ * wanted Ritz pair meets opts.arnoldi_tol; after opts.block_max_iters
+ * iterations it falls back to thick-restart Arnoldi.  Levels without a basis
+ * use Arnoldi.  Per-level matvec counts and the method used go to gs_info.
+ * Errors: GS_ESTATE, GS_EINVAL, GS_ESINGULAR, GS_EDEVICE. */
+int gs_lowrank(gs_ctx* ctx, int rank, const float* const* warm);
+
+/* The network of the learned start (not in the paper): a 3-layer perceptron
+ * in -> hidden -> hidden -> out with tanh after the first two layers, all
+ * float32 on the GPU, trained with the rotation-invariant subspace loss
+ * ||Y^T Y||_F^2 - 2 ||W^T Y||_F^2 + k_w against bases W from the library's own
+ * Arnoldi.  Parameters are packed W1 (in x hidden, row-major), b1, W2, b2, W3,
+ * b3.  Layer widths <= 64.  Errors: GS_EINVAL, GS_EDEVICE. */
+typedef struct gs_mlp gs_mlp;
+int gs_mlp_create(gs_mlp** mlp, int in_dim, int hidden, int out_dim, int device, void* stream);
+void gs_mlp_destroy(gs_mlp* mlp);
+int gs_mlp_nparams(const gs_mlp* mlp);
+const char* gs_mlp_last_error(const gs_mlp* mlp);
+/* host arrays of gs_mlp_nparams floats; set_params also resets Adam state */
+int gs_mlp_set_params(gs_mlp* mlp, const float* params);
+int gs_mlp_get_params(const gs_mlp* mlp, float* params);
+int gs_mlp_get_grads(const gs_mlp* mlp, float* grads);
+int gs_mlp_zero_grad(gs_mlp* mlp);
+/* Y = network(X): device, X rows x in, Y rows x out, row-major float32 */
+int gs_mlp_forward(gs_mlp* mlp, const float* X, int64_t rows, float* Y);
+/* Forward on X, loss against the target basis W (device, rows x kw
+ * row-major), gradients added to the accumulated ones; *loss on the host. */
+int gs_mlp_loss_backward(gs_mlp* mlp, const float* X, const float* W, int64_t rows, int kw,
+                         double* loss);
+/* One Adam update (bias-corrected) of the parameters with the accumulated
+ * gradients. */
+int gs_mlp_adam_step(gs_mlp* mlp, float lr, float beta1, float beta2, float eps);
 
 /* ---------------------------------------------------------------- measurement */
 /* Run `reps` applies of x (as gs_apply) with a HIP event pair recorded on the

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libgemslr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GEMSLR_ARCH", "gfx950")
 
-HIP_SOURCES = ["kernels.hip", "engine.hip", "api.hip"]
+HIP_SOURCES = ["kernels.hip", "engine.hip", "api.hip", "mlp.hip"]
 HOST_SOURCES = ["host_setup.cpp", "host_dense.cpp"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

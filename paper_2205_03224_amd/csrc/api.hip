@@ -37,6 +37,7 @@ struct gs_ctx {
   size_t pin_bytes = 0;
   gs_info info{};
   std::vector<std::string> step_labels;  // of the last gs_apply_profile
+  int nparts = 1;                         // of the last gs_setup (feature cut flags)
 };
 
 static std::string g_create_error;
@@ -79,6 +80,85 @@ static void cgs2(const DT* V, int64_t ld, int ncol, DT* w, int64_t n, DT* partia
     launch_gemv_sub<DT>(V, ld, ncol, h, w, n, hacc, st);
   }
 }
+
+// Schur form Sm = Q T Q^H (m x m) reordered so the k wanted Ritz values come
+// first (k raised by one for a real matrix rather than split a pair); returns
+// the basis G (m x kk) of the wanted invariant subspace and R = G^H Sm G:
+// for complex data G = Q_k and R = T_k; for real data G is a real
+// orthonormal basis of the conjugate-closed subspace (pivoted Gram-Schmidt on
+// [Re Q_k, Im Q_k]) and R = G^T Sm G.
+template <class T>
+static int schur_basis(int m, const std::vector<cplx>& Sm, int k, std::vector<cplx>& Tm,
+                       std::vector<cplx>& Q, std::vector<cplx>& theta_k, std::vector<T>& G,
+                       std::vector<T>& R) {
+  const bool real = std::is_same<T, double>::value;
+  Tm = Sm;
+  schur_complex(m, Tm, Q);
+  std::vector<cplx> theta(m);
+  for (int i = 0; i < m; ++i) theta[i] = Tm[(size_t)i * m + i];
+  std::vector<int> sel = select_wanted(theta, k, real);
+  schur_reorder(m, Tm, Q, sel);
+  int kk = 0;
+  for (int x : sel) kk += x;
+  theta_k.assign(kk, 0.0);
+  for (int i = 0; i < kk; ++i) theta_k[i] = Tm[(size_t)i * m + i];
+  G.assign((size_t)m * kk, T(0));
+  R.assign((size_t)kk * kk, T(0));
+  if (real) {
+    std::vector<std::vector<double>> X;
+    for (int j = 0; j < kk; ++j) {
+      std::vector<double> re(m), im(m);
+      for (int i = 0; i < m; ++i) { re[i] = Q[(size_t)j * m + i].real(); im[i] = Q[(size_t)j * m + i].imag(); }
+      X.push_back(re);
+      X.push_back(im);
+    }
+    double first = -1;
+    double* g = (double*)G.data();
+    for (int q = 0; q < kk; ++q) {
+      int best = -1;
+      double bn = -1;
+      for (size_t x = 0; x < X.size(); ++x) {
+        double nn2 = 0;
+        for (double e : X[x]) nn2 += e * e;
+        if (nn2 > bn) { bn = nn2; best = (int)x; }
+      }
+      bn = std::sqrt(bn);
+      if (first < 0) first = bn;
+      if (bn <= 1e-8 * first) throw Error(GS_EINVAL, "wanted Ritz set is not closed under conjugation");
+      std::vector<double> qv = X[best];
+      for (double& e : qv) e /= bn;
+      X.erase(X.begin() + best);
+      for (int pass = 0; pass < 2; ++pass)
+        for (auto& x : X) {
+          double d = 0;
+          for (int i = 0; i < m; ++i) d += qv[i] * x[i];
+          for (int i = 0; i < m; ++i) x[i] -= d * qv[i];
+        }
+      for (int i = 0; i < m; ++i) g[(size_t)q * m + i] = qv[i];
+    }
+    double* r = (double*)R.data();
+    for (int b = 0; b < kk; ++b)
+      for (int a = 0; a < kk; ++a) {
+        double acc = 0;
+        for (int i = 0; i < m; ++i) {
+          double sg = 0;
+          for (int j = 0; j < m; ++j) sg += Sm[(size_t)j * m + i].real() * g[(size_t)b * m + j];
+          acc += g[(size_t)a * m + i] * sg;
+        }
+        r[(size_t)b * kk + a] = acc;
+      }
+  } else {
+    for (int j = 0; j < kk; ++j)
+      for (int i = 0; i < m; ++i) std::memcpy((void*)&G[(size_t)j * m + i], &Q[(size_t)j * m + i], sizeof(cplx));
+    for (int j = 0; j < kk; ++j)
+      for (int i = 0; i < kk; ++i) std::memcpy((void*)&R[(size_t)j * kk + i], &Tm[(size_t)j * m + i], sizeof(cplx));
+  }
+  return kk;
+}
+
+template <class T> static cplx to_cplx(const void* p, size_t i);
+template <> cplx to_cplx<double>(const void* p, size_t i) { return cplx(((const double*)p)[i], 0.0); }
+template <> cplx to_cplx<cplx>(const void* p, size_t i) { return ((const cplx*)p)[i]; }
 
 // ------------------------------------------------------------ low-rank setup
 // Thick-restart (Krylov-Schur) Arnoldi on Ĝ_l on the GPU (Sec. 2.3, Sec. 4.2):
@@ -163,19 +243,11 @@ static void lowrank_level(gs_ctx* c, int l, int kreq) {
       }
     }
     // Schur form of the m x m Rayleigh matrix, wanted values first
-    std::vector<cplx> Tm((size_t)m * m), Q;
+    std::vector<cplx> Sorig((size_t)m * m), Tm, Q, thk;
     for (int j = 0; j < m; ++j)
-      for (int i = 0; i < m; ++i) Tm[(size_t)j * m + i] = Sat(i, j);
-    const std::vector<cplx> Sorig = Tm;
-    schur_complex(m, Tm, Q);
-    std::vector<cplx> theta(m);
-    for (int i = 0; i < m; ++i) theta[i] = Tm[(size_t)i * m + i];
-    std::vector<int> sel = select_wanted(theta, k, real);
-    schur_reorder(m, Tm, Q, sel);
-    int kk = 0;
-    for (int x : sel) kk += x;
-    std::vector<cplx> thk(kk);
-    for (int i = 0; i < kk; ++i) thk[i] = Tm[(size_t)i * m + i];
+      for (int i = 0; i < m; ++i) Sorig[(size_t)j * m + i] = Sat(i, j);
+    std::vector<T> G, R;
+    const int kk = schur_basis<T>(m, Sorig, k, Tm, Q, thk, G, R);
     // residuals of the wanted Ritz pairs: |b Q_k y_i|
     std::vector<cplx> Tk((size_t)kk * kk), Y;
     for (int j = 0; j < kk; ++j)
@@ -189,57 +261,6 @@ static void lowrank_level(gs_ctx* c, int l, int kreq) {
       cplx r = 0;
       for (int j = 0; j < kk; ++j) r += bq[j] * Y[(size_t)i * kk + j];
       if (std::abs(r) > c->opts.arnoldi_tol * std::abs(thk[i])) conv = false;
-    }
-    // basis G (m x kk) and R = G^H S G
-    std::vector<T> G((size_t)m * kk), R((size_t)kk * kk);
-    if (real) {
-      // real orthonormal basis of the conjugate-closed invariant subspace:
-      // pivoted Gram-Schmidt on [Re Q_k, Im Q_k]
-      std::vector<std::vector<double>> X;
-      for (int j = 0; j < kk; ++j) {
-        std::vector<double> re(m), im(m);
-        for (int i = 0; i < m; ++i) { re[i] = Q[(size_t)j * m + i].real(); im[i] = Q[(size_t)j * m + i].imag(); }
-        X.push_back(re);
-        X.push_back(im);
-      }
-      double first = -1;
-      for (int q = 0; q < kk; ++q) {
-        int best = -1;
-        double bn = -1;
-        for (size_t x = 0; x < X.size(); ++x) {
-          double nn2 = 0;
-          for (double e : X[x]) nn2 += e * e;
-          if (nn2 > bn) { bn = nn2; best = (int)x; }
-        }
-        bn = std::sqrt(bn);
-        if (first < 0) first = bn;
-        if (bn <= 1e-8 * first) throw Error(GS_EINVAL, "wanted Ritz set is not closed under conjugation");
-        std::vector<double> qv = X[best];
-        for (double& e : qv) e /= bn;
-        X.erase(X.begin() + best);
-        for (int pass = 0; pass < 2; ++pass)
-          for (auto& x : X) {
-            double d = 0;
-            for (int i = 0; i < m; ++i) d += qv[i] * x[i];
-            for (int i = 0; i < m; ++i) x[i] -= d * qv[i];
-          }
-        for (int i = 0; i < m; ++i) ((double*)G.data())[(size_t)q * m + i] = qv[i];
-      }
-      for (int b = 0; b < kk; ++b)
-        for (int a = 0; a < kk; ++a) {
-          double acc = 0;
-          for (int i = 0; i < m; ++i) {
-            double sg = 0;
-            for (int j = 0; j < m; ++j) sg += Sorig[(size_t)j * m + i].real() * ((double*)G.data())[(size_t)b * m + j];
-            acc += ((double*)G.data())[(size_t)a * m + i] * sg;
-          }
-          ((double*)R.data())[(size_t)b * kk + a] = acc;
-        }
-    } else {
-      for (int j = 0; j < kk; ++j)
-        for (int i = 0; i < m; ++i) std::memcpy((void*)&G[(size_t)j * m + i], &Q[(size_t)j * m + i], sizeof(cplx));
-      for (int j = 0; j < kk; ++j)
-        for (int i = 0; i < kk; ++i) std::memcpy((void*)&R[(size_t)j * kk + i], &Tm[(size_t)j * m + i], sizeof(cplx));
     }
     HIPCHK(hipMemcpyAsync(Gd, G.data(), G.size() * sizeof(DT), hipMemcpyHostToDevice, st));
     const bool last = conv || cycle == maxcyc - 1 || kk >= m;
@@ -280,6 +301,137 @@ static void lowrank_level(gs_ctx* c, int l, int kreq) {
     for (int j = 0; j < kk; ++j) Sat(kk, j) = bg[j];
     j0 = kk;
   }
+}
+
+
+// Block Rayleigh-Ritz iteration from a given starting basis Y (s x k, row-major
+// float32, device): V = orth(Y); repeat { Ritz pairs of T = V^H G V; accept if
+// every wanted pair has ||(G V - V T) y|| <= tol |theta|; otherwise expand by
+// the orthonormalised block residual P, Rayleigh-Ritz on [V P] and restart
+// to the k wanted Ritz vectors }.  k Ĝ_l products per iteration.  Returns
+// true and installs W_l, H_l on acceptance; matvecs are counted in h.
+template <class T>
+static bool lowrank_block(gs_ctx* c, int l, int kreq, const float* Y) {
+  using DT = typename DevOf<T>::type;
+  HostSetup<T>& S = host<T>(c);
+  HostLevel<T>& h = S.lv[l];
+  const hipStream_t st = c->stream;
+  const int64_t s = h.s;
+  const int k = (int)std::min<int64_t>(kreq, s);
+  if (k <= 0) return true;
+  const int kmax = (int)std::min<int64_t>(k + 1, s);
+  const int wmax = (int)std::min<int64_t>(2 * (int64_t)kmax, s);
+  DevMem mem;
+  DT* Sv = mem.alloc<DT>((size_t)s * 2 * kmax);   // [V P]
+  DT* GSv = mem.alloc<DT>((size_t)s * 2 * kmax);  // [G V, G P]
+  DT* tmp = mem.alloc<DT>((size_t)s * 2 * kmax);
+  DT* part = mem.alloc<DT>((size_t)256 * 2 * kmax);
+  DT* hd = mem.alloc<DT>(2 * kmax);
+  DT* Td = mem.alloc<DT>((size_t)4 * kmax * kmax);
+  DT* Gd = mem.alloc<DT>((size_t)4 * kmax * kmax);
+  double* npart = mem.alloc<double>(256);
+  double* nrm = mem.alloc<double>(2);
+  std::vector<DT> hv(s);
+  std::vector<double> v0(s);
+  int nmv = 0;
+  auto col = [&](DT* base, int j) { return base + (size_t)j * s; };
+  // orthonormalise column j of Sv against columns [0, j); a vanishing column
+  // is replaced by a fresh generator vector
+  auto orth_col = [&](int j) {
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      launch_norm<DT>(col(Sv, j), s, npart, nrm + 1, st);
+      if (j > 0) cgs2<DT>(Sv, s, j, col(Sv, j), s, part, hd, nullptr, st);
+      launch_norm<DT>(col(Sv, j), s, npart, nrm, st);
+      double nn[2];
+      HIPCHK(hipMemcpyAsync(nn, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (nn[0] > 1e-10 * nn[1] && nn[0] > 0) {
+        launch_scale_inv<DT>(col(Sv, j), nrm, col(Sv, j), s, st);
+        return;
+      }
+      start_vector(c->opts.seed + (uint64_t)l + 0x9E3779B9ULL * (uint64_t)(j + 1 + 97 * attempt), s,
+                   v0.data());
+      for (int64_t i = 0; i < s; ++i) hv[i] = from_host<DT>(v0[i]);
+      HIPCHK(hipMemcpyAsync(col(Sv, j), hv.data(), s * sizeof(DT), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    throw Error(GS_EINVAL, "could not extend the block basis");
+  };
+  // host copy of a w x w device matrix (column-major) as complex
+  auto fetch = [&](const DT* d, int r, int cc) {
+    std::vector<DT> tmph((size_t)r * cc);
+    HIPCHK(hipMemcpyAsync(tmph.data(), d, tmph.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<cplx> out((size_t)r * cc);
+    for (size_t i = 0; i < out.size(); ++i) out[i] = to_cplx<T>(tmph.data(), i);
+    return out;
+  };
+  launch_rows_to_cols<DT>(Y, s, k, kreq, Sv, s, st);
+  int w = k;
+  for (int j = 0; j < w; ++j) orth_col(j);
+  for (int j = 0; j < w; ++j, ++nmv) c->eng->ghat(l, col(Sv, j), col(GSv, j));
+  const int maxit = std::max(1, c->opts.block_max_iters);
+  for (int it = 0; it < maxit; ++it) {
+    // T = V^H G V and the block residual R = G V - V T (into the P slot)
+    for (int j = 0; j < w; ++j) launch_multidot<DT>(Sv, s, w, col(GSv, j), s, part, Td + (size_t)j * w, st);
+    launch_gemm_small<DT>(Sv, s, w, Td, w, tmp, s, s, st);
+    launch_sub<DT>(GSv, tmp, col(Sv, w), (int64_t)s * w, st);
+    for (int j = 0; j < w; ++j) launch_multidot<DT>(col(Sv, w), s, w, col(Sv, w + j), s, part, Gd + (size_t)j * w, st);
+    const std::vector<cplx> Tw = fetch(Td, w, w);
+    const std::vector<cplx> Nw = fetch(Gd, w, w);
+    std::vector<cplx> Tm, Q, thk;
+    std::vector<T> G, R;
+    const int kk = schur_basis<T>(w, Tw, k, Tm, Q, thk, G, R);
+    // Ritz pair residuals ||R y_i||^2 = y_i^H N y_i with y_i = Q_k e_i-eigvec
+    std::vector<cplx> Tk((size_t)kk * kk), Ye;
+    for (int j = 0; j < kk; ++j)
+      for (int i = 0; i < kk; ++i) Tk[(size_t)j * kk + i] = Tm[(size_t)j * w + i];
+    triu_eigvecs(kk, Tk, Ye);
+    bool conv = true;
+    for (int e = 0; e < kk && conv; ++e) {
+      std::vector<cplx> y(w, 0.0);
+      for (int j = 0; j < kk; ++j)
+        for (int i = 0; i < w; ++i) y[i] += Q[(size_t)j * w + i] * Ye[(size_t)e * kk + j];
+      cplx q = 0;
+      for (int a = 0; a < w; ++a)
+        for (int b = 0; b < w; ++b) q += std::conj(y[a]) * Nw[(size_t)b * w + a] * y[b];
+      const double res = std::sqrt(std::max(0.0, q.real()));
+      if (res > c->opts.arnoldi_tol * std::abs(thk[e])) conv = false;
+    }
+    if (conv) {
+      HIPCHK(hipMemcpyAsync(Gd, G.data(), G.size() * sizeof(DT), hipMemcpyHostToDevice, st));
+      launch_gemm_small<DT>(Sv, s, w, Gd, kk, tmp, s, s, st);
+      h.W.resize((size_t)s * kk);
+      HIPCHK(hipMemcpyAsync(h.W.data(), tmp, h.W.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      h.k = kk;
+      h.H = correction_matrix<T>(kk, R, thk);
+      h.arnoldi_cycles = it + 1;
+      h.arnoldi_matvecs = nmv;
+      h.arnoldi_converged = 1;
+      c->eng->set_lowrank(l, kk, h.W.data(), h.H.data());
+      return true;
+    }
+    if (it == maxit - 1 || 2 * w > wmax) break;
+    // expand by the orthonormalised residual block and its products
+    for (int j = 0; j < w; ++j) orth_col(w + j);
+    for (int j = 0; j < w; ++j, ++nmv) c->eng->ghat(l, col(Sv, w + j), col(GSv, w + j));
+    // Rayleigh-Ritz on [V P]; restart to the wanted Ritz vectors
+    const int w2 = 2 * w;
+    for (int j = 0; j < w2; ++j) launch_multidot<DT>(Sv, s, w2, col(GSv, j), s, part, Td + (size_t)j * w2, st);
+    const std::vector<cplx> T2 = fetch(Td, w2, w2);
+    std::vector<T> G2, R2;
+    const int k2 = schur_basis<T>(w2, T2, k, Tm, Q, thk, G2, R2);
+    HIPCHK(hipMemcpyAsync(Gd, G2.data(), G2.size() * sizeof(DT), hipMemcpyHostToDevice, st));
+    launch_gemm_small<DT>(Sv, s, w2, Gd, k2, tmp, s, s, st);
+    launch_copy<DT>(tmp, Sv, (int64_t)s * k2, st);
+    launch_gemm_small<DT>(GSv, s, w2, Gd, k2, tmp, s, s, st);
+    launch_copy<DT>(tmp, GSv, (int64_t)s * k2, st);
+    HIPCHK(hipStreamSynchronize(st));
+    w = k2;
+  }
+  h.arnoldi_matvecs = nmv;
+  return false;
 }
 
 // ------------------------------------------------------------ FGMRES
@@ -496,9 +648,11 @@ static void setup_native(gs_ctx* c, int64_t n, const int64_t* rp, const int32_t*
   c->eng = make_engine(host<T>(c), c->precision, c->stream);
   double t3 = now_s();
   HostSetup<T>& H = host<T>(c);
-  for (int l = H.L() - 1; l >= 0; --l) {
-    if (l == H.L() - 1 && !c->opts.lowrank_last_level) continue;
-    lowrank_level<T>(c, l, rank);
+  if (!c->opts.defer_lowrank) {
+    for (int l = H.L() - 1; l >= 0; --l) {
+      if (l == H.L() - 1 && !c->opts.lowrank_last_level) continue;
+      lowrank_level<T>(c, l, rank);
+    }
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   double t4 = now_s();
@@ -573,6 +727,135 @@ static void setup_explicit(gs_ctx* c, int64_t n, const int64_t* rp, const int32_
   c->eng = make_engine(host<T>(c), c->precision, c->stream);
   c->info = gs_info{};
   finish_setup<T>(c);
+}
+
+
+// ------------------------------------------------------------ learned start
+template <class T>
+static int features(gs_ctx* c, int l, float* X, int64_t rows_cap, int cols_cap) {
+  HostSetup<T>& S = host<T>(c);
+  if (l < 0 || l >= S.L()) throw Error(GS_EINVAL, "features: level out of range");
+  const int nd = c->opts.grid_ndim;
+  if (nd <= 0) throw Error(GS_EINVAL, "features need grid dimensions");
+  const int NF = 38;
+  const HostLevel<T>& h = S.lv[l];
+  if (rows_cap < h.s || cols_cap < NF) throw Error(GS_EINVAL, "feature array too small");
+  const int64_t n = S.n;
+  int dims[3] = {1, 1, 1};
+  for (int a = 0; a < nd; ++a) dims[a] = c->opts.grid_dims[a];
+  int q = 1;
+  while (true) {
+    int64_t p = 1;
+    for (int a = 0; a < nd; ++a) p *= (q + 1);
+    if (p > c->nparts) break;
+    ++q;
+  }
+  const CSR<T>& A = S.A;
+  std::vector<double> ldiag(n, 0.0);
+  double mean = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p)
+      if (A.ci[p] == i) ldiag[i] = absval(A.v[p]);
+    mean += ldiag[i];
+  }
+  mean /= (double)n;
+  std::vector<double> lg(n);
+  for (int64_t i = 0; i < n; ++i) lg[i] = std::log(std::max(ldiag[i], 1e-300) / mean);
+  // E row sums and F column sums of level l (rows / columns indexed in C_l)
+  std::vector<double> esum(h.s, 0.0), fsum(h.s, 0.0);
+  for (int64_t j = 0; j < h.s; ++j)
+    for (int64_t p = h.E.rp[j]; p < h.E.rp[j + 1]; ++p) esum[j] += absval(h.E.v[p]);
+  for (int64_t i = 0; i < h.d; ++i)
+    for (int64_t p = h.F.rp[i]; p < h.F.rp[i + 1]; ++p) fsum[h.F.ci[p]] += absval(h.F.v[p]);
+  const int64_t stride[3] = {1, dims[0], (int64_t)dims[0] * dims[1]};
+  const double pi = 3.14159265358979323846;
+  for (int64_t j = 0; j < h.s; ++j) {
+    const int64_t o = S.perm[h.start + h.d + j];
+    float* f = X + (size_t)j * cols_cap;
+    int crd[3] = {0, 0, 0};
+    int64_t r = o;
+    for (int a = 0; a < nd; ++a) { crd[a] = (int)(r % dims[a]); r /= dims[a]; }
+    int fi = 0;
+    double u[3];
+    for (int a = 0; a < 3; ++a) {
+      u[a] = a < nd ? (crd[a] + 1.0) / (dims[a] + 1.0) : 0.0;
+      f[fi++] = (float)u[a];
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int m = 1; m <= 4; ++m) {
+        f[fi++] = (float)std::sin(m * pi * u[a]);
+        f[fi++] = (float)std::cos(m * pi * u[a]);
+      }
+    for (int a = 0; a < 3; ++a) {
+      bool cut = false;
+      if (a < nd)
+        for (int jj = 1; jj < q; ++jj)
+          if (crd[a] == (int)(((int64_t)jj * (dims[a] + 1)) / q)) cut = true;
+      f[fi++] = cut ? 1.0f : 0.0f;
+    }
+    f[fi++] = (float)lg[o];
+    double nsum = 0;
+    int ncnt = 0;
+    double conv[3] = {0, 0, 0};
+    for (int64_t p = A.rp[o]; p < A.rp[o + 1]; ++p) {
+      const int64_t cidx = A.ci[p];
+      if (cidx == o) continue;
+      nsum += lg[cidx];
+      ++ncnt;
+      for (int a = 0; a < nd; ++a) {
+        if (cidx == o + stride[a]) conv[a] += realpart(A.v[p]);
+        if (cidx == o - stride[a]) conv[a] -= realpart(A.v[p]);
+      }
+    }
+    f[fi++] = (float)(ncnt ? nsum / ncnt : lg[o]);
+    for (int a = 0; a < 3; ++a) f[fi++] = (float)(conv[a] / std::max(ldiag[o], 1e-300));
+    f[fi++] = (float)(esum[j] / std::max(ldiag[o], 1e-300));
+    f[fi++] = (float)(fsum[j] / std::max(ldiag[o], 1e-300));
+    f[fi++] = (float)((double)l / (double)S.L());
+    (void)fi;
+  }
+  return NF;
+}
+
+template <class T>
+static void lowrank_all(gs_ctx* c, int rank, const float* const* warm) {
+  HostSetup<T>& H = host<T>(c);
+  const double t0 = now_s();
+  for (int l = H.L() - 1; l >= 0; --l) {
+    HostLevel<T>& h = H.lv[l];
+    h.k = 0;
+    h.arnoldi_cycles = h.arnoldi_matvecs = h.arnoldi_converged = 0;
+    c->eng->set_lowrank(l, 0, nullptr, nullptr);
+    int method = 0;
+    if (l == H.L() - 1 && !c->opts.lowrank_last_level) {
+      c->info.lowrank_method[l] = 0;
+      continue;
+    }
+    if (warm && warm[l]) {
+      method = 1;
+      if (!lowrank_block<T>(c, l, rank, warm[l])) {
+        const int used = h.arnoldi_matvecs;
+        method = 2;
+        lowrank_level<T>(c, l, rank);
+        h.arnoldi_matvecs += used;
+      }
+    } else {
+      lowrank_level<T>(c, l, rank);
+    }
+    if (l <= GS_MAX_LEVELS) c->info.lowrank_method[l] = method;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->info.t_lowrank = now_s() - t0;
+  const double tl = c->info.t_lowrank;
+  int methods[GS_MAX_LEVELS + 1];
+  std::memcpy(methods, c->info.lowrank_method, sizeof(methods));
+  const double tp = c->info.t_partition, tf = c->info.t_factor, ty = c->info.t_layout;
+  finish_setup<T>(c);
+  c->info.t_partition = tp;
+  c->info.t_factor = tf;
+  c->info.t_layout = ty;
+  c->info.t_lowrank = tl;
+  std::memcpy(c->info.lowrank_method, methods, sizeof(methods));
 }
 
 }  // namespace gs
@@ -665,6 +948,8 @@ void gs_opts_default(gs_opts* o) {
   o->grid_ndim = 0;
   o->seed = 0;
   o->nthreads = 0;
+  o->defer_lowrank = 0;
+  o->block_max_iters = 8;
 }
 
 int gs_create(gs_ctx** ctx, int device, void* stream) {
@@ -731,6 +1016,7 @@ int gs_setup(gs_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col, co
     c->hz.reset();
     c->dtype = dtype;
     c->precision = c->opts.precision;
+    c->nparts = nparts;
     if (dtype == GS_F64) setup_native<double>(c, n, rowptr, col, val, levels, nparts, rank, drop_tol);
     else setup_native<cplx>(c, n, rowptr, col, val, levels, nparts, rank, drop_tol);
     return GS_OK;
@@ -856,6 +1142,32 @@ int gs_solve(gs_ctx* c, const void* b, void* x, double tol, gs_info* info) {
     if (!(tol > 0)) throw Error(GS_EINVAL, "tol must be positive");
     if (c->dtype == GS_F64) return fgmres<double>(c, b, x, tol, info);
     return fgmres<cplx>(c, b, x, tol, info);
+  });
+}
+
+
+int gs_features(const gs_ctx* cc, int level, float* X, int64_t rows_cap, int cols_cap,
+                int* ncols) {
+  if (!cc || !X || !ncols) return GS_EINVAL;
+  gs_ctx* c = const_cast<gs_ctx*>(cc);
+  if (!c->ready) return GS_ESTATE;
+  GS_GUARD(c, {
+    *ncols = c->dtype == GS_F64 ? features<double>(c, level, X, rows_cap, cols_cap)
+                                : features<cplx>(c, level, X, rows_cap, cols_cap);
+    return GS_OK;
+  });
+}
+
+int gs_lowrank(gs_ctx* c, int rank, const float* const* warm) {
+  if (!c) return GS_EINVAL;
+  GS_GUARD(c, {
+    int r = need_device(c);
+    if (r) return r;
+    if (!c->ready) throw Error(GS_ESTATE, "lowrank before setup");
+    if (rank < 0) throw Error(GS_EINVAL, "rank < 0");
+    if (c->dtype == GS_F64) lowrank_all<double>(c, rank, warm);
+    else lowrank_all<cplx>(c, rank, warm);
+    return GS_OK;
   });
 }
 

@@ -87,6 +87,24 @@ struct CsrDev {
 
 enum { TRI_DOWN = 0, TRI_UP = 1 };
 
+// Streamed form of the same stages: each block's L stages, then its U
+// stages, packed into chunks of whole stages, each chunk one contiguous,
+// 16-byte aligned byte range:
+//   values       entries x V            (offset 0)
+//   inverse diag rows x D               (U chunks only)
+//   row info     rows x uint32: block-local row | count << 16 | stage rows << 24
+//   columns      entries x uint16
+// Section offsets are in 16-byte units.  A stage's first row and first
+// entry follow from the previous stage (rows and entries are consecutive),
+// so the consumer needs no stage table.
+struct ChunkDesc {
+  uint32_t off;      // byte offset of the chunk in the level's blob
+  uint16_t n16;      // chunk size in 16-byte units
+  uint16_t nst;      // stages in the chunk | 0x8000 for U chunks
+  uint16_t nrows;    // rows in the chunk
+  uint16_t dinv16, info16, col16;
+};
+
 template <class P>
 struct TriArgs {
   TriDev<P> lo, up;
@@ -96,6 +114,12 @@ struct TriArgs {
   CsrDev<P> F;               // UP mode: F_l (rows of B_l, cols of C_l)
   typename P::X* xg;         // scratch (d entries) when blocks exceed LDS
   int32_t nb;
+  // streamed layout (used when `blob` is set)
+  const uint8_t* blob;
+  const ChunkDesc* chunk;
+  const int32_t* blk_chunk;  // nb+1 chunk ranges
+  int32_t chunk_cap;         // max chunk bytes (multiple of 1 KiB)
+  int32_t x_bytes;           // LDS bytes reserved for the block's vector (16-aligned)
 };
 
 template <class P>
@@ -114,7 +138,15 @@ struct IfArgs {
 // ------------------------------------------------------------ launchers
 template <class P> void launch_trisolve(const TriArgs<P>& a, int mode, int maxslot,
                                         int max_block_rows, hipStream_t st);
+// streamed variant: one producer wave stages chunks into LDS, one consumer
+// wave sweeps; needs a.blob, x in LDS, and maxslot <= 16
+template <class P> void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot,
+                                                 int max_block_rows, hipStream_t st);
+// maximum chunk size the streamed kernel stages (bytes)
+constexpr int kChunkCapMax = 24576;
 template <class P> void launch_interface(const IfArgs<P>& a, hipStream_t st);
+// workgroups launch_interface uses for s interface rows (size of `partial`)
+template <class P> int interface_blocks(int64_t s);
 template <class P> void launch_lowrank_update(typename P::X* tc, int64_t s, int k,
                                               const typename P::V* W,
                                               const typename P::C* tprime, hipStream_t st);
@@ -148,6 +180,12 @@ template <class T> void launch_gemv_add(const T* Z, int64_t ld, int ncol, const 
 template <class T> void launch_gemm_small(const T* V, int64_t ld, int m, const T* G, int k,
                                           T* Y, int64_t ldy, int64_t n, hipStream_t st);
 template <class T> void launch_fill(T* x, T v, int64_t n, hipStream_t st);
+// V[:, c] (column-major, ld) = Y[:, c], c < k, for a row-major float32
+// block Y with row stride ldy >= k
+template <class T> void launch_rows_to_cols(const float* Y, int64_t s, int k, int ldy, T* V,
+                                            int64_t ld, hipStream_t st);
+// out = a - b (n entries)
+template <class T> void launch_sub(const T* a, const T* b, T* out, int64_t n, hipStream_t st);
 // y[i] = x[perm[i]] (gather into reordered numbering) / y[perm[i]] = x[i]
 template <class T> void launch_permute(const T* x, const int32_t* perm, T* y, int64_t n,
                                        bool scatter, hipStream_t st);

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -142,6 +143,82 @@ TriHost<T> build_tri(const CSR<T>& M, const std::vector<int64_t>& blocks, bool u
   return h;
 }
 
+
+// Pack the stages of every block (L stages, then U stages) into chunks of
+// whole stages of at most `cap` bytes (see ChunkDesc).  Returns false if a
+// single stage does not fit.
+template <class V, class D, class T>
+bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap,
+                  std::vector<uint8_t>& blob, std::vector<ChunkDesc>& desc,
+                  std::vector<int32_t>& blk_chunk) {
+  auto pad = [](size_t x) { return (x + 15) & ~(size_t)15; };
+  blob.clear();
+  desc.clear();
+  blk_chunk.assign(1, 0);
+  for (int b = 0; b < nb; ++b) {
+    for (int tri = 0; tri < 2; ++tri) {
+      const TriHost<T>& h = tri == 0 ? lo : up;
+      const bool isU = tri == 1;
+      const int sb = h.blk_stage[b], se = h.blk_stage[b + 1];
+      auto size_of = [&](int s0, int s1) {
+        const size_t rows = h.stage_row[s1] - h.stage_row[s0];
+        const size_t ents = h.stage_ent[s1] - h.stage_ent[s0];
+        return pad(ents * sizeof(V)) + (isU ? pad(rows * sizeof(D)) : 0) + pad(rows * 4) +
+               pad(ents * 2);
+      };
+      int s = sb;
+      while (s < se) {
+        int s2 = s;
+        while (s2 < se && size_of(s, s2 + 1) <= (size_t)cap) ++s2;
+        if (s2 == s) return false;
+        const size_t rows = h.stage_row[s2] - h.stage_row[s];
+        const size_t ents = h.stage_ent[s2] - h.stage_ent[s];
+        if (rows > 65535 || ents > 65535) return false;
+        ChunkDesc cd{};
+        const size_t base = blob.size();
+        if (base > 0xffffffffull) throw Error(GS_EINVAL, "level too large for 32-bit offsets");
+        cd.off = (uint32_t)base;
+        const size_t o_val = 0;
+        const size_t o_dinv = pad(ents * sizeof(V));
+        const size_t o_info = o_dinv + (isU ? pad(rows * sizeof(D)) : 0);
+        const size_t o_col = o_info + pad(rows * 4);
+        const size_t total = o_col + pad(ents * 2);
+        cd.n16 = (uint16_t)(total / 16);
+        cd.nst = (uint16_t)((s2 - s) | (isU ? 0x8000 : 0));
+        cd.nrows = (uint16_t)rows;
+        cd.dinv16 = (uint16_t)(o_dinv / 16);
+        cd.info16 = (uint16_t)(o_info / 16);
+        cd.col16 = (uint16_t)(o_col / 16);
+        blob.resize(base + total, 0);
+        uint8_t* p = blob.data() + base;
+        const int32_t rb = h.stage_row[s], eb = h.stage_ent[s];
+        for (size_t q = 0; q < ents; ++q) {
+          const V v = to_store<V, T>(h.val[eb + q]);
+          std::memcpy(p + o_val + q * sizeof(V), &v, sizeof(V));
+          std::memcpy(p + o_col + q * 2, &h.col[eb + q], 2);
+        }
+        for (int k = s; k < s2; ++k) {
+          const uint32_t nrs = (uint32_t)(h.stage_row[k + 1] - h.stage_row[k]);
+          for (int32_t q = h.stage_row[k]; q < h.stage_row[k + 1]; ++q) {
+            const uint32_t inf = h.rowinfo[q];
+            if ((inf >> 16) > 255) return false;
+            const uint32_t w = (inf & 0x00ffffffu) | (nrs << 24);
+            std::memcpy(p + o_info + (size_t)(q - rb) * 4, &w, 4);
+            if (isU) {
+              const D dv = to_store<D, T>(h.dinv[q]);
+              std::memcpy(p + o_dinv + (size_t)(q - rb) * sizeof(D), &dv, sizeof(D));
+            }
+          }
+        }
+        desc.push_back(cd);
+        s = s2;
+      }
+    }
+    blk_chunk.push_back((int32_t)desc.size());
+  }
+  return true;
+}
+
 // ====================================================================== engine
 
 template <class P, class T>
@@ -165,6 +242,12 @@ struct EngineT final : Engine {
     uint32_t* counter = nullptr;
     int kcap = 0;
     int64_t nnz_lu = 0, nnz_e = 0, nnz_f = 0, nstages = 0;
+    // streamed layout (null when the level uses the register-prefetch kernel)
+    const uint8_t* blob = nullptr;
+    const ChunkDesc* chunk = nullptr;
+    const int32_t* blk_chunk = nullptr;
+    int chunk_cap = 0, x_bytes = 0;
+    int64_t nchunks = 0;
     int depth_l = 0, depth_u = 0;
   };
 
@@ -215,8 +298,20 @@ struct EngineT final : Engine {
     return d;
   }
 
+  int lds_budget = 65536;
+  bool no_stream = std::getenv("GEMSLR_NO_STREAM") != nullptr;
+
   EngineT(const HostSetup<T>& S, hipStream_t stream) : st(stream) {
     n = S.n;
+    {
+      int dev = 0, maxlds = 65536;
+      HIPCHK(hipGetDevice(&dev));
+      if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        maxlds = 65536;
+      // two workgroups per CU when the device allows more than 64 KiB each
+      lds_budget = std::min(maxlds, 81920);
+      if (const char* e = std::getenv("GEMSLR_LDS_BUDGET")) lds_budget = std::atoi(e);
+    }
     std::vector<int32_t> p32(S.perm.begin(), S.perm.end());
     perm_d = upload(p32);
     t = mem.alloc<X>(n);
@@ -239,6 +334,27 @@ struct EngineT final : Engine {
       L.depth_l = tl.depth;
       L.depth_u = tu.depth;
       L.nstages = (int64_t)(tl.stage_row.size() + tu.stage_row.size()) - 2;
+      {
+        // streamed layout: block vector and two chunk buffers in LDS, sized so
+        // that two workgroups share one CU
+        const int xb = (int)((L.max_block_rows * sizeof(C) + 15) & ~(size_t)15);
+        int cap = std::min(kChunkCapMax, ((lds_budget - xb - 1024) / 2) & ~1023);
+        if (L.nb > 0 && L.maxslot <= 16 && cap >= 4096) {
+          std::vector<uint8_t> blob;
+          std::vector<ChunkDesc> desc;
+          std::vector<int32_t> bc;
+          if (build_chunks<V, D, T>(tl, tu, L.nb, cap, blob, desc, bc)) {
+            L.blob = upload(blob);
+            std::vector<uint8_t> draw(desc.size() * sizeof(ChunkDesc));
+            if (!desc.empty()) std::memcpy(draw.data(), desc.data(), draw.size());
+            L.chunk = (const ChunkDesc*)upload(draw);
+            L.blk_chunk = upload(bc);
+            L.chunk_cap = cap;
+            L.x_bytes = xb;
+            L.nchunks = (int64_t)desc.size();
+          }
+        }
+      }
       L.lo = upload_tri(tl, false);
       L.up = upload_tri(tu, true);
       L.nnz_lu = h.L.nnz() + h.U.nnz();
@@ -260,7 +376,7 @@ struct EngineT final : Engine {
   void set_lowrank_host(int l, int k, const std::vector<T>& W, const std::vector<T>& H) {
     Lev& L = lv[l];
     if (k > L.kcap) {
-      const int nblk = (int)((L.s + 255) / 256);
+      const int nblk = interface_blocks<P>(L.s);
       L.partial = mem.alloc<C>((size_t)nblk * k);
       L.tprime = mem.alloc<C>(k);
       L.counter = mem.alloc<uint32_t>(1);
@@ -293,7 +409,19 @@ struct EngineT final : Engine {
     a.F = L.F;
     a.xg = reinterpret_cast<X*>(xg);
     a.nb = L.nb;
+    a.blob = L.blob;
+    a.chunk = L.chunk;
+    a.blk_chunk = L.blk_chunk;
+    a.chunk_cap = L.chunk_cap;
+    a.x_bytes = L.x_bytes;
     return a;
+  }
+  void trisolve(int l, int mode) {
+    const Lev& L = lv[l];
+    if (L.blob && !no_stream)
+      launch_trisolve_streamed<P>(tri_args(l), mode, L.maxslot, L.max_block_rows, st);
+    else
+      launch_trisolve<P>(tri_args(l), mode, L.maxslot, L.max_block_rows, st);
   }
 
   hipEvent_t ev_at(size_t i) {
@@ -336,7 +464,7 @@ struct EngineT final : Engine {
     const double vb = sizeof(V), xb = sizeof(X), db = sizeof(D);
     double b = (double)(L.nnz_lu - L.d) * (vb + 2)   // factor value + 16-bit column
                + 2.0 * L.d * 4 + L.d * db              // row info (L and U), 1/u_ii
-               + 8.0 * L.nstages + 12.0 * (L.nb + 1)   // stage and block tables
+               + 4.0 * L.nstages + 8.0 * (L.nb + 1)    // stage and block tables
                + 2.0 * L.d * xb;                       // right-hand side in, result out
     if (mode == TRI_UP)
       b += (double)L.nnz_f * (vb + 4) + (double)(L.d + 1) * 4  // F_l
@@ -379,7 +507,7 @@ struct EngineT final : Engine {
     if (lv[l].nb > 0)
       step("trisolve_down L" + std::to_string(l), l == 0 ? KIND_TRI0 : KIND_TRI,
            tri_bytes(l, TRI_DOWN), [&] {
-             launch_trisolve<P>(tri_args(l), TRI_DOWN, lv[l].maxslot, lv[l].max_block_rows, st);
+             trisolve(l, TRI_DOWN);
            });
     if (l + 1 < (int)lv.size()) interface(l, lv[l].k);
   }
@@ -387,7 +515,7 @@ struct EngineT final : Engine {
     if (lv[l].nb > 0)
       step("trisolve_up L" + std::to_string(l), l == 0 ? KIND_TRI0 : KIND_TRI,
            tri_bytes(l, TRI_UP), [&] {
-             launch_trisolve<P>(tri_args(l), TRI_UP, lv[l].maxslot, lv[l].max_block_rows, st);
+             trisolve(l, TRI_UP);
            });
   }
   void run_from(int l0) {

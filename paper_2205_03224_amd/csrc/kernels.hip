@@ -16,6 +16,9 @@ namespace {
 constexpr int kWave = 64;
 
 template <class T> __device__ inline T zero();
+template <class T> __device__ inline T cvt_rc(float v);
+template <> __device__ inline double cvt_rc<double>(float v) { return (double)v; }
+template <> __device__ inline dcplx cvt_rc<dcplx>(float v) { return mk((double)v, 0.0); }
 template <> __device__ inline double zero<double>() { return 0.0; }
 template <> __device__ inline float zero<float>() { return 0.0f; }
 template <> __device__ inline dcplx zero<dcplx>() { return mk(0.0, 0.0); }
@@ -90,10 +93,20 @@ __device__ __forceinline__ void stage_compute(const StageRegs<P, MS>& r,
   using C = typename P::C;
   const int nz = (int)(r.info >> 16);
   const int row = (int)(r.info & 0xffffu);
-  C acc = x[row];
+  const int maxnz = __builtin_amdgcn_readfirstlane(nz);
+  // all gathers first (masked slots read x[row]), then the accumulation
+  C xv[MS > 0 ? MS : 1];
 #pragma unroll
   for (int j = 0; j < MS; ++j)
-    if (j < nz) acc -= r.v[j] * x[r.c[j]];
+    if (j < maxnz) xv[j] = x[nz > j ? (int)r.c[j] : row];
+  C acc = x[row];
+#pragma unroll
+  for (int j = 0; j < MS; ++j) {
+    if (j < maxnz) {
+      const C t = r.v[j] * xv[j];
+      acc = nz > j ? acc - t : acc;
+    }
+  }
   if (ISU) acc *= r.dinv;
   x[row] = acc;
 }
@@ -207,36 +220,296 @@ void launch_trisolve(const TriArgs<P>& a, int mode, int maxslot, int max_block_r
 }
 
 // ======================================================================
+// Streamed batched block triangular solve: two wavefronts per diagonal
+// block.  Wave 1 (producer) copies the block's chunks -- whole stages of
+// factor entries, row info and inverse diagonals, packed contiguously --
+// from HBM into one of two LDS buffers with 16-byte coalesced loads, while
+// wave 0 (consumer) runs the dependent sweep over the other buffer out of
+// LDS only.  One workgroup barrier per chunk hands the buffers over.  HBM
+// latency is paid once per chunk instead of once per wavefront level.
+// ======================================================================
+constexpr int kNV = kChunkCapMax / (16 * 64);  // 16-byte loads per lane per chunk
+
+template <class P>
+__device__ __forceinline__ void copy_chunk(const TriArgs<P>& a, int c, uint8_t* dst, int lane) {
+  const ChunkDesc cd = a.chunk[c];
+  const uint4* src = reinterpret_cast<const uint4*>(a.blob + cd.off);
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  const int nv = cd.n16;
+  uint4 tmp[kNV];
+#pragma unroll
+  for (int i = 0; i < kNV; ++i) {
+    const int idx = lane + kWave * i;
+    if (idx < nv) tmp[i] = src[idx];
+  }
+#pragma unroll
+  for (int i = 0; i < kNV; ++i) {
+    const int idx = lane + kWave * i;
+    if (idx < nv) d[idx] = tmp[i];
+  }
+}
+
+// Sweep the stages of one chunk held in LDS.  Branch-free per lane: every
+// lane issues the same LDS reads (inactive slots are masked afterwards), so
+// the gathers of a stage are in flight together, and the next stage's row
+// info and entries are fetched while the current stage accumulates.
+template <class P, int MS, bool ISU>
+__device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& cd, int lane,
+                                            typename P::C* x) {
+  using C = typename P::C;
+  using V = typename P::V;
+  using D = typename P::D;
+  const V* val = reinterpret_cast<const V*>(cb);
+  const D* dinv = reinterpret_cast<const D*>(cb + 16 * (int)cd.dinv16);
+  const uint32_t* rinfo = reinterpret_cast<const uint32_t*>(cb + 16 * (int)cd.info16);
+  const uint16_t* col = reinterpret_cast<const uint16_t*>(cb + 16 * (int)cd.col16);
+  const int nst = cd.nst & 0x7fff;
+  int r0 = 0, e = 0;
+  uint32_t info = rinfo[lane];
+  int nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
+  bool act = lane < nr;
+  int nz = act ? (int)((info >> 16) & 0xffu) : 0;
+  int maxnz = __builtin_amdgcn_readfirstlane(nz);
+  C v[MS];
+  uint16_t c[MS];
+#pragma unroll
+  for (int j = 0; j < MS; ++j) {
+    if (j < maxnz) {
+      const unsigned long long m = __ballot(nz > j);
+      v[j] = cvt<C>(val[e + lane]);
+      c[j] = col[e + lane];
+      e += __popcll(m);
+    }
+  }
+  for (int s = 0; s < nst; ++s) {
+    // gathers of stage s, its own rhs and 1/u_ii, and the next stage's row info
+    C xv[MS];
+#pragma unroll
+    for (int j = 0; j < MS; ++j)
+      if (j < maxnz) xv[j] = x[nz > j ? (int)c[j] : 0];
+    const int row = act ? (int)(info & 0xffffu) : 0;
+    C acc = x[row];
+    C dv = zero<C>();
+    if (ISU) dv = cvt<C>(dinv[act ? r0 + lane : 0]);
+    const int r0n = r0 + nr;
+    const bool more = s + 1 < nst;
+    const uint32_t infon = more ? rinfo[r0n + lane] : 0u;
+    // entries of stage s+1 (independent of x)
+    const int nrn = (int)__builtin_amdgcn_readfirstlane(infon >> 24);
+    const bool actn = lane < nrn;
+    const int nzn = actn ? (int)((infon >> 16) & 0xffu) : 0;
+    const int maxnzn = __builtin_amdgcn_readfirstlane(nzn);
+    C vn[MS];
+    uint16_t cn[MS];
+#pragma unroll
+    for (int j = 0; j < MS; ++j) {
+      if (j < maxnzn) {
+        const unsigned long long m = __ballot(nzn > j);
+        vn[j] = cvt<C>(val[e + lane]);
+        cn[j] = col[e + lane];
+        e += __popcll(m);
+      }
+    }
+    // accumulate stage s
+#pragma unroll
+    for (int j = 0; j < MS; ++j) {
+      if (j < maxnz) {
+        const C t = v[j] * xv[j];
+        acc = nz > j ? acc - t : acc;
+      }
+    }
+    if (ISU) acc *= dv;
+    if (act) x[row] = acc;
+    // advance
+    r0 = r0n;
+    info = infon;
+    nr = nrn;
+    act = actn;
+    nz = nzn;
+    maxnz = maxnzn;
+#pragma unroll
+    for (int j = 0; j < MS; ++j) {
+      v[j] = vn[j];
+      c[j] = cn[j];
+    }
+  }
+}
+
+// Right-hand side of a block into LDS: DOWN reads b1, UP forms F_l y2.
+// Eight rows per thread are in flight at once.
+template <class P, int MODE, int NT>
+__device__ __forceinline__ void load_rhs(const TriArgs<P>& a, int r0, int nr, int tid,
+                                         typename P::C* x) {
+  using C = typename P::C;
+  constexpr int U = 8;
+  for (int i0 = tid; i0 < nr; i0 += NT * U) {
+    C r[U];
+    if (MODE == TRI_DOWN) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * NT;
+        if (i < nr) r[u] = cvt<C>(a.t[r0 + i]);
+      }
+    } else {
+      int p0[U], p1[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * NT;
+        p0[u] = i < nr ? a.F.rp[r0 + i] : 0;
+        p1[u] = i < nr ? a.F.rp[r0 + i + 1] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        r[u] = zero<C>();
+        for (int p = p0[u]; p < p1[u]; ++p)
+          r[u] += cvt<C>(a.F.v[p]) * cvt<C>(a.t[a.d + a.F.ci[p]]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * NT;
+      if (i < nr) x[i] = r[u];
+    }
+  }
+}
+
+// Result of a block from LDS: DOWN stores z1, UP stores z1 - (LU)^{-1} F y2.
+template <class P, int MODE, int NT>
+__device__ __forceinline__ void store_result(const TriArgs<P>& a, int r0, int nr, int tid,
+                                             const typename P::C* x) {
+  using C = typename P::C;
+  using X = typename P::X;
+  constexpr int U = 8;
+  for (int i0 = tid; i0 < nr; i0 += NT * U) {
+    if (MODE == TRI_DOWN) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * NT;
+        if (i < nr) a.t[r0 + i] = cvt<X>(x[i]);
+      }
+    } else {
+      C z[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * NT;
+        if (i < nr) z[u] = cvt<C>(a.t[r0 + i]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * NT;
+        if (i < nr) a.t[r0 + i] = cvt<X>(z[u] - x[i]);
+      }
+    }
+  }
+}
+
+template <class P, int MS, int MODE>
+__global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
+  using C = typename P::C;
+  using X = typename P::X;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int r0 = a.blk_row[b];
+  const int nr = a.blk_row[b + 1] - r0;
+  C* x = reinterpret_cast<C*>(smem_raw);
+  uint8_t* buf0 = smem_raw + a.x_bytes;
+  uint8_t* buf1 = buf0 + a.chunk_cap;
+  const int c0 = a.blk_chunk[b], c1 = a.blk_chunk[b + 1];
+  if (wave == 1 && c0 < c1) copy_chunk<P>(a, c0, buf0, lane);
+  load_rhs<P, MODE, 2 * kWave>(a, r0, nr, tid, x);
+  __syncthreads();
+  for (int c = c0; c < c1; ++c) {
+    const bool odd = ((c - c0) & 1) != 0;
+    uint8_t* cur = odd ? buf1 : buf0;
+    uint8_t* nxt = odd ? buf0 : buf1;
+    if (wave == 1) {
+      if (c + 1 < c1) copy_chunk<P>(a, c + 1, nxt, lane);
+    } else {
+      const ChunkDesc cd = a.chunk[c];
+      if (cd.nst & 0x8000) chunk_sweep<P, MS, true>(cur, cd, lane, x);
+      else chunk_sweep<P, MS, false>(cur, cd, lane, x);
+    }
+    __syncthreads();
+  }
+  store_result<P, MODE, 2 * kWave>(a, r0, nr, tid, x);
+}
+
+template <class P, int MS, int MODE>
+static void launch_stream_ms(const TriArgs<P>& a, hipStream_t st) {
+  // 1 KiB of slack after the second buffer: lanes past the end of a stage
+  // read (and then discard) up to 63 elements beyond a section
+  const size_t lds = (size_t)a.x_bytes + 2 * (size_t)a.chunk_cap + 1024;
+  auto kern = k_trisolve_streamed<P, MS, MODE>;
+  static size_t attr_set = 65536;
+  if (lds > attr_set) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    attr_set = lds;
+  }
+  hipLaunchKernelGGL(kern, dim3(a.nb), dim3(2 * kWave), lds, st, a);
+}
+
+template <class P, int MODE>
+static void launch_stream_mode(const TriArgs<P>& a, int maxslot, hipStream_t st) {
+  if (maxslot <= 4) launch_stream_ms<P, 4, MODE>(a, st);
+  else if (maxslot <= 8) launch_stream_ms<P, 8, MODE>(a, st);
+  else if (maxslot <= 12) launch_stream_ms<P, 12, MODE>(a, st);
+  else launch_stream_ms<P, 16, MODE>(a, st);
+}
+
+template <class P>
+void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot, int max_block_rows,
+                              hipStream_t st) {
+  (void)max_block_rows;
+  if (a.nb <= 0) return;
+  if (mode == TRI_DOWN) launch_stream_mode<P, TRI_DOWN>(a, maxslot, st);
+  else launch_stream_mode<P, TRI_UP>(a, maxslot, st);
+}
+
+// ======================================================================
 // Interface step of one level: z2 = b2 - E_l z1 written in place, and the
 // projection W^H z2 of the low-rank term: every workgroup leaves its
 // partial sums, the last workgroup to finish adds them in workgroup order
 // (deterministic) and applies H = (I - R)^{-1} - I, giving t' = H W^H z2.
 // ======================================================================
 constexpr int kIfThreads = 256;
+constexpr int kIfRows = 4;  // rows per thread
 
 template <class P>
 __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
   using C = typename P::C;
   using X = typename P::X;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* red = reinterpret_cast<C*>(smem_raw);            // 4 x k
+  C* red = reinterpret_cast<C*>(smem_raw);            // 4 x k, then reused
   __shared__ int is_last;
   const int tid = threadIdx.x;
-  const int64_t j = (int64_t)blockIdx.x * kIfThreads + tid;
-  const bool act = j < a.s;
-  C z = zero<C>();
-  if (act) {
-    C acc = cvt<C>(a.t[a.d + j]);
-    const int p0 = a.E.rp[j], p1 = a.E.rp[j + 1];
-    for (int p = p0; p < p1; ++p) acc -= cvt<C>(a.E.v[p]) * cvt<C>(a.t[a.E.ci[p]]);
-    a.t[a.d + j] = cvt<X>(acc);
-    z = acc;
+  const int64_t base = (int64_t)blockIdx.x * kIfThreads * kIfRows + tid;
+  C z[kIfRows];
+#pragma unroll
+  for (int q = 0; q < kIfRows; ++q) {
+    const int64_t j = base + (int64_t)q * kIfThreads;
+    z[q] = zero<C>();
+    if (j < a.s) {
+      C acc = cvt<C>(a.t[a.d + j]);
+      const int p0 = a.E.rp[j], p1 = a.E.rp[j + 1];
+      for (int p = p0; p < p1; ++p) acc -= cvt<C>(a.E.v[p]) * cvt<C>(a.t[a.E.ci[p]]);
+      a.t[a.d + j] = cvt<X>(acc);
+      z[q] = acc;
+    }
   }
   if (a.k == 0) return;
   const int wave = tid / kWave, lane = tid % kWave;
   for (int c = 0; c < a.k; ++c) {
-    C w = act ? cvt<C>(a.W[j + (int64_t)c * a.s]) : zero<C>();
-    C pr = wave_sum(conj(w) * z);
+    C pr = zero<C>();
+#pragma unroll
+    for (int q = 0; q < kIfRows; ++q) {
+      const int64_t j = base + (int64_t)q * kIfThreads;
+      if (j < a.s) pr += conj(cvt<C>(a.W[j + (int64_t)c * a.s])) * z[q];
+    }
+    pr = wave_sum(pr);
     if (lane == 0) red[wave * a.k + c] = pr;
   }
   __syncthreads();
@@ -254,10 +527,21 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
   __syncthreads();
   if (!is_last) return;
   __threadfence();
-  C* tv = red;  // reuse: k entries
-  for (int c = tid; c < a.k; c += kIfThreads) {
+  // fixed-order two-stage sum of the partials: G groups of workgroups per
+  // column, then the G group sums
+  const int G = a.k >= kIfThreads ? 1 : kIfThreads / a.k;
+  const int nb = (int)gridDim.x;
+  for (int idx = tid; idx < a.k * G; idx += kIfThreads) {
+    const int c = idx % a.k, g = idx / a.k;
     C s = zero<C>();
-    for (unsigned bb = 0; bb < gridDim.x; ++bb) s += a.partial[(int64_t)bb * a.k + c];
+    for (int bb = g; bb < nb; bb += G) s += a.partial[(int64_t)bb * a.k + c];
+    red[idx] = s;
+  }
+  __syncthreads();
+  C* tv = red + (size_t)a.k * G;
+  for (int c = tid; c < a.k; c += kIfThreads) {
+    C s = red[c];
+    for (int g = 1; g < G; ++g) s += red[g * a.k + c];
     tv[c] = s;
   }
   __syncthreads();
@@ -270,11 +554,18 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
 }
 
 template <class P>
+int interface_blocks(int64_t s) {
+  return (int)((s + kIfThreads * kIfRows - 1) / (kIfThreads * kIfRows));
+}
+
+template <class P>
 void launch_interface(const IfArgs<P>& a, hipStream_t st) {
   if (a.s <= 0) return;
   using C = typename P::C;
-  const int nblk = (int)((a.s + kIfThreads - 1) / kIfThreads);
-  const size_t lds = (size_t)(kIfThreads / kWave) * (a.k > 0 ? a.k : 1) * sizeof(C);
+  const int nblk = interface_blocks<P>(a.s);
+  const int k = a.k > 0 ? a.k : 1;
+  const int G = k >= kIfThreads ? 1 : kIfThreads / k;
+  const size_t lds = (size_t)(std::max(4 * k, k * G) + k) * sizeof(C);
   hipLaunchKernelGGL(k_interface<P>, dim3(nblk), dim3(kIfThreads), lds, st, a);
 }
 
@@ -563,10 +854,37 @@ void launch_permute(const T* x, const int32_t* perm, T* y, int64_t n, bool scatt
                      y, n, scatter ? 1 : 0);
 }
 
+template <class T>
+__global__ void k_rows_to_cols(const float* Y, int64_t s, int k, int ldy, T* V, int64_t ld) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s * k) return;
+  const int64_t r = i / k, c = i % k;
+  V[r + c * ld] = cvt_rc<T>(Y[r * ldy + c]);
+}
+template <class T>
+void launch_rows_to_cols(const float* Y, int64_t s, int k, int ldy, T* V, int64_t ld,
+                         hipStream_t st) {
+  if (s * k <= 0) return;
+  hipLaunchKernelGGL(k_rows_to_cols<T>, dim3((unsigned)((s * k + 255) / 256)), dim3(256), 0, st,
+                     Y, s, k, ldy, V, ld);
+}
+template <class T>
+__global__ void k_sub(const T* a, const T* b, T* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+template <class T>
+void launch_sub(const T* a, const T* b, T* out, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_sub<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, out, n);
+}
+
 // ---------------------------------------------------------------- instances
 #define GS_PREC_INSTANCES(P)                                                                   \
   template void launch_trisolve<P>(const TriArgs<P>&, int, int, int, hipStream_t);             \
+  template void launch_trisolve_streamed<P>(const TriArgs<P>&, int, int, int, hipStream_t);    \
   template void launch_interface<P>(const IfArgs<P>&, hipStream_t);                            \
+  template int interface_blocks<P>(int64_t);                                                   \
   template void launch_lowrank_update<P>(P::X*, int64_t, int, const P::V*, const P::C*,        \
                                          hipStream_t);                                         \
   template void launch_gather<P>(const P::O*, const int32_t*, P::X*, int64_t, hipStream_t);    \
@@ -593,7 +911,10 @@ GS_PREC_INSTANCES(PBF16)
                                      int64_t, hipStream_t);                                    \
   template void launch_fill<T>(T*, T, int64_t, hipStream_t);                                   \
   template void launch_copy<T>(const T*, T*, int64_t, hipStream_t);                          \
-  template void launch_permute<T>(const T*, const int32_t*, T*, int64_t, bool, hipStream_t);
+  template void launch_permute<T>(const T*, const int32_t*, T*, int64_t, bool, hipStream_t);   \
+  template void launch_rows_to_cols<T>(const float*, int64_t, int, int, T*, int64_t,         \
+                                       hipStream_t);                                          \
+  template void launch_sub<T>(const T*, const T*, T*, int64_t, hipStream_t);
 GS_VEC_INSTANCES(double)
 GS_VEC_INSTANCES(dcplx)
 template void launch_fill<float>(float*, float, int64_t, hipStream_t);

@@ -37,7 +37,8 @@ class GsOpts(ct.Structure):
                 ("arnoldi_tol", ct.c_double), ("arnoldi_max_cycles", ct.c_int),
                 ("lowrank_last_level", ct.c_int), ("precision", ct.c_int),
                 ("grid_ndim", ct.c_int), ("grid_dims", ct.c_int32 * 3),
-                ("seed", ct.c_uint64), ("nthreads", ct.c_int)]
+                ("seed", ct.c_uint64), ("nthreads", ct.c_int),
+                ("defer_lowrank", ct.c_int), ("block_max_iters", ct.c_int)]
 
 
 _L1 = GS_MAX_LEVELS + 1
@@ -51,6 +52,7 @@ class GsInfo(ct.Structure):
                 ("arnoldi_cycles", ct.c_int32 * _L1),
                 ("arnoldi_matvecs", ct.c_int32 * _L1),
                 ("arnoldi_converged", ct.c_int32 * _L1),
+                ("lowrank_method", ct.c_int32 * _L1),
                 ("nnz_lu", ct.c_int64), ("nnz_ef", ct.c_int64), ("nnz_a", ct.c_int64),
                 ("fill", ct.c_double), ("fill_lowrank", ct.c_double),
                 ("apply_bytes", ct.c_double), ("t_partition", ct.c_double),
@@ -108,9 +110,24 @@ SIGNATURES = [
                                      _p, _p, ct.POINTER(ct.c_int), _p, _p, ct.c_int64]),
     ("gs_ilu", ct.c_int, [ct.c_int64, _p, _p, _p, ct.c_int, ct.c_int, ct.c_double, ct.c_int,
                           _p, _p, _p, ct.c_int64, _p, _p, _p, ct.c_int64]),
+    ("gs_features", ct.c_int, [_p, ct.c_int, _p, ct.c_int64, ct.c_int,
+                                ct.POINTER(ct.c_int)]),
+    ("gs_lowrank", ct.c_int, [_p, ct.c_int, _p]),
     ("gs_get_level_sizes", ct.c_int, [_p, ct.c_int, _p]),
     ("gs_get_level", ct.c_int, [_p, ct.c_int] + [_p] * 15),
     ("gs_get_perm", ct.c_int, [_p, _p]),
+    ("gs_mlp_create", ct.c_int, [ct.POINTER(_p), ct.c_int, ct.c_int, ct.c_int, ct.c_int, _p]),
+    ("gs_mlp_destroy", None, [_p]),
+    ("gs_mlp_nparams", ct.c_int, [_p]),
+    ("gs_mlp_last_error", ct.c_char_p, [_p]),
+    ("gs_mlp_set_params", ct.c_int, [_p, _p]),
+    ("gs_mlp_get_params", ct.c_int, [_p, _p]),
+    ("gs_mlp_get_grads", ct.c_int, [_p, _p]),
+    ("gs_mlp_zero_grad", ct.c_int, [_p]),
+    ("gs_mlp_forward", ct.c_int, [_p, _p, ct.c_int64, _p]),
+    ("gs_mlp_loss_backward", ct.c_int, [_p, _p, _p, ct.c_int64, ct.c_int,
+                                        ct.POINTER(ct.c_double)]),
+    ("gs_mlp_adam_step", ct.c_int, [_p, ct.c_float, ct.c_float, ct.c_float, ct.c_float]),
 ]
 
 
@@ -297,6 +314,39 @@ class Context:
         d["status"] = rc
         return d
 
+    def features(self, level, cols_cap=64):
+        s = self.level_size(level)[1]
+        X = np.zeros((s, cols_cap), dtype=np.float32)
+        nc = ct.c_int()
+        self._check(lib().gs_features(self._h, level, _ptr(X), s, cols_cap, ct.byref(nc)))
+        return np.ascontiguousarray(X[:, :nc.value])
+
+    def lowrank(self, rank, warm=None):
+        """warm: None or a list (one per level) of None / float32 device
+        tensors of shape (s_l, rank), row-major."""
+        arr = None
+        if warm is not None:
+            L = self.info()["nlevels"]
+            if len(warm) > L:
+                raise ValueError(f"warm has {len(warm)} entries for {L} levels")
+            arr = (ct.c_void_p * L)()
+            for i, t in enumerate(warm):
+                if t is None:
+                    continue
+                s = self.level_size(i)[1]
+                if (tuple(t.shape) != (s, rank) or str(t.dtype) != "torch.float32"
+                        or not t.is_contiguous() or not t.is_cuda):
+                    raise ValueError(f"warm[{i}] must be a contiguous float32 CUDA tensor "
+                                     f"of shape ({s}, {rank})")
+                arr[i] = t.data_ptr()
+        self._check(lib().gs_lowrank(self._h, rank, arr))
+        return self.info()
+
+    def level_size(self, l):
+        z = np.zeros(8, dtype=np.int64)
+        self._check(lib().gs_get_level_sizes(self._h, l, _ptr(z)))
+        return [int(v) for v in z]
+
     def info(self):
         info = GsInfo()
         self._check(lib().gs_get_info(self._h, ct.byref(info)))
@@ -370,3 +420,81 @@ def ilu(rowptr, col, val, kind="ilut", tau=0.0, lfil=10):
         raise GemslrError(rc, lib().gs_last_error(None).decode())
     nl, nu = int(lr[-1]), int(ur[-1])
     return (lr, lc[:nl].copy(), lv[:nl].copy()), (ur, uc[:nu].copy(), uv[:nu].copy())
+
+
+class Mlp:
+    """The learned-start network on one GPU (gs_mlp_*)."""
+
+    def __init__(self, in_dim, hidden, out_dim, device=0, stream=None):
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = ct.c_void_p()
+        rc = lib().gs_mlp_create(ct.byref(h), in_dim, hidden, out_dim, device,
+                                 ct.c_void_p(stream or 0))
+        if rc != GS_OK:
+            raise GemslrError(rc, "gs_mlp_create failed")
+        self._h = h
+        self.dims = (in_dim, hidden, out_dim)
+        self.nparams = lib().gs_mlp_nparams(h)
+
+    def _check(self, rc):
+        if rc != GS_OK:
+            raise GemslrError(rc, lib().gs_mlp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gs_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        p = np.ascontiguousarray(flat, dtype=np.float32)
+        assert p.size == self.nparams
+        self._check(lib().gs_mlp_set_params(self._h, _ptr(p)))
+
+    def get_params(self):
+        p = np.zeros(self.nparams, np.float32)
+        self._check(lib().gs_mlp_get_params(self._h, _ptr(p)))
+        return p
+
+    def get_grads(self):
+        g = np.zeros(self.nparams, np.float32)
+        self._check(lib().gs_mlp_get_grads(self._h, _ptr(g)))
+        return g
+
+    def zero_grad(self):
+        self._check(lib().gs_mlp_zero_grad(self._h))
+
+    def forward(self, X, Y):
+        self._check(lib().gs_mlp_forward(self._h, _ptr(X), X.shape[0], _ptr(Y)))
+
+    def loss_backward(self, X, W):
+        loss = ct.c_double()
+        self._check(lib().gs_mlp_loss_backward(self._h, _ptr(X), _ptr(W), X.shape[0],
+                                               W.shape[1], ct.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(lib().gs_mlp_adam_step(self._h, lr, beta1, beta2, eps))
+
+
+def pack_params(params):
+    """[W1, b1, W2, b2, W3, b3] (row-major weights) -> flat float32."""
+    return np.concatenate([np.asarray(p, np.float32).ravel() for p in params])
+
+
+def unpack_params(flat, dims):
+    i, h, o = dims
+    sizes = [(i, h), (h,), (h, h), (h,), (h, o), (o,)]
+    out, pos = [], 0
+    for sh in sizes:
+        n = int(np.prod(sh))
+        out.append(np.asarray(flat[pos:pos + n]).reshape(sh))
+        pos += n
+    return out

@@ -1,0 +1,182 @@
+"""Learned warm start for the low-rank setup (not in the paper; the paper
+names a block or randomised-subspace setup as future work, Sec. 6).
+
+Pipeline, all device arithmetic in libgemslr:
+  * training data: for each member of a parametric matrix family, a plain
+    setup (thick-restart Arnoldi) gives the bases W_l; gs_features gives the
+    per-node features X_l of the interface unknowns;
+  * training: the 3-layer perceptron (gs_mlp_*) minimises the subspace loss
+    ||Y^T Y||^2 - 2 ||W^T Y||^2 + k with Adam, one (instance, level) pair per
+    step;
+  * use: setup with the low-rank stage deferred, Y_l = network(X_l) on the
+    GPU, then gs_lowrank runs the block Rayleigh-Ritz iteration from Y_l with
+    Arnoldi as the fallback.
+This module only orders those calls and moves arrays between them.
+"""
+import time
+
+import numpy as np
+
+from . import gemslr
+from . import workloads as wl
+
+NFEAT = 38
+HIDDEN = 64
+
+
+def init_params(seed, dims):
+    """Glorot-uniform weights, zero biases, from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    i, h, o = dims
+    out = []
+    for a, b in ((i, h), (h, h), (h, o)):
+        lim = np.sqrt(6.0 / (a + b))
+        out.append(rng.uniform(-lim, lim, (a, b)))
+        out.append(np.zeros(b))
+    return out
+
+
+def family_member(instance, N=64, nparts=64):
+    return wl.lognormal_convdiff3d_64(instance, N=N, nparts=nparts)
+
+
+def setup_kwargs(w):
+    return dict(lfil=w.lfil, grid_dims=w.dims, fgmres_restart=w.restart)
+
+
+def collect(instances, N=64, nparts=64, rank=32, levels=(0, 1), log=None):
+    """Per (instance, level): features X (s x 38) and the Arnoldi basis W
+    (s x k), both float32 row-major numpy arrays."""
+    data = []
+    for i in instances:
+        w = family_member(i, N, nparts)
+        ctx = gemslr.Context(0)
+        ctx.setup(w.rowptr, w.col, w.val, w.levels, w.nparts, rank, w.drop_tol,
+                  **setup_kwargs(w))
+        for l in levels:
+            if l >= ctx.info()["nlevels"]:
+                continue
+            X = ctx.features(l)
+            W = np.ascontiguousarray(ctx.level(l)["W"], dtype=np.float32)
+            data.append({"instance": i, "level": l, "X": X, "W": W})
+        ctx.close()
+        if log:
+            log(f"[learned] collected instance {i}")
+    return data
+
+
+def train(data, epochs=30, lr=1e-3, seed=0, out_dim=32, log=None):
+    """Train the network on the GPU; returns (Mlp, loss history per epoch)."""
+    import torch
+    dims = (NFEAT, HIDDEN, out_dim)
+    mlp = gemslr.Mlp(*dims)
+    mlp.set_params(gemslr.pack_params(init_params(seed, dims)))
+    Xs = [torch.from_numpy(d["X"]).cuda() for d in data]
+    Ws = [torch.from_numpy(d["W"]).cuda() for d in data]
+    rng = np.random.default_rng(seed + 1)
+    hist = []
+    for ep in range(epochs):
+        tot = 0.0
+        for j in rng.permutation(len(data)):
+            mlp.zero_grad()
+            loss = mlp.loss_backward(Xs[j], Ws[j])
+            mlp.adam_step(lr)
+            tot += loss / Ws[j].shape[1]
+        hist.append(tot / max(1, len(data)))
+        if log and (ep % 5 == 0 or ep == epochs - 1):
+            log(f"[learned] epoch {ep}: mean normalised loss {hist[-1]:.4f}")
+    return mlp, hist
+
+
+def predicted_bases(ctx, mlp, levels, out_dim):
+    import torch
+    warm = [None] * ctx.info()["nlevels"]
+    for l in levels:
+        if l >= len(warm):
+            continue
+        X = torch.from_numpy(ctx.features(l)).cuda()
+        Y = torch.empty((X.shape[0], out_dim), dtype=torch.float32, device="cuda")
+        mlp.forward(X, Y)
+        warm[l] = Y
+    return warm
+
+
+def random_bases(ctx, levels, out_dim, seed):
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    warm = [None] * ctx.info()["nlevels"]
+    for l in levels:
+        if l >= len(warm):
+            continue
+        s = ctx.level_size(l)[1]
+        warm[l] = torch.randn((s, out_dim), generator=g, device="cuda", dtype=torch.float32)
+    return warm
+
+
+def setup_with(w, rank, mode, mlp=None, levels=(0, 1), seed=0, **extra):
+    """Setup with the low-rank stage run by `mode`: "arnoldi" (plain),
+    "learned" (block iteration from the network's bases) or "random" (block
+    iteration from random bases, the control).  Returns (ctx, seconds spent
+    on the low-rank stage incl. the network)."""
+    import torch
+    ctx = gemslr.Context(0)
+    kw = setup_kwargs(w)
+    kw.update(extra)
+    ctx.setup(w.rowptr, w.col, w.val, w.levels, w.nparts, rank, w.drop_tol, defer_lowrank=1,
+              **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if mode == "arnoldi":
+        ctx.lowrank(rank)
+    elif mode == "learned":
+        ctx.lowrank(rank, predicted_bases(ctx, mlp, levels, rank))
+    elif mode == "random":
+        ctx.lowrank(rank, random_bases(ctx, levels, rank, seed))
+    else:
+        raise ValueError(mode)
+    torch.cuda.synchronize()
+    return ctx, time.perf_counter() - t0
+
+
+def evaluate(instances, mlp, N=64, nparts=64, rank=32, tol=1e-8, levels=(0, 1)):
+    """Per held-out instance and mode: matvecs of the low-rank stage, its
+    time, FGMRES iterations, true relative residual and time to tol."""
+    import torch
+    rows = []
+    for i in instances:
+        w = family_member(i, N, nparts)
+        for mode in ("arnoldi", "learned", "random"):
+            ctx, t_lr = setup_with(w, rank, mode, mlp, levels, seed=1000 + i)
+            info = ctx.info()
+            b = torch.from_numpy(w.b).cuda()
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.solve(b, x, tol)
+            t_s = time.perf_counter() - t0
+            rows.append({"instance": i, "mode": mode,
+                         "matvecs": int(sum(info["arnoldi_matvecs"])),
+                         "methods": info["lowrank_method"], "t_lowrank_s": t_lr,
+                         "its": res["its"], "relres": res["relres"],
+                         "converged": bool(res["converged"]), "t_solve_s": t_s,
+                         "time_to_tol_s": t_lr + t_s})
+            ctx.close()
+    return rows
+
+
+def summarise(rows):
+    out = {}
+    for mode in ("arnoldi", "learned", "random"):
+        r = [x for x in rows if x["mode"] == mode]
+        if not r:
+            continue
+        out[mode] = {k: float(np.mean([x[k] for x in r]))
+                     for k in ("matvecs", "t_lowrank_s", "its", "relres", "time_to_tol_s")}
+        out[mode]["median_time_to_tol_s"] = float(np.median([x["time_to_tol_s"] for x in r]))
+    if "learned" in out and "arnoldi" in out:
+        lr = {x["instance"]: x for x in rows if x["mode"] == "learned"}
+        ar = {x["instance"]: x for x in rows if x["mode"] == "arnoldi"}
+        wins = [lr[i]["time_to_tol_s"] < ar[i]["time_to_tol_s"] for i in lr if i in ar]
+        out["learned_win_fraction_vs_arnoldi"] = float(np.mean(wins)) if wins else None
+    return out

@@ -148,3 +148,31 @@ def test_native_setup_solves(torch_dev):
     assert res["converged"], res
     assert relerr(xg, w.x_true) <= 1e-8
     ctx.close()
+
+
+@pytest.mark.parametrize("env", [{"GEMSLR_NO_STREAM": "1"}, {"GEMSLR_LDS_BUDGET": "16384"},
+                                 {"GEMSLR_LDS_BUDGET": "20480"}])
+@pytest.mark.parametrize("name", ["convdiff3d_20_p27", "helmholtz3d_16_p8"])
+def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
+    """Both block-trisolve kernels (register prefetch; LDS-streamed with small
+    chunks so that each block takes many producer/consumer hand-offs) give the
+    oracle's apply."""
+    torch = torch_dev
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    w, kw = _case(name)
+    print(f"[kernel variant] {name} {env}", flush=True)
+    st = _oracle_setup(w, kw)
+    ctx = _ctx_explicit(torch, w, st)
+    x = np.random.default_rng(5).standard_normal(w.n)
+    if w.is_complex:
+        x = x + 1j * np.random.default_rng(6).standard_normal(w.n)
+    ref = og.apply(st, x)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    ctx.apply(xd, yd)
+    torch.cuda.synchronize()
+    err = relerr(yd.cpu().numpy(), ref)
+    print(f"  rel err {err:.3e}", flush=True)
+    assert err <= APPLY_TOL_F64
+    ctx.close()
