@@ -66,6 +66,50 @@ def cpu_baseline(seconds=12.0):
                        f"{dt:.1f} s on 1 thread = {rate:.2f}/s, scaled by n ratio {scale:.6f}")}
 
 
+def helmholtz(N, K, log):
+    """Complex128 path: the shifted Helmholtz operator at N^3 (512 subdomains,
+    ILUT(1e-4, 10), rank 64): applies/s and its HBM rate, time to 1e-8."""
+    import numpy as np
+    import torch
+
+    from paper_2205_03224_amd import gemslr, workloads as wl
+    w = wl.helmholtz3d_128(N=N, nparts=512 if N >= 64 else 8)
+    ctx = gemslr.Context(0)
+    t0 = time.perf_counter()
+    ctx.setup(w.rowptr, w.col, w.val, w.levels, w.nparts, w.rank, w.drop_tol, lfil=w.lfil,
+              grid_dims=w.dims, fgmres_restart=w.restart)
+    t_setup = time.perf_counter() - t0
+    info = ctx.info()
+    b = torch.from_numpy(w.b).cuda()
+    y = torch.empty_like(b)
+    for _ in range(10):
+        ctx.apply(b, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        ctx.apply(b, y)
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) * 1e6 / K
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.solve(b, x, 1e-8)
+    ts = time.perf_counter() - t0
+    xh = x.cpu().numpy()
+    out = {"workload": f"helmholtz3d_{N} (complex128, k^2h^2=(2pi/10)^2, damping 0.05)",
+           "n": w.n, "levels": info["nlevels"], "rank": w.rank, "ilu": f"ILUT({w.drop_tol},{w.lfil})",
+           "setup_s": t_setup, "t_lowrank_s": info["t_lowrank"], "fill": info["fill"],
+           "us_per_apply": us, "applies_per_s": 1e6 / us, "apply_bytes": info["apply_bytes"],
+           "apply_GBps": info["apply_bytes"] / (us * 1e-6) / 1e9,
+           "its": res["its"], "relres": res["relres"], "converged": bool(res["converged"]),
+           "t_solve_s": ts, "time_to_tol_s": info["t_lowrank"] + ts,
+           "err_vs_x_true": float(np.linalg.norm(xh - w.x_true) / np.linalg.norm(w.x_true))}
+    log(f"[bench] c128: {us:.1f} us/apply, {out['apply_GBps']:.0f} GB/s; solve its {res['its']} "
+        f"relres {res['relres']:.2e} in {ts:.2f} s (+ lowrank {info['t_lowrank']:.2f} s)")
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,7 +119,12 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the time-to-tolerance runs of the three storage forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c128", action="store_true",
+                    help="skip the complex Helmholtz apply rate and time to tolerance")
     ap.add_argument("--breakdown", action="store_true", help="print per-launch profile")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, copy a MIB-sized float64 buffer once (a plain "
+                         "copy kernel of known traffic for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU: this build holds all subdomains on a single "
@@ -129,6 +178,44 @@ def main():
         f"{apply_bytes / (ms_per_apply * 1e-3) / 1e9:.0f} GB/s; level-0 trisolve "
         f"{k_ms * 1e3:.1f} us/launch, {achieved:.0f} GB/s ({launches} launches)")
 
+    # per-apply distribution with events on the library's stream (torch's
+    # current stream): warm = back-to-back applies on one setup; cold = a
+    # 1 GiB buffer written between applies, which evicts the 256 MiB
+    # last-level cache, so every factor byte comes from HBM
+    def distribution(reps, flush=None):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for e0, e1 in ev:
+            if flush is not None:
+                flush.fill_(1.0)
+            e0.record()
+            ctx.apply(b, y)
+            e1.record()
+        torch.cuda.synchronize()
+        us = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev])
+        return {"median_us": float(np.median(us)), "p10_us": float(np.percentile(us, 10)),
+                "p90_us": float(np.percentile(us, 90)), "reps": reps}
+
+    dist = {"warm": distribution(100)}
+    flush = torch.empty((1 << 30) // 8, dtype=torch.float64, device="cuda")
+    dist["cold"] = distribution(50, flush)
+    del flush
+    for key in ("warm", "cold"):
+        d = dist[key]
+        d["GBps_at_median"] = apply_bytes / (d["median_us"] * 1e-6) / 1e9
+        log(f"[bench] {key}: median {d['median_us']:.1f} us (p10 {d['p10_us']:.1f}, "
+            f"p90 {d['p90_us']:.1f}), {d['GBps_at_median']:.0f} GB/s")
+
+    if args.calibrate_copy:
+        nel = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nel * 8} bytes read, {nel * 8} bytes written")
+        del src, dst
+
     breakdown = None
     if args.breakdown:
         breakdown = ctx.apply_profile(b, y, reps=5)
@@ -146,6 +233,7 @@ def main():
                    "ilu": f"ILUT({w.drop_tol},{w.lfil})", "parallelism": "single GPU"},
         "apply_GBps": apply_bytes / (ms_per_apply * 1e-3) / 1e9,
         "apply_bytes": apply_bytes,
+        "apply_distribution": dist,
         "roofline": {"bound": "hbm", "kernel": "k_trisolve level 0 (down + up)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
@@ -182,6 +270,23 @@ def main():
         out["time_to_tol"] = forms
 
     ctx.close()
+    if not args.no_forms and not args.no_c128:
+        out["c128"] = helmholtz(args.N, args.steps // 2, log)
+    params = os.path.join(ROOT, "paper_2205_03224_amd", "data", "mlp_lognormal64.npz")
+    if not args.no_forms and os.path.exists(params):
+        # learned warm start on held-out members of the log-normal family it
+        # was trained on (64^3, 64 subdomains, rank 32): Arnoldi vs learned
+        # vs random-start block iteration, time to 1e-8 each
+        from paper_2205_03224_amd import learned
+        z = np.load(params)
+        mlp = gemslr.Mlp(*[int(v) for v in z["dims"]])
+        mlp.set_params(z["params"])
+        rows = learned.evaluate(range(100000, 100004), mlp, N=64, nparts=64, rank=32,
+                                levels=tuple(int(v) for v in z["levels"]))
+        out["learned"] = learned.summarise(rows)
+        out["learned"]["workload"] = "lognormal_convdiff3d_64, held-out members 100000-100003"
+        log(f"[bench] learned: {json.dumps(out['learned'])}")
+        mlp.close()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on its bounded sample ...")
         out["cpu_baseline"] = cpu_baseline()

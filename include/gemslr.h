@@ -67,8 +67,9 @@ typedef struct {
   int nthreads;           /* host threads for the factorisation (0 = all)     */
   int defer_lowrank;      /* 1: gs_setup stops after the factorisation; the
                              rank-k terms are built later by gs_lowrank  [0]  */
-  int block_max_iters;    /* gs_lowrank: block iterations from a starting
-                             basis before falling back to Arnoldi        [8]  */
+  int block_max_iters;    /* gs_lowrank: the block iteration from a starting
+                             basis may use block_max_iters * k products of
+                             G_l before falling back to Arnoldi          [8]  */
 } gs_opts;
 
 /* Fill *opts with the defaults shown in brackets above. */
@@ -208,11 +209,13 @@ int gs_features(const gs_ctx* ctx, int level, float* X, int64_t rows_cap, int co
  * GPU (Sec. 4.2).  warm: NULL, or L device pointers (entries may be NULL);
  * warm[l] is a float32 s_l x rank row-major starting basis for level l (the
  * future-work "block" setup of Sec. 6): the level then runs a block
- * Rayleigh-Ritz iteration -- Ritz pairs of span(V), expansion by the block
- * residual G V - V (V^H G V), restart to the wanted k -- accepted when every
- * wanted Ritz pair meets opts.arnoldi_tol; after opts.block_max_iters
- * iterations it falls back to thick-restart Arnoldi.  Levels without a basis
- * use Arnoldi.  Per-level matvec counts and the method used go to gs_info.
+ * Rayleigh-Ritz iteration -- Ritz pairs of the search space V (starting as
+ * orth(warm[l]), at most 3k columns), expansion by the residuals of the
+ * wanted pairs not yet accepted, thick restart to the leading wanted Ritz
+ * vectors when full -- accepted when every wanted Ritz pair meets
+ * opts.arnoldi_tol; after opts.block_max_iters * k products it falls back to
+ * thick-restart Arnoldi.  Levels without a basis use Arnoldi.  Per-level
+ * product counts (both methods together) and the method used go to gs_info.
  * Errors: GS_ESTATE, GS_EINVAL, GS_ESINGULAR, GS_EDEVICE. */
 int gs_lowrank(gs_ctx* ctx, int rank, const float* const* warm);
 

@@ -305,102 +305,154 @@ static void lowrank_level(gs_ctx* c, int l, int kreq) {
 
 
 // Block Rayleigh-Ritz iteration from a given starting basis Y (s x k, row-major
-// float32, device): V = orth(Y); repeat { Ritz pairs of T = V^H G V; accept if
-// every wanted pair has ||(G V - V T) y|| <= tol |theta|; otherwise expand by
-// the orthonormalised block residual P, Rayleigh-Ritz on [V P] and restart
-// to the k wanted Ritz vectors }.  k Ĝ_l products per iteration.  Returns
-// true and installs W_l, H_l on acceptance; matvecs are counted in h.
+// float32, device).  The search space V (orthonormal, at most mmax = 3k
+// columns) starts as orth(Y).  Each iteration takes the Ritz pairs of
+// T = V^H G V for the k wanted values, accepts when every pair has
+// ||G x - theta x|| <= tol |theta|, and otherwise adds the residuals of the
+// pairs not yet accepted (accepted pairs cost no further products); when the
+// space would exceed mmax it is first truncated to the leading wanted Ritz
+// vectors (a thick restart).  T and M = (G V)^H (G V) are kept up to date
+// column by column, so each residual norm is sqrt(y^H M y - |theta|^2) for
+// the unit coefficient vector y, with no pass over the residual block.
+// Returns true and installs W_l, H_l on acceptance; fails once the products
+// reach block_max_iters * k (the caller then runs the restarted Arnoldi).
 template <class T>
 static bool lowrank_block(gs_ctx* c, int l, int kreq, const float* Y) {
   using DT = typename DevOf<T>::type;
+  const bool real = std::is_same<T, double>::value;
   HostSetup<T>& S = host<T>(c);
   HostLevel<T>& h = S.lv[l];
   const hipStream_t st = c->stream;
   const int64_t s = h.s;
   const int k = (int)std::min<int64_t>(kreq, s);
   if (k <= 0) return true;
-  const int kmax = (int)std::min<int64_t>(k + 1, s);
-  const int wmax = (int)std::min<int64_t>(2 * (int64_t)kmax, s);
+  const int mmax = (int)std::min<int64_t>(std::max(3 * k, k + 8), s);
+  const int cap = mmax + 2;           // a kept conjugate pair may add one
+  const int bmax = 2 * k + 2;         // staged expansion columns
   DevMem mem;
-  DT* Sv = mem.alloc<DT>((size_t)s * 2 * kmax);   // [V P]
-  DT* GSv = mem.alloc<DT>((size_t)s * 2 * kmax);  // [G V, G P]
-  DT* tmp = mem.alloc<DT>((size_t)s * 2 * kmax);
-  DT* part = mem.alloc<DT>((size_t)256 * 2 * kmax);
-  DT* hd = mem.alloc<DT>(2 * kmax);
-  DT* Td = mem.alloc<DT>((size_t)4 * kmax * kmax);
-  DT* Gd = mem.alloc<DT>((size_t)4 * kmax * kmax);
+  DT* Sv = mem.alloc<DT>((size_t)s * cap);   // V
+  DT* GSv = mem.alloc<DT>((size_t)s * cap);  // G V
+  DT* X = mem.alloc<DT>((size_t)s * bmax);   // staged new directions
+  DT* tmp = mem.alloc<DT>((size_t)s * std::max(cap, bmax));
+  DT* part = mem.alloc<DT>((size_t)256 * cap);
+  DT* hd = mem.alloc<DT>(cap);
+  DT* Td = mem.alloc<DT>((size_t)cap * cap);  // dots, column-major, ld cap
+  DT* Md = mem.alloc<DT>((size_t)cap * cap);
+  DT* Cd = mem.alloc<DT>((size_t)cap * std::max(cap, bmax));  // small coefficient blocks
   double* npart = mem.alloc<double>(256);
   double* nrm = mem.alloc<double>(2);
   std::vector<DT> hv(s);
   std::vector<double> v0(s);
-  int nmv = 0;
+  std::vector<cplx> Th((size_t)cap * cap, 0.0), Mh((size_t)cap * cap, 0.0);
   auto col = [&](DT* base, int j) { return base + (size_t)j * s; };
-  // orthonormalise column j of Sv against columns [0, j); a vanishing column
-  // is replaced by a fresh generator vector
-  auto orth_col = [&](int j) {
-    for (int attempt = 0; attempt < 3; ++attempt) {
-      launch_norm<DT>(col(Sv, j), s, npart, nrm + 1, st);
-      if (j > 0) cgs2<DT>(Sv, s, j, col(Sv, j), s, part, hd, nullptr, st);
-      launch_norm<DT>(col(Sv, j), s, npart, nrm, st);
-      double nn[2];
-      HIPCHK(hipMemcpyAsync(nn, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (nn[0] > 1e-10 * nn[1] && nn[0] > 0) {
-        launch_scale_inv<DT>(col(Sv, j), nrm, col(Sv, j), s, st);
-        return;
-      }
-      start_vector(c->opts.seed + (uint64_t)l + 0x9E3779B9ULL * (uint64_t)(j + 1 + 97 * attempt), s,
-                   v0.data());
-      for (int64_t i = 0; i < s; ++i) hv[i] = from_host<DT>(v0[i]);
-      HIPCHK(hipMemcpyAsync(col(Sv, j), hv.data(), s * sizeof(DT), hipMemcpyHostToDevice, st));
-      HIPCHK(hipStreamSynchronize(st));
+  auto at = [&](std::vector<cplx>& A, int i, int j) -> cplx& { return A[(size_t)j * cap + i]; };
+  int w = 0, nmv = 0, fresh = 0;
+  const int budget = std::max(1, c->opts.block_max_iters) * k;
+
+  auto upload = [&](const std::vector<cplx>& A, int r, int cc, DT* dst) {
+    std::vector<DT> t((size_t)r * cc);
+    for (size_t i = 0; i < t.size(); ++i) {
+      if (real) ((double*)t.data())[i] = A[i].real();
+      else std::memcpy((void*)&t[i], &A[i], sizeof(cplx));
     }
-    throw Error(GS_EINVAL, "could not extend the block basis");
-  };
-  // host copy of a w x w device matrix (column-major) as complex
-  auto fetch = [&](const DT* d, int r, int cc) {
-    std::vector<DT> tmph((size_t)r * cc);
-    HIPCHK(hipMemcpyAsync(tmph.data(), d, tmph.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(dst, t.data(), t.size() * sizeof(DT), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
-    std::vector<cplx> out((size_t)r * cc);
-    for (size_t i = 0; i < out.size(); ++i) out[i] = to_cplx<T>(tmph.data(), i);
+  };
+  // append column src to V if it keeps a relative norm > 1e-6 after two
+  // Gram-Schmidt passes against V; then its product with G
+  auto append = [&](const DT* src) -> bool {
+    launch_copy<DT>(src, col(Sv, w), s, st);
+    launch_norm<DT>(col(Sv, w), s, npart, nrm + 1, st);
+    if (w > 0) cgs2<DT>(Sv, s, w, col(Sv, w), s, part, hd, nullptr, st);
+    launch_norm<DT>(col(Sv, w), s, npart, nrm, st);
+    double nn[2];
+    HIPCHK(hipMemcpyAsync(nn, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (!(nn[0] > 1e-6 * nn[1] && nn[0] > 0)) return false;
+    launch_scale_inv<DT>(col(Sv, w), nrm, col(Sv, w), s, st);
+    c->eng->ghat(l, col(Sv, w), col(GSv, w));
+    ++nmv;
+    ++w;
+    return true;
+  };
+  // T and M entries that involve the columns [w0, w)
+  auto extend_dots = [&](int w0) {
+    if (w0 == w) return;
+    for (int j = w0; j < w; ++j) {
+      launch_multidot<DT>(Sv, s, w, col(GSv, j), s, part, Td + (size_t)j * cap, st);
+      launch_multidot<DT>(GSv, s, w, col(GSv, j), s, part, Md + (size_t)j * cap, st);
+    }
+    for (int i = 0; i < w0; ++i)
+      launch_multidot<DT>(col(Sv, w0), s, w - w0, col(GSv, i), s, part, Td + (size_t)i * cap + w0, st);
+    std::vector<DT> tt((size_t)cap * cap), mm((size_t)cap * cap);
+    HIPCHK(hipMemcpyAsync(tt.data(), Td, tt.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(mm.data(), Md, mm.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int j = w0; j < w; ++j)
+      for (int i = 0; i < w; ++i) {
+        at(Th, i, j) = to_cplx<T>(tt.data(), (size_t)j * cap + i);
+        at(Mh, i, j) = to_cplx<T>(mm.data(), (size_t)j * cap + i);
+        at(Mh, j, i) = std::conj(at(Mh, i, j));
+      }
+    for (int i = 0; i < w0; ++i)
+      for (int j = w0; j < w; ++j) at(Th, j, i) = to_cplx<T>(tt.data(), (size_t)i * cap + j);
+  };
+  auto square = [&](const std::vector<cplx>& A, int m) {
+    std::vector<cplx> B((size_t)m * m);
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) B[(size_t)j * m + i] = A[(size_t)j * cap + i];
+    return B;
+  };
+  auto as_cplx = [&](const std::vector<T>& G) {
+    std::vector<cplx> out(G.size());
+    for (size_t i = 0; i < G.size(); ++i) out[i] = to_cplx<T>(G.data(), i);
     return out;
   };
-  launch_rows_to_cols<DT>(Y, s, k, kreq, Sv, s, st);
-  int w = k;
-  for (int j = 0; j < w; ++j) orth_col(j);
-  for (int j = 0; j < w; ++j, ++nmv) c->eng->ghat(l, col(Sv, j), col(GSv, j));
-  const int maxit = std::max(1, c->opts.block_max_iters);
-  for (int it = 0; it < maxit; ++it) {
-    // T = V^H G V and the block residual R = G V - V T (into the P slot)
-    for (int j = 0; j < w; ++j) launch_multidot<DT>(Sv, s, w, col(GSv, j), s, part, Td + (size_t)j * w, st);
-    launch_gemm_small<DT>(Sv, s, w, Td, w, tmp, s, s, st);
-    launch_sub<DT>(GSv, tmp, col(Sv, w), (int64_t)s * w, st);
-    for (int j = 0; j < w; ++j) launch_multidot<DT>(col(Sv, w), s, w, col(Sv, w + j), s, part, Gd + (size_t)j * w, st);
-    const std::vector<cplx> Tw = fetch(Td, w, w);
-    const std::vector<cplx> Nw = fetch(Gd, w, w);
+
+  // initial space: the columns of Y, topped up with generator vectors
+  launch_rows_to_cols<DT>(Y, s, k, kreq, X, s, st);
+  for (int j = 0; j < k; ++j) append(col(X, j));
+  while (w < k) {
+    if (fresh > 4 * k) throw Error(GS_EINVAL, "could not build the block basis");
+    start_vector(c->opts.seed + (uint64_t)l + 0x9E3779B9ULL * (uint64_t)(++fresh), s, v0.data());
+    for (int64_t i = 0; i < s; ++i) hv[i] = from_host<DT>(v0[i]);
+    HIPCHK(hipMemcpyAsync(X, hv.data(), s * sizeof(DT), hipMemcpyHostToDevice, st));
+    append(X);
+  }
+  extend_dots(0);
+  for (int it = 0;; ++it) {
+    const std::vector<cplx> Tw = square(Th, w);
     std::vector<cplx> Tm, Q, thk;
     std::vector<T> G, R;
     const int kk = schur_basis<T>(w, Tw, k, Tm, Q, thk, G, R);
-    // Ritz pair residuals ||R y_i||^2 = y_i^H N y_i with y_i = Q_k e_i-eigvec
     std::vector<cplx> Tk((size_t)kk * kk), Ye;
     for (int j = 0; j < kk; ++j)
       for (int i = 0; i < kk; ++i) Tk[(size_t)j * kk + i] = Tm[(size_t)j * w + i];
     triu_eigvecs(kk, Tk, Ye);
-    bool conv = true;
-    for (int e = 0; e < kk && conv; ++e) {
+    // unit coefficient vectors y_e = Q_k Ye[:, e] and their residual norms
+    std::vector<std::vector<cplx>> todo;
+    for (int e = 0; e < kk; ++e) {
       std::vector<cplx> y(w, 0.0);
       for (int j = 0; j < kk; ++j)
         for (int i = 0; i < w; ++i) y[i] += Q[(size_t)j * w + i] * Ye[(size_t)e * kk + j];
+      double yn = 0;
+      for (const cplx& v : y) yn += std::norm(v);
+      yn = std::sqrt(yn);
+      for (cplx& v : y) v /= yn;
       cplx q = 0;
-      for (int a = 0; a < w; ++a)
-        for (int b = 0; b < w; ++b) q += std::conj(y[a]) * Nw[(size_t)b * w + a] * y[b];
-      const double res = std::sqrt(std::max(0.0, q.real()));
-      if (res > c->opts.arnoldi_tol * std::abs(thk[e])) conv = false;
+      for (int b = 0; b < w; ++b) {
+        cplx mb = 0;
+        for (int a = 0; a < w; ++a) mb += std::conj(y[a]) * at(Mh, a, b);
+        q += mb * y[b];
+      }
+      const double res2 = q.real() - std::norm(thk[e]);
+      if (std::sqrt(std::max(0.0, res2)) <= c->opts.arnoldi_tol * std::abs(thk[e])) continue;
+      if (real && thk[e].imag() < -1e-10 * std::abs(thk[e])) continue;  // partner of a pair
+      todo.push_back(y);
     }
-    if (conv) {
-      HIPCHK(hipMemcpyAsync(Gd, G.data(), G.size() * sizeof(DT), hipMemcpyHostToDevice, st));
-      launch_gemm_small<DT>(Sv, s, w, Gd, kk, tmp, s, s, st);
+    if (todo.empty()) {
+      upload(as_cplx(G), w, kk, Cd);
+      launch_gemm_small<DT>(Sv, s, w, Cd, kk, tmp, s, s, st);
       h.W.resize((size_t)s * kk);
       HIPCHK(hipMemcpyAsync(h.W.data(), tmp, h.W.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -412,23 +464,81 @@ static bool lowrank_block(gs_ctx* c, int l, int kreq, const float* Y) {
       c->eng->set_lowrank(l, kk, h.W.data(), h.H.data());
       return true;
     }
-    if (it == maxit - 1 || 2 * w > wmax) break;
-    // expand by the orthonormalised residual block and its products
-    for (int j = 0; j < w; ++j) orth_col(w + j);
-    for (int j = 0; j < w; ++j, ++nmv) c->eng->ghat(l, col(Sv, w + j), col(GSv, w + j));
-    // Rayleigh-Ritz on [V P]; restart to the wanted Ritz vectors
-    const int w2 = 2 * w;
-    for (int j = 0; j < w2; ++j) launch_multidot<DT>(Sv, s, w2, col(GSv, j), s, part, Td + (size_t)j * w2, st);
-    const std::vector<cplx> T2 = fetch(Td, w2, w2);
-    std::vector<T> G2, R2;
-    const int k2 = schur_basis<T>(w2, T2, k, Tm, Q, thk, G2, R2);
-    HIPCHK(hipMemcpyAsync(Gd, G2.data(), G2.size() * sizeof(DT), hipMemcpyHostToDevice, st));
-    launch_gemm_small<DT>(Sv, s, w2, Gd, k2, tmp, s, s, st);
-    launch_copy<DT>(tmp, Sv, (int64_t)s * k2, st);
-    launch_gemm_small<DT>(GSv, s, w2, Gd, k2, tmp, s, s, st);
-    launch_copy<DT>(tmp, GSv, (int64_t)s * k2, st);
-    HIPCHK(hipStreamSynchronize(st));
-    w = k2;
+    if (nmv >= budget) break;
+    // coefficient block P (w x nb): y_e, or for real data Re y_e and Im y_e
+    // (a real eigenvalue's vector is rotated to be real first)
+    std::vector<cplx> P;
+    int nb = 0;
+    for (std::vector<cplx>& y : todo) {
+      if (real) {
+        size_t big = 0;
+        for (size_t i = 1; i < y.size(); ++i)
+          if (std::abs(y[i]) > std::abs(y[big])) big = i;
+        const cplx ph = std::abs(y[big]) > 0 ? std::conj(y[big]) / std::abs(y[big]) : cplx(1.0);
+        for (cplx& v : y) v *= ph;
+        for (int part_im = 0; part_im < 2 && nb < bmax; ++part_im) {
+          double pn = 0;
+          for (const cplx& v : y) pn += part_im ? v.imag() * v.imag() : v.real() * v.real();
+          if (part_im && pn <= 1e-20) break;
+          for (const cplx& v : y) P.push_back(part_im ? v.imag() : v.real());
+          ++nb;
+        }
+      } else if (nb < bmax) {
+        P.insert(P.end(), y.begin(), y.end());
+        ++nb;
+      }
+    }
+    // X = (G V) P - V (T P): the residual block of the chosen vectors
+    std::vector<cplx> TP((size_t)w * nb, 0.0);
+    for (int j = 0; j < nb; ++j)
+      for (int a = 0; a < w; ++a) {
+        const cplx pa = P[(size_t)j * w + a];
+        for (int i = 0; i < w; ++i) TP[(size_t)j * w + i] += Tw[(size_t)a * w + i] * pa;
+      }
+    upload(P, w, nb, Cd);
+    launch_gemm_small<DT>(GSv, s, w, Cd, nb, X, s, s, st);
+    upload(TP, w, nb, Cd);
+    launch_gemm_small<DT>(Sv, s, w, Cd, nb, tmp, s, s, st);
+    launch_sub<DT>(X, tmp, X, (int64_t)s * nb, st);
+    // thick restart to the leading wanted Ritz vectors when the space is full
+    if (w + nb > mmax) {
+      const int keep = std::max(k, mmax - nb);
+      if (keep < w) {
+        std::vector<cplx> Tm2, Q2, th2;
+        std::vector<T> G2, R2;
+        const int k2 = schur_basis<T>(w, Tw, keep, Tm2, Q2, th2, G2, R2);
+        const std::vector<cplx> Gc = as_cplx(G2);
+        upload(Gc, w, k2, Cd);
+        launch_gemm_small<DT>(Sv, s, w, Cd, k2, tmp, s, s, st);
+        launch_copy<DT>(tmp, Sv, (int64_t)s * k2, st);
+        launch_gemm_small<DT>(GSv, s, w, Cd, k2, tmp, s, s, st);
+        launch_copy<DT>(tmp, GSv, (int64_t)s * k2, st);
+        // T <- G^H T G, M <- G^H M G
+        std::vector<cplx> T2((size_t)cap * cap, 0.0), M2((size_t)cap * cap, 0.0);
+        for (int pass = 0; pass < 2; ++pass) {
+          std::vector<cplx>& A = pass ? Mh : Th;
+          std::vector<cplx>& B = pass ? M2 : T2;
+          std::vector<cplx> AG((size_t)w * k2, 0.0);
+          for (int j = 0; j < k2; ++j)
+            for (int a = 0; a < w; ++a) {
+              const cplx g = Gc[(size_t)j * w + a];
+              for (int i = 0; i < w; ++i) AG[(size_t)j * w + i] += at(A, i, a) * g;
+            }
+          for (int j = 0; j < k2; ++j)
+            for (int i = 0; i < k2; ++i) {
+              cplx v = 0;
+              for (int a = 0; a < w; ++a) v += std::conj(Gc[(size_t)i * w + a]) * AG[(size_t)j * w + a];
+              B[(size_t)j * cap + i] = v;
+            }
+          A.swap(B);
+        }
+        w = k2;
+      }
+    }
+    const int w0 = w;
+    for (int j = 0; j < nb && w < cap; ++j) append(col(X, j));
+    if (w == w0) break;  // no new direction survived: stagnation
+    extend_dots(w0);
   }
   h.arnoldi_matvecs = nmv;
   return false;

@@ -236,12 +236,13 @@ __device__ __forceinline__ void copy_chunk(const TriArgs<P>& a, int c, uint8_t* 
   const uint4* src = reinterpret_cast<const uint4*>(a.blob + cd.off);
   uint4* d = reinterpret_cast<uint4*>(dst);
   const int nv = cd.n16;
+  const int last = nv - 1;
+  // every element is loaded (lanes past the end re-read the chunk's last 16
+  // bytes), so the staging array is fully defined and stays in registers;
+  // all loads are in flight before the first LDS store
   uint4 tmp[kNV];
 #pragma unroll
-  for (int i = 0; i < kNV; ++i) {
-    const int idx = lane + kWave * i;
-    if (idx < nv) tmp[i] = src[idx];
-  }
+  for (int i = 0; i < kNV; ++i) tmp[i] = src[min(lane + kWave * i, last)];
 #pragma unroll
   for (int i = 0; i < kNV; ++i) {
     const int idx = lane + kWave * i;
@@ -249,10 +250,13 @@ __device__ __forceinline__ void copy_chunk(const TriArgs<P>& a, int c, uint8_t* 
   }
 }
 
-// Sweep the stages of one chunk held in LDS.  Branch-free per lane: every
-// lane issues the same LDS reads (inactive slots are masked afterwards), so
-// the gathers of a stage are in flight together, and the next stage's row
-// info and entries are fetched while the current stage accumulates.
+// Sweep the stages of one chunk held in LDS.  The stage body is straight-
+// line code: every lane issues all MS slot reads and gathers (slots beyond a
+// row's count read in-bounds filler -- past the end of a section at most 63
+// elements, inside the chunk or the LDS slack -- and are discarded by a
+// select), so the compiler keeps all gathers of a stage in flight together
+// instead of waiting at every branch join.  The next stage's row info and
+// entries are fetched while the current stage accumulates.
 template <class P, int MS, bool ISU>
 __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& cd, int lane,
                                             typename P::C* x) {
@@ -269,24 +273,20 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
   int nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
   bool act = lane < nr;
   int nz = act ? (int)((info >> 16) & 0xffu) : 0;
-  int maxnz = __builtin_amdgcn_readfirstlane(nz);
   C v[MS];
-  uint16_t c[MS];
+  int c[MS];
 #pragma unroll
   for (int j = 0; j < MS; ++j) {
-    if (j < maxnz) {
-      const unsigned long long m = __ballot(nz > j);
-      v[j] = cvt<C>(val[e + lane]);
-      c[j] = col[e + lane];
-      e += __popcll(m);
-    }
+    const unsigned long long m = __ballot(nz > j);
+    v[j] = cvt<C>(val[e + lane]);
+    c[j] = nz > j ? (int)col[e + lane] : 0;
+    e += __popcll(m);
   }
   for (int s = 0; s < nst; ++s) {
     // gathers of stage s, its own rhs and 1/u_ii, and the next stage's row info
     C xv[MS];
 #pragma unroll
-    for (int j = 0; j < MS; ++j)
-      if (j < maxnz) xv[j] = x[nz > j ? (int)c[j] : 0];
+    for (int j = 0; j < MS; ++j) xv[j] = x[c[j]];
     const int row = act ? (int)(info & 0xffffu) : 0;
     C acc = x[row];
     C dv = zero<C>();
@@ -298,25 +298,20 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
     const int nrn = (int)__builtin_amdgcn_readfirstlane(infon >> 24);
     const bool actn = lane < nrn;
     const int nzn = actn ? (int)((infon >> 16) & 0xffu) : 0;
-    const int maxnzn = __builtin_amdgcn_readfirstlane(nzn);
     C vn[MS];
-    uint16_t cn[MS];
+    int cn[MS];
 #pragma unroll
     for (int j = 0; j < MS; ++j) {
-      if (j < maxnzn) {
-        const unsigned long long m = __ballot(nzn > j);
-        vn[j] = cvt<C>(val[e + lane]);
-        cn[j] = col[e + lane];
-        e += __popcll(m);
-      }
+      const unsigned long long m = __ballot(nzn > j);
+      vn[j] = cvt<C>(val[e + lane]);
+      cn[j] = nzn > j ? (int)col[e + lane] : 0;
+      e += __popcll(m);
     }
-    // accumulate stage s
+    // accumulate stage s (slots past the row's count are dropped)
 #pragma unroll
     for (int j = 0; j < MS; ++j) {
-      if (j < maxnz) {
-        const C t = v[j] * xv[j];
-        acc = nz > j ? acc - t : acc;
-      }
+      const C t = v[j] * xv[j];
+      acc = nz > j ? acc - t : acc;
     }
     if (ISU) acc *= dv;
     if (act) x[row] = acc;
@@ -326,7 +321,6 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
     nr = nrn;
     act = actn;
     nz = nzn;
-    maxnz = maxnzn;
 #pragma unroll
     for (int j = 0; j < MS; ++j) {
       v[j] = vn[j];
@@ -502,15 +496,27 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
   }
   if (a.k == 0) return;
   const int wave = tid / kWave, lane = tid % kWave;
-  for (int c = 0; c < a.k; ++c) {
-    C pr = zero<C>();
+  // columns in groups of 8: all W loads of a group are issued before the
+  // first reduction waits on them
+  constexpr int CG = 8;
+  for (int c0 = 0; c0 < a.k; c0 += CG) {
+    C pr[CG];
+#pragma unroll
+    for (int u = 0; u < CG; ++u) pr[u] = zero<C>();
 #pragma unroll
     for (int q = 0; q < kIfRows; ++q) {
       const int64_t j = base + (int64_t)q * kIfThreads;
-      if (j < a.s) pr += conj(cvt<C>(a.W[j + (int64_t)c * a.s])) * z[q];
+      if (j < a.s) {
+#pragma unroll
+        for (int u = 0; u < CG; ++u)
+          if (c0 + u < a.k) pr[u] += conj(cvt<C>(a.W[j + (int64_t)(c0 + u) * a.s])) * z[q];
+      }
     }
-    pr = wave_sum(pr);
-    if (lane == 0) red[wave * a.k + c] = pr;
+#pragma unroll
+    for (int u = 0; u < CG; ++u) {
+      const C r = wave_sum(pr[u]);
+      if (lane == 0 && c0 + u < a.k) red[wave * a.k + c0 + u] = r;
+    }
   }
   __syncthreads();
   for (int c = tid; c < a.k; c += kIfThreads) {
@@ -693,13 +699,18 @@ __global__ __launch_bounds__(256) void k_multidot(const T* V, int64_t ld, int nc
     partial[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
   }
 }
+// h[c] = sum_b partial[c][b]: one workgroup per column, fixed-order tree
 template <class T>
-__global__ void k_sum_partials(const T* partial, int nparts, int ncol, T* h) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncol) return;
-  T s = zero<T>();
-  for (int b = 0; b < nparts; ++b) s += partial[(int64_t)c * nparts + b];
-  h[c] = s;
+__global__ __launch_bounds__(256) void k_sum_partials(const T* partial, int nparts, int ncol,
+                                                      T* h) {
+  __shared__ T red[4];
+  const int c = blockIdx.x;
+  T s = threadIdx.x < nparts ? partial[(int64_t)c * nparts + threadIdx.x] : zero<T>();
+  s = wave_sum(s);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) h[c] = red[0] + red[1] + red[2] + red[3];
 }
 template <class T>
 void launch_multidot(const T* V, int64_t ld, int ncol, const T* w, int64_t n, T* partial, T* h,
@@ -708,8 +719,7 @@ void launch_multidot(const T* V, int64_t ld, int ncol, const T* w, int64_t n, T*
   const int nb = (int)std::min<int64_t>(kDotBlocks, (n + 255) / 256);
   dim3 grid(nb, (ncol + kDotChunk - 1) / kDotChunk);
   hipLaunchKernelGGL(k_multidot<T>, grid, dim3(256), 0, st, V, ld, ncol, w, n, partial);
-  hipLaunchKernelGGL(k_sum_partials<T>, dim3((ncol + 63) / 64), dim3(64), 0, st, partial, nb,
-                     ncol, h);
+  hipLaunchKernelGGL(k_sum_partials<T>, dim3(ncol), dim3(256), 0, st, partial, nb, ncol, h);
 }
 
 template <class T>
@@ -748,17 +758,21 @@ __global__ __launch_bounds__(256) void k_norm_part(const T* w, int64_t n, double
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
-__global__ void k_norm_final(const double* partial, int nparts, double* out) {
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += partial[b];
-  out[0] = sqrt(s);
+__global__ __launch_bounds__(256) void k_norm_final(const double* partial, int nparts,
+                                                    double* out) {
+  __shared__ double red[4];
+  double s = threadIdx.x < nparts ? partial[threadIdx.x] : 0.0;
+  s = wave_sum(s);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = sqrt(red[0] + red[1] + red[2] + red[3]);
 }
 template <class T>
 void launch_norm(const T* w, int64_t n, double* partial, double* out, hipStream_t st) {
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (n + 255) / 256));
   hipLaunchKernelGGL(k_norm_part<T>, dim3(nb), dim3(256), 0, st, w, n, partial);
-  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(64), 0, st, partial, nb, out);
+  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, partial, nb, out);
 }
 
 template <class T>

@@ -172,6 +172,8 @@ struct Mlp {
 
   void ensure(int64_t rows) {
     if (rows <= cap_rows) return;
+    // the old buffers may still be read by queued kernels
+    hipcheck(hipStreamSynchronize(st), "mlp grow");
     work = std::make_unique<DevMem>();
     cap_rows = rows;
     a1 = work->alloc<float>(rows * hid);
@@ -209,8 +211,11 @@ struct Mlp {
     hipLaunchKernelGGL(k_sum_blocks, dim3((len + 255) / 256), dim3(256), 0, st, partial, nb, len,
                        outp, acc ? 1 : 0);
   }
+  // Y must be valid for `rows` rows: callers that use the internal y buffer
+  // call ensure(rows) first and pass it afterwards
   void forward(const float* X, int64_t rows, float* Y) {
     ensure(rows);
+    if (!Y) throw Error(GS_EINVAL, "null network output");
     dense(X, rows, in, W1(), b1(), hid, a1, true);
     dense(a1, rows, hid, W2(), b2(), hid, a2, true);
     dense(a2, rows, hid, W3(), b3(), out, Y, false);
@@ -331,6 +336,7 @@ int gs_mlp_loss_backward(gs_mlp* h, const float* X, const float* Wt, int64_t row
   if (!h || !X || !Wt || !loss || rows <= 0 || kw < 1 || kw > gs::kMaxDim) return GS_EINVAL;
   MLP_GUARD(h, {
     Mlp& m = h->m;
+    m.ensure(rows);  // before taking m.y: growing reallocates it
     m.forward(X, rows, m.y);
     const int ky = m.out;
     // Gram matrices G1 = Y^T Y (ky x ky), G2 = W^T Y (kw x ky)

@@ -279,17 +279,32 @@ class Context:
         self._check(lib().gs_set_precision(self._h, PRECISIONS.get(precision, precision)))
 
     # ---------------------------------------------------------------- apply / solve
+    def _vec(self, t, count=1):
+        """Device pointer of a contiguous CUDA tensor holding `count` vectors
+        of length n in the setup's value type (the library cannot check the
+        extent of a raw device pointer, so it is checked here)."""
+        if self.n is None:
+            return _ptr(t)  # the library reports the missing setup
+        vb = 16 if self.dtype == GS_C128 else 8
+        kinds = ("torch.complex128", "torch.float64") if vb == 16 else ("torch.float64",)
+        if (not getattr(t, "is_cuda", False) or not t.is_contiguous()
+                or str(t.dtype) not in kinds or t.numel() * t.element_size() != count * self.n * vb):
+            raise ValueError(f"expected a contiguous CUDA tensor of {count} x {self.n} "
+                             f"{'complex128' if vb == 16 else 'float64'} values")
+        return _ptr(t)
+
     def apply(self, x, y):
-        self._check(lib().gs_apply(self._h, _ptr(x), _ptr(y)))
+        self._check(lib().gs_apply(self._h, self._vec(x), self._vec(y)))
 
     def apply_many(self, nrhs, x, y):
-        self._check(lib().gs_apply_many(self._h, nrhs, _ptr(x), _ptr(y)))
+        self._check(lib().gs_apply_many(self._h, nrhs, self._vec(x, nrhs), self._vec(y, nrhs)))
 
     def apply_profile(self, x, y, reps=10, cap=256):
         ms = np.zeros(cap)
         by = np.zeros(cap)
         ns = ct.c_int()
-        self._check(lib().gs_apply_profile(self._h, _ptr(x), _ptr(y), reps, _ptr(ms), _ptr(by),
+        self._check(lib().gs_apply_profile(self._h, self._vec(x), self._vec(y), reps, _ptr(ms),
+                                           _ptr(by),
                                            cap, ct.byref(ns)))
         k = ns.value
         labels = [lib().gs_apply_step_label(self._h, i).decode() for i in range(k)]
@@ -308,7 +323,8 @@ class Context:
 
     def solve(self, b, x, tol):
         info = GsInfo()
-        rc = self._check(lib().gs_solve(self._h, _ptr(b), _ptr(x), tol, ct.byref(info)),
+        rc = self._check(lib().gs_solve(self._h, self._vec(b), self._vec(x), tol,
+                                        ct.byref(info)),
                          ok=(GS_OK, GS_NOT_CONVERGED))
         d = info.as_dict()
         d["status"] = rc
@@ -498,3 +514,41 @@ def unpack_params(flat, dims):
         out.append(np.asarray(flat[pos:pos + n]).reshape(sh))
         pos += n
     return out
+
+
+# ---------------------------------------------------------------- checkpoint
+def save_setup(ctx, path, rowptr, col, val):
+    """Write the installed preconditioner (permutation, per-level factors,
+    E, F, W, H) and A to an .npz file; load_setup restores it bit for bit."""
+    info = ctx.info()
+    L = info["nlevels"]
+    arrs = {"n": ctx.n, "nlevels": L, "perm": ctx.perm(), "rowptr": np.asarray(rowptr),
+            "col": np.asarray(col), "val": np.asarray(val)}
+    for l in range(L + 1):
+        lv = ctx.level(l)
+        arrs[f"l{l}_d"] = lv["d"]
+        arrs[f"l{l}_block_ptr"] = lv["block_ptr"]
+        for name in ("L", "U", "E", "F"):
+            for j, part in enumerate(("rowptr", "col", "val")):
+                arrs[f"l{l}_{name}_{part}"] = lv[name][j]
+        arrs[f"l{l}_W"] = lv["W"]
+        arrs[f"l{l}_H"] = lv["H"]
+    np.savez(path, **arrs)
+
+
+def load_setup(path, device=0, **opts_kw):
+    z = np.load(path)
+    L = int(z["nlevels"])
+    levels = []
+    for l in range(L + 1):
+        d = {"d": int(z[f"l{l}_d"]), "block_ptr": z[f"l{l}_block_ptr"]}
+        for name in ("L", "U"):
+            d[name] = tuple(z[f"l{l}_{name}_{p}"] for p in ("rowptr", "col", "val"))
+        if l < L:
+            for name in ("E", "F"):
+                d[name] = tuple(z[f"l{l}_{name}_{p}"] for p in ("rowptr", "col", "val"))
+            d["W"], d["H"] = z[f"l{l}_W"], z[f"l{l}_H"]
+        levels.append(d)
+    ctx = Context(device)
+    ctx.setup_explicit(z["rowptr"], z["col"], z["val"], z["perm"], levels, **opts_kw)
+    return ctx

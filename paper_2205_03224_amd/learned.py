@@ -57,8 +57,11 @@ def collect(instances, N=64, nparts=64, rank=32, levels=(0, 1), log=None):
             if l >= ctx.info()["nlevels"]:
                 continue
             X = ctx.features(l)
-            W = np.ascontiguousarray(ctx.level(l)["W"], dtype=np.float32)
-            data.append({"instance": i, "level": l, "X": X, "W": W})
+            W = ctx.level(l)["W"]
+            # same subspace, entries O(1) like the network's outputs: the loss
+            # is minimised at Y = sqrt(s) W Q for any orthogonal Q
+            Wt = np.ascontiguousarray(W * np.sqrt(W.shape[0]), dtype=np.float32)
+            data.append({"instance": i, "level": l, "X": X, "W": Wt})
         ctx.close()
         if log:
             log(f"[learned] collected instance {i}")
@@ -81,7 +84,9 @@ def train(data, epochs=30, lr=1e-3, seed=0, out_dim=32, log=None):
             mlp.zero_grad()
             loss = mlp.loss_backward(Xs[j], Ws[j])
             mlp.adam_step(lr)
-            tot += loss / Ws[j].shape[1]
+            s, kw = Ws[j].shape
+            # back to ||Y Y^T - W W^T||^2 / k for Y scaled by 1/sqrt(s)
+            tot += ((loss - kw) / float(s) ** 2 + kw) / kw
         hist.append(tot / max(1, len(data)))
         if log and (ep % 5 == 0 or ep == epochs - 1):
             log(f"[learned] epoch {ep}: mean normalised loss {hist[-1]:.4f}")
@@ -180,3 +185,62 @@ def summarise(rows):
         wins = [lr[i]["time_to_tol_s"] < ar[i]["time_to_tol_s"] for i in lr if i in ar]
         out["learned_win_fraction_vs_arnoldi"] = float(np.mean(wins)) if wins else None
     return out
+
+
+def main(argv=None):
+    """python -m paper_2205_03224_amd.learned train|evaluate ...
+
+    train:    collect bases of members 0..n_train-1, train, save the
+              parameters (npz) and the loss history.
+    evaluate: load the parameters and compare Arnoldi / learned / random
+              starts on held-out members 100000.. (JSON report)."""
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train", "evaluate"])
+    ap.add_argument("--N", type=int, default=64)
+    ap.add_argument("--nparts", type=int, default=64)
+    ap.add_argument("--rank", type=int, default=32)
+    ap.add_argument("--n-train", type=int, default=512)
+    ap.add_argument("--n-heldout", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--levels", default="0,1")
+    ap.add_argument("--params", required=True, help="npz file to write (train) / read")
+    ap.add_argument("--report", default=None)
+    a = ap.parse_args(argv)
+
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
+
+    levels = tuple(int(x) for x in a.levels.split(","))
+    if a.cmd == "train":
+        t0 = time.perf_counter()
+        data = collect(range(a.n_train), a.N, a.nparts, a.rank, levels, log=log)
+        t1 = time.perf_counter()
+        mlp, hist = train(data, a.epochs, a.lr, seed=0, out_dim=a.rank, log=log)
+        t2 = time.perf_counter()
+        np.savez(a.params, params=mlp.get_params(), dims=np.array(mlp.dims),
+                 loss=np.array(hist), n_train=a.n_train, N=a.N, nparts=a.nparts,
+                 rank=a.rank, levels=np.array(levels))
+        rep = {"collect_s": t1 - t0, "train_s": t2 - t1, "loss_first": hist[0],
+               "loss_last": hist[-1], "pairs": len(data)}
+        log(f"[learned] trained: {rep}")
+    else:
+        z = np.load(a.params)
+        dims = tuple(int(x) for x in z["dims"])
+        mlp = gemslr.Mlp(*dims)
+        mlp.set_params(z["params"])
+        rows = evaluate(range(100000, 100000 + a.n_heldout), mlp, a.N, a.nparts, a.rank,
+                        levels=levels)
+        rep = {"summary": summarise(rows), "rows": rows}
+        log(f"[learned] summary: {json.dumps(rep['summary'])}")
+    if a.report:
+        with open(a.report, "w") as f:
+            json.dump(rep, f, indent=1, default=float)
+
+
+if __name__ == "__main__":
+    main()

@@ -41,6 +41,11 @@ def test_aliasing_and_bad_csr(G):
     with pytest.raises(G.GemslrError) as e:
         ctx.apply(x, x)
     assert e.value.code == G.GS_EINVAL
+    for wrong in (torch.ones(63, dtype=torch.float64, device="cuda"),
+                  torch.ones(64, dtype=torch.float32, device="cuda"),
+                  torch.ones(64, dtype=torch.float64)):
+        with pytest.raises(ValueError):   # extent / dtype / device checked in the binding
+            ctx.apply(wrong, torch.empty(64, dtype=torch.float64, device="cuda"))
     bad = c.copy()
     bad[0] = 63  # first row's columns no longer ascending
     with pytest.raises(G.GemslrError) as e:

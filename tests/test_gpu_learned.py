@@ -78,6 +78,26 @@ def test_mlp_matches_oracle(torch_dev):
     mlp.close()
 
 
+def test_mlp_loss_backward_as_first_call(torch_dev):
+    """Regression: a fresh network whose first call is loss_backward (no
+    forward before it) must size its buffers before using them."""
+    torch = torch_dev
+    from paper_2205_03224_amd import gemslr, learned
+    dims = (38, 64, 6)
+    params = learned.init_params(3, dims)
+    rs = np.random.default_rng(9)
+    X = rs.standard_normal((1141, 38)).astype(np.float32)
+    W, _ = np.linalg.qr(rs.standard_normal((1141, 7)))
+    W = W.astype(np.float32)
+    mlp = gemslr.Mlp(*dims)
+    mlp.set_params(gemslr.pack_params(params))
+    loss = mlp.loss_backward(torch.from_numpy(X).cuda(), torch.from_numpy(W).cuda())
+    P64 = [p.astype(np.float32).astype(np.float64) for p in params]
+    lo, _ = omlp.loss_and_grad(P64, X.astype(np.float64), W.astype(np.float64))
+    assert abs(loss - lo) <= 1e-5 * max(1.0, abs(lo))
+    mlp.close()
+
+
 def _small():
     return wl.lognormal_convdiff3d_64(3, N=20, nparts=8)
 
@@ -128,6 +148,7 @@ def test_block_setup_from_random_basis(torch_dev):
     ctx.close()
 
 
+@pytest.mark.slow
 def test_learned_gain_small_family(torch_dev):
     """Train on 24 members of the log-normal family (20^3, 8 parts, rank 6)
     and compare on 6 held-out members: the learned start needs fewer Ĝ
