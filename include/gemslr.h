@@ -70,6 +70,12 @@ typedef struct {
   int block_max_iters;    /* gs_lowrank: the block iteration from a starting
                              basis may use block_max_iters * k products of
                              G_l before falling back to Arnoldi          [8]  */
+  int inner_gmres_its;    /* steps of right-preconditioned GMRES on
+                             S_hat_0 = C_0 - E_0 U_0^{-1} L_0^{-1} F_0 inside
+                             every apply (Alg. 2, l = 0), preconditioned by
+                             the l > 0 branch; 0 = none, at most 16, float64
+                             and complex128 forms only.  Nonzero makes M^{-1}
+                             vary with its input (FGMRES handles that)   [0]  */
 } gs_opts;
 
 /* Fill *opts with the defaults shown in brackets above. */
@@ -181,7 +187,8 @@ int gs_setup_explicit(gs_ctx* ctx, int64_t n, const int64_t* rowptr,
 int gs_set_precision(gs_ctx* ctx, int precision);
 
 /* ---------------------------------------------------------------- apply */
-/* y = M^{-1} x (Alg. 2 with no inner iteration at level 0).  x, y: device,
+/* y = M^{-1} x (Alg. 2; opts.inner_gmres_its inner steps at level 0, none by
+ * default, in which case M^{-1} is a fixed linear operator).  x, y: device,
  * n values of the context's dtype, original (unpermuted) ordering; they must
  * not alias.  Asynchronous on the context's stream.
  * Errors: GS_ESTATE (no setup), GS_EINVAL (NULL or aliasing), GS_EDEVICE. */

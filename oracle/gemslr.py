@@ -12,8 +12,8 @@ of the levels below l (Sec. 4.2).  The last separator C_{L-1} is kept only
 on its diagonal blocks (block Jacobi) and factored the same way (Sec. 4.3);
 it is stored here as level L with no interface (s = 0).
 
-Apply (Alg. 2) with zero inner GMRES iterations at level 0 and a low-rank
-term at every level, the last one included:
+Apply (Alg. 2) with a low-rank term at every level, the last one included,
+and by default zero inner GMRES iterations at level 0:
     z1 = U_l^{-1} L_l^{-1} b1
     z2 = b2 - E_l z1
     u2 = W_l [(I - R_l)^{-1} - I] W_l^H z2
@@ -85,33 +85,85 @@ def trisolve(lv, b):
     return spsolve_triangular(lv.Uf, y, lower=False)
 
 
-def apply_level(st, l, b):
-    """M_l^{-1} b on the index range of level l (Alg. 2)."""
+def lowrank_then_lower(st, l, z2):
+    """The interface branch of Alg. 2 for l > 0: M_{l+1}^{-1} (z2 + u2) with
+    u2 = W_l [(I - R_l)^{-1} - I] W_l^H z2."""
+    lv = st.levels[l]
+    if lv.W is not None and lv.W.shape[1] > 0:
+        u2 = lv.W @ (lv.H @ (lv.W.conj().T @ z2))
+    else:
+        u2 = np.zeros_like(z2)
+    return apply_level(st, l + 1, u2 + z2)
+
+
+def schur_matvec(st, v):
+    """S_hat_0 v = C_0 v - E_0 U_0^{-1} L_0^{-1} F_0 v: the root-level Schur
+    complement with B_0^{-1} replaced by the ILU solve (Sec. 3, the operator
+    of the inner iteration of Alg. 2 at l = 0)."""
+    lv = st.levels[0]
+    C = st.Ap[lv.d:, lv.d:]
+    return C @ v - lv.E @ trisolve(lv, lv.F @ v)
+
+
+def inner_gmres(st, z2, its):
+    """`its` steps of right-preconditioned GMRES for S_hat_0 y = z2 from
+    y = 0 (Alg. 2, l = 0), preconditioned by the l > 0 branch of Alg. 2
+    applied at level 0, P v = M_1^{-1}(v + W_0 H_0 W_0^H v).
+
+    Written from the definition of GMRES (Saad and Schultz 1986): with K an
+    orthonormal basis of the Krylov space span{z2, (S P) z2, ...,
+    (S P)^{its-1} z2}, y = P K c where c minimises ||z2 - S P K c||_2.  The
+    basis stops early when the space becomes invariant."""
+    beta = np.linalg.norm(z2)
+    if beta == 0:
+        return np.zeros_like(z2)
+
+    def P(v):
+        return lowrank_then_lower(st, 0, v)
+
+    basis = [z2 / beta]
+    for _ in range(1, its):
+        w = schur_matvec(st, P(basis[-1]))
+        wn = np.linalg.norm(w)
+        K = np.column_stack(basis)
+        for _ in range(2):
+            w = w - K @ (K.conj().T @ w)
+        if np.linalg.norm(w) <= 1e-12 * wn:
+            break
+        basis.append(w / np.linalg.norm(w))
+    PK = np.column_stack([P(k) for k in basis])
+    SPK = np.column_stack([schur_matvec(st, PK[:, j]) for j in range(PK.shape[1])])
+    c = np.linalg.lstsq(SPK, z2, rcond=None)[0]
+    return PK @ c
+
+
+def apply_level(st, l, b, inner_its=0):
+    """M_l^{-1} b on the index range of level l (Alg. 2); inner_its > 0 runs
+    that many inner GMRES steps on S_hat_0 at the root level."""
     lv = st.levels[l]
     if l == st.nlevels:
         return trisolve(lv, b)
     b1, b2 = b[:lv.d], b[lv.d:]
     z1 = trisolve(lv, b1)
     z2 = b2 - lv.E @ z1
-    if lv.W is not None and lv.W.shape[1] > 0:
-        u2 = lv.W @ (lv.H @ (lv.W.conj().T @ z2))
+    if l == 0 and inner_its > 0:
+        y2 = inner_gmres(st, z2, inner_its)
     else:
-        u2 = np.zeros_like(z2)
-    y2 = apply_level(st, l + 1, u2 + z2)
+        y2 = lowrank_then_lower(st, l, z2)
     y1 = z1 - trisolve(lv, lv.F @ y2)
     return np.concatenate([y1, y2], axis=0)
 
 
-def apply(st, x):
+def apply(st, x, inner_its=0):
     """y = M^{-1} x in the original ordering."""
-    q = apply_level(st, 0, x[st.perm])
+    q = apply_level(st, 0, x[st.perm], inner_its)
     y = np.empty_like(q)
     y[st.perm] = q
     return y
 
 
-def apply_permuted(st, xp):
-    return apply_level(st, 0, xp)
+def apply_permuted(st, xp, inner_its=0):
+    return apply_level(st, 0, xp, inner_its)
 
 
 def ghat_matvec(st, l, v):

@@ -756,6 +756,7 @@ static void setup_native(gs_ctx* c, int64_t n, const int64_t* rp, const int32_t*
   if (std::is_same<T, double>::value) c->hd.reset((HostSetup<double>*)S.release());
   else c->hz.reset((HostSetup<cplx>*)S.release());
   c->eng = make_engine(host<T>(c), c->precision, c->stream);
+  c->eng->set_inner(c->opts.inner_gmres_its);
   double t3 = now_s();
   HostSetup<T>& H = host<T>(c);
   if (!c->opts.defer_lowrank) {
@@ -835,6 +836,7 @@ static void setup_explicit(gs_ctx* c, int64_t n, const int64_t* rp, const int32_
   if (std::is_same<T, double>::value) c->hd.reset((HostSetup<double>*)S.release());
   else c->hz.reset((HostSetup<cplx>*)S.release());
   c->eng = make_engine(host<T>(c), c->precision, c->stream);
+  c->eng->set_inner(c->opts.inner_gmres_its);
   c->info = gs_info{};
   finish_setup<T>(c);
 }
@@ -1060,6 +1062,7 @@ void gs_opts_default(gs_opts* o) {
   o->nthreads = 0;
   o->defer_lowrank = 0;
   o->block_max_iters = 8;
+  o->inner_gmres_its = 0;
 }
 
 int gs_create(gs_ctx** ctx, int device, void* stream) {
@@ -1163,9 +1166,11 @@ int gs_set_precision(gs_ctx* c, int precision) {
     if (r) return r;
     if (!c->ready) throw Error(GS_ESTATE, "no setup");
     if (precision == c->precision) return GS_OK;
-    c->eng.reset();
-    if (c->dtype == GS_F64) c->eng = make_engine(*c->hd, precision, c->stream);
-    else c->eng = make_engine(*c->hz, precision, c->stream);
+    // build the new engine first: on error the current one stays in place
+    std::unique_ptr<Engine> e = c->dtype == GS_F64 ? make_engine(*c->hd, precision, c->stream)
+                                                   : make_engine(*c->hz, precision, c->stream);
+    e->set_inner(c->opts.inner_gmres_its);
+    c->eng = std::move(e);
     c->precision = precision;
     c->eng->stats(&c->info, 0);
     c->info.apply_bytes = c->eng->bytes_per_apply();

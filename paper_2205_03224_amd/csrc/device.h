@@ -190,5 +190,11 @@ template <class T> void launch_sub(const T* a, const T* b, T* out, int64_t n, hi
 template <class T> void launch_permute(const T* x, const int32_t* perm, T* y, int64_t n,
                                        bool scatter, hipStream_t st);
 template <class T> void launch_copy(const T* x, T* y, int64_t n, hipStream_t st);
+// inner GMRES at the root level: c (m) minimising ||beta e1 - Hbar c|| for
+// the Arnoldi columns h ((m+1) x m, column-major), subdiagonal norms sub and
+// pre-orthogonalisation norms wn (m+1 each, entry 0 unused)
+constexpr int kInnerMax = 16;
+template <class T> void launch_inner_lsq(const T* h, const double* sub, const double* wn,
+                                         const double* beta, int m, T* c, hipStream_t st);
 
 }  // namespace gs

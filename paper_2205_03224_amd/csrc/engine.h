@@ -57,6 +57,9 @@ struct Engine {
   // max_launches); probe_read synchronises and returns count, ms and bytes.
   virtual void probe_enable(int kind, int max_launches) = 0;
   virtual void probe_read(int64_t* launches, double* ms, double* bytes) = 0;
+  // m > 0: m inner GMRES steps on S_hat_0 at the root level of every apply
+  // (float64 / complex128 forms only); 0 switches them off
+  virtual void set_inner(int m) = 0;
 };
 
 // kernel classes for the measurement probe

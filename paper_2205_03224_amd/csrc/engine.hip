@@ -12,6 +12,7 @@
 #include <functional>
 #include <memory>
 #include <string>
+#include <type_traits>
 
 #include "device.h"
 #include "engine.h"
@@ -183,6 +184,8 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap,
         const size_t o_info = o_dinv + (isU ? pad(rows * sizeof(D)) : 0);
         const size_t o_col = o_info + pad(rows * 4);
         const size_t total = o_col + pad(ents * 2);
+        // the device copies whole 1 KiB rows of the chunk buffer
+        if (total > (size_t)cap || cap % 1024 != 0) return false;
         cd.n16 = (uint16_t)(total / 16);
         cd.nst = (uint16_t)((s2 - s) | (isU ? 0x8000 : 0));
         cd.nrows = (uint16_t)rows;
@@ -337,7 +340,8 @@ struct EngineT final : Engine {
       {
         // streamed layout: block vector and two chunk buffers in LDS, sized so
         // that two workgroups share one CU
-        const int xb = (int)((L.max_block_rows * sizeof(C) + 15) & ~(size_t)15);
+        // (one slot more than the largest block: idle lanes store there)
+        const int xb = (int)(((L.max_block_rows + 1) * sizeof(C) + 15) & ~(size_t)15);
         int cap = std::min(kChunkCapMax, ((lds_budget - xb - 1024) / 2) & ~1023);
         if (L.nb > 0 && L.maxslot <= 16 && cap >= 4096) {
           std::vector<uint8_t> blob;
@@ -371,6 +375,121 @@ struct EngineT final : Engine {
       if (h.k > 0) set_lowrank_host((int)l, h.k, h.W, h.H);
     }
     xg = mem.alloc<C>(maxd);
+    // C_0 (the interface block of P^T A P) for the inner iteration's S_hat_0
+    if constexpr (kInnerCapable) {
+      if (lv.size() >= 2 && lv[0].s > 0) {
+        const int64_t d0 = lv[0].d, s0 = lv[0].s;
+        std::vector<int32_t> rp(1, 0), ci;
+        std::vector<X> va;
+        for (int64_t i = d0; i < n; ++i) {
+          for (int64_t p = S.Ap.rp[i]; p < S.Ap.rp[i + 1]; ++p)
+            if (S.Ap.ci[p] >= d0) {
+              ci.push_back((int32_t)(S.Ap.ci[p] - d0));
+              va.push_back(to_store<X, T>(S.Ap.v[p]));
+            }
+          rp.push_back((int32_t)ci.size());
+        }
+        (void)s0;
+        c0_rp = upload(rp);
+        c0_ci = upload(ci);
+        c0_v = upload(va);
+        c0_nnz = (int64_t)ci.size();
+      }
+    }
+  }
+
+  // ---- inner GMRES on S_hat_0 = C_0 - E_0 U_0^{-1} L_0^{-1} F_0 at the root
+  // level (Alg. 2, l = 0), right-preconditioned by the l > 0 branch
+  static constexpr bool kInnerCapable =
+      std::is_same<X, double>::value || std::is_same<X, dcplx>::value;
+  int inner_m = 0;
+  std::unique_ptr<DevMem> imem;
+  int32_t* c0_rp = nullptr;
+  int32_t* c0_ci = nullptr;
+  X* c0_v = nullptr;
+  int64_t c0_nnz = 0;
+  X *iV = nullptr, *iZ = nullptr, *iz1 = nullptr, *iw = nullptr, *ih = nullptr, *ipart = nullptr,
+    *ihd = nullptr, *ic = nullptr;
+  double *isub = nullptr, *iwn = nullptr, *inpart = nullptr, *ibeta = nullptr;
+
+  void set_inner(int m) override {
+    if (m <= 0 || lv.size() < 2 || lv[0].s == 0) {
+      inner_m = 0;
+      return;
+    }
+    if constexpr (!kInnerCapable) {
+      throw Error(GS_EINVAL, "inner GMRES runs in the float64 / complex128 forms only");
+    } else {
+      if (m > kInnerMax) throw Error(GS_EINVAL, "inner GMRES: at most 16 steps");
+      const int64_t d = lv[0].d, s = lv[0].s;
+      imem = std::make_unique<DevMem>();
+      iV = imem->alloc<X>((size_t)s * (m + 1));
+      iZ = imem->alloc<X>((size_t)s * m);
+      iz1 = imem->alloc<X>(std::max<int64_t>(d, 1));
+      iw = imem->alloc<X>(s);
+      ih = imem->alloc<X>((size_t)(m + 1) * m);
+      ipart = imem->alloc<X>((size_t)256 * (m + 1));
+      ihd = imem->alloc<X>(m + 1);
+      ic = imem->alloc<X>(m);
+      isub = imem->alloc<double>(m + 1);
+      iwn = imem->alloc<double>(m + 1);
+      inpart = imem->alloc<double>(256);
+      ibeta = imem->alloc<double>(1);
+      inner_m = m;
+    }
+  }
+
+  // Root level with inner iterations: z1, z2 as usual, then m Arnoldi steps
+  // on S_hat_0 P from v_0 = z2 / ||z2|| with P v = M_1^{-1}(v + W_0 H_0 W_0^H v)
+  // and Z_j = P v_j kept, the small least-squares problem on the device,
+  // y2 = Z c, and y1 = z1 - U^{-1} L^{-1} F y2.  Runs on the stream with no
+  // host synchronisation.
+  void inner_root() {
+    if constexpr (kInnerCapable) {
+      Lev& L = lv[0];
+      const int64_t d = L.d, s = L.s;
+      const int m = inner_m;
+      X* tc = t + d;
+      const X zx = zero_x();
+      if (L.nb > 0)
+        step("trisolve_down L0", KIND_TRI0, tri_bytes(0, TRI_DOWN), [&] { trisolve(0, TRI_DOWN); });
+      interface(0, 0);
+      launch_copy<X>(t, iz1, d, st);
+      launch_norm<X>(tc, s, inpart, ibeta, st);
+      launch_scale_inv<X>(tc, ibeta, iV, s, st);
+      for (int j = 0; j < m; ++j) {
+        X* vj = iV + (size_t)j * s;
+        X* zj = iZ + (size_t)j * s;
+        // z_j = P v_j
+        launch_copy<X>(vj, tc, s, st);
+        launch_fill<X>(t, zx, d, st);
+        interface(0, L.k);
+        run_from(1);
+        launch_copy<X>(tc, zj, s, st);
+        // w = C_0 z_j - E_0 U^{-1} L^{-1} F_0 z_j
+        launch_fill<X>(t, zx, d, st);
+        up(0);
+        launch_spmv<X>(c0_rp, c0_ci, c0_v, zj, iw, s, st);
+        launch_fill<X>(tc, zx, s, st);
+        interface(0, 0);
+        launch_sub<X>(iw, tc, iw, s, st);
+        // Arnoldi step: two Gram-Schmidt passes, column j of Hbar
+        launch_norm<X>(iw, s, inpart, iwn + j + 1, st);
+        X* hj = ih + (size_t)j * (m + 1);
+        launch_fill<X>(hj, zx, j + 1, st);
+        for (int pass = 0; pass < 2; ++pass) {
+          launch_multidot<X>(iV, s, j + 1, iw, s, ipart, ihd, st);
+          launch_gemv_sub<X>(iV, s, j + 1, ihd, iw, s, hj, st);
+        }
+        launch_norm<X>(iw, s, inpart, isub + j + 1, st);
+        launch_scale_inv<X>(iw, isub + j + 1, iV + (size_t)(j + 1) * s, s, st);
+      }
+      launch_inner_lsq<X>(ih, isub, iwn, ibeta, m, ic, st);
+      launch_fill<X>(tc, zx, s, st);
+      launch_gemv_add<X>(iZ, s, m, ic, tc, s, st);
+      launch_copy<X>(iz1, t, d, st);
+      up(0);
+    }
   }
 
   void set_lowrank_host(int l, int k, const std::vector<T>& W, const std::vector<T>& H) {
@@ -527,7 +646,8 @@ struct EngineT final : Engine {
   void apply(const void* x, void* y, bool permuted) override {
     step("gather", KIND_PERM, perm_bytes(n),
          [&] { launch_gather<P>((const O*)x, permuted ? nullptr : perm_d, t, n, st); });
-    run_from(0);
+    if (inner_m > 0) inner_root();
+    else run_from(0);
     step("scatter", KIND_PERM, perm_bytes(n),
          [&] { launch_scatter<P>(t, permuted ? nullptr : perm_d, (O*)y, n, st); });
   }
@@ -612,8 +732,27 @@ struct EngineT final : Engine {
   // Compulsory HBM traffic of one whole apply: the sum over its launches.
   double bytes_per_apply() const override {
     double b = 2 * perm_bytes(n);
+    if (inner_m > 0) {
+      // root level with inner steps: down + interface, per step one product
+      // with P (interface with W, levels >= 1) and one with S_hat_0 (up,
+      // interface, C_0) plus the Arnoldi vectors, then the final up
+      const Lev& R = lv[0];
+      const double xb = sizeof(X);
+      const double lower = apply_bytes_from(1);
+      double step_b = if_bytes(0, R.k) + upd_bytes(0, R.k) + lower + tri_bytes(0, TRI_UP) +
+                      if_bytes(0, 0) + (double)c0_nnz * (xb + 4) + (double)(R.s + 1) * 4;
+      b += tri_bytes(0, TRI_DOWN) + if_bytes(0, 0) + tri_bytes(0, TRI_UP);
+      for (int j = 0; j < inner_m; ++j) b += step_b + (double)R.s * xb * (2.0 * (j + 1) * 2 + 8);
+      b += (double)R.s * xb * (inner_m + 2);
+      return b;
+    }
+    return b + apply_bytes_from(0);
+  }
+  // bytes of run_from(l0)
+  double apply_bytes_from(int l0) const {
+    double b = 0;
     const int L = (int)lv.size() - 1;
-    for (int l = 0; l <= L; ++l) {
+    for (int l = l0; l <= L; ++l) {
       if (lv[l].nb > 0) b += tri_bytes(l, TRI_DOWN);
       if (l < L) {
         b += if_bytes(l, lv[l].k);

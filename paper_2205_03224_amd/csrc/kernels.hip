@@ -29,6 +29,12 @@ __device__ inline dcplx shfl_xor(dcplx v, int m) {
   return mk(__shfl_xor(v.x, m, kWave), __shfl_xor(v.y, m, kWave));
 }
 
+// c ? a : b, component-wise for complex values (a select of the struct as
+// a whole is lowered through scratch memory)
+__device__ inline double sel(bool c, double a, double b) { return c ? a : b; }
+__device__ inline float sel(bool c, float a, float b) { return c ? a : b; }
+__device__ inline dcplx sel(bool c, dcplx a, dcplx b) { return mk(c ? a.x : b.x, c ? a.y : b.y); }
+
 // Sum over the 64 lanes of a wavefront (butterfly; every lane gets the sum).
 template <class T> __device__ inline T wave_sum(T v) {
 #pragma unroll
@@ -84,7 +90,7 @@ __device__ __forceinline__ void stage_load(const TriDev<P>& tri, int s, int lane
       e += __popcll(m);
     }
   }
-  if (ISU) r.dinv = act ? cvt<C>(tri.dinv[r0 + lane]) : zero<C>();
+  if (ISU) r.dinv = sel(act, cvt<C>(tri.dinv[r0 + lane]), zero<C>());
 }
 
 template <class P, int MS, bool ISU>
@@ -104,7 +110,7 @@ __device__ __forceinline__ void stage_compute(const StageRegs<P, MS>& r,
   for (int j = 0; j < MS; ++j) {
     if (j < maxnz) {
       const C t = r.v[j] * xv[j];
-      acc = nz > j ? acc - t : acc;
+      acc = sel(nz > j, acc - t, acc);
     }
   }
   if (ISU) acc *= r.dinv;
@@ -125,7 +131,7 @@ __device__ void sweep_generic(const TriDev<P>& tri, int s0, int s1, int lane,
     const uint32_t info = act ? tri.rowinfo[r0 + lane] : 0u;
     const int nz = (int)(info >> 16);
     const int maxnz = __builtin_amdgcn_readfirstlane(nz);
-    C acc = act ? x[info & 0xffffu] : zero<C>();
+    C acc = sel(act, x[info & 0xffffu], zero<C>());
     for (int j = 0; j < maxnz; ++j) {
       const unsigned long long m = __ballot(nz > j);
       if (nz > j) acc -= cvt<C>(tri.val[e + lane]) * x[tri.col[e + lane]];
@@ -228,39 +234,92 @@ void launch_trisolve(const TriArgs<P>& a, int mode, int maxslot, int max_block_r
 // LDS only.  One workgroup barrier per chunk hands the buffers over.  HBM
 // latency is paid once per chunk instead of once per wavefront level.
 // ======================================================================
-constexpr int kNV = kChunkCapMax / (16 * 64);  // 16-byte loads per lane per chunk
 
 template <class P>
 __device__ __forceinline__ void copy_chunk(const TriArgs<P>& a, int c, uint8_t* dst, int lane) {
+  // Direct HBM -> LDS copies (global_load_lds, 16 bytes per lane): iteration
+  // i fills dst[1 KiB i, 1 KiB (i+1)), lane l its 16 bytes at 16 l.  The
+  // loads carry no register data and no wait, so the whole chunk is in flight
+  // at once; the barrier that follows waits for them.  Lanes past the end
+  // re-read the last 16 bytes and land behind the chunk, inside the buffer
+  // (iterations * 1 KiB <= chunk_cap, a multiple of 1 KiB).
   const ChunkDesc cd = a.chunk[c];
   const uint4* src = reinterpret_cast<const uint4*>(a.blob + cd.off);
-  uint4* d = reinterpret_cast<uint4*>(dst);
   const int nv = cd.n16;
   const int last = nv - 1;
-  // every element is loaded (lanes past the end re-read the chunk's last 16
-  // bytes), so the staging array is fully defined and stays in registers;
-  // all loads are in flight before the first LDS store
-  uint4 tmp[kNV];
-#pragma unroll
-  for (int i = 0; i < kNV; ++i) tmp[i] = src[min(lane + kWave * i, last)];
-#pragma unroll
-  for (int i = 0; i < kNV; ++i) {
-    const int idx = lane + kWave * i;
-    if (idx < nv) d[idx] = tmp[i];
-  }
+  const int iters = (nv + kWave - 1) / kWave;
+  for (int i = 0; i < iters; ++i)
+    __builtin_amdgcn_global_load_lds(src + min(lane + kWave * i, last),
+                                     (__attribute__((address_space(3))) void*)(dst + 1024 * i),
+                                     16, 0, 0);
 }
 
-// Sweep the stages of one chunk held in LDS.  The stage body is straight-
-// line code: every lane issues all MS slot reads and gathers (slots beyond a
-// row's count read in-bounds filler -- past the end of a section at most 63
-// elements, inside the chunk or the LDS slack -- and are discarded by a
-// select), so the compiler keeps all gathers of a stage in flight together
-// instead of waiting at every branch join.  The next stage's row info and
-// entries are fetched while the current stage accumulates.
+// One stage of a chunk in registers: the entries of each lane's row
+// (slot-major), their block-local columns, 1/u_ii, the target row.
+template <class P, int MS>
+struct SweepRegs {
+  typename P::C v[MS];
+  int c[MS];
+  typename P::C dv;
+  int row;  // the lane's row, or the block's dummy slot for idle lanes
+  int nz;   // entries of the lane's row (0 for idle lanes)
+  int nr;   // rows of the stage (uniform; 0 past the chunk's last stage)
+};
+
+// Fill R from the stage's row info (0 past the last stage) starting at row
+// r0 and entry e (advanced past the stage).  Every read is issued by every
+// lane: reads past the end of a section stay within 63 elements, inside the
+// chunk or the LDS slack, and their values are dropped by selects.
+template <class P, int MS, bool ISU>
+__device__ __forceinline__ void sweep_load(const typename P::V* val, const typename P::D* dinv,
+                                           const uint16_t* col, uint32_t info, int r0, int& e,
+                                           int lane, int dummy, SweepRegs<P, MS>& R) {
+  using C = typename P::C;
+  R.nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
+  const bool act = lane < R.nr;
+  R.nz = act ? (int)((info >> 16) & 0xffu) : 0;
+  R.row = act ? (int)(info & 0xffffu) : dummy;
+#pragma unroll
+  for (int j = 0; j < MS; ++j) {
+    const unsigned long long m = __ballot(R.nz > j);
+    R.v[j] = cvt<C>(val[e + lane]);
+    const int cj = (int)col[e + lane];
+    R.c[j] = R.nz > j ? cj : 0;
+    e += __popcll(m);
+  }
+  if (ISU) R.dv = cvt<C>(dinv[r0 + lane]);
+}
+
+// x[row] = (x[row] - sum_j v_j x[c_j]) (* 1/u_ii): all gathers first, two
+// partial sums; idle lanes write the dummy slot.
+template <class P, int MS, bool ISU>
+__device__ __forceinline__ void sweep_compute(const SweepRegs<P, MS>& R, typename P::C* x) {
+  using C = typename P::C;
+  C xv[MS];
+#pragma unroll
+  for (int j = 0; j < MS; ++j) xv[j] = x[R.c[j]];
+  const C b = x[R.row];
+  C s0 = zero<C>(), s1 = zero<C>();
+#pragma unroll
+  for (int j = 0; j < MS; j += 2) {
+    s0 = sel(R.nz > j, s0 + R.v[j] * xv[j], s0);
+    if (j + 1 < MS) s1 = sel(R.nz > j + 1, s1 + R.v[j + 1] * xv[j + 1], s1);
+  }
+  C acc = b - (s0 + s1);
+  if (ISU) acc *= R.dv;
+  x[R.row] = acc;
+}
+
+// Sweep the stages of one chunk held in LDS, two stages per trip with two
+// register sets and no register copies.  Straight-line code (no branch
+// around an LDS access), so the compiler's waits are exact: the row info of
+// stage s+1 is read one stage ahead, the entries of stage s+1 are fetched
+// before the gathers of stage s, and a stage waits only for its own gathers.
+// LDS executes one wavefront's accesses in order, so a gather issued after
+// the previous stage's store sees the stored value.
 template <class P, int MS, bool ISU>
 __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& cd, int lane,
-                                            typename P::C* x) {
-  using C = typename P::C;
+                                            typename P::C* x, int dummy) {
   using V = typename P::V;
   using D = typename P::D;
   const V* val = reinterpret_cast<const V*>(cb);
@@ -268,64 +327,25 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
   const uint32_t* rinfo = reinterpret_cast<const uint32_t*>(cb + 16 * (int)cd.info16);
   const uint16_t* col = reinterpret_cast<const uint16_t*>(cb + 16 * (int)cd.col16);
   const int nst = cd.nst & 0x7fff;
-  int r0 = 0, e = 0;
-  uint32_t info = rinfo[lane];
-  int nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
-  bool act = lane < nr;
-  int nz = act ? (int)((info >> 16) & 0xffu) : 0;
-  C v[MS];
-  int c[MS];
-#pragma unroll
-  for (int j = 0; j < MS; ++j) {
-    const unsigned long long m = __ballot(nz > j);
-    v[j] = cvt<C>(val[e + lane]);
-    c[j] = nz > j ? (int)col[e + lane] : 0;
-    e += __popcll(m);
-  }
-  for (int s = 0; s < nst; ++s) {
-    // gathers of stage s, its own rhs and 1/u_ii, and the next stage's row info
-    C xv[MS];
-#pragma unroll
-    for (int j = 0; j < MS; ++j) xv[j] = x[c[j]];
-    const int row = act ? (int)(info & 0xffffu) : 0;
-    C acc = x[row];
-    C dv = zero<C>();
-    if (ISU) dv = cvt<C>(dinv[act ? r0 + lane : 0]);
-    const int r0n = r0 + nr;
-    const bool more = s + 1 < nst;
-    const uint32_t infon = more ? rinfo[r0n + lane] : 0u;
-    // entries of stage s+1 (independent of x)
-    const int nrn = (int)__builtin_amdgcn_readfirstlane(infon >> 24);
-    const bool actn = lane < nrn;
-    const int nzn = actn ? (int)((infon >> 16) & 0xffu) : 0;
-    C vn[MS];
-    int cn[MS];
-#pragma unroll
-    for (int j = 0; j < MS; ++j) {
-      const unsigned long long m = __ballot(nzn > j);
-      vn[j] = cvt<C>(val[e + lane]);
-      cn[j] = nzn > j ? (int)col[e + lane] : 0;
-      e += __popcll(m);
-    }
-    // accumulate stage s (slots past the row's count are dropped)
-#pragma unroll
-    for (int j = 0; j < MS; ++j) {
-      const C t = v[j] * xv[j];
-      acc = nz > j ? acc - t : acc;
-    }
-    if (ISU) acc *= dv;
-    if (act) x[row] = acc;
-    // advance
-    r0 = r0n;
-    info = infon;
-    nr = nrn;
-    act = actn;
-    nz = nzn;
-#pragma unroll
-    for (int j = 0; j < MS; ++j) {
-      v[j] = vn[j];
-      c[j] = cn[j];
-    }
+  SweepRegs<P, MS> A, B;
+  int e = 0;
+  sweep_load<P, MS, ISU>(val, dinv, col, rinfo[lane], 0, e, lane, dummy, A);
+  int r1 = A.nr;
+  uint32_t i1 = rinfo[r1 + lane];
+  i1 = nst > 1 ? i1 : 0u;
+  for (int s = 0; s < nst; s += 2) {
+    sweep_load<P, MS, ISU>(val, dinv, col, i1, r1, e, lane, dummy, B);  // stage s+1
+    const int r2 = r1 + B.nr;
+    uint32_t i2 = rinfo[r2 + lane];
+    i2 = s + 2 < nst ? i2 : 0u;
+    sweep_compute<P, MS, ISU>(A, x);                                     // stage s
+    sweep_load<P, MS, ISU>(val, dinv, col, i2, r2, e, lane, dummy, A);  // stage s+2
+    const int r3 = r2 + A.nr;
+    uint32_t i3 = rinfo[r3 + lane];
+    i3 = s + 3 < nst ? i3 : 0u;
+    sweep_compute<P, MS, ISU>(B, x);                                     // stage s+1
+    r1 = r3;
+    i1 = i3;
   }
 }
 
@@ -423,8 +443,8 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
       if (c + 1 < c1) copy_chunk<P>(a, c + 1, nxt, lane);
     } else {
       const ChunkDesc cd = a.chunk[c];
-      if (cd.nst & 0x8000) chunk_sweep<P, MS, true>(cur, cd, lane, x);
-      else chunk_sweep<P, MS, false>(cur, cd, lane, x);
+      if (cd.nst & 0x8000) chunk_sweep<P, MS, true>(cur, cd, lane, x, nr);
+      else chunk_sweep<P, MS, false>(cur, cd, lane, x, nr);
     }
     __syncthreads();
   }
@@ -894,6 +914,82 @@ void launch_sub(const T* a, const T* b, T* out, int64_t n, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- instances
+// ======================================================================
+// Small least-squares problem of the inner GMRES at the root level: with
+// the Arnoldi relation S Z_m = V_{m+1} Hbar_m, c minimises
+// ||beta e_1 - Hbar_m c||.  Hbar's column j holds h[j (m+1) + i], i <= j,
+// and the real subdiagonal sub[j+1]; a step whose new direction vanished
+// (sub[j+1] <= 1e-12 wn[j+1], wn = norm before orthogonalisation) ends the
+// space there and later coefficients are zero.  Plane rotations with a real
+// cosine reduce Hbar to triangular form; one thread, m <= kInnerMax.
+// ======================================================================
+__device__ inline double absv(double a) { return fabs(a); }
+__device__ inline double absv(dcplx a) { return sqrt(norm2(a)); }
+__device__ inline double scal(double a, double s) { return a * s; }
+__device__ inline dcplx scal(dcplx a, double s) { return a * s; }
+__device__ inline double divv(double a, double b) { return a / b; }
+__device__ inline dcplx divv(dcplx a, dcplx b) { return scal(a * conj(b), 1.0 / norm2(b)); }
+template <class T> __device__ inline T from_real(double a);
+template <> __device__ inline double from_real<double>(double a) { return a; }
+template <> __device__ inline dcplx from_real<dcplx>(double a) { return mk(a, 0.0); }
+
+template <class T>
+__global__ void k_inner_lsq(const T* h, const double* sub, const double* wn, const double* beta,
+                            int m, T* c) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  T R[kInnerMax * kInnerMax];
+  T g[kInnerMax + 1];
+  double cs[kInnerMax];
+  T sn[kInnerMax];
+  for (int j = 0; j < m; ++j) c[j] = from_real<T>(0.0);
+  if (!(beta[0] > 0)) return;
+  int me = m;
+  for (int j = 0; j < m; ++j)
+    if (!(sub[j + 1] > 1e-12 * wn[j + 1])) { me = j + 1; break; }
+  for (int i = 0; i <= m; ++i) g[i] = from_real<T>(0.0);
+  g[0] = from_real<T>(beta[0]);
+  for (int j = 0; j < me; ++j) {
+    T col[kInnerMax + 1];
+    for (int i = 0; i <= j; ++i) col[i] = h[(size_t)j * (m + 1) + i];
+    col[j + 1] = from_real<T>(sub[j + 1]);
+    for (int i = 0; i < j; ++i) {
+      const T x = col[i], y = col[i + 1];
+      col[i] = scal(x, cs[i]) + sn[i] * y;
+      col[i + 1] = scal(y, cs[i]) - conj(sn[i]) * x;
+    }
+    const double aa = absv(col[j]), bb = sub[j + 1];
+    const double r = sqrt(aa * aa + bb * bb);
+    if (r == 0) {
+      cs[j] = 1.0;
+      sn[j] = from_real<T>(0.0);
+    } else if (aa == 0) {
+      cs[j] = 0.0;
+      sn[j] = from_real<T>(1.0);
+    } else {
+      cs[j] = aa / r;
+      sn[j] = scal(col[j], bb / (aa * r));  // (a/|a|) conj(b) / r with b real
+    }
+    const T x = col[j];
+    col[j] = scal(x, cs[j]) + scal(sn[j], bb);
+    for (int i = 0; i <= j; ++i) R[j * kInnerMax + i] = col[i];
+    const T gx = g[j], gy = g[j + 1];
+    g[j] = scal(gx, cs[j]) + sn[j] * gy;
+    g[j + 1] = scal(gy, cs[j]) - conj(sn[j]) * gx;
+  }
+  for (int j = me - 1; j >= 0; --j) {
+    T acc = g[j];
+    for (int i = j + 1; i < me; ++i) acc -= R[i * kInnerMax + j] * c[i];
+    const T d = R[j * kInnerMax + j];
+    c[j] = absv(d) > 0 ? divv(acc, d) : from_real<T>(0.0);
+  }
+}
+
+template <class T>
+void launch_inner_lsq(const T* h, const double* sub, const double* wn, const double* beta, int m,
+                      T* c, hipStream_t st) {
+  hipLaunchKernelGGL(k_inner_lsq<T>, dim3(1), dim3(64), 0, st, h, sub, wn, beta, m, c);
+}
+
 #define GS_PREC_INSTANCES(P)                                                                   \
   template void launch_trisolve<P>(const TriArgs<P>&, int, int, int, hipStream_t);             \
   template void launch_trisolve_streamed<P>(const TriArgs<P>&, int, int, int, hipStream_t);    \
@@ -928,7 +1024,9 @@ GS_PREC_INSTANCES(PBF16)
   template void launch_permute<T>(const T*, const int32_t*, T*, int64_t, bool, hipStream_t);   \
   template void launch_rows_to_cols<T>(const float*, int64_t, int, int, T*, int64_t,         \
                                        hipStream_t);                                          \
-  template void launch_sub<T>(const T*, const T*, T*, int64_t, hipStream_t);
+  template void launch_sub<T>(const T*, const T*, T*, int64_t, hipStream_t);                  \
+  template void launch_inner_lsq<T>(const T*, const double*, const double*, const double*, int, \
+                                    T*, hipStream_t);
 GS_VEC_INSTANCES(double)
 GS_VEC_INSTANCES(dcplx)
 template void launch_fill<float>(float*, float, int64_t, hipStream_t);

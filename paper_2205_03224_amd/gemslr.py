@@ -38,7 +38,8 @@ class GsOpts(ct.Structure):
                 ("lowrank_last_level", ct.c_int), ("precision", ct.c_int),
                 ("grid_ndim", ct.c_int), ("grid_dims", ct.c_int32 * 3),
                 ("seed", ct.c_uint64), ("nthreads", ct.c_int),
-                ("defer_lowrank", ct.c_int), ("block_max_iters", ct.c_int)]
+                ("defer_lowrank", ct.c_int), ("block_max_iters", ct.c_int),
+                ("inner_gmres_its", ct.c_int)]
 
 
 _L1 = GS_MAX_LEVELS + 1
@@ -183,8 +184,10 @@ def opts(**kw):
             o.precision = PRECISIONS.get(v, v)
         elif k in ("ilu", "ilu_kind"):
             o.ilu_kind = ILU_KINDS.get(v, v)
-        else:
+        elif k in dict(GsOpts._fields_):
             setattr(o, k, v)
+        else:
+            raise TypeError(f"unknown option {k!r}")
     return o
 
 

@@ -390,6 +390,75 @@ def test_lowrank_terms_properties_krylov():
     assert np.all(res <= 1e-2 * np.abs(ev) + 1e-12)
 
 
+# ---------------------------------------------------------------- inner GMRES (level 0)
+
+def _inner_case(rank, exact=False):
+    r, c, v = wl.convdiff3d(7, (.3, .2, .1))
+    part = partition.wirebasket((7,) * 3, 8, 3, r, c)
+    kw = FULL if exact else dict(ilu="ilut", drop_tol=1e-2, lfil=3, rank=rank)
+    return gemslr.setup(r, c, v, part, **kw), r, c, v, part
+
+
+def _dense_schur_hat(st):
+    """C_0 - E_0 U^{-1} L^{-1} F_0 from dense copies of the factors."""
+    lv = st.levels[0]
+    Ld = lv.Lf.toarray() + np.eye(lv.d)
+    Ud = lv.Uf.toarray()
+    X = sla.solve_triangular(Ud, sla.solve_triangular(Ld, lv.F.toarray(), lower=True,
+                                                      unit_diagonal=True))
+    C = st.Ap.toarray()[lv.d:, lv.d:]
+    return C - lv.E.toarray() @ X
+
+
+def test_schur_hat_with_exact_factors_is_schur_complement():
+    st, r, c, v, part = _inner_case(0, exact=True)
+    A = sp.csr_matrix((v, c, r)).toarray()[np.ix_(part.perm, part.perm)]
+    d = st.levels[0].d
+    S = A[d:, d:] - A[d:, :d] @ np.linalg.solve(A[:d, :d], A[:d, d:])
+    x = np.random.default_rng(1).standard_normal(S.shape[0])
+    np.testing.assert_allclose(gemslr.schur_matvec(st, x), S @ x, rtol=1e-11, atol=1e-11)
+
+
+def test_inner_gmres_one_step_closed_form():
+    st, *_ = _inner_case(4)
+    s = st.levels[0].s
+    z = np.random.default_rng(2).standard_normal(s)
+    pz = gemslr.lowrank_then_lower(st, 0, z)
+    spz = _dense_schur_hat(st) @ pz
+    alpha = (spz @ z) / (spz @ spz)
+    np.testing.assert_allclose(gemslr.inner_gmres(st, z, 1), alpha * pz, rtol=1e-11)
+
+
+def test_inner_gmres_full_space_solves_schur_hat():
+    st, *_ = _inner_case(4)
+    s = st.levels[0].s
+    z = np.random.default_rng(3).standard_normal(s)
+    Sh = _dense_schur_hat(st)
+    y = gemslr.inner_gmres(st, z, s)
+    np.testing.assert_allclose(y, np.linalg.solve(Sh, z), rtol=1e-8, atol=1e-10)
+
+
+def test_inner_gmres_residual_does_not_grow():
+    st, *_ = _inner_case(2)
+    s = st.levels[0].s
+    z = np.random.default_rng(4).standard_normal(s)
+    Sh = _dense_schur_hat(st)
+    res = [np.linalg.norm(z - Sh @ gemslr.inner_gmres(st, z, m)) for m in range(1, 6)]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(res, res[1:]))
+    assert res[-1] < res[0]
+
+
+def test_inner_gmres_exact_case_is_exact_inverse():
+    # exact factors and full rank: the preconditioner of the inner iteration is
+    # S^{-1} itself, one step is exact and the space is then invariant
+    st, r, c, v, part = _inner_case(0, exact=True)
+    A = sp.csr_matrix((v, c, r)).toarray()
+    x = np.random.default_rng(5).standard_normal(A.shape[0])
+    for its in (1, 3):
+        y = gemslr.apply(st, x, inner_its=its)
+        np.testing.assert_allclose(y, np.linalg.solve(A, x), rtol=1e-10, atol=1e-12)
+
+
 # ---------------------------------------------------------------- FGMRES
 
 def test_fgmres_identity_preconditioner_full_space():
