@@ -34,6 +34,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per level-0 trisolve launch from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, calibrated on a copy of known
+    size), or None when the kernel sources differ from the ones it was
+    measured with."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "trisolve_l0_convdiff3d_128.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        k, _, v = line.strip().partition(": ")
+        if k in ("traffic_bytes_per_launch", "source_sha256"):
+            fields[k] = v.strip()
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device.h", "engine.hip"):
+        with open(os.path.join(ROOT, "paper_2205_03224_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(seconds=12.0):
     """Oracle apply timed on the host, one thread, on a bounded sample: the
     32^3 member of the same operator family with 8 subdomains of the same
@@ -236,7 +259,7 @@ def main():
         "apply_distribution": dist,
         "roofline": {"bound": "hbm", "kernel": "k_trisolve level 0 (down + up)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
                      "bytes_per_launch": k_bytes, "us_per_launch": k_ms * 1e3},
     }
     del y

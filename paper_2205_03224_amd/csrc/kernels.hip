@@ -490,9 +490,33 @@ void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot, int ma
 // (deterministic) and applies H = (I - R)^{-1} - I, giving t' = H W^H z2.
 // ======================================================================
 constexpr int kIfThreads = 256;
-constexpr int kIfRows = 4;  // rows per thread
 
+// z2[j] = t[d + j] - sum_p E[j, p] t[ci[p]] for one row: the entries in
+// batches of 8 (column indices, then the gathers, then the products), so a
+// row costs a few dependent memory round trips, not two per entry.
 template <class P>
+__device__ __forceinline__ typename P::C interface_row(const IfArgs<P>& a, int64_t j) {
+  using C = typename P::C;
+  C acc = cvt<C>(a.t[a.d + j]);
+  const int p0 = a.E.rp[j], p1 = a.E.rp[j + 1];
+  for (int p = p0; p < p1; p += 8) {
+    int ci[8];
+    C ev[8], tv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = min(p + u, p1 - 1);
+      ci[u] = a.E.ci[q];
+      ev[u] = cvt<C>(a.E.v[q]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tv[u] = cvt<C>(a.t[ci[u]]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = sel(p + u < p1, acc - ev[u] * tv[u], acc);
+  }
+  return acc;
+}
+
+template <class P, int R>
 __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
   using C = typename P::C;
   using X = typename P::X;
@@ -500,16 +524,14 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
   C* red = reinterpret_cast<C*>(smem_raw);            // 4 x k, then reused
   __shared__ int is_last;
   const int tid = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * kIfThreads * kIfRows + tid;
-  C z[kIfRows];
+  const int64_t base = (int64_t)blockIdx.x * kIfThreads * R + tid;
+  C z[R];
 #pragma unroll
-  for (int q = 0; q < kIfRows; ++q) {
+  for (int q = 0; q < R; ++q) {
     const int64_t j = base + (int64_t)q * kIfThreads;
     z[q] = zero<C>();
     if (j < a.s) {
-      C acc = cvt<C>(a.t[a.d + j]);
-      const int p0 = a.E.rp[j], p1 = a.E.rp[j + 1];
-      for (int p = p0; p < p1; ++p) acc -= cvt<C>(a.E.v[p]) * cvt<C>(a.t[a.E.ci[p]]);
+      const C acc = interface_row<P>(a, j);
       a.t[a.d + j] = cvt<X>(acc);
       z[q] = acc;
     }
@@ -524,7 +546,7 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
 #pragma unroll
     for (int u = 0; u < CG; ++u) pr[u] = zero<C>();
 #pragma unroll
-    for (int q = 0; q < kIfRows; ++q) {
+    for (int q = 0; q < R; ++q) {
       const int64_t j = base + (int64_t)q * kIfThreads;
       if (j < a.s) {
 #pragma unroll
@@ -554,13 +576,23 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
   if (!is_last) return;
   __threadfence();
   // fixed-order two-stage sum of the partials: G groups of workgroups per
-  // column, then the G group sums
+  // column (workgroups g, g+G, ... in order, loads in batches of 8), then
+  // the G group sums
   const int G = a.k >= kIfThreads ? 1 : kIfThreads / a.k;
   const int nb = (int)gridDim.x;
   for (int idx = tid; idx < a.k * G; idx += kIfThreads) {
     const int c = idx % a.k, g = idx / a.k;
     C s = zero<C>();
-    for (int bb = g; bb < nb; bb += G) s += a.partial[(int64_t)bb * a.k + c];
+    for (int bb = g; bb < nb; bb += 8 * G) {
+      C v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int b2 = min(bb + u * G, nb - 1);
+        v[u] = a.partial[(int64_t)b2 * a.k + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = sel(bb + u * G < nb, s + v[u], s);
+    }
     red[idx] = s;
   }
   __syncthreads();
@@ -571,17 +603,29 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
     tv[c] = s;
   }
   __syncthreads();
+  // t' = H t, H read in batches of 8 columns
   for (int r = tid; r < a.k; r += kIfThreads) {
     C s = zero<C>();
-    for (int c = 0; c < a.k; ++c) s += a.H[r + c * a.k] * tv[c];
+    for (int c = 0; c < a.k; c += 8) {
+      C h[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) h[u] = a.H[r + (int64_t)min(c + u, a.k - 1) * a.k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = sel(c + u < a.k, s + h[u] * tv[min(c + u, a.k - 1)], s);
+    }
     a.tprime[r] = s;
   }
   if (tid == 0) *a.counter = 0u;
 }
 
+// workgroups launch_interface uses for s interface rows (size of `partial`):
+// 4 rows per thread when that still gives a few hundred workgroups, else 1
+static int interface_rows(int64_t s) { return s >= (int64_t)kIfThreads * 4 * 256 ? 4 : 1; }
+
 template <class P>
 int interface_blocks(int64_t s) {
-  return (int)((s + kIfThreads * kIfRows - 1) / (kIfThreads * kIfRows));
+  const int R = interface_rows(s);
+  return (int)((s + (int64_t)kIfThreads * R - 1) / ((int64_t)kIfThreads * R));
 }
 
 template <class P>
@@ -592,7 +636,10 @@ void launch_interface(const IfArgs<P>& a, hipStream_t st) {
   const int k = a.k > 0 ? a.k : 1;
   const int G = k >= kIfThreads ? 1 : kIfThreads / k;
   const size_t lds = (size_t)(std::max(4 * k, k * G) + k) * sizeof(C);
-  hipLaunchKernelGGL(k_interface<P>, dim3(nblk), dim3(kIfThreads), lds, st, a);
+  if (interface_rows(a.s) == 4)
+    hipLaunchKernelGGL((k_interface<P, 4>), dim3(nblk), dim3(kIfThreads), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_interface<P, 1>), dim3(nblk), dim3(kIfThreads), lds, st, a);
 }
 
 // t_C += W t'
