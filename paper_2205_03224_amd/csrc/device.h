@@ -90,13 +90,17 @@ enum { TRI_DOWN = 0, TRI_UP = 1 };
 // Streamed form of the same stages: each block's L stages, then its U
 // stages, packed into chunks of whole stages, each chunk one contiguous,
 // 16-byte aligned byte range:
-//   values       entries x V            (offset 0)
+//   values       MS x rows x V          (offset 0)
 //   inverse diag rows x D               (U chunks only)
 //   row info     rows x uint32: block-local row | count << 16 | stage rows << 24
-//   columns      entries x uint16
-// Section offsets are in 16-byte units.  A stage's first row and first
-// entry follow from the previous stage (rows and entries are consecutive),
-// so the consumer needs no stage table.
+//   columns      MS x rows x uint16, then 64 zero entries
+// Every stage holds exactly MS slots (MS = stream_slots(level's longest
+// row)): slot j of a stage with r rows is r consecutive entries, the j-th
+// entry of each row or a zero value (column 0) for rows with fewer entries.
+// Columns are stored as LDS byte offsets of the block-vector element
+// (row * kColScale<C>), so a gather needs no index arithmetic.  Section
+// offsets are in 16-byte units.  A stage's first row and first entry follow
+// from the previous stage, so the consumer needs no stage table.
 struct ChunkDesc {
   uint32_t off;      // byte offset of the chunk in the level's blob
   uint16_t n16;      // chunk size in 16-byte units
@@ -104,6 +108,17 @@ struct ChunkDesc {
   uint16_t nrows;    // rows in the chunk
   uint16_t dinv16, info16, col16;
 };
+
+// slot count of the streamed layout for a level whose longest row has
+// `maxslot` off-diagonal entries (0: no streamed kernel for it)
+__host__ __device__ constexpr int stream_slots(int maxslot) {
+  return maxslot <= 4 ? 4 : maxslot <= 8 ? 8 : maxslot <= 10 ? 10 : maxslot <= 12 ? 12
+         : maxslot <= 16 ? 16 : 0;
+}
+// byte scale of the stored column: sizeof(C), except 8 for complex128
+// (16-bit offsets then cover 8192 rows; the kernel doubles them)
+template <class C> struct ColScale { static constexpr int value = (int)sizeof(C); };
+template <> struct ColScale<dcplx> { static constexpr int value = 8; };
 
 template <class P>
 struct TriArgs {

@@ -149,10 +149,12 @@ TriHost<T> build_tri(const CSR<T>& M, const std::vector<int64_t>& blocks, bool u
 // whole stages of at most `cap` bytes (see ChunkDesc).  Returns false if a
 // single stage does not fit.
 template <class V, class D, class T>
-bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap,
-                  std::vector<uint8_t>& blob, std::vector<ChunkDesc>& desc,
-                  std::vector<int32_t>& blk_chunk) {
+bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, int ms,
+                  int col_scale, int max_rows, std::vector<uint8_t>& blob,
+                  std::vector<ChunkDesc>& desc, std::vector<int32_t>& blk_chunk) {
   auto pad = [](size_t x) { return (x + 15) & ~(size_t)15; };
+  // block-vector byte offsets must fit the 16-bit column field
+  if ((size_t)max_rows * (size_t)col_scale > 65535) return false;
   blob.clear();
   desc.clear();
   blk_chunk.assign(1, 0);
@@ -163,9 +165,9 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap,
       const int sb = h.blk_stage[b], se = h.blk_stage[b + 1];
       auto size_of = [&](int s0, int s1) {
         const size_t rows = h.stage_row[s1] - h.stage_row[s0];
-        const size_t ents = h.stage_ent[s1] - h.stage_ent[s0];
+        const size_t ents = rows * (size_t)ms;
         return pad(ents * sizeof(V)) + (isU ? pad(rows * sizeof(D)) : 0) + pad(rows * 4) +
-               pad(ents * 2);
+               pad(ents * 2 + 128);
       };
       int s = sb;
       while (s < se) {
@@ -173,8 +175,8 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap,
         while (s2 < se && size_of(s, s2 + 1) <= (size_t)cap) ++s2;
         if (s2 == s) return false;
         const size_t rows = h.stage_row[s2] - h.stage_row[s];
-        const size_t ents = h.stage_ent[s2] - h.stage_ent[s];
-        if (rows > 65535 || ents > 65535) return false;
+        const size_t ents = rows * (size_t)ms;
+        if (rows > 65535) return false;
         ChunkDesc cd{};
         const size_t base = blob.size();
         if (base > 0xffffffffull) throw Error(GS_EINVAL, "level too large for 32-bit offsets");
@@ -183,7 +185,7 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap,
         const size_t o_dinv = pad(ents * sizeof(V));
         const size_t o_info = o_dinv + (isU ? pad(rows * sizeof(D)) : 0);
         const size_t o_col = o_info + pad(rows * 4);
-        const size_t total = o_col + pad(ents * 2);
+        const size_t total = o_col + pad(ents * 2 + 128);
         // the device copies whole 1 KiB rows of the chunk buffer
         if (total > (size_t)cap || cap % 1024 != 0) return false;
         cd.n16 = (uint16_t)(total / 16);
@@ -192,17 +194,31 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap,
         cd.dinv16 = (uint16_t)(o_dinv / 16);
         cd.info16 = (uint16_t)(o_info / 16);
         cd.col16 = (uint16_t)(o_col / 16);
-        blob.resize(base + total, 0);
+        blob.resize(base + total, 0);  // zero values / columns for the padding
         uint8_t* p = blob.data() + base;
-        const int32_t rb = h.stage_row[s], eb = h.stage_ent[s];
-        for (size_t q = 0; q < ents; ++q) {
-          const V v = to_store<V, T>(h.val[eb + q]);
-          std::memcpy(p + o_val + q * sizeof(V), &v, sizeof(V));
-          std::memcpy(p + o_col + q * 2, &h.col[eb + q], 2);
-        }
+        const int32_t rb = h.stage_row[s];
+        size_t q0 = 0;  // first padded entry of the current stage
         for (int k = s; k < s2; ++k) {
-          const uint32_t nrs = (uint32_t)(h.stage_row[k + 1] - h.stage_row[k]);
-          for (int32_t q = h.stage_row[k]; q < h.stage_row[k + 1]; ++q) {
+          const int32_t r0 = h.stage_row[k], r1 = h.stage_row[k + 1];
+          const uint32_t nrs = (uint32_t)(r1 - r0);
+          // compact slot-major source: slot j holds the rows with more than
+          // j entries, which lead the stage (rows sorted by count)
+          int32_t src = h.stage_ent[k];
+          for (int j = 0; j < ms; ++j) {
+            for (int32_t q = r0; q < r1; ++q) {
+              const uint32_t cnt = (h.rowinfo[q] >> 16) & 0xffffu;
+              if ((uint32_t)j >= cnt) continue;
+              if (cnt > (uint32_t)ms) return false;
+              const size_t dst = q0 + (size_t)j * nrs + (size_t)(q - r0);
+              const V v = to_store<V, T>(h.val[src]);
+              const uint16_t cb = (uint16_t)((uint32_t)h.col[src] * (uint32_t)col_scale);
+              std::memcpy(p + o_val + dst * sizeof(V), &v, sizeof(V));
+              std::memcpy(p + o_col + dst * 2, &cb, 2);
+              ++src;
+            }
+          }
+          if (src != h.stage_ent[k + 1]) return false;
+          for (int32_t q = r0; q < r1; ++q) {
             const uint32_t inf = h.rowinfo[q];
             if ((inf >> 16) > 255) return false;
             const uint32_t w = (inf & 0x00ffffffu) | (nrs << 24);
@@ -212,6 +228,7 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap,
               std::memcpy(p + o_dinv + (size_t)(q - rb) * sizeof(D), &dv, sizeof(D));
             }
           }
+          q0 += (size_t)nrs * ms;
         }
         desc.push_back(cd);
         s = s2;
@@ -343,11 +360,13 @@ struct EngineT final : Engine {
         // (one slot more than the largest block: idle lanes store there)
         const int xb = (int)(((L.max_block_rows + 1) * sizeof(C) + 15) & ~(size_t)15);
         int cap = std::min(kChunkCapMax, ((lds_budget - xb - 1024) / 2) & ~1023);
-        if (L.nb > 0 && L.maxslot <= 16 && cap >= 4096) {
+        const int ms = stream_slots(L.maxslot);
+        if (L.nb > 0 && ms > 0 && cap >= 4096) {
           std::vector<uint8_t> blob;
           std::vector<ChunkDesc> desc;
           std::vector<int32_t> bc;
-          if (build_chunks<V, D, T>(tl, tu, L.nb, cap, blob, desc, bc)) {
+          if (build_chunks<V, D, T>(tl, tu, L.nb, cap, ms, ColScale<C>::value,
+                                    L.max_block_rows + 1, blob, desc, bc)) {
             L.blob = upload(blob);
             std::vector<uint8_t> draw(desc.size() * sizeof(ChunkDesc));
             if (!desc.empty()) std::memcpy(draw.data(), desc.data(), draw.size());

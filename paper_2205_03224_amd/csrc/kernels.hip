@@ -254,56 +254,55 @@ __device__ __forceinline__ void copy_chunk(const TriArgs<P>& a, int c, uint8_t* 
                                      16, 0, 0);
 }
 
-// One stage of a chunk in registers: the entries of each lane's row
-// (slot-major), their block-local columns, 1/u_ii, the target row.
+// One stage of a chunk in registers: the MS padded entries of each lane's
+// row (zeros past the row's length), their block-vector byte offsets, 1/u_ii
+// and the target row.
 template <class P, int MS>
 struct SweepRegs {
   typename P::C v[MS];
-  int c[MS];
+  uint32_t c[MS];
   typename P::C dv;
   int row;  // the lane's row, or the block's dummy slot for idle lanes
-  int nz;   // entries of the lane's row (0 for idle lanes)
   int nr;   // rows of the stage (uniform; 0 past the chunk's last stage)
 };
 
 // Fill R from the stage's row info (0 past the last stage) starting at row
-// r0 and entry e (advanced past the stage).  Every read is issued by every
-// lane: reads past the end of a section stay within 63 elements, inside the
-// chunk or the LDS slack, and their values are dropped by selects.
+// r0 and entry e (advanced past the stage's MS x nr entries).  Every read is
+// issued by every lane; an idle lane's column reads stay inside the column
+// section or its 64 zero entries, so every gather address is a valid
+// block-vector element, and its values only reach the dummy slot.
 template <class P, int MS, bool ISU>
 __device__ __forceinline__ void sweep_load(const typename P::V* val, const typename P::D* dinv,
                                            const uint16_t* col, uint32_t info, int r0, int& e,
                                            int lane, int dummy, SweepRegs<P, MS>& R) {
   using C = typename P::C;
   R.nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
-  const bool act = lane < R.nr;
-  R.nz = act ? (int)((info >> 16) & 0xffu) : 0;
-  R.row = act ? (int)(info & 0xffffu) : dummy;
+  R.row = lane < R.nr ? (int)(info & 0xffffu) : dummy;
 #pragma unroll
   for (int j = 0; j < MS; ++j) {
-    const unsigned long long m = __ballot(R.nz > j);
-    R.v[j] = cvt<C>(val[e + lane]);
-    const int cj = (int)col[e + lane];
-    R.c[j] = R.nz > j ? cj : 0;
-    e += __popcll(m);
+    R.v[j] = cvt<C>(val[e + j * R.nr + lane]);
+    R.c[j] = col[e + j * R.nr + lane];
   }
+  e += MS * R.nr;
   if (ISU) R.dv = cvt<C>(dinv[r0 + lane]);
 }
 
 // x[row] = (x[row] - sum_j v_j x[c_j]) (* 1/u_ii): all gathers first, two
-// partial sums; idle lanes write the dummy slot.
+// partial sums (padded entries are zero); idle lanes write the dummy slot.
 template <class P, int MS, bool ISU>
 __device__ __forceinline__ void sweep_compute(const SweepRegs<P, MS>& R, typename P::C* x) {
   using C = typename P::C;
+  constexpr int kMul = (int)sizeof(C) / ColScale<C>::value;
+  const unsigned char* xb = reinterpret_cast<const unsigned char*>(x);
   C xv[MS];
 #pragma unroll
-  for (int j = 0; j < MS; ++j) xv[j] = x[R.c[j]];
+  for (int j = 0; j < MS; ++j) xv[j] = *reinterpret_cast<const C*>(xb + R.c[j] * kMul);
   const C b = x[R.row];
   C s0 = zero<C>(), s1 = zero<C>();
 #pragma unroll
   for (int j = 0; j < MS; j += 2) {
-    s0 = sel(R.nz > j, s0 + R.v[j] * xv[j], s0);
-    if (j + 1 < MS) s1 = sel(R.nz > j + 1, s1 + R.v[j + 1] * xv[j + 1], s1);
+    s0 += R.v[j] * xv[j];
+    if (j + 1 < MS) s1 += R.v[j + 1] * xv[j + 1];
   }
   C acc = b - (s0 + s1);
   if (ISU) acc *= R.dv;
@@ -468,9 +467,12 @@ static void launch_stream_ms(const TriArgs<P>& a, hipStream_t st) {
 
 template <class P, int MODE>
 static void launch_stream_mode(const TriArgs<P>& a, int maxslot, hipStream_t st) {
-  if (maxslot <= 4) launch_stream_ms<P, 4, MODE>(a, st);
-  else if (maxslot <= 8) launch_stream_ms<P, 8, MODE>(a, st);
-  else if (maxslot <= 12) launch_stream_ms<P, 12, MODE>(a, st);
+  // the layout was padded to stream_slots(maxslot) slots per stage
+  const int ms = stream_slots(maxslot);
+  if (ms == 4) launch_stream_ms<P, 4, MODE>(a, st);
+  else if (ms == 8) launch_stream_ms<P, 8, MODE>(a, st);
+  else if (ms == 10) launch_stream_ms<P, 10, MODE>(a, st);
+  else if (ms == 12) launch_stream_ms<P, 12, MODE>(a, st);
   else launch_stream_ms<P, 16, MODE>(a, st);
 }
 
