@@ -146,8 +146,7 @@ struct IfArgs {
   const typename P::V* W;    // s x k column-major
   const typename P::C* H;    // k x k column-major, compute type
   typename P::C* partial;    // gridDim x k partial sums of W^H z2
-  typename P::C* tprime;     // k: H (W^H z2)
-  uint32_t* counter;         // zero between launches
+  typename P::C* tprime;     // k: H (W^H z2), written by a second launch
 };
 
 // ------------------------------------------------------------ launchers

@@ -259,7 +259,6 @@ struct EngineT final : Engine {
     C* H = nullptr;
     C* partial = nullptr;
     C* tprime = nullptr;
-    uint32_t* counter = nullptr;
     int kcap = 0;
     int64_t nnz_lu = 0, nnz_e = 0, nnz_f = 0, nstages = 0;
     // streamed layout (null when the level uses the register-prefetch kernel)
@@ -511,20 +510,26 @@ struct EngineT final : Engine {
     }
   }
 
+  // Install W_l, H_l; buffers grow with k and are reused by later calls.
   void set_lowrank_host(int l, int k, const std::vector<T>& W, const std::vector<T>& H) {
     Lev& L = lv[l];
+    if (k > 1024) throw Error(GS_EINVAL, "rank above 1024 per level is not supported");
     if (k > L.kcap) {
       const int nblk = interface_blocks<P>(L.s);
       L.partial = mem.alloc<C>((size_t)nblk * k);
       L.tprime = mem.alloc<C>(k);
-      L.counter = mem.alloc<uint32_t>(1);
-      HIPCHK(hipMemsetAsync(L.counter, 0, sizeof(uint32_t), st));
+      L.W = mem.alloc<V>((size_t)L.s * k);
+      L.H = mem.alloc<C>((size_t)k * k);
       L.kcap = k;
     }
-    L.W = upload(convert<V, T>(W));
+    const std::vector<V> wv = convert<V, T>(W);
     std::vector<C> hc(H.size());
     for (size_t i = 0; i < H.size(); ++i) hc[i] = to_compute(H[i]);
-    L.H = upload(hc);
+    if (!wv.empty())
+      HIPCHK(hipMemcpyAsync(L.W, wv.data(), wv.size() * sizeof(V), hipMemcpyHostToDevice, st));
+    if (!hc.empty())
+      HIPCHK(hipMemcpyAsync(L.H, hc.data(), hc.size() * sizeof(C), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
     L.k = k;
   }
   static C to_compute(const T& x);
@@ -633,7 +638,6 @@ struct EngineT final : Engine {
     a.H = L.H;
     a.partial = L.partial;
     a.tprime = L.tprime;
-    a.counter = L.counter;
     step("interface L" + std::to_string(l), KIND_INTERFACE, if_bytes(l, k),
          [&] { launch_interface<P>(a, st); });
     if (k > 0)

@@ -23,23 +23,53 @@ template <> __device__ inline double zero<double>() { return 0.0; }
 template <> __device__ inline float zero<float>() { return 0.0f; }
 template <> __device__ inline dcplx zero<dcplx>() { return mk(0.0, 0.0); }
 
-__device__ inline double shfl_xor(double v, int m) { return __shfl_xor(v, m, kWave); }
-__device__ inline float shfl_xor(float v, int m) { return __shfl_xor(v, m, kWave); }
-__device__ inline dcplx shfl_xor(dcplx v, int m) {
-  return mk(__shfl_xor(v.x, m, kWave), __shfl_xor(v.y, m, kWave));
-}
-
 // c ? a : b, component-wise for complex values (a select of the struct as
 // a whole is lowered through scratch memory)
 __device__ inline double sel(bool c, double a, double b) { return c ? a : b; }
 __device__ inline float sel(bool c, float a, float b) { return c ? a : b; }
 __device__ inline dcplx sel(bool c, dcplx a, dcplx b) { return mk(c ? a.x : b.x, c ? a.y : b.y); }
 
-// Sum over the 64 lanes of a wavefront (butterfly; every lane gets the sum).
-template <class T> __device__ inline T wave_sum(T v) {
+// Fixed-order sums over the 256 threads of a workgroup through LDS (two
+// read rounds; a shuffle chain costs one LDS round trip per step).
+// block_sum8: thread c < 8 gets the sum of every thread's v[c]; red holds
+// 9 x 256 values.  block_sum1: thread 0 gets the sum of v; red holds 288.
+// Both end with a barrier, so red may be reused right after.
+constexpr int kRedThreads = 256;
+template <class T>
+__device__ inline T block_sum8(const T (&v)[8], T* red, int tid) {
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor(v, m);
-  return v;
+  for (int u = 0; u < 8; ++u) red[u * kRedThreads + tid] = v[u];
+  __syncthreads();
+  {
+    const int u = tid / 32, g = tid % 32;
+    T s = zero<T>();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += red[u * kRedThreads + g * 8 + i];
+    red[8 * kRedThreads + tid] = s;
+  }
+  __syncthreads();
+  T r = zero<T>();
+  if (tid < 8)
+    for (int g = 0; g < 32; ++g) r += red[8 * kRedThreads + tid * 32 + g];
+  __syncthreads();
+  return r;
+}
+template <class T>
+__device__ inline T block_sum1(T v, T* red, int tid) {
+  red[tid] = v;
+  __syncthreads();
+  if (tid < 32) {
+    T s = zero<T>();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += red[tid * 8 + i];
+    red[kRedThreads + tid] = s;
+  }
+  __syncthreads();
+  T r = zero<T>();
+  if (tid == 0)
+    for (int g = 0; g < 32; ++g) r += red[kRedThreads + g];
+  __syncthreads();
+  return r;
 }
 
 }  // namespace
@@ -523,8 +553,7 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
   using C = typename P::C;
   using X = typename P::X;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* red = reinterpret_cast<C*>(smem_raw);            // 4 x k, then reused
-  __shared__ int is_last;
+  C* red = reinterpret_cast<C*>(smem_raw);  // 9 x kIfThreads (block_sum8)
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * kIfThreads * R + tid;
   C z[R];
@@ -539,85 +568,82 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
     }
   }
   if (a.k == 0) return;
-  const int wave = tid / kWave, lane = tid % kWave;
-  // columns in groups of 8: all W loads of a group are issued before the
-  // first reduction waits on them
-  constexpr int CG = 8;
-  for (int c0 = 0; c0 < a.k; c0 += CG) {
-    C pr[CG];
+  // W^H z2 for this workgroup's rows, 8 columns at a time, each group summed
+  // over the workgroup in fixed order through LDS
+  for (int c0 = 0; c0 < a.k; c0 += 8) {
+    C pr[8];
 #pragma unroll
-    for (int u = 0; u < CG; ++u) pr[u] = zero<C>();
+    for (int u = 0; u < 8; ++u) pr[u] = zero<C>();
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int64_t j = base + (int64_t)q * kIfThreads;
       if (j < a.s) {
 #pragma unroll
-        for (int u = 0; u < CG; ++u)
+        for (int u = 0; u < 8; ++u)
           if (c0 + u < a.k) pr[u] += conj(cvt<C>(a.W[j + (int64_t)(c0 + u) * a.s])) * z[q];
       }
     }
-#pragma unroll
-    for (int u = 0; u < CG; ++u) {
-      const C r = wave_sum(pr[u]);
-      if (lane == 0 && c0 + u < a.k) red[wave * a.k + c0 + u] = r;
-    }
+    const C sm = block_sum8(pr, red, tid);
+    if (tid < 8 && c0 + tid < a.k) a.partial[(int64_t)blockIdx.x * a.k + c0 + tid] = sm;
   }
-  __syncthreads();
-  for (int c = tid; c < a.k; c += kIfThreads) {
-    C s = red[c];
-    for (int w = 1; w < kIfThreads / kWave; ++w) s += red[w * a.k + c];
-    a.partial[(int64_t)blockIdx.x * a.k + c] = s;
-  }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned prev = atomicAdd(a.counter, 1u);
-    is_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  // fixed-order two-stage sum of the partials: G groups of workgroups per
-  // column (workgroups g, g+G, ... in order, loads in batches of 8), then
-  // the G group sums
-  const int G = a.k >= kIfThreads ? 1 : kIfThreads / a.k;
-  const int nb = (int)gridDim.x;
-  for (int idx = tid; idx < a.k * G; idx += kIfThreads) {
-    const int c = idx % a.k, g = idx / a.k;
-    C s = zero<C>();
-    for (int bb = g; bb < nb; bb += 8 * G) {
+}
+
+// t' = H (sum over workgroups of the partials), one workgroup of 1024
+// threads: T = 1024 / k threads per column sum the partials of workgroups
+// g, g+T, ... (coalesced: consecutive threads read consecutive columns, in
+// batches of 8 loads), the T group sums are added in order in LDS; then
+// thread (r, q) forms the part of row r of H t over columns q, q+T, ... and
+// the parts are added in order.  Deterministic; no atomics.
+constexpr int kFinishThreads = 1024;
+
+template <class P>
+__global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typename P::C* partial,
+                                                                   int nb, int k,
+                                                                   const typename P::C* H,
+                                                                   typename P::C* tprime) {
+  using C = typename P::C;
+  __shared__ C red[kFinishThreads];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tv = reinterpret_cast<C*>(smem_raw);  // k
+  const int tid = threadIdx.x;
+  const int T = kFinishThreads / k;
+  const int c = tid % k, g = tid / k;
+  C s = zero<C>();
+  if (g < T) {
+    for (int b = g; b < nb; b += 8 * T) {
       C v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int b2 = min(bb + u * G, nb - 1);
-        v[u] = a.partial[(int64_t)b2 * a.k + c];
-      }
+      for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)min(b + u * T, nb - 1) * k + c];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s = sel(bb + u * G < nb, s + v[u], s);
+      for (int u = 0; u < 8; ++u) s = sel(b + u * T < nb, s + v[u], s);
     }
-    red[idx] = s;
+  }
+  red[tid] = s;
+  __syncthreads();
+  if (tid < k) {
+    C t = zero<C>();
+    for (int q = 0; q < T; ++q) t += red[q * k + tid];
+    tv[tid] = t;
   }
   __syncthreads();
-  C* tv = red + (size_t)a.k * G;
-  for (int c = tid; c < a.k; c += kIfThreads) {
-    C s = red[c];
-    for (int g = 1; g < G; ++g) s += red[g * a.k + c];
-    tv[c] = s;
-  }
-  __syncthreads();
-  // t' = H t, H read in batches of 8 columns
-  for (int r = tid; r < a.k; r += kIfThreads) {
-    C s = zero<C>();
-    for (int c = 0; c < a.k; c += 8) {
+  s = zero<C>();
+  if (g < T) {
+    for (int cc = g; cc < k; cc += 8 * T) {
       C h[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) h[u] = a.H[r + (int64_t)min(c + u, a.k - 1) * a.k];
+      for (int u = 0; u < 8; ++u) h[u] = H[c + (int64_t)min(cc + u * T, k - 1) * k];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s = sel(c + u < a.k, s + h[u] * tv[min(c + u, a.k - 1)], s);
+      for (int u = 0; u < 8; ++u) s = sel(cc + u * T < k, s + h[u] * tv[min(cc + u * T, k - 1)], s);
     }
-    a.tprime[r] = s;
   }
-  if (tid == 0) *a.counter = 0u;
+  __syncthreads();
+  red[tid] = s;
+  __syncthreads();
+  if (tid < k) {
+    C t = zero<C>();
+    for (int q = 0; q < T; ++q) t += red[q * k + tid];
+    tprime[tid] = t;
+  }
 }
 
 // workgroups launch_interface uses for s interface rows (size of `partial`):
@@ -635,13 +661,14 @@ void launch_interface(const IfArgs<P>& a, hipStream_t st) {
   if (a.s <= 0) return;
   using C = typename P::C;
   const int nblk = interface_blocks<P>(a.s);
-  const int k = a.k > 0 ? a.k : 1;
-  const int G = k >= kIfThreads ? 1 : kIfThreads / k;
-  const size_t lds = (size_t)(std::max(4 * k, k * G) + k) * sizeof(C);
+  const size_t lds = (size_t)9 * kRedThreads * sizeof(C);
   if (interface_rows(a.s) == 4)
     hipLaunchKernelGGL((k_interface<P, 4>), dim3(nblk), dim3(kIfThreads), lds, st, a);
   else
     hipLaunchKernelGGL((k_interface<P, 1>), dim3(nblk), dim3(kIfThreads), lds, st, a);
+  if (a.k > 0)
+    hipLaunchKernelGGL(k_project_finish<P>, dim3(1), dim3(kFinishThreads), (size_t)a.k * sizeof(C),
+                       st, a.partial, nblk, a.k, a.H, a.tprime);
 }
 
 // t_C += W t'
@@ -742,7 +769,7 @@ constexpr int kDotBlocks = 256;  // workgroups along the rows
 template <class T>
 __global__ __launch_bounds__(256) void k_multidot(const T* V, int64_t ld, int ncol,
                                                   const T* w, int64_t n, T* partial) {
-  __shared__ T red[4][kDotChunk];
+  __shared__ T red[9 * kRedThreads];
   const int c0 = blockIdx.y * kDotChunk;
   const int nc = min(kDotChunk, ncol - c0);
   T acc[kDotChunk];
@@ -755,31 +782,18 @@ __global__ __launch_bounds__(256) void k_multidot(const T* V, int64_t ld, int nc
     for (int c = 0; c < kDotChunk; ++c)
       if (c < nc) acc[c] += conj(V[i + (int64_t)(c0 + c) * ld]) * wi;
   }
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-#pragma unroll
-  for (int c = 0; c < kDotChunk; ++c) {
-    T s = wave_sum(acc[c]);
-    if (lane == 0) red[wave][c] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < nc) {
-    T s = red[0][threadIdx.x];
-    for (int w2 = 1; w2 < 4; ++w2) s += red[w2][threadIdx.x];
-    partial[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
-  }
+  const T s = block_sum8(acc, red, threadIdx.x);
+  if (threadIdx.x < nc) partial[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
 }
 // h[c] = sum_b partial[c][b]: one workgroup per column, fixed-order tree
 template <class T>
 __global__ __launch_bounds__(256) void k_sum_partials(const T* partial, int nparts, int ncol,
                                                       T* h) {
-  __shared__ T red[4];
+  __shared__ T red[kRedThreads + 32];
   const int c = blockIdx.x;
   T s = threadIdx.x < nparts ? partial[(int64_t)c * nparts + threadIdx.x] : zero<T>();
-  s = wave_sum(s);
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  if (lane == 0) red[wave] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) h[c] = red[0] + red[1] + red[2] + red[3];
+  s = block_sum1(s, red, threadIdx.x);
+  if (threadIdx.x == 0) h[c] = s;
 }
 template <class T>
 void launch_multidot(const T* V, int64_t ld, int ncol, const T* w, int64_t n, T* partial, T* h,
@@ -816,26 +830,20 @@ void launch_gemv_sub(const T* V, int64_t ld, int ncol, const T* h, T* w, int64_t
 
 template <class T>
 __global__ __launch_bounds__(256) void k_norm_part(const T* w, int64_t n, double* partial) {
-  __shared__ double red[4];
+  __shared__ double red[kRedThreads + 32];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     acc += norm2(w[i]);
-  acc = wave_sum(acc);
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  if (lane == 0) red[wave] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  acc = block_sum1(acc, red, threadIdx.x);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 __global__ __launch_bounds__(256) void k_norm_final(const double* partial, int nparts,
                                                     double* out) {
-  __shared__ double red[4];
+  __shared__ double red[kRedThreads + 32];
   double s = threadIdx.x < nparts ? partial[threadIdx.x] : 0.0;
-  s = wave_sum(s);
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  if (lane == 0) red[wave] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) out[0] = sqrt(red[0] + red[1] + red[2] + red[3]);
+  s = block_sum1(s, red, threadIdx.x);
+  if (threadIdx.x == 0) out[0] = sqrt(s);
 }
 template <class T>
 void launch_norm(const T* w, int64_t n, double* partial, double* out, hipStream_t st) {
