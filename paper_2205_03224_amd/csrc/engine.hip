@@ -317,7 +317,9 @@ struct EngineT final : Engine {
     return d;
   }
 
-  int lds_budget = 65536;
+  int lds_budget = 65536;  // LDS per workgroup of the streamed trisolve, at most
+  int num_cus = 256, lds_per_cu = 163840;
+  bool fixed_budget = false;
   bool no_stream = std::getenv("GEMSLR_NO_STREAM") != nullptr;
 
   EngineT(const HostSetup<T>& S, hipStream_t stream) : st(stream) {
@@ -329,7 +331,18 @@ struct EngineT final : Engine {
         maxlds = 65536;
       // two workgroups per CU when the device allows more than 64 KiB each
       lds_budget = std::min(maxlds, 81920);
-      if (const char* e = std::getenv("GEMSLR_LDS_BUDGET")) lds_budget = std::atoi(e);
+      int cus = 256, cu_lds = 163840;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+      if (hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                dev) != hipSuccess || cu_lds <= 0)
+        cu_lds = 2 * lds_budget;
+      num_cus = std::max(1, cus);
+      lds_per_cu = std::max(cu_lds, lds_budget);
+      if (const char* e = std::getenv("GEMSLR_LDS_BUDGET")) {
+        lds_budget = std::atoi(e);
+        fixed_budget = true;
+      }
     }
     std::vector<int32_t> p32(S.perm.begin(), S.perm.end());
     perm_d = upload(p32);
@@ -358,7 +371,15 @@ struct EngineT final : Engine {
         // that two workgroups share one CU
         // (one slot more than the largest block: idle lanes store there)
         const int xb = (int)(((L.max_block_rows + 1) * sizeof(C) + 15) & ~(size_t)15);
-        int cap = std::min(kChunkCapMax, ((lds_budget - xb - 1024) / 2) & ~1023);
+        // LDS per workgroup: small enough that all blocks of the level are
+        // resident at once (ceil(nb / CUs) workgroups per CU), at most the
+        // two-per-CU budget
+        int budget = lds_budget;
+        if (!fixed_budget && L.nb > 0) {
+          const int per_cu = (L.nb + num_cus - 1) / num_cus;
+          budget = std::min(lds_budget, lds_per_cu / std::max(1, per_cu));
+        }
+        int cap = std::min(kChunkCapMax, ((budget - xb - 1024) / 2) & ~1023);
         const int ms = stream_slots(L.maxslot);
         if (L.nb > 0 && ms > 0 && cap >= 4096) {
           std::vector<uint8_t> blob;

@@ -72,6 +72,43 @@ __device__ inline T block_sum1(T v, T* red, int tid) {
   return r;
 }
 
+// r[u] = sum_p val[p] * x[ci[p]] over the CSR rows row[u] (row < 0: none)
+// of one thread, with every row's entries fetched together: row pointers,
+// then up to B entries of every row (indices and values), then the gathers.
+// A row of length n costs ceil(n / B) rounds, all rows at once.
+template <class C, class VT, class XT, int U, int B>
+__device__ __forceinline__ void csr_rows(const int32_t* rp, const int32_t* ci, const VT* val,
+                                         const XT* x, const int (&row)[U], C (&r)[U]) {
+  int p0[U], p1[U];
+  int mx = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    p0[u] = row[u] >= 0 ? rp[row[u]] : 0;
+    p1[u] = row[u] >= 0 ? rp[row[u] + 1] : 0;
+    r[u] = zero<C>();
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) mx = max(mx, p1[u] - p0[u]);
+  for (int m = 0; m < mx; m += B) {  // mx > 0 implies at least one entry exists
+    int cc[U][B];
+    C fv[U][B];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < B; ++t) {
+        const int q = p0[u] + m + t;
+        const bool ok = q < p1[u];
+        const int qq = ok ? q : 0;
+        cc[u][t] = ci[qq];
+        fv[u][t] = sel(ok, cvt<C>(val[qq]), zero<C>());
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < B; ++t) r[u] += fv[u][t] * cvt<C>(x[cc[u][t]]);
+  }
+}
+
 }  // namespace
 
 // ======================================================================
@@ -394,19 +431,13 @@ __device__ __forceinline__ void load_rhs(const TriArgs<P>& a, int r0, int nr, in
         if (i < nr) r[u] = cvt<C>(a.t[r0 + i]);
       }
     } else {
-      int p0[U], p1[U];
+      int rows[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * NT;
-        p0[u] = i < nr ? a.F.rp[r0 + i] : 0;
-        p1[u] = i < nr ? a.F.rp[r0 + i + 1] : 0;
+        rows[u] = i < nr ? r0 + i : -1;
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        r[u] = zero<C>();
-        for (int p = p0[u]; p < p1[u]; ++p)
-          r[u] += cvt<C>(a.F.v[p]) * cvt<C>(a.t[a.d + a.F.ci[p]]);
-      }
+      csr_rows<C, typename P::V, typename P::X, U, 2>(a.F.rp, a.F.ci, a.F.v, a.t + a.d, rows, r);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -523,31 +554,6 @@ void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot, int ma
 // ======================================================================
 constexpr int kIfThreads = 256;
 
-// z2[j] = t[d + j] - sum_p E[j, p] t[ci[p]] for one row: the entries in
-// batches of 8 (column indices, then the gathers, then the products), so a
-// row costs a few dependent memory round trips, not two per entry.
-template <class P>
-__device__ __forceinline__ typename P::C interface_row(const IfArgs<P>& a, int64_t j) {
-  using C = typename P::C;
-  C acc = cvt<C>(a.t[a.d + j]);
-  const int p0 = a.E.rp[j], p1 = a.E.rp[j + 1];
-  for (int p = p0; p < p1; p += 8) {
-    int ci[8];
-    C ev[8], tv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int q = min(p + u, p1 - 1);
-      ci[u] = a.E.ci[q];
-      ev[u] = cvt<C>(a.E.v[q]);
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) tv[u] = cvt<C>(a.t[ci[u]]);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc = sel(p + u < p1, acc - ev[u] * tv[u], acc);
-  }
-  return acc;
-}
-
 template <class P, int R>
 __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
   using C = typename P::C;
@@ -557,14 +563,23 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * kIfThreads * R + tid;
   C z[R];
+  {
+    int rows[R];
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int64_t j = base + (int64_t)q * kIfThreads;
-    z[q] = zero<C>();
-    if (j < a.s) {
-      const C acc = interface_row<P>(a, j);
-      a.t[a.d + j] = cvt<X>(acc);
-      z[q] = acc;
+    for (int q = 0; q < R; ++q) {
+      const int64_t j = base + (int64_t)q * kIfThreads;
+      rows[q] = j < a.s ? (int)j : -1;
+    }
+    C ez[R];
+    csr_rows<C, typename P::V, X, R, 4>(a.E.rp, a.E.ci, a.E.v, a.t, rows, ez);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      z[q] = zero<C>();
+      if (rows[q] >= 0) {
+        const C acc = cvt<C>(a.t[a.d + rows[q]]) - ez[q];
+        a.t[a.d + rows[q]] = cvt<X>(acc);
+        z[q] = acc;
+      }
     }
   }
   if (a.k == 0) return;
