@@ -589,13 +589,16 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
     C pr[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) pr[u] = zero<C>();
+    // unconditional loads at clamped indices (rows past s carry z = 0,
+    // columns past k are never written), so all 8R loads are in flight at
+    // once instead of one guarded load and wait each
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int64_t j = base + (int64_t)q * kIfThreads;
-      if (j < a.s) {
+      const int64_t j = min(base + (int64_t)q * kIfThreads, a.s - 1);
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (c0 + u < a.k) pr[u] += conj(cvt<C>(a.W[j + (int64_t)(c0 + u) * a.s])) * z[q];
+      for (int u = 0; u < 8; ++u) {
+        const int64_t cu = min(c0 + u, a.k - 1);
+        pr[u] += conj(cvt<C>(a.W[j + cu * a.s])) * z[q];
       }
     }
     const C sm = block_sum8(pr, red, tid);
