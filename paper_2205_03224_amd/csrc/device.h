@@ -128,6 +128,7 @@ struct TriArgs {
   int64_t d;                 // rows of B_l
   CsrDev<P> F;               // UP mode: F_l (rows of B_l, cols of C_l)
   typename P::X* xg;         // scratch (d entries) when blocks exceed LDS
+  typename P::C* fy;         // streamed UP mode: F_l y2 (d entries), formed first
   int32_t nb;
   // streamed layout (used when `blob` is set)
   const uint8_t* blob;

@@ -287,6 +287,7 @@ struct EngineT final : Engine {
   int32_t* perm_d = nullptr;
   X* t = nullptr;
   C* xg = nullptr;
+  C* fy = nullptr;  // F_l y2 of the streamed up sweep
   std::vector<Lev> lv;
 
   template <class U> U* upload(const std::vector<U>& h) {
@@ -414,6 +415,7 @@ struct EngineT final : Engine {
       if (h.k > 0) set_lowrank_host((int)l, h.k, h.W, h.H);
     }
     xg = mem.alloc<C>(maxd);
+    fy = mem.alloc<C>(maxd);
     // C_0 (the interface block of P^T A P) for the inner iteration's S_hat_0
     if constexpr (kInnerCapable) {
       if (lv.size() >= 2 && lv[0].s > 0) {
@@ -572,6 +574,7 @@ struct EngineT final : Engine {
     a.d = L.d;
     a.F = L.F;
     a.xg = reinterpret_cast<X*>(xg);
+    a.fy = fy;
     a.nb = L.nb;
     a.blob = L.blob;
     a.chunk = L.chunk;

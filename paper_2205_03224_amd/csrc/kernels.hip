@@ -431,13 +431,11 @@ __device__ __forceinline__ void load_rhs(const TriArgs<P>& a, int r0, int nr, in
         if (i < nr) r[u] = cvt<C>(a.t[r0 + i]);
       }
     } else {
-      int rows[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * NT;
-        rows[u] = i < nr ? r0 + i : -1;
+        if (i < nr) r[u] = a.fy[r0 + i];
       }
-      csr_rows<C, typename P::V, typename P::X, U, 2>(a.F.rp, a.F.ci, a.F.v, a.t + a.d, rows, r);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -537,13 +535,32 @@ static void launch_stream_mode(const TriArgs<P>& a, int maxslot, hipStream_t st)
   else launch_stream_ms<P, 16, MODE>(a, st);
 }
 
+// fy = F_l y2, one thread per row of B_l (most rows have no entry), so the
+// up sweep's right-hand side is a plain load like the down sweep's
+template <class P>
+__global__ __launch_bounds__(256) void k_fy(CsrDev<P> F, const typename P::X* y2,
+                                            typename P::C* fy, int64_t d) {
+  using C = typename P::C;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d) return;
+  const int rows[1] = {(int)i};
+  C r[1];
+  csr_rows<C, typename P::V, typename P::X, 1, 4>(F.rp, F.ci, F.v, y2, rows, r);
+  fy[i] = r[0];
+}
+
 template <class P>
 void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot, int max_block_rows,
                               hipStream_t st) {
   (void)max_block_rows;
   if (a.nb <= 0) return;
-  if (mode == TRI_DOWN) launch_stream_mode<P, TRI_DOWN>(a, maxslot, st);
-  else launch_stream_mode<P, TRI_UP>(a, maxslot, st);
+  if (mode == TRI_DOWN) {
+    launch_stream_mode<P, TRI_DOWN>(a, maxslot, st);
+  } else {
+    hipLaunchKernelGGL(k_fy<P>, dim3((unsigned)((a.d + 255) / 256)), dim3(256), 0, st, a.F,
+                       a.t + a.d, a.fy, a.d);
+    launch_stream_mode<P, TRI_UP>(a, maxslot, st);
+  }
 }
 
 // ======================================================================
