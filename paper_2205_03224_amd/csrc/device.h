@@ -90,17 +90,19 @@ enum { TRI_DOWN = 0, TRI_UP = 1 };
 // Streamed form of the same stages: each block's L stages, then its U
 // stages, packed into chunks of whole stages, each chunk one contiguous,
 // 16-byte aligned byte range:
-//   values       MS x rows x V          (offset 0)
+//   values       rows x VS x V          (offset 0)
 //   inverse diag rows x D               (U chunks only)
 //   row info     rows x uint32: block-local row | count << 16 | stage rows << 24
-//   columns      MS x rows x uint16, then 64 zero entries
-// Every stage holds exactly MS slots (MS = stream_slots(level's longest
-// row)): slot j of a stage with r rows is r consecutive entries, the j-th
-// entry of each row or a zero value (column 0) for rows with fewer entries.
-// Columns are stored as LDS byte offsets of the block-vector element
-// (row * kColScale<C>), so a gather needs no index arithmetic.  Section
-// offsets are in 16-byte units.  A stage's first row and first entry follow
-// from the previous stage, so the consumer needs no stage table.
+//   columns      (rows + 1) x CS x uint16 (the last row all zero)
+// Each row of the chunk (rows of consecutive stages follow each other) holds
+// its MS slots contiguously (MS = stream_slots(level's longest row)): the
+// row's entries, then zero values with column 0.  The row strides VS =
+// MS + 1 values and CS column entries make the per-lane accesses of a wave
+// free of LDS bank conflicts, and let every slot be an immediate offset from
+// one address per stage.  Columns are stored as LDS byte offsets of the
+// block-vector element (row * ColScale<C>), so a gather needs no index
+// arithmetic.  Section offsets are in 16-byte units.  A stage's first row
+// follows from the previous stage, so the consumer needs no stage table.
 struct ChunkDesc {
   uint32_t off;      // byte offset of the chunk in the level's blob
   uint16_t n16;      // chunk size in 16-byte units
@@ -115,6 +117,8 @@ __host__ __device__ constexpr int stream_slots(int maxslot) {
   return maxslot <= 4 ? 4 : maxslot <= 8 ? 8 : maxslot <= 10 ? 10 : maxslot <= 12 ? 12
          : maxslot <= 16 ? 16 : 0;
 }
+__host__ __device__ constexpr int stream_vstride(int ms) { return ms + 1; }
+__host__ __device__ constexpr int stream_cstride(int ms) { return ms <= 4 ? 4 : ms <= 12 ? 12 : 20; }
 // byte scale of the stored column: sizeof(C), except 8 for complex128
 // (16-bit offsets then cover 8192 rows; the kernel doubles them)
 template <class C> struct ColScale { static constexpr int value = (int)sizeof(C); };

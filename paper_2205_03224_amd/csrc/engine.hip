@@ -163,11 +163,11 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, i
       const TriHost<T>& h = tri == 0 ? lo : up;
       const bool isU = tri == 1;
       const int sb = h.blk_stage[b], se = h.blk_stage[b + 1];
+      const int VS = stream_vstride(ms), CS = stream_cstride(ms);
       auto size_of = [&](int s0, int s1) {
         const size_t rows = h.stage_row[s1] - h.stage_row[s0];
-        const size_t ents = rows * (size_t)ms;
-        return pad(ents * sizeof(V)) + (isU ? pad(rows * sizeof(D)) : 0) + pad(rows * 4) +
-               pad(ents * 2 + 128);
+        return pad(rows * VS * sizeof(V)) + (isU ? pad(rows * sizeof(D)) : 0) + pad(rows * 4) +
+               pad((rows + 1) * CS * 2);
       };
       int s = sb;
       while (s < se) {
@@ -175,17 +175,16 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, i
         while (s2 < se && size_of(s, s2 + 1) <= (size_t)cap) ++s2;
         if (s2 == s) return false;
         const size_t rows = h.stage_row[s2] - h.stage_row[s];
-        const size_t ents = rows * (size_t)ms;
         if (rows > 65535) return false;
         ChunkDesc cd{};
         const size_t base = blob.size();
         if (base > 0xffffffffull) throw Error(GS_EINVAL, "level too large for 32-bit offsets");
         cd.off = (uint32_t)base;
         const size_t o_val = 0;
-        const size_t o_dinv = pad(ents * sizeof(V));
+        const size_t o_dinv = pad(rows * VS * sizeof(V));
         const size_t o_info = o_dinv + (isU ? pad(rows * sizeof(D)) : 0);
         const size_t o_col = o_info + pad(rows * 4);
-        const size_t total = o_col + pad(ents * 2 + 128);
+        const size_t total = o_col + pad((rows + 1) * CS * 2);
         // the device copies whole 1 KiB rows of the chunk buffer
         if (total > (size_t)cap || cap % 1024 != 0) return false;
         cd.n16 = (uint16_t)(total / 16);
@@ -197,7 +196,6 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, i
         blob.resize(base + total, 0);  // zero values / columns for the padding
         uint8_t* p = blob.data() + base;
         const int32_t rb = h.stage_row[s];
-        size_t q0 = 0;  // first padded entry of the current stage
         for (int k = s; k < s2; ++k) {
           const int32_t r0 = h.stage_row[k], r1 = h.stage_row[k + 1];
           const uint32_t nrs = (uint32_t)(r1 - r0);
@@ -209,11 +207,11 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, i
               const uint32_t cnt = (h.rowinfo[q] >> 16) & 0xffffu;
               if ((uint32_t)j >= cnt) continue;
               if (cnt > (uint32_t)ms) return false;
-              const size_t dst = q0 + (size_t)j * nrs + (size_t)(q - r0);
+              const size_t row = (size_t)(q - rb);
               const V v = to_store<V, T>(h.val[src]);
               const uint16_t cb = (uint16_t)((uint32_t)h.col[src] * (uint32_t)col_scale);
-              std::memcpy(p + o_val + dst * sizeof(V), &v, sizeof(V));
-              std::memcpy(p + o_col + dst * 2, &cb, 2);
+              std::memcpy(p + o_val + (row * VS + j) * sizeof(V), &v, sizeof(V));
+              std::memcpy(p + o_col + (row * CS + j) * 2, &cb, 2);
               ++src;
             }
           }
@@ -228,7 +226,6 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, i
               std::memcpy(p + o_dinv + (size_t)(q - rb) * sizeof(D), &dv, sizeof(D));
             }
           }
-          q0 += (size_t)nrs * ms;
         }
         desc.push_back(cd);
         s = s2;

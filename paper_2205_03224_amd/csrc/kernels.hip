@@ -333,25 +333,33 @@ struct SweepRegs {
   int nr;   // rows of the stage (uniform; 0 past the chunk's last stage)
 };
 
-// Fill R from the stage's row info (0 past the last stage) starting at row
-// r0 and entry e (advanced past the stage's MS x nr entries).  Every read is
-// issued by every lane; an idle lane's column reads stay inside the column
-// section or its 64 zero entries, so every gather address is a valid
-// block-vector element, and its values only reach the dummy slot.
+// Fill R from the stage's row info (0 past the last stage) for the stage
+// whose first row in the chunk is r0.  Lane l reads row r0 + l of the chunk,
+// idle lanes row r0 (past the last stage that is the zero row closing the
+// column section), so every column read is a valid block-vector offset and
+// an idle lane's values only reach the dummy slot.  All MS slots of a row
+// are immediate offsets from one address.
 template <class P, int MS, bool ISU>
 __device__ __forceinline__ void sweep_load(const typename P::V* val, const typename P::D* dinv,
-                                           const uint16_t* col, uint32_t info, int r0, int& e,
-                                           int lane, int dummy, SweepRegs<P, MS>& R) {
+                                           const uint16_t* col, uint32_t info, int r0, int lane,
+                                           int dummy, SweepRegs<P, MS>& R) {
   using C = typename P::C;
+  constexpr int VS = stream_vstride(MS), CS = stream_cstride(MS);
   R.nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
-  R.row = lane < R.nr ? (int)(info & 0xffffu) : dummy;
+  const bool act = lane < R.nr;
+  R.row = act ? (int)(info & 0xffffu) : dummy;
+  const int q = act ? r0 + lane : r0;
+  const typename P::V* vr = val + q * VS;
+  const uint32_t* cr = reinterpret_cast<const uint32_t*>(col + q * CS);
 #pragma unroll
-  for (int j = 0; j < MS; ++j) {
-    R.v[j] = cvt<C>(val[e + j * R.nr + lane]);
-    R.c[j] = col[e + j * R.nr + lane];
+  for (int j = 0; j < MS; ++j) R.v[j] = cvt<C>(vr[j]);
+#pragma unroll
+  for (int j = 0; j < MS; j += 2) {
+    const uint32_t w = cr[j / 2];
+    R.c[j] = w & 0xffffu;
+    if (j + 1 < MS) R.c[j + 1] = w >> 16;
   }
-  e += MS * R.nr;
-  if (ISU) R.dv = cvt<C>(dinv[r0 + lane]);
+  if (ISU) R.dv = cvt<C>(dinv[q]);
 }
 
 // x[row] = (x[row] - sum_j v_j x[c_j]) (* 1/u_ii): all gathers first, two
@@ -394,22 +402,21 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
   const uint16_t* col = reinterpret_cast<const uint16_t*>(cb + 16 * (int)cd.col16);
   const int nst = cd.nst & 0x7fff;
   SweepRegs<P, MS> A, B;
-  int e = 0;
-  sweep_load<P, MS, ISU>(val, dinv, col, rinfo[lane], 0, e, lane, dummy, A);
+  sweep_load<P, MS, ISU>(val, dinv, col, rinfo[lane], 0, lane, dummy, A);
   int r1 = A.nr;
-  uint32_t i1 = rinfo[r1 + lane];
+  uint32_t i1 = rinfo[min(r1 + lane, (int)cd.nrows)];
   i1 = nst > 1 ? i1 : 0u;
   for (int s = 0; s < nst; s += 2) {
-    sweep_load<P, MS, ISU>(val, dinv, col, i1, r1, e, lane, dummy, B);  // stage s+1
+    sweep_load<P, MS, ISU>(val, dinv, col, i1, r1, lane, dummy, B);  // stage s+1
     const int r2 = r1 + B.nr;
-    uint32_t i2 = rinfo[r2 + lane];
+    uint32_t i2 = rinfo[min(r2 + lane, (int)cd.nrows)];
     i2 = s + 2 < nst ? i2 : 0u;
-    sweep_compute<P, MS, ISU>(A, x);                                     // stage s
-    sweep_load<P, MS, ISU>(val, dinv, col, i2, r2, e, lane, dummy, A);  // stage s+2
+    sweep_compute<P, MS, ISU>(A, x);                                 // stage s
+    sweep_load<P, MS, ISU>(val, dinv, col, i2, r2, lane, dummy, A);  // stage s+2
     const int r3 = r2 + A.nr;
-    uint32_t i3 = rinfo[r3 + lane];
+    uint32_t i3 = rinfo[min(r3 + lane, (int)cd.nrows)];
     i3 = s + 3 < nst ? i3 : 0u;
-    sweep_compute<P, MS, ISU>(B, x);                                     // stage s+1
+    sweep_compute<P, MS, ISU>(B, x);                                 // stage s+1
     r1 = r3;
     i1 = i3;
   }
@@ -426,16 +433,10 @@ __device__ __forceinline__ void load_rhs(const TriArgs<P>& a, int r0, int nr, in
     C r[U];
     if (MODE == TRI_DOWN) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * NT;
-        if (i < nr) r[u] = cvt<C>(a.t[r0 + i]);
-      }
+      for (int u = 0; u < U; ++u) r[u] = cvt<C>(a.t[r0 + min(i0 + u * NT, nr - 1)]);
     } else {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * NT;
-        if (i < nr) r[u] = a.fy[r0 + i];
-      }
+      for (int u = 0; u < U; ++u) r[u] = a.fy[r0 + min(i0 + u * NT, nr - 1)];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -460,12 +461,10 @@ __device__ __forceinline__ void store_result(const TriArgs<P>& a, int r0, int nr
         if (i < nr) a.t[r0 + i] = cvt<X>(x[i]);
       }
     } else {
+      // unconditional clamped loads: all U in flight before the stores
       C z[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * NT;
-        if (i < nr) z[u] = cvt<C>(a.t[r0 + i]);
-      }
+      for (int u = 0; u < U; ++u) z[u] = cvt<C>(a.t[r0 + min(i0 + u * NT, nr - 1)]);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * NT;
