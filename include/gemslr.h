@@ -76,6 +76,11 @@ typedef struct {
                              the l > 0 branch; 0 = none, at most 16, float64
                              and complex128 forms only.  Nonzero makes M^{-1}
                              vary with its input (FGMRES handles that)   [0]  */
+  double ilu_shift;       /* s: every on-diagonal block (B_l and the blocks of
+                             C_last) is factored as B + i s mean|a_ii| I, the
+                             mean over A's diagonal (Sec. 5, Helmholtz: the
+                             paper uses s = 0.05); complex A only; E, F and
+                             the Schur products keep A unshifted         [0]  */
 } gs_opts;
 
 /* Fill *opts with the defaults shown in brackets above. */

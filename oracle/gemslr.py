@@ -177,10 +177,16 @@ def ghat_matvec(st, l, v):
 
 def setup(rowptr, col, val, part, ilu="ilut", drop_tol=1e-3, lfil=10,
           rank=32, seed=0, lowrank_last_level=True, dense_max=2000,
-          arnoldi_tol=1e-2, max_cycles=20):
+          arnoldi_tol=1e-2, max_cycles=20, ilu_shift=0.0):
+    """ilu_shift s: each on-diagonal block is factored as B + i s m I with m
+    the mean of |a_ii| over A (the complex shift of the Helmholtz tests,
+    Sec. 5); E, F and C keep A's entries."""
     n = len(rowptr) - 1
     A = csr(rowptr, col, val, n)
     real = not np.iscomplexobj(val)
+    if ilu_shift != 0.0 and real:
+        raise ValueError("a complex shift needs a complex matrix")
+    sigma = ilu_shift * np.mean(np.abs(A.diagonal()))
     perm = part.perm
     Ap = A[perm][:, perm].tocsr()
     Ap.sort_indices()
@@ -199,7 +205,8 @@ def setup(rowptr, col, val, part, ilu="ilut", drop_tol=1e-3, lfil=10,
         else:
             E = Ap[b:, a:b].tocsr()
             F = Ap[a:b, b:].tocsr()
-        Lf, Uf = ilu_mod.factor(B, ilu, drop_tol, lfil)
+        Bf = B if ilu_shift == 0.0 else (B + 1j * sigma * sp.identity(B.shape[0])).tocsr()
+        Lf, Uf = ilu_mod.factor(Bf, ilu, drop_tol, lfil)
         levels.append(Level(int(a), int(b - a), int(n - b), blocks, Lf, Uf,
                             E, F))
     st = Setup(n, perm, levels, Ap, real)

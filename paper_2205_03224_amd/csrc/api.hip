@@ -739,6 +739,9 @@ static void copy_csr(int64_t nr, int64_t nc, const int64_t* rp, const int32_t* c
   if (nnz) std::memcpy((void*)out.v.data(), v, nnz * sizeof(T));
 }
 
+static inline void set_imag_shift(double& s, double v) { (void)v; s = 0.0; }
+static inline void set_imag_shift(cplx& s, double v) { s = cplx(0.0, v); }
+
 template <class T>
 static void setup_native(gs_ctx* c, int64_t n, const int64_t* rp, const int32_t* ci,
                          const void* val, int levels, int nparts, int rank, double drop_tol) {
@@ -751,7 +754,18 @@ static void setup_native(gs_ctx* c, int64_t n, const int64_t* rp, const int32_t*
   if (part.L > GS_MAX_LEVELS) throw Error(GS_EINVAL, "too many levels");
   double t1 = now_s();
   extract_levels<T>(S->A, part, *S);
-  factor_levels<T>(*S, c->opts.ilu_kind, drop_tol, c->opts.lfil, c->opts.nthreads);
+  T shift = T(0);
+  if (c->opts.ilu_shift != 0.0) {
+    if (!std::is_same<T, cplx>::value)
+      throw Error(GS_EINVAL, "ilu_shift needs a complex matrix (the shifted factors are complex)");
+    if (!std::isfinite(c->opts.ilu_shift)) throw Error(GS_EINVAL, "ilu_shift is not finite");
+    double sum = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t p = S->A.rp[i]; p < S->A.rp[i + 1]; ++p)
+        if (S->A.ci[p] == i) sum += std::abs(S->A.v[p]);
+    set_imag_shift(shift, c->opts.ilu_shift * sum / (double)n);
+  }
+  factor_levels<T>(*S, c->opts.ilu_kind, drop_tol, c->opts.lfil, c->opts.nthreads, shift);
   double t2 = now_s();
   if (std::is_same<T, double>::value) c->hd.reset((HostSetup<double>*)S.release());
   else c->hz.reset((HostSetup<cplx>*)S.release());
@@ -1063,6 +1077,7 @@ void gs_opts_default(gs_opts* o) {
   o->defer_lowrank = 0;
   o->block_max_iters = 8;
   o->inner_gmres_its = 0;
+  o->ilu_shift = 0.0;
 }
 
 int gs_create(gs_ctx** ctx, int device, void* stream) {

@@ -94,8 +94,10 @@ void extract_levels(const CSR<T>& A, const Partition& part, HostSetup<T>& S);
 
 // Factor every diagonal block of every level with `nthreads` host threads.
 template <class T>
+// shift: added to every diagonal entry of each block before its ILU (the
+// complex shift of the Helmholtz experiments; zero otherwise)
 void factor_levels(HostSetup<T>& S, int kind, double tau, int lfil,
-                   int nthreads);
+                   int nthreads, T shift = T(0));
 
 // --------------------------------------------------------------- small dense
 // Complex Schur decomposition A = Q T Q^H of an m x m column-major matrix by

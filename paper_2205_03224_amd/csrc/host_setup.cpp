@@ -416,7 +416,7 @@ void ilut(const CSR<T>& B, double tau, int lfil, CSR<T>& L, CSR<T>& U) {
 // Factor every diagonal block of every level on `nthreads` host threads.
 template <class T>
 void factor_levels(HostSetup<T>& S, int kind, double tau, int lfil,
-                   int nthreads) {
+                   int nthreads, T shift) {
   struct Job { int l; int64_t b; };
   std::vector<Job> jobs;
   for (int l = 0; l <= S.L(); ++l)
@@ -451,7 +451,7 @@ void factor_levels(HostSetup<T>& S, int kind, double tau, int lfil,
           int64_t c = B.ci[p];
           if (c < r0 || c >= r1) continue;  // cannot happen for components
           blk.ci.push_back((int32_t)(c - r0));
-          blk.v.push_back(B.v[p]);
+          blk.v.push_back(c == i ? B.v[p] + shift : B.v[p]);
         }
         blk.rp.push_back((int64_t)blk.ci.size());
       }
@@ -514,8 +514,8 @@ template CSR<double> permute<double>(const CSR<double>&, const std::vector<int64
 template CSR<cplx> permute<cplx>(const CSR<cplx>&, const std::vector<int64_t>&);
 template void extract_levels<double>(const CSR<double>&, const Partition&, HostSetup<double>&);
 template void extract_levels<cplx>(const CSR<cplx>&, const Partition&, HostSetup<cplx>&);
-template void factor_levels<double>(HostSetup<double>&, int, double, int, int);
-template void factor_levels<cplx>(HostSetup<cplx>&, int, double, int, int);
+template void factor_levels<double>(HostSetup<double>&, int, double, int, int, double);
+template void factor_levels<cplx>(HostSetup<cplx>&, int, double, int, int, cplx);
 template void ilu0<double>(const CSR<double>&, CSR<double>&, CSR<double>&);
 template void ilu0<cplx>(const CSR<cplx>&, CSR<cplx>&, CSR<cplx>&);
 template void ilut<double>(const CSR<double>&, double, int, CSR<double>&, CSR<double>&);

@@ -459,6 +459,41 @@ def test_inner_gmres_exact_case_is_exact_inverse():
         np.testing.assert_allclose(y, np.linalg.solve(A, x), rtol=1e-10, atol=1e-12)
 
 
+# ---------------------------------------------------------------- complex shift
+
+def test_shifted_exact_factors_reproduce_shifted_blocks():
+    """With exact factors, L U of every block equals B + i s m I, m = mean
+    |a_ii| of A; E and F keep A's entries."""
+    r, c, v = wl.helmholtz3d(6, 0.39)
+    part = partition.wirebasket((6,) * 3, 8, 3, r, c)
+    st = gemslr.setup(r, c, v, part, ilu_shift=0.05, **FULL)
+    A = sp.csr_matrix((v, c, r)).toarray()
+    m = np.mean(np.abs(np.diag(A)))
+    Ap = A[np.ix_(part.perm, part.perm)]
+    for l, lv in enumerate(st.levels):
+        a, b = lv.start, lv.start + lv.d
+        B = Ap[a:b, a:b].copy()
+        if l == st.nlevels:
+            lab = np.repeat(np.arange(len(lv.blocks) - 1), np.diff(lv.blocks))
+            B[lab[:, None] != lab[None, :]] = 0
+        LU = (lv.Lf.toarray() + np.eye(lv.d)) @ lv.Uf.toarray()
+        np.testing.assert_allclose(LU, B + 1j * 0.05 * m * np.eye(lv.d), atol=1e-12)
+        if lv.s:
+            np.testing.assert_array_equal(lv.E.toarray(), Ap[b:, a:b])
+
+
+def test_zero_shift_is_unshifted_setup():
+    r, c, v = wl.helmholtz3d(6, 0.39)
+    part = partition.wirebasket((6,) * 3, 8, 3, r, c)
+    a = gemslr.setup(r, c, v, part, ilu="ilut", drop_tol=1e-4, lfil=10, rank=4)
+    b = gemslr.setup(r, c, v, part, ilu="ilut", drop_tol=1e-4, lfil=10, rank=4, ilu_shift=0.0)
+    for la, lb in zip(a.levels, b.levels):
+        np.testing.assert_array_equal(la.Uf.toarray(), lb.Uf.toarray())
+    with pytest.raises(ValueError):
+        rr, cc, vv = wl.laplace2d(8)
+        gemslr.setup(rr, cc, vv, partition.wirebasket((8, 8), 4, 2, rr, cc), ilu_shift=0.05)
+
+
 # ---------------------------------------------------------------- FGMRES
 
 def test_fgmres_identity_preconditioner_full_space():
