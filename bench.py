@@ -171,6 +171,7 @@ def main():
     ctx = gemslr.Context(0)
     t0 = time.perf_counter()
     ctx.setup(w.rowptr, w.col, w.val, w.levels, w.nparts, w.rank, w.drop_tol, **setup_kw)
+    setup_s = time.perf_counter() - t0
     info = ctx.info()
     log(f"[bench] setup {time.perf_counter() - t0:.1f} s: partition {info['t_partition']:.2f} "
         f"factor {info['t_factor']:.2f} layout {info['t_layout']:.2f} lowrank "
@@ -259,6 +260,12 @@ def main():
         "apply_GBps": apply_bytes / (ms_per_apply * 1e-3) / 1e9,
         "apply_bytes": apply_bytes,
         "apply_distribution": dist,
+        "setup": {"total_s": setup_s, "partition_s": info["t_partition"],
+                  "factor_s": info["t_factor"], "layout_s": info["t_layout"],
+                  "lowrank_s": info["t_lowrank"], "fill": info["fill"],
+                  "depth_L": list(info["depth_l"][:info["nlevels"] + 1]),
+                  "depth_U": list(info["depth_u"][:info["nlevels"] + 1]),
+                  "host_threads": os.cpu_count()},
         "roofline": {"bound": "hbm", "kernel": "k_trisolve level 0 (down + up)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),

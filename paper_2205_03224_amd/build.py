@@ -26,6 +26,11 @@ HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
              "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off",
               f"-I{INCLUDE}", f"-I{CSRC}"]
+# per-file additions: the ILU must round like the oracle's (no contraction);
+# the small dense Schur/eigen code does not, and with limited-range complex
+# arithmetic its multiplies and divides are inlined (no Inf/NaN recovery
+# calls), about 1.4x faster
+HOST_EXTRA = {"host_dense.cpp": ["-O3", "-fcx-limited-range"]}
 
 
 def _run(cmd):
@@ -45,7 +50,8 @@ def build(verbose=False, jobs=None):
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        cmds.append(["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append(["g++"] + HOST_FLAGS + HOST_EXTRA.get(src, []) +
+                    ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     jobs = jobs or min(8, len(cmds))
     with ThreadPoolExecutor(jobs) as ex:

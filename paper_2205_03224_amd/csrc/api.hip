@@ -88,12 +88,26 @@ static void cgs2(const DT* V, int64_t ld, int ncol, DT* w, int64_t n, DT* partia
 // orthonormal basis of the conjugate-closed subspace (pivoted Gram-Schmidt on
 // [Re Q_k, Im Q_k]) and R = G^T Sm G.
 template <class T>
+static int schur_basis_from(int m, const std::vector<cplx>& Sm, int k, std::vector<cplx>& Tm,
+                            std::vector<cplx>& Q, std::vector<cplx>& theta_k, std::vector<T>& G,
+                            std::vector<T>& R);
+
+template <class T>
 static int schur_basis(int m, const std::vector<cplx>& Sm, int k, std::vector<cplx>& Tm,
                        std::vector<cplx>& Q, std::vector<cplx>& theta_k, std::vector<T>& G,
                        std::vector<T>& R) {
-  const bool real = std::is_same<T, double>::value;
   Tm = Sm;
   schur_complex(m, Tm, Q);
+  return schur_basis_from<T>(m, Sm, k, Tm, Q, theta_k, G, R);
+}
+
+// The same from a complex Schur form Tm = Q^H Sm Q already at hand (any
+// order of the diagonal): reorder so the k wanted values lead, then G, R.
+template <class T>
+static int schur_basis_from(int m, const std::vector<cplx>& Sm, int k, std::vector<cplx>& Tm,
+                            std::vector<cplx>& Q, std::vector<cplx>& theta_k, std::vector<T>& G,
+                            std::vector<T>& R) {
+  const bool real = std::is_same<T, double>::value;
   std::vector<cplx> theta(m);
   for (int i = 0; i < m; ++i) theta[i] = Tm[(size_t)i * m + i];
   std::vector<int> sel = select_wanted(theta, k, real);
@@ -382,9 +396,13 @@ static bool lowrank_block(gs_ctx* c, int l, int kreq, const float* Y) {
       launch_multidot<DT>(Sv, s, w, col(GSv, j), s, part, Td + (size_t)j * cap, st);
       launch_multidot<DT>(GSv, s, w, col(GSv, j), s, part, Md + (size_t)j * cap, st);
     }
-    for (int i = 0; i < w0; ++i)
-      launch_multidot<DT>(col(Sv, w0), s, w - w0, col(GSv, i), s, part, Td + (size_t)i * cap + w0, st);
-    std::vector<DT> tt((size_t)cap * cap), mm((size_t)cap * cap);
+    // T[i, j] for a new column i and an old column j is conj((G v_j)^H v_i):
+    // one multi-dot per new column against the old products (staged in Cd)
+    // instead of one per old column
+    for (int i = w0; i < w; ++i)
+      launch_multidot<DT>(GSv, s, w0, col(Sv, i), s, part, Cd + (size_t)(i - w0) * cap, st);
+    std::vector<DT> tt((size_t)cap * cap), mm((size_t)cap * cap), tn((size_t)cap * (w - w0));
+    HIPCHK(hipMemcpyAsync(tn.data(), Cd, tn.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(tt.data(), Td, tt.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(mm.data(), Md, mm.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -395,7 +413,8 @@ static bool lowrank_block(gs_ctx* c, int l, int kreq, const float* Y) {
         at(Mh, j, i) = std::conj(at(Mh, i, j));
       }
     for (int i = 0; i < w0; ++i)
-      for (int j = w0; j < w; ++j) at(Th, j, i) = to_cplx<T>(tt.data(), (size_t)i * cap + j);
+      for (int j = w0; j < w; ++j)
+        at(Th, j, i) = std::conj(to_cplx<T>(tn.data(), (size_t)(j - w0) * cap + i));
   };
   auto square = [&](const std::vector<cplx>& A, int m) {
     std::vector<cplx> B((size_t)m * m);
@@ -504,9 +523,10 @@ static bool lowrank_block(gs_ctx* c, int l, int kreq, const float* Y) {
     if (w + nb > mmax) {
       const int keep = std::max(k, mmax - nb);
       if (keep < w) {
-        std::vector<cplx> Tm2, Q2, th2;
+        // the Schur form of T from this iteration, reordered for `keep`
+        std::vector<cplx> Tm2 = Tm, Q2 = Q, th2;
         std::vector<T> G2, R2;
-        const int k2 = schur_basis<T>(w, Tw, keep, Tm2, Q2, th2, G2, R2);
+        const int k2 = schur_basis_from<T>(w, Tw, keep, Tm2, Q2, th2, G2, R2);
         const std::vector<cplx> Gc = as_cplx(G2);
         upload(Gc, w, k2, Cd);
         launch_gemm_small<DT>(Sv, s, w, Cd, k2, tmp, s, s, st);
@@ -739,6 +759,16 @@ static void copy_csr(int64_t nr, int64_t nc, const int64_t* rp, const int32_t* c
   if (nnz) std::memcpy((void*)out.v.data(), v, nnz * sizeof(T));
 }
 
+// the low-rank kernels take k <= 1024 per level (k = min(rank, s_l)); checked
+// before any factorisation or Arnoldi work
+template <class T>
+static void check_rank(const HostSetup<T>& S, int rank) {
+  for (int l = 0; l < S.L(); ++l)
+    if (std::min<int64_t>(rank, S.lv[l].s) > 1024)
+      throw Error(GS_EINVAL, "rank above 1024 on level " + std::to_string(l) +
+                                 " is not supported");
+}
+
 static inline void set_imag_shift(double& s, double v) { (void)v; s = 0.0; }
 static inline void set_imag_shift(cplx& s, double v) { s = cplx(0.0, v); }
 
@@ -754,6 +784,7 @@ static void setup_native(gs_ctx* c, int64_t n, const int64_t* rp, const int32_t*
   if (part.L > GS_MAX_LEVELS) throw Error(GS_EINVAL, "too many levels");
   double t1 = now_s();
   extract_levels<T>(S->A, part, *S);
+  check_rank<T>(*S, rank);
   T shift = T(0);
   if (c->opts.ilu_shift != 0.0) {
     if (!std::is_same<T, cplx>::value)
@@ -946,6 +977,7 @@ static int features(gs_ctx* c, int l, float* X, int64_t rows_cap, int cols_cap) 
 template <class T>
 static void lowrank_all(gs_ctx* c, int rank, const float* const* warm) {
   HostSetup<T>& H = host<T>(c);
+  check_rank<T>(H, rank);
   const double t0 = now_s();
   for (int l = H.L() - 1; l >= 0; --l) {
     HostLevel<T>& h = H.lv[l];

@@ -144,7 +144,7 @@ def setup_with(w, rank, mode, mlp=None, levels=(0, 1), seed=0, **extra):
     return ctx, time.perf_counter() - t0
 
 
-def evaluate(instances, mlp, N=64, nparts=64, rank=32, tol=1e-8, levels=(0, 1)):
+def evaluate(instances, mlp, N=64, nparts=64, rank=32, tol=1e-8, levels=(0, 1), log=None):
     """Per held-out instance and mode: matvecs of the low-rank stage, its
     time, FGMRES iterations, true relative residual and time to tol."""
     import torch
@@ -167,6 +167,10 @@ def evaluate(instances, mlp, N=64, nparts=64, rank=32, tol=1e-8, levels=(0, 1)):
                          "converged": bool(res["converged"]), "t_solve_s": t_s,
                          "time_to_tol_s": t_lr + t_s})
             ctx.close()
+            if log:
+                r = rows[-1]
+                log(f"[learned] instance {i} {mode}: matvecs {r['matvecs']} lowrank "
+                    f"{r['t_lowrank_s']:.3f} s its {r['its']} time-to-tol {r['time_to_tol_s']:.3f} s")
     return rows
 
 
@@ -234,7 +238,7 @@ def main(argv=None):
         mlp = gemslr.Mlp(*dims)
         mlp.set_params(z["params"])
         rows = evaluate(range(100000, 100000 + a.n_heldout), mlp, a.N, a.nparts, a.rank,
-                        levels=levels)
+                        levels=levels, log=log)
         rep = {"summary": summarise(rows), "rows": rows}
         log(f"[learned] summary: {json.dumps(rep['summary'])}")
     if a.report:

@@ -95,3 +95,18 @@ def test_not_converged_status(G):
     assert info["status"] == G.GS_NOT_CONVERGED and info["its"] == 2
     assert not info["converged"] and info["relres"] > 1e-12
     ctx.close()
+
+
+def test_rank_limit_rejected_before_setup_work(G):
+    """k = min(rank, s_l) above 1024 on some level is refused right after the
+    partition (before factorisation or Arnoldi)."""
+    import time
+    w = wl.convdiff3d_64(N=20, nparts=8)
+    ctx = G.Context(0)
+    t0 = time.perf_counter()
+    with pytest.raises(G.GemslrError) as e:
+        ctx.setup(w.rowptr, w.col, w.val, w.levels, w.nparts, 1100, w.drop_tol, lfil=w.lfil,
+                  grid_dims=w.dims)
+    assert e.value.code == G.GS_EINVAL and "1024" in str(e.value)
+    assert time.perf_counter() - t0 < 5.0
+    ctx.close()
