@@ -61,7 +61,9 @@ typedef struct {
   int precision;          /* GS_PREC_*: storage of L, U, E, F, W in the apply;
                              F32/BF16 solve in float32           [GS_PREC_F64] */
   int grid_ndim;          /* >0: A is a grid operator with lexicographic
-                             numbering x + N0*y + N0*N1*z                 [0]  */
+                             numbering x + N0*y + N0*N1*z (geometric
+                             separator); 0: nested dissection of the graph
+                             of A (gs_partition_graph)                   [0]  */
   int32_t grid_dims[3];   /* points per axis for the geometric separator     */
   uint64_t seed;          /* Arnoldi start vectors (SplitMix64)        [0]    */
   int nthreads;           /* host threads for the factorisation (0 = all)     */
@@ -135,8 +137,9 @@ const char* gs_last_error(const gs_ctx* ctx);
 /* Build M^{-1} for the n x n matrix A (Alg. 1, Sec. 4.2):
  *  - reorder A with a multilevel p-way vertex separator (Alg. 3, Sec. 3)
  *    into `levels` levels of `nparts` parts (fewer when the separator is too
- *    small to split, Sec. 3.2); this build takes the geometric separator of
- *    a grid graph, so opts->grid_ndim/grid_dims are required;
+ *    small to split, Sec. 3.2): the geometric separator when
+ *    opts->grid_ndim > 0, else nested dissection of A's graph (nparts a
+ *    power of two);
  *  - incomplete LU of every diagonal block of B_l (ILUT(drop_tol, lfil) or
  *    ILU(0)), and block-Jacobi ILU of the last separator (Sec. 4.3);
  *  - rank-`rank` Schur-complement correction W_l, R_l at every level,
@@ -309,6 +312,26 @@ int gs_partition_grid(int ndim, const int32_t* dims, int nparts, int levels,
                       int64_t* perm, int64_t* level_start, int* nlevels,
                       int64_t* block_ptr, int64_t* block_count,
                       int64_t block_cap);
+
+/* The same level structure for a matrix without grid coordinates (the paper
+ * partitions with ParMETIS, Sec. 3.2; here: nested dissection by
+ * breadth-first level structures).  nparts must be a power of two.  One
+ * bisection of a vertex set P: if P's subgraph is disconnected, its
+ * components (largest first, ties by smallest vertex) go to the lighter half
+ * with no separator; otherwise the breadth-first levels from a
+ * pseudo-peripheral vertex (start at the smallest vertex, move to the
+ * smallest vertex of the last level while the eccentricity grows, at most
+ * 10 moves) are split at the level m of the median vertex in (level, index)
+ * order (the last level is replaced by the one before it): the separator is
+ * the level-m vertices with a neighbour in level m+1.  log2(nparts) rounds of
+ * bisection give a p-way separator; the separator is partitioned again at
+ * the next level (Alg. 3); vertex classes, the stop rule, block order and
+ * outputs are those of gs_partition_grid, with at most as many levels as
+ * separator classes.  gs_setup uses it when opts.grid_ndim is 0.  Host only.
+ * Errors: GS_EINVAL. */
+int gs_partition_graph(int nparts, int levels, int64_t n, const int64_t* rowptr,
+                       const int32_t* col, int64_t* perm, int64_t* level_start, int* nlevels,
+                       int64_t* block_ptr, int64_t* block_count, int64_t block_cap);
 
 /* Incomplete LU of one square host CSR matrix (ILUT(tau, lfil) or ILU(0),
  * row-wise IKJ).  Host only.  L (strictly lower, unit diagonal implied) and U

@@ -778,9 +778,10 @@ static void setup_native(gs_ctx* c, int64_t n, const int64_t* rp, const int32_t*
   auto S = std::make_unique<HostSetup<T>>();
   copy_csr<T>(n, n, rp, ci, val, S->A);
   double t0 = now_s();
-  if (c->opts.grid_ndim <= 0)
-    throw Error(GS_EINVAL, "the geometric separator needs opts.grid_ndim / grid_dims");
-  Partition part = partition_grid(c->opts.grid_ndim, c->opts.grid_dims, nparts, levels, n, rp, ci);
+  // geometric separator for grid operators, nested dissection otherwise
+  Partition part = c->opts.grid_ndim > 0
+                       ? partition_grid(c->opts.grid_ndim, c->opts.grid_dims, nparts, levels, n, rp, ci)
+                       : partition_graph(nparts, levels, n, rp, ci);
   if (part.L > GS_MAX_LEVELS) throw Error(GS_EINVAL, "too many levels");
   double t1 = now_s();
   extract_levels<T>(S->A, part, *S);
@@ -1340,6 +1341,15 @@ int gs_get_info(const gs_ctx* c, gs_info* info) {
   return GS_OK;
 }
 
+static int export_partition_impl(const Partition& p, int64_t* perm, int64_t* level_start,
+                                 int* nlevels, int64_t* block_ptr, int64_t* block_count,
+                                 int64_t block_cap);
+static int export_partition(const Partition& p, int64_t* perm, int64_t* level_start,
+                            int* nlevels, int64_t* block_ptr, int64_t* block_count,
+                            int64_t block_cap) {
+  return export_partition_impl(p, perm, level_start, nlevels, block_ptr, block_count, block_cap);
+}
+
 int gs_partition_grid(int ndim, const int32_t* dims, int nparts, int levels, int64_t n,
                       const int64_t* rowptr, const int32_t* col, int64_t* perm,
                       int64_t* level_start, int* nlevels, int64_t* block_ptr,
@@ -1350,6 +1360,27 @@ int gs_partition_grid(int ndim, const int32_t* dims, int nparts, int levels, int
       throw Error(GS_EINVAL, "NULL output");
     validate_csr(n, rowptr, col, false);
     Partition p = partition_grid(ndim, dims, nparts, levels, n, rowptr, col);
+    return export_partition(p, perm, level_start, nlevels, block_ptr, block_count, block_cap);
+  });
+}
+
+int gs_partition_graph(int nparts, int levels, int64_t n, const int64_t* rowptr,
+                       const int32_t* col, int64_t* perm, int64_t* level_start, int* nlevels,
+                       int64_t* block_ptr, int64_t* block_count, int64_t block_cap) {
+  gs_ctx* none = nullptr;
+  GS_GUARD(none, {
+    if (!perm || !level_start || !nlevels || !block_ptr || !block_count)
+      throw Error(GS_EINVAL, "NULL output");
+    validate_csr(n, rowptr, col, false);
+    Partition p = partition_graph(nparts, levels, n, rowptr, col);
+    return export_partition(p, perm, level_start, nlevels, block_ptr, block_count, block_cap);
+  });
+}
+
+static int export_partition_impl(const Partition& p, int64_t* perm, int64_t* level_start,
+                                 int* nlevels, int64_t* block_ptr, int64_t* block_count,
+                                 int64_t block_cap) {
+  {
     int64_t need = 0;
     for (auto& b : p.blocks) need += (int64_t)b.size();
     if (need > block_cap) throw Error(GS_EINVAL, "block_cap too small");
@@ -1362,7 +1393,7 @@ int gs_partition_grid(int ndim, const int32_t* dims, int nparts, int levels, int
       for (int64_t x : p.blocks[l]) block_ptr[pos++] = x;
     }
     return GS_OK;
-  });
+  }
 }
 
 int gs_ilu(int64_t n, const int64_t* rowptr, const int32_t* col, const void* val, int dtype,

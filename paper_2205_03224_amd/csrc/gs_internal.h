@@ -54,6 +54,10 @@ void validate_csr(int64_t n, const int64_t* rp, const int32_t* ci,
 Partition partition_grid(int ndim, const int32_t* dims, int nparts,
                          int levels, int64_t n, const int64_t* rp,
                          const int32_t* ci);
+// Nested dissection by breadth-first level structures (no coordinates
+// needed); nparts a power of two.
+Partition partition_graph(int nparts, int levels, int64_t n, const int64_t* rp,
+                          const int32_t* ci);
 
 // --------------------------------------------------------------- ILU
 template <class T>

@@ -111,6 +111,8 @@ bool has_edges(const Graph& g, const std::vector<char>& in_set) {
   return false;
 }
 
+Partition assemble(const Graph& g, const std::vector<int>& cls, int nparts, int Lmax);
+
 }  // namespace
 
 Partition partition_grid(int ndim, const int32_t* dims, int nparts, int levels,
@@ -156,17 +158,23 @@ Partition partition_grid(int ndim, const int32_t* dims, int nparts, int levels,
     cls[i] = c;
   }
   Graph g = sym_graph(n, rp, ci);
-  int L;
-  if (q == 1) {
-    L = 1;
-  } else {
-    L = std::min(levels, ndim);
-    for (int l = 0; l < L - 1; ++l) {
-      std::vector<char> rest(n);
-      int64_t cnt = 0;
-      for (int64_t i = 0; i < n; ++i) { rest[i] = cls[i] > l; cnt += rest[i]; }
-      if (cnt < nparts || !has_edges(g, rest)) { L = l + 1; break; }
-    }
+  return assemble(g, cls, nparts, q == 1 ? 1 : std::min(levels, ndim));
+}
+
+namespace {
+
+// The level structure from vertex classes (B_l = class l, C_l = class > l):
+// at most Lmax levels, fewer when the next separator has fewer than nparts
+// vertices or no edges (Sec. 3.2); blocks are the connected components in
+// order of their smallest vertex, rows ascending inside a block.
+Partition assemble(const Graph& g, const std::vector<int>& cls, int nparts, int Lmax) {
+  const int64_t n = (int64_t)cls.size();
+  int L = std::max(1, Lmax);
+  for (int l = 0; l < L - 1; ++l) {
+    std::vector<char> rest(n);
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i) { rest[i] = cls[i] > l; cnt += rest[i]; }
+    if (cnt < nparts || !has_edges(g, rest)) { L = l + 1; break; }
   }
   Partition P;
   P.L = L;
@@ -186,6 +194,146 @@ Partition partition_grid(int ndim, const int32_t* dims, int nparts, int levels,
     P.level_start.push_back(pos);
   }
   return P;
+}
+
+// ---- algebraic separator: nested dissection by breadth-first level
+// structures (the rules of the algebraic partitioner, stated in
+// include/gemslr.h at gs_partition_graph).  Work arrays are indexed by the
+// position of a vertex in the current part P.
+struct NdWork {
+  std::vector<int64_t> loc;   // vertex -> position in P, -1 outside
+  std::vector<int> lev;       // BFS level per position, -1 unreached
+  std::vector<int64_t> queue;
+  explicit NdWork(int64_t n) : loc(n, -1) {}
+};
+
+// BFS levels over P from position r; returns the eccentricity
+static int bfs_levels(const Graph& g, const std::vector<int64_t>& P, NdWork& W, int64_t r) {
+  W.lev.assign(P.size(), -1);
+  W.queue.clear();
+  W.queue.push_back(r);
+  W.lev[r] = 0;
+  int ecc = 0;
+  for (size_t h = 0; h < W.queue.size(); ++h) {
+    const int64_t u = W.queue[h];
+    const int lu = W.lev[u];
+    ecc = std::max(ecc, lu);
+    for (int64_t p = g.xadj[P[u]]; p < g.xadj[P[u] + 1]; ++p) {
+      const int64_t w = W.loc[g.adj[p]];
+      if (w >= 0 && W.lev[w] < 0) { W.lev[w] = lu + 1; W.queue.push_back(w); }
+    }
+  }
+  return ecc;
+}
+
+// Bisect P (sorted) into A, B and separator S.
+static void bisect(const Graph& g, const std::vector<int64_t>& P, NdWork& W,
+                   std::vector<int64_t>& A, std::vector<int64_t>& B, std::vector<int64_t>& S) {
+  A.clear(); B.clear(); S.clear();
+  if (P.size() <= 1) { A = P; return; }
+  for (size_t i = 0; i < P.size(); ++i) W.loc[P[i]] = (int64_t)i;
+  // connected components of P (each sorted, in order of the smallest vertex)
+  std::vector<std::vector<int64_t>> comps;
+  {
+    std::vector<int> comp(P.size(), -1);
+    for (size_t i = 0; i < P.size(); ++i) {
+      if (comp[i] >= 0) continue;
+      bfs_levels(g, P, W, (int64_t)i);
+      std::vector<int64_t> c;
+      for (size_t j = 0; j < P.size(); ++j)
+        if (W.lev[j] >= 0) { comp[j] = (int)comps.size(); c.push_back(P[j]); }
+      comps.push_back(std::move(c));
+    }
+  }
+  if (comps.size() > 1) {
+    std::vector<size_t> order(comps.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+      if (comps[x].size() != comps[y].size()) return comps[x].size() > comps[y].size();
+      return comps[x][0] < comps[y][0];
+    });
+    size_t na = 0, nb = 0;
+    for (size_t i : order) {
+      if (na <= nb) { A.insert(A.end(), comps[i].begin(), comps[i].end()); na += comps[i].size(); }
+      else { B.insert(B.end(), comps[i].begin(), comps[i].end()); nb += comps[i].size(); }
+    }
+    std::sort(A.begin(), A.end());
+    std::sort(B.begin(), B.end());
+  } else {
+    // pseudo-peripheral start: smallest vertex, then the smallest vertex of
+    // the last level while the eccentricity grows (at most 10 moves)
+    int64_t r = 0;
+    int ecc = bfs_levels(g, P, W, r);
+    for (int it = 0; it < 10; ++it) {
+      int64_t cand = -1;
+      for (size_t j = 0; j < P.size(); ++j)
+        if (W.lev[j] == ecc) { cand = (int64_t)j; break; }  // P sorted: smallest vertex
+      std::vector<int> keep = W.lev;
+      const int ecc2 = bfs_levels(g, P, W, cand);
+      if (ecc2 <= ecc) { W.lev = keep; break; }
+      r = cand;
+      ecc = ecc2;
+    }
+    // level of the median vertex in (level, index) order
+    std::vector<int64_t> cnt(ecc + 2, 0);
+    for (int l : W.lev) ++cnt[l];
+    const int64_t half = (int64_t)P.size() / 2;
+    int m = 0;
+    for (int64_t acc = 0; m <= ecc; ++m) {
+      if (acc + cnt[m] > half) break;
+      acc += cnt[m];
+    }
+    if (m == ecc) m = ecc - 1;
+    for (size_t j = 0; j < P.size(); ++j) {
+      const int lj = W.lev[j];
+      if (lj < m) { A.push_back(P[j]); continue; }
+      if (lj > m) { B.push_back(P[j]); continue; }
+      bool sep = false;
+      for (int64_t p = g.xadj[P[j]]; p < g.xadj[P[j] + 1] && !sep; ++p) {
+        const int64_t w = W.loc[g.adj[p]];
+        sep = w >= 0 && W.lev[w] == m + 1;
+      }
+      (sep ? S : A).push_back(P[j]);
+    }
+  }
+  for (int64_t v : P) W.loc[v] = -1;
+}
+
+}  // namespace
+
+Partition partition_graph(int nparts, int levels, int64_t n, const int64_t* rp,
+                          const int32_t* ci) {
+  if (nparts < 1 || (nparts & (nparts - 1)) != 0)
+    throw Error(GS_EINVAL, "the algebraic partitioner needs nparts = a power of two");
+  if (levels < 1) throw Error(GS_EINVAL, "levels must be >= 1");
+  int d = 0;
+  while ((1 << d) < nparts) ++d;
+  Graph g = sym_graph(n, rp, ci);
+  std::vector<int> cls(n, 0);
+  std::vector<int64_t> active(n);
+  for (int64_t i = 0; i < n; ++i) active[i] = i;
+  NdWork W(n);
+  std::vector<int64_t> A, B, S;
+  for (int l = 0; l < levels && d > 0 && !active.empty(); ++l) {
+    std::vector<std::vector<int64_t>> parts{active};
+    std::vector<int64_t> seps;
+    for (int r = 0; r < d; ++r) {
+      std::vector<std::vector<int64_t>> next;
+      for (auto& Pp : parts) {
+        bisect(g, Pp, W, A, B, S);
+        seps.insert(seps.end(), S.begin(), S.end());
+        next.push_back(A);
+        next.push_back(B);
+      }
+      parts.swap(next);
+    }
+    std::sort(seps.begin(), seps.end());
+    for (int64_t v : seps) cls[v] = l + 1;
+    active.swap(seps);
+  }
+  int maxc = 0;
+  for (int c : cls) maxc = std::max(maxc, c);
+  return assemble(g, cls, nparts, (nparts == 1 || maxc == 0) ? 1 : std::min(levels, maxc));
 }
 
 // ---------------------------------------------------------------- levels

@@ -109,6 +109,8 @@ SIGNATURES = [
     ("gs_get_info", ct.c_int, [_p, ct.POINTER(GsInfo)]),
     ("gs_partition_grid", ct.c_int, [ct.c_int, _p, ct.c_int, ct.c_int, ct.c_int64, _p, _p,
                                      _p, _p, ct.POINTER(ct.c_int), _p, _p, ct.c_int64]),
+    ("gs_partition_graph", ct.c_int, [ct.c_int, ct.c_int, ct.c_int64, _p, _p, _p, _p,
+                                      ct.POINTER(ct.c_int), _p, _p, ct.c_int64]),
     ("gs_ilu", ct.c_int, [ct.c_int64, _p, _p, _p, ct.c_int, ct.c_int, ct.c_double, ct.c_int,
                           _p, _p, _p, ct.c_int64, _p, _p, _p, ct.c_int64]),
     ("gs_features", ct.c_int, [_p, ct.c_int, _p, ct.c_int64, ct.c_int,
@@ -411,6 +413,30 @@ def partition_grid(dims, nparts, levels, rowptr, col):
     bc = np.zeros(levels + 1, np.int64)
     rc = lib().gs_partition_grid(len(d), _ptr(d), nparts, levels, n, _ptr(rp), _ptr(ci),
                                  _ptr(perm), _ptr(ls), ct.byref(nl), _ptr(bp), _ptr(bc), cap)
+    if rc != GS_OK:
+        raise GemslrError(rc, lib().gs_last_error(None).decode())
+    L = nl.value
+    blocks, pos = [], 0
+    for l in range(L + 1):
+        cnt = int(bc[l]) + 1
+        blocks.append(bp[pos:pos + cnt].copy())
+        pos += cnt
+    return perm, ls[:L + 2].copy(), L, blocks
+
+
+def partition_graph(nparts, levels, rowptr, col):
+    """gs_partition_graph: (perm, level_start, L, blocks) for a matrix without
+    grid coordinates."""
+    rp, ci = _i64(rowptr), _i32(col)
+    n = len(rp) - 1
+    perm = np.zeros(n, np.int64)
+    ls = np.zeros(levels + 2, np.int64)
+    nl = ct.c_int()
+    cap = n + levels + 2
+    bp = np.zeros(cap, np.int64)
+    bc = np.zeros(levels + 1, np.int64)
+    rc = lib().gs_partition_graph(nparts, levels, n, _ptr(rp), _ptr(ci), _ptr(perm), _ptr(ls),
+                                  ct.byref(nl), _ptr(bp), _ptr(bc), cap)
     if rc != GS_OK:
         raise GemslrError(rc, lib().gs_last_error(None).decode())
     L = nl.value
