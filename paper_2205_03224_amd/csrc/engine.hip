@@ -9,9 +9,11 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <functional>
 #include <memory>
 #include <string>
+#include <thread>
 #include <type_traits>
 
 #include "device.h"
@@ -149,7 +151,7 @@ TriHost<T> build_tri(const CSR<T>& M, const std::vector<int64_t>& blocks, bool u
 // whole stages of at most `cap` bytes (see ChunkDesc).  Returns false if a
 // single stage does not fit.
 template <class V, class D, class T>
-bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, int ms,
+bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, int cap, int ms,
                   int col_scale, int max_rows, std::vector<uint8_t>& blob,
                   std::vector<ChunkDesc>& desc, std::vector<int32_t>& blk_chunk) {
   auto pad = [](size_t x) { return (x + 15) & ~(size_t)15; };
@@ -158,7 +160,7 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, i
   blob.clear();
   desc.clear();
   blk_chunk.assign(1, 0);
-  for (int b = 0; b < nb; ++b) {
+  for (int b = b0; b < b1; ++b) {
     for (int tri = 0; tri < 2; ++tri) {
       const TriHost<T>& h = tri == 0 ? lo : up;
       const bool isU = tri == 1;
@@ -232,6 +234,95 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, i
       }
     }
     blk_chunk.push_back((int32_t)desc.size());
+  }
+  return true;
+}
+
+// ---- the same two builders over block ranges on host threads, merged in
+// block order (the result is identical to one sequential pass)
+static int layout_threads(size_t nb) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  return (int)std::max<size_t>(1, std::min<size_t>({(size_t)hw, (size_t)16, nb / 8 + 1}));
+}
+
+template <class T>
+TriHost<T> build_tri_par(const CSR<T>& M, const std::vector<int64_t>& blocks, bool upper) {
+  const size_t nb = blocks.size() - 1;
+  const int nt = layout_threads(nb);
+  if (nt <= 1) return build_tri(M, blocks, upper);
+  std::vector<TriHost<T>> part(nt);
+  std::vector<std::exception_ptr> err(nt);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      try {
+        const size_t b0 = nb * t / nt, b1 = nb * (t + 1) / nt;
+        std::vector<int64_t> sub(blocks.begin() + b0, blocks.begin() + b1 + 1);
+        part[t] = build_tri(M, sub, upper);
+      } catch (...) {
+        err[t] = std::current_exception();
+      }
+    });
+  for (auto& x : th) x.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+  TriHost<T> h = std::move(part[0]);
+  for (int t = 1; t < nt; ++t) {
+    const TriHost<T>& q = part[t];
+    const int32_t so = (int32_t)h.stage_row.size() - 1;
+    const int32_t ro = (int32_t)h.rowinfo.size(), eo = (int32_t)h.val.size();
+    for (size_t i = 1; i < q.blk_stage.size(); ++i) h.blk_stage.push_back(q.blk_stage[i] + so);
+    for (size_t i = 1; i < q.stage_row.size(); ++i) h.stage_row.push_back(q.stage_row[i] + ro);
+    for (size_t i = 1; i < q.stage_ent.size(); ++i) h.stage_ent.push_back(q.stage_ent[i] + eo);
+    h.rowinfo.insert(h.rowinfo.end(), q.rowinfo.begin(), q.rowinfo.end());
+    h.dinv.insert(h.dinv.end(), q.dinv.begin(), q.dinv.end());
+    h.val.insert(h.val.end(), q.val.begin(), q.val.end());
+    h.col.insert(h.col.end(), q.col.begin(), q.col.end());
+    h.maxslot = std::max(h.maxslot, q.maxslot);
+    h.depth = std::max(h.depth, q.depth);
+  }
+  return h;
+}
+
+template <class V, class D, class T>
+bool build_chunks_par(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, int ms,
+                      int col_scale, int max_rows, std::vector<uint8_t>& blob,
+                      std::vector<ChunkDesc>& desc, std::vector<int32_t>& blk_chunk) {
+  const int nt = layout_threads((size_t)nb);
+  std::vector<std::vector<uint8_t>> pb(nt);
+  std::vector<std::vector<ChunkDesc>> pd(nt);
+  std::vector<std::vector<int32_t>> pc(nt);
+  std::vector<char> ok(nt, 0);
+  std::vector<std::exception_ptr> err(nt);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      try {
+        const int b0 = (int)((int64_t)nb * t / nt), b1 = (int)((int64_t)nb * (t + 1) / nt);
+        ok[t] = build_chunks<V, D, T>(lo, up, b0, b1, cap, ms, col_scale, max_rows, pb[t], pd[t],
+                                      pc[t]);
+      } catch (...) {
+        err[t] = std::current_exception();
+      }
+    });
+  for (auto& x : th) x.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+  for (char o : ok)
+    if (!o) return false;
+  blob.clear();
+  desc.clear();
+  blk_chunk.assign(1, 0);
+  for (int t = 0; t < nt; ++t) {
+    const size_t base = blob.size();
+    if (base + pb[t].size() > 0xffffffffull) throw Error(GS_EINVAL, "level too large for 32-bit offsets");
+    const int32_t d0 = (int32_t)desc.size();
+    blob.insert(blob.end(), pb[t].begin(), pb[t].end());
+    for (ChunkDesc cd : pd[t]) {
+      cd.off += (uint32_t)base;
+      desc.push_back(cd);
+    }
+    for (size_t i = 1; i < pc[t].size(); ++i) blk_chunk.push_back(pc[t][i] + d0);
   }
   return true;
 }
@@ -358,8 +449,8 @@ struct EngineT final : Engine {
       for (int b = 0; b < L.nb; ++b)
         L.max_block_rows = std::max<int>(L.max_block_rows, (int)(h.blocks[b + 1] - h.blocks[b]));
       L.blk_row = upload(br);
-      TriHost<T> tl = build_tri(h.L, h.blocks, false);
-      TriHost<T> tu = build_tri(h.U, h.blocks, true);
+      TriHost<T> tl = build_tri_par(h.L, h.blocks, false);
+      TriHost<T> tu = build_tri_par(h.U, h.blocks, true);
       L.maxslot = std::max(tl.maxslot, tu.maxslot);
       L.depth_l = tl.depth;
       L.depth_u = tu.depth;
@@ -383,8 +474,8 @@ struct EngineT final : Engine {
           std::vector<uint8_t> blob;
           std::vector<ChunkDesc> desc;
           std::vector<int32_t> bc;
-          if (build_chunks<V, D, T>(tl, tu, L.nb, cap, ms, ColScale<C>::value,
-                                    L.max_block_rows + 1, blob, desc, bc)) {
+          if (build_chunks_par<V, D, T>(tl, tu, L.nb, cap, ms, ColScale<C>::value,
+                                        L.max_block_rows + 1, blob, desc, bc)) {
             L.blob = upload(blob);
             std::vector<uint8_t> draw(desc.size() * sizeof(ChunkDesc));
             if (!desc.empty()) std::memcpy(draw.data(), desc.data(), draw.size());
@@ -396,8 +487,12 @@ struct EngineT final : Engine {
           }
         }
       }
-      L.lo = upload_tri(tl, false);
-      L.up = upload_tri(tu, true);
+      // the per-stage layout only feeds the register-prefetch kernel, used
+      // when the streamed layout is unavailable or switched off
+      if (!L.blob || no_stream) {
+        L.lo = upload_tri(tl, false);
+        L.up = upload_tri(tu, true);
+      }
       L.nnz_lu = h.L.nnz() + h.U.nnz();
       if (h.s > 0) {
         L.E = upload_csr(h.E);
