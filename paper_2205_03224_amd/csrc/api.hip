@@ -150,15 +150,19 @@ static int schur_basis_from(int m, const std::vector<cplx>& Sm, int k, std::vect
         }
       for (int i = 0; i < m; ++i) g[(size_t)q * m + i] = qv[i];
     }
+    // R = G^T (Sm G): Sm G once (m x kk), then the kk x kk product
     double* r = (double*)R.data();
+    std::vector<double> sg((size_t)m * kk, 0.0);
+    for (int b = 0; b < kk; ++b)
+      for (int j = 0; j < m; ++j) {
+        const double gj = g[(size_t)b * m + j];
+        if (gj == 0.0) continue;
+        for (int i = 0; i < m; ++i) sg[(size_t)b * m + i] += Sm[(size_t)j * m + i].real() * gj;
+      }
     for (int b = 0; b < kk; ++b)
       for (int a = 0; a < kk; ++a) {
         double acc = 0;
-        for (int i = 0; i < m; ++i) {
-          double sg = 0;
-          for (int j = 0; j < m; ++j) sg += Sm[(size_t)j * m + i].real() * g[(size_t)b * m + j];
-          acc += g[(size_t)a * m + i] * sg;
-        }
+        for (int i = 0; i < m; ++i) acc += g[(size_t)a * m + i] * sg[(size_t)b * m + i];
         r[(size_t)b * kk + a] = acc;
       }
   } else {
