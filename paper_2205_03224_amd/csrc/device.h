@@ -92,7 +92,8 @@ enum { TRI_DOWN = 0, TRI_UP = 1 };
 // 16-byte aligned byte range:
 //   values       rows x VS x V          (offset 0)
 //   inverse diag rows x D               (U chunks only)
-//   row info     rows x uint32: block-local row | count << 16 | stage rows << 24
+//   row info     (rows + 1) x uint32: block-local row | count << 16 | stage rows << 24
+//                (the last word zero: reading past the last stage gives 0 rows)
 //   columns      (rows + 1) x CS x uint16 (the last row all zero)
 // Each row of the chunk (rows of consecutive stages follow each other) holds
 // its MS slots contiguously (MS = stream_slots(level's longest row)): the
@@ -119,10 +120,10 @@ __host__ __device__ constexpr int stream_slots(int maxslot) {
 }
 __host__ __device__ constexpr int stream_vstride(int ms) { return ms + 1; }
 __host__ __device__ constexpr int stream_cstride(int ms) { return ms <= 4 ? 4 : ms <= 12 ? 12 : 20; }
-// byte scale of the stored column: sizeof(C), except 8 for complex128
-// (16-bit offsets then cover 8192 rows; the kernel doubles them)
+// byte scale of the stored column: the element size, so the stored value is
+// the element's LDS byte offset (16-bit: blocks of up to 65536 / sizeof(C)
+// rows use the streamed layout)
 template <class C> struct ColScale { static constexpr int value = (int)sizeof(C); };
-template <> struct ColScale<dcplx> { static constexpr int value = 8; };
 
 template <class P>
 struct TriArgs {
@@ -140,6 +141,7 @@ struct TriArgs {
   const int32_t* blk_chunk;  // nb+1 chunk ranges
   int32_t chunk_cap;         // max chunk bytes (multiple of 1 KiB)
   int32_t x_bytes;           // LDS bytes reserved for the block's vector (16-aligned)
+  int32_t nbuf;              // chunk buffers in LDS: 2 (one chunk in flight) or 3 (two)
 };
 
 template <class P>

@@ -155,8 +155,9 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, in
                   int col_scale, int max_rows, std::vector<uint8_t>& blob,
                   std::vector<ChunkDesc>& desc, std::vector<int32_t>& blk_chunk) {
   auto pad = [](size_t x) { return (x + 15) & ~(size_t)15; };
-  // block-vector byte offsets must fit the 16-bit column field
-  if ((size_t)max_rows * (size_t)col_scale > 65535) return false;
+  // block-vector byte offsets of the columns (rows 0 .. max_rows - 1) must
+  // fit the 16-bit column field
+  if (max_rows > 0 && (size_t)(max_rows - 1) * (size_t)col_scale > 65535) return false;
   blob.clear();
   desc.clear();
   blk_chunk.assign(1, 0);
@@ -168,8 +169,8 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, in
       const int VS = stream_vstride(ms), CS = stream_cstride(ms);
       auto size_of = [&](int s0, int s1) {
         const size_t rows = h.stage_row[s1] - h.stage_row[s0];
-        return pad(rows * VS * sizeof(V)) + (isU ? pad(rows * sizeof(D)) : 0) + pad(rows * 4) +
-               pad((rows + 1) * CS * 2);
+        return pad(rows * VS * sizeof(V)) + (isU ? pad(rows * sizeof(D)) : 0) +
+               pad((rows + 1) * 4) + pad((rows + 1) * CS * 2);
       };
       int s = sb;
       while (s < se) {
@@ -185,7 +186,7 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, in
         const size_t o_val = 0;
         const size_t o_dinv = pad(rows * VS * sizeof(V));
         const size_t o_info = o_dinv + (isU ? pad(rows * sizeof(D)) : 0);
-        const size_t o_col = o_info + pad(rows * 4);
+        const size_t o_col = o_info + pad((rows + 1) * 4);  // zero word after the last row
         const size_t total = o_col + pad((rows + 1) * CS * 2);
         // the device copies whole 1 KiB rows of the chunk buffer
         if (total > (size_t)cap || cap % 1024 != 0) return false;
@@ -353,7 +354,7 @@ struct EngineT final : Engine {
     const uint8_t* blob = nullptr;
     const ChunkDesc* chunk = nullptr;
     const int32_t* blk_chunk = nullptr;
-    int chunk_cap = 0, x_bytes = 0;
+    int chunk_cap = 0, x_bytes = 0, nbuf = 2;
     int64_t nchunks = 0;
     int depth_l = 0, depth_u = 0;
   };
@@ -410,6 +411,10 @@ struct EngineT final : Engine {
   int num_cus = 256, lds_per_cu = 163840;
   bool fixed_budget = false;
   bool no_stream = std::getenv("GEMSLR_NO_STREAM") != nullptr;
+  // chunk buffers per workgroup: 2 (one copy in flight while a chunk is
+  // swept) measures faster than 3 (two in flight, but chunks a third smaller
+  // and more hand-offs); GEMSLR_CHUNK_BUFS=3 selects the latter
+  int chunk_bufs = 2;
 
   EngineT(const HostSetup<T>& S, hipStream_t stream) : st(stream) {
     n = S.n;
@@ -428,6 +433,7 @@ struct EngineT final : Engine {
         cu_lds = 2 * lds_budget;
       num_cus = std::max(1, cus);
       lds_per_cu = std::max(cu_lds, lds_budget);
+      if (const char* e = std::getenv("GEMSLR_CHUNK_BUFS")) chunk_bufs = std::atoi(e) == 3 ? 3 : 2;
       if (const char* e = std::getenv("GEMSLR_LDS_BUDGET")) {
         lds_budget = std::atoi(e);
         fixed_budget = true;
@@ -468,14 +474,14 @@ struct EngineT final : Engine {
           const int per_cu = (L.nb + num_cus - 1) / num_cus;
           budget = std::min(lds_budget, lds_per_cu / std::max(1, per_cu));
         }
-        int cap = std::min(kChunkCapMax, ((budget - xb - 1024) / 2) & ~1023);
+        int cap = std::min(kChunkCapMax, ((budget - xb - 1024) / chunk_bufs) & ~1023);
         const int ms = stream_slots(L.maxslot);
         if (L.nb > 0 && ms > 0 && cap >= 4096) {
           std::vector<uint8_t> blob;
           std::vector<ChunkDesc> desc;
           std::vector<int32_t> bc;
           if (build_chunks_par<V, D, T>(tl, tu, L.nb, cap, ms, ColScale<C>::value,
-                                        L.max_block_rows + 1, blob, desc, bc)) {
+                                        L.max_block_rows, blob, desc, bc)) {
             L.blob = upload(blob);
             std::vector<uint8_t> draw(desc.size() * sizeof(ChunkDesc));
             if (!desc.empty()) std::memcpy(draw.data(), desc.data(), draw.size());
@@ -483,6 +489,7 @@ struct EngineT final : Engine {
             L.blk_chunk = upload(bc);
             L.chunk_cap = cap;
             L.x_bytes = xb;
+            L.nbuf = chunk_bufs;
             L.nchunks = (int64_t)desc.size();
           }
         }
@@ -673,6 +680,7 @@ struct EngineT final : Engine {
     a.blk_chunk = L.blk_chunk;
     a.chunk_cap = L.chunk_cap;
     a.x_bytes = L.x_bytes;
+    a.nbuf = L.nbuf;
     return a;
   }
   void trisolve(int l, int mode) {

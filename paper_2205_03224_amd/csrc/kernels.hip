@@ -303,23 +303,78 @@ void launch_trisolve(const TriArgs<P>& a, int mode, int maxslot, int max_block_r
 // ======================================================================
 
 template <class P>
-__device__ __forceinline__ void copy_chunk(const TriArgs<P>& a, int c, uint8_t* dst, int lane) {
+__device__ __forceinline__ void copy_chunk(const TriArgs<P>& a, const ChunkDesc& cd, uint8_t* dst,
+                                           int lane, int iters) {
   // Direct HBM -> LDS copies (global_load_lds, 16 bytes per lane): iteration
   // i fills dst[1 KiB i, 1 KiB (i+1)), lane l its 16 bytes at 16 l.  The
   // loads carry no register data and no wait, so the whole chunk is in flight
-  // at once; the barrier that follows waits for them.  Lanes past the end
-  // re-read the last 16 bytes and land behind the chunk, inside the buffer
-  // (iterations * 1 KiB <= chunk_cap, a multiple of 1 KiB).
-  const ChunkDesc cd = a.chunk[c];
+  // at once.  Lanes past the end re-read the last 16 bytes and land behind
+  // the chunk, inside the buffer (iters * 1 KiB <= chunk_cap, a multiple of
+  // 1 KiB); a caller may ask for more iterations than the chunk needs.
   const uint4* src = reinterpret_cast<const uint4*>(a.blob + cd.off);
-  const int nv = cd.n16;
-  const int last = nv - 1;
-  const int iters = (nv + kWave - 1) / kWave;
+  const int last = (int)cd.n16 - 1;
   for (int i = 0; i < iters; ++i)
     __builtin_amdgcn_global_load_lds(src + min(lane + kWave * i, last),
                                      (__attribute__((address_space(3))) void*)(dst + 1024 * i),
                                      16, 0, 0);
 }
+
+// s_waitcnt immediates (vmcnt n; expcnt and lgkmcnt at their maxima)
+#define GS_VMCNT_IMM(n) (((n) & 15) | (((n) >> 4) << 14) | 0x0F70)
+
+// Chunk descriptors of a block held in registers, lane j holding chunk
+// base + j: reading one is a lane read, not a memory load.  (A per-chunk
+// global load would put its latency on the consumer's path, and on the
+// producer's it would wait behind the copies in flight, since vector-memory
+// loads complete in order.)  Refilled once per 64 chunks.
+struct DescCache {
+  uint32_t w[4];
+  int base;
+};
+template <class P>
+__device__ __forceinline__ void desc_fill(const TriArgs<P>& a, int first, int c1, int lane,
+                                          DescCache& d) {
+  const uint4 v = reinterpret_cast<const uint4*>(a.chunk)[min(first + lane, c1 - 1)];
+  // wait here, inside the refill, so that no wait is left pending on the
+  // common path (vector-memory loads complete in order: a wait outside
+  // would also wait for the copies in flight)
+  __builtin_amdgcn_s_waitcnt(GS_VMCNT_IMM(0));
+  d.w[0] = v.x;
+  d.w[1] = v.y;
+  d.w[2] = v.z;
+  d.w[3] = v.w;
+  d.base = __builtin_amdgcn_readfirstlane(first);
+}
+template <class P>
+__device__ __forceinline__ ChunkDesc desc_get(const TriArgs<P>& a, int c, int c1, int lane,
+                                              DescCache& d) {
+  static_assert(sizeof(ChunkDesc) == 16, "ChunkDesc is four words");
+  if (c - d.base >= kWave) desc_fill<P>(a, c, c1, lane, d);
+  const int j = c - d.base;
+  uint32_t w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) w[q] = (uint32_t)__builtin_amdgcn_readlane((int)d.w[q], j);
+  ChunkDesc cd;
+  __builtin_memcpy(&cd, w, sizeof(cd));
+  return cd;
+}
+
+// s_waitcnt with a uniform run-time vector-memory count (the instruction
+// takes an immediate): expcnt and lgkmcnt left at their maxima.
+#define GS_VMCNT_CASE(n) case n: __builtin_amdgcn_s_waitcnt(GS_VMCNT_IMM(n)); break;
+__device__ __forceinline__ void wait_vmcnt(int n) {
+  switch (n) {
+    GS_VMCNT_CASE(1) GS_VMCNT_CASE(2) GS_VMCNT_CASE(3) GS_VMCNT_CASE(4) GS_VMCNT_CASE(5)
+    GS_VMCNT_CASE(6) GS_VMCNT_CASE(7) GS_VMCNT_CASE(8) GS_VMCNT_CASE(9) GS_VMCNT_CASE(10)
+    GS_VMCNT_CASE(11) GS_VMCNT_CASE(12) GS_VMCNT_CASE(13) GS_VMCNT_CASE(14)
+    GS_VMCNT_CASE(15) GS_VMCNT_CASE(16) GS_VMCNT_CASE(17) GS_VMCNT_CASE(18)
+    GS_VMCNT_CASE(19) GS_VMCNT_CASE(20) GS_VMCNT_CASE(21) GS_VMCNT_CASE(22)
+    GS_VMCNT_CASE(23) GS_VMCNT_CASE(24)
+    default: __builtin_amdgcn_s_waitcnt(GS_VMCNT_IMM(0)); break;
+  }
+}
+// lgkmcnt(0) alone (vmcnt and expcnt at their maxima)
+#define GS_LGKM0_IMM 0xC07F
 
 // One stage of a chunk in registers: the MS padded entries of each lane's
 // row (zeros past the row's length), their block-vector byte offsets, 1/u_ii
@@ -481,30 +536,57 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
-  const int wave = tid / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // uniform: scalar branches
   const int lane = tid % kWave;
   const int r0 = a.blk_row[b];
   const int nr = a.blk_row[b + 1] - r0;
   C* x = reinterpret_cast<C*>(smem_raw);
-  uint8_t* buf0 = smem_raw + a.x_bytes;
-  uint8_t* buf1 = buf0 + a.chunk_cap;
+  uint8_t* bufs = smem_raw + a.x_bytes;  // nbuf buffers of chunk_cap bytes
+  const int nbuf = a.nbuf;
+  const int full = a.chunk_cap >> 10;    // copy iterations of a full buffer
   const int c0 = a.blk_chunk[b], c1 = a.blk_chunk[b + 1];
-  if (wave == 1 && c0 < c1) copy_chunk<P>(a, c0, buf0, lane);
+  DescCache dc;
+  if (c0 < c1) desc_fill<P>(a, c0, c1, lane, dc);
+  // With three buffers every copy issues `full` iterations, so the producer
+  // can wait for the older of two chunks in flight with a fixed count.
+  const auto iters = [&](const ChunkDesc& cd) {
+    return nbuf == 3 ? full : ((int)cd.n16 + kWave - 1) / kWave;
+  };
+  if (wave == 1) {
+    if (c0 < c1) {
+      const ChunkDesc cd = desc_get<P>(a, c0, c1, lane, dc);
+      copy_chunk<P>(a, cd, bufs, lane, iters(cd));
+    }
+    if (nbuf == 3 && c0 + 1 < c1)
+      copy_chunk<P>(a, desc_get<P>(a, c0 + 1, c1, lane, dc), bufs + a.chunk_cap, lane, full);
+  }
   load_rhs<P, MODE, 2 * kWave>(a, r0, nr, tid, x);
   __syncthreads();
   for (int c = c0; c < c1; ++c) {
-    const bool odd = ((c - c0) & 1) != 0;
-    uint8_t* cur = odd ? buf1 : buf0;
-    uint8_t* nxt = odd ? buf0 : buf1;
+    const int k = c - c0;
     if (wave == 1) {
-      if (c + 1 < c1) copy_chunk<P>(a, c + 1, nxt, lane);
+      // the buffer of chunk c - 1 is free: fill it with the chunk nbuf - 1
+      // ahead, then wait until chunk c + 1 has landed
+      const int cn = c + nbuf - 1;
+      if (cn < c1) {
+        const ChunkDesc cd = desc_get<P>(a, cn, c1, lane, dc);
+        copy_chunk<P>(a, cd, bufs + ((k + nbuf - 1) % nbuf) * a.chunk_cap, lane, iters(cd));
+        wait_vmcnt(nbuf == 3 ? full : 0);
+      } else {
+        wait_vmcnt(0);
+      }
     } else {
-      const ChunkDesc cd = a.chunk[c];
+      const ChunkDesc cd = desc_get<P>(a, c, c1, lane, dc);
+      uint8_t* cur = bufs + (k % nbuf) * a.chunk_cap;
       if (cd.nst & 0x8000) chunk_sweep<P, MS, true>(cur, cd, lane, x, nr);
       else chunk_sweep<P, MS, false>(cur, cd, lane, x, nr);
+      // every read of the buffer done before the producer may refill it
+      __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);
     }
-    __syncthreads();
+    // hand-over without a memory fence: copies of later chunks stay in flight
+    __builtin_amdgcn_s_barrier();
   }
+  __syncthreads();
   store_result<P, MODE, 2 * kWave>(a, r0, nr, tid, x);
 }
 
@@ -512,7 +594,7 @@ template <class P, int MS, int MODE>
 static void launch_stream_ms(const TriArgs<P>& a, hipStream_t st) {
   // 1 KiB of slack after the second buffer: lanes past the end of a stage
   // read (and then discard) up to 63 elements beyond a section
-  const size_t lds = (size_t)a.x_bytes + 2 * (size_t)a.chunk_cap + 1024;
+  const size_t lds = (size_t)a.x_bytes + (size_t)a.nbuf * (size_t)a.chunk_cap + 1024;
   auto kern = k_trisolve_streamed<P, MS, MODE>;
   static size_t attr_set = 65536;
   if (lds > attr_set) {

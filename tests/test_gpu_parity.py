@@ -151,12 +151,13 @@ def test_native_setup_solves(torch_dev):
 
 
 @pytest.mark.parametrize("env", [{"GEMSLR_NO_STREAM": "1"}, {"GEMSLR_LDS_BUDGET": "16384"},
-                                 {"GEMSLR_LDS_BUDGET": "20480"}])
+                                 {"GEMSLR_LDS_BUDGET": "20480"}, {"GEMSLR_CHUNK_BUFS": "3"},
+                                 {"GEMSLR_CHUNK_BUFS": "3", "GEMSLR_LDS_BUDGET": "16384"}])
 @pytest.mark.parametrize("name", ["convdiff3d_20_p27", "helmholtz3d_16_p8"])
 def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
     """Both block-trisolve kernels (register prefetch; LDS-streamed with small
-    chunks so that each block takes many producer/consumer hand-offs) give the
-    oracle's apply."""
+    chunks so that each block takes many producer/consumer hand-offs, with
+    two or three chunk buffers) give the oracle's apply."""
     torch = torch_dev
     for k, v in env.items():
         monkeypatch.setenv(k, v)
