@@ -166,7 +166,8 @@ template <class P> void launch_trisolve_streamed(const TriArgs<P>& a, int mode, 
 // maximum chunk size the streamed kernel stages (bytes)
 constexpr int kChunkCapMax = 24576;
 template <class P> void launch_interface(const IfArgs<P>& a, hipStream_t st);
-// workgroups launch_interface uses for s interface rows (size of `partial`)
+// upper bound of the workgroups launch_interface uses for s interface rows
+// (`partial` holds this many times k entries)
 template <class P> int interface_blocks(int64_t s);
 template <class P> void launch_lowrank_update(typename P::X* tc, int64_t s, int k,
                                               const typename P::V* W,

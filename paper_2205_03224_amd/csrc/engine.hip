@@ -239,6 +239,36 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, in
   return true;
 }
 
+// Diagonal blocks of a level swept by one workgroup.  Consecutive blocks are
+// grouped: their union is still block diagonal, so its wavefront levels are
+// the blocks' levels merged and every row is computed exactly as before,
+// while one wavefront sweeps several blocks side by side (one sweep per CU
+// runs faster per stage than several contending for it, and small blocks
+// leave most lanes idle).  Only levels of small blocks (at most 1024 rows
+// on average) are grouped: large blocks already fill the lanes, and pairing
+// them measured slower (longer merged stages, one producer per CU).
+// ceil(nb / CUs) blocks per group, as long as the group's 16-bit column
+// offsets ((rows - 1) * elem <= 65535) and row indices hold.
+static std::vector<int64_t> group_blocks(const std::vector<int64_t>& blocks, int num_cus,
+                                         size_t elem) {
+  const int64_t nb = (int64_t)blocks.size() - 1;
+  if (nb <= num_cus || num_cus <= 0) return blocks;
+  if (blocks[nb] - blocks[0] > 1024 * nb) return blocks;
+  const int64_t per = (nb + num_cus - 1) / num_cus;
+  const int64_t maxrows = std::min<int64_t>(65535 / (int64_t)elem + 1, 65535);
+  std::vector<int64_t> g{blocks[0]};
+  int64_t cnt = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    if (cnt > 0 && (cnt == per || blocks[b + 1] - g.back() > maxrows)) {
+      g.push_back(blocks[b]);
+      cnt = 0;
+    }
+    ++cnt;
+  }
+  g.push_back(blocks[nb]);
+  return g;
+}
+
 // ---- the same two builders over block ranges on host threads, merged in
 // block order (the result is identical to one sequential pass)
 static int layout_threads(size_t nb) {
@@ -411,6 +441,11 @@ struct EngineT final : Engine {
   int num_cus = 256, lds_per_cu = 163840;
   bool fixed_budget = false;
   bool no_stream = std::getenv("GEMSLR_NO_STREAM") != nullptr;
+  // GEMSLR_NO_GROUP: one workgroup per diagonal block (no grouping);
+  // GEMSLR_GROUP_CUS=c: group as if the device had c CUs (tests use it to
+  // form groups from a few blocks)
+  bool no_group = std::getenv("GEMSLR_NO_GROUP") != nullptr;
+  int group_cus = 256;
   // chunk buffers per workgroup: 2 (one copy in flight while a chunk is
   // swept) measures faster than 3 (two in flight, but chunks a third smaller
   // and more hand-offs); GEMSLR_CHUNK_BUFS=3 selects the latter
@@ -423,8 +458,9 @@ struct EngineT final : Engine {
       HIPCHK(hipGetDevice(&dev));
       if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         maxlds = 65536;
-      // two workgroups per CU when the device allows more than 64 KiB each
-      lds_budget = std::min(maxlds, 81920);
+      // up to the device's per-workgroup limit (one group per CU); levels
+      // with more groups than CUs share a CU's LDS below
+      lds_budget = maxlds;
       int cus = 256, cu_lds = 163840;
       if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
@@ -432,6 +468,8 @@ struct EngineT final : Engine {
                                 dev) != hipSuccess || cu_lds <= 0)
         cu_lds = 2 * lds_budget;
       num_cus = std::max(1, cus);
+      group_cus = num_cus;
+      if (const char* e = std::getenv("GEMSLR_GROUP_CUS")) group_cus = std::max(1, std::atoi(e));
       lds_per_cu = std::max(cu_lds, lds_budget);
       if (const char* e = std::getenv("GEMSLR_CHUNK_BUFS")) chunk_bufs = std::atoi(e) == 3 ? 3 : 2;
       if (const char* e = std::getenv("GEMSLR_LDS_BUDGET")) {
@@ -450,13 +488,16 @@ struct EngineT final : Engine {
       L.start = h.start;
       L.d = h.d;
       L.s = h.s;
-      L.nb = (int)h.blocks.size() - 1;
-      std::vector<int32_t> br(h.blocks.begin(), h.blocks.end());
+      // the triangular solves sweep groups of consecutive blocks
+      const std::vector<int64_t> grp =
+          no_group ? h.blocks : group_blocks(h.blocks, group_cus, sizeof(C));
+      L.nb = (int)grp.size() - 1;
+      std::vector<int32_t> br(grp.begin(), grp.end());
       for (int b = 0; b < L.nb; ++b)
-        L.max_block_rows = std::max<int>(L.max_block_rows, (int)(h.blocks[b + 1] - h.blocks[b]));
+        L.max_block_rows = std::max<int>(L.max_block_rows, (int)(grp[b + 1] - grp[b]));
       L.blk_row = upload(br);
-      TriHost<T> tl = build_tri_par(h.L, h.blocks, false);
-      TriHost<T> tu = build_tri_par(h.U, h.blocks, true);
+      TriHost<T> tl = build_tri_par(h.L, grp, false);
+      TriHost<T> tu = build_tri_par(h.U, grp, true);
       L.maxslot = std::max(tl.maxslot, tu.maxslot);
       L.depth_l = tl.depth;
       L.depth_u = tu.depth;
@@ -466,9 +507,8 @@ struct EngineT final : Engine {
         // that two workgroups share one CU
         // (one slot more than the largest block: idle lanes store there)
         const int xb = (int)(((L.max_block_rows + 1) * sizeof(C) + 15) & ~(size_t)15);
-        // LDS per workgroup: small enough that all blocks of the level are
-        // resident at once (ceil(nb / CUs) workgroups per CU), at most the
-        // two-per-CU budget
+        // LDS per workgroup: small enough that all groups of the level are
+        // resident at once (ceil(nb / CUs) workgroups per CU)
         int budget = lds_budget;
         if (!fixed_budget && L.nb > 0) {
           const int per_cu = (L.nb + num_cus - 1) / num_cus;

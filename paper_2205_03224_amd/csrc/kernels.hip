@@ -477,13 +477,14 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
   }
 }
 
-// Right-hand side of a block into LDS: DOWN reads b1, UP forms F_l y2.
-// Eight rows per thread are in flight at once.
+// Right-hand side of a block into LDS: DOWN reads b1, UP reads F_l y2.
+// 256 bytes of loads per thread in flight at once (a whole 4096-row float64
+// block in one round trip with 128 threads).
 template <class P, int MODE, int NT>
 __device__ __forceinline__ void load_rhs(const TriArgs<P>& a, int r0, int nr, int tid,
                                          typename P::C* x) {
   using C = typename P::C;
-  constexpr int U = 8;
+  constexpr int U = 256 / (int)sizeof(C) < 32 ? 256 / (int)sizeof(C) : 32;
   for (int i0 = tid; i0 < nr; i0 += NT * U) {
     C r[U];
     if (MODE == TRI_DOWN) {
@@ -616,18 +617,27 @@ static void launch_stream_mode(const TriArgs<P>& a, int maxslot, hipStream_t st)
   else launch_stream_ms<P, 16, MODE>(a, st);
 }
 
-// fy = F_l y2, one thread per row of B_l (most rows have no entry), so the
-// up sweep's right-hand side is a plain load like the down sweep's
+// fy = F_l y2 (most rows of B_l have no entry), so the up sweep's
+// right-hand side is a plain load like the down sweep's.  Four rows per
+// thread, 256 apart: four independent row-pointer -> entry -> y2 chains in
+// flight per thread instead of one.
+constexpr int kFyRows = 4;
 template <class P>
 __global__ __launch_bounds__(256) void k_fy(CsrDev<P> F, const typename P::X* y2,
                                             typename P::C* fy, int64_t d) {
   using C = typename P::C;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d) return;
-  const int rows[1] = {(int)i};
-  C r[1];
-  csr_rows<C, typename P::V, typename P::X, 1, 4>(F.rp, F.ci, F.v, y2, rows, r);
-  fy[i] = r[0];
+  const int64_t i0 = (int64_t)blockIdx.x * 256 * kFyRows + threadIdx.x;
+  int rows[kFyRows];
+#pragma unroll
+  for (int q = 0; q < kFyRows; ++q) {
+    const int64_t i = i0 + (int64_t)q * 256;
+    rows[q] = i < d ? (int)i : -1;
+  }
+  C r[kFyRows];
+  csr_rows<C, typename P::V, typename P::X, kFyRows, 2>(F.rp, F.ci, F.v, y2, rows, r);
+#pragma unroll
+  for (int q = 0; q < kFyRows; ++q)
+    if (rows[q] >= 0) fy[rows[q]] = r[q];
 }
 
 template <class P>
@@ -638,8 +648,8 @@ void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot, int ma
   if (mode == TRI_DOWN) {
     launch_stream_mode<P, TRI_DOWN>(a, maxslot, st);
   } else {
-    hipLaunchKernelGGL(k_fy<P>, dim3((unsigned)((a.d + 255) / 256)), dim3(256), 0, st, a.F,
-                       a.t + a.d, a.fy, a.d);
+    hipLaunchKernelGGL(k_fy<P>, dim3((unsigned)((a.d + 256 * kFyRows - 1) / (256 * kFyRows))),
+                       dim3(256), 0, st, a.F, a.t + a.d, a.fy, a.d);
     launch_stream_mode<P, TRI_UP>(a, maxslot, st);
   }
 }
@@ -652,7 +662,7 @@ void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot, int ma
 // ======================================================================
 constexpr int kIfThreads = 256;
 
-template <class P, int R>
+template <class P, int R, int KG>
 __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
   using C = typename P::C;
   using X = typename P::X;
@@ -681,26 +691,34 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
     }
   }
   if (a.k == 0) return;
-  // W^H z2 for this workgroup's rows, 8 columns at a time, each group summed
-  // over the workgroup in fixed order through LDS
-  for (int c0 = 0; c0 < a.k; c0 += 8) {
-    C pr[8];
+  // W^H z2 for this workgroup's rows, KG columns at a time: the loads of all
+  // KG columns are in flight together (unconditional, at clamped indices:
+  // rows past s carry z = 0, columns past k are never written), then the KG
+  // sums go over the workgroup 8 at a time, in fixed order, through LDS
+  for (int c0 = 0; c0 < a.k; c0 += KG) {
+    C pr[KG];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) pr[u] = zero<C>();
-    // unconditional loads at clamped indices (rows past s carry z = 0,
-    // columns past k are never written), so all 8R loads are in flight at
-    // once instead of one guarded load and wait each
+    for (int u = 0; u < KG; ++u) pr[u] = zero<C>();
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int64_t j = min(base + (int64_t)q * kIfThreads, a.s - 1);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < KG; ++u) {
         const int64_t cu = min(c0 + u, a.k - 1);
         pr[u] += conj(cvt<C>(a.W[j + cu * a.s])) * z[q];
       }
     }
-    const C sm = block_sum8(pr, red, tid);
-    if (tid < 8 && c0 + tid < a.k) a.partial[(int64_t)blockIdx.x * a.k + c0 + tid] = sm;
+#pragma unroll
+    for (int u0 = 0; u0 < KG; u0 += 8) {
+      if (c0 + u0 < a.k) {
+        C p8[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) p8[v] = pr[u0 + v];
+        const C sm = block_sum8(p8, red, tid);
+        if (tid < 8 && c0 + u0 + tid < a.k)
+          a.partial[(int64_t)blockIdx.x * a.k + c0 + u0 + tid] = sm;
+      }
+    }
   }
 }
 
@@ -762,26 +780,42 @@ __global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typenam
   }
 }
 
-// workgroups launch_interface uses for s interface rows (size of `partial`):
-// 4 rows per thread when that still gives a few hundred workgroups, else 1
-static int interface_rows(int64_t s) { return s >= (int64_t)kIfThreads * 4 * 256 ? 4 : 1; }
+// rows per thread of the interface kernel: 2 when that still leaves two
+// workgroups per CU and the column batch fits the registers of a resident
+// workgroup (real types, k <= 40), else 1
+template <class P>
+static int interface_rows(int64_t s, int k) {
+  using C = typename P::C;
+  return sizeof(C) < 16 && k <= 40 && s >= (int64_t)kIfThreads * 2 * 512 ? 2 : 1;
+}
 
+// upper bound of the workgroups launch_interface uses for s interface rows
+// (the size of `partial` is this times k)
 template <class P>
 int interface_blocks(int64_t s) {
-  const int R = interface_rows(s);
-  return (int)((s + (int64_t)kIfThreads * R - 1) / ((int64_t)kIfThreads * R));
+  return (int)((s + kIfThreads - 1) / kIfThreads);
 }
 
 template <class P>
 void launch_interface(const IfArgs<P>& a, hipStream_t st) {
   if (a.s <= 0) return;
   using C = typename P::C;
-  const int nblk = interface_blocks<P>(a.s);
+  const int R = interface_rows<P>(a.s, a.k);
+  const int nblk = (int)((a.s + (int64_t)kIfThreads * R - 1) / ((int64_t)kIfThreads * R));
   const size_t lds = (size_t)9 * kRedThreads * sizeof(C);
-  if (interface_rows(a.s) == 4)
-    hipLaunchKernelGGL((k_interface<P, 4>), dim3(nblk), dim3(kIfThreads), lds, st, a);
-  else
-    hipLaunchKernelGGL((k_interface<P, 1>), dim3(nblk), dim3(kIfThreads), lds, st, a);
+  // columns per load batch: all of k when it is small, else batches sized so
+  // that the registers still allow every workgroup to be resident at once
+#define GS_IF_LAUNCH(R_, KG) \
+  hipLaunchKernelGGL((k_interface<P, R_, KG>), dim3(nblk), dim3(kIfThreads), lds, st, a)
+  if constexpr (sizeof(C) == 16) {
+    GS_IF_LAUNCH(1, 16);
+  } else {
+    if (R == 2 && a.k <= 16) GS_IF_LAUNCH(2, 16);
+    else if (R == 2) GS_IF_LAUNCH(2, 40);
+    else if (a.k <= 16) GS_IF_LAUNCH(1, 16);
+    else GS_IF_LAUNCH(1, 40);
+  }
+#undef GS_IF_LAUNCH
   if (a.k > 0)
     hipLaunchKernelGGL(k_project_finish<P>, dim3(1), dim3(kFinishThreads), (size_t)a.k * sizeof(C),
                        st, a.partial, nblk, a.k, a.H, a.tprime);
