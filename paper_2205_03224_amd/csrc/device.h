@@ -142,6 +142,13 @@ struct TriArgs {
   int32_t chunk_cap;         // max chunk bytes (multiple of 1 KiB)
   int32_t x_bytes;           // LDS bytes reserved for the block's vector (16-aligned)
   int32_t nbuf;              // chunk buffers in LDS: 2 (one chunk in flight) or 3 (two)
+  // level 0 of an apply (streamed kernel only): DOWN reads its right-hand
+  // side from the caller's vector, xin[perm[row]], instead of t; UP writes
+  // its result to yout[perm[row]] instead of t.  null: use t.  perm null:
+  // identity (vectors already in the permuted order).
+  const typename P::O* xin;
+  typename P::O* yout;
+  const int32_t* perm;
 };
 
 template <class P>
@@ -166,6 +173,9 @@ template <class P> void launch_trisolve_streamed(const TriArgs<P>& a, int mode, 
 // maximum chunk size the streamed kernel stages (bytes)
 constexpr int kChunkCapMax = 24576;
 template <class P> void launch_interface(const IfArgs<P>& a, hipStream_t st);
+// the interface step and the low-rank update of a small level (s <= 4096,
+// k <= 64) in one launch; returns false (launching nothing) otherwise
+template <class P> bool launch_interface_small(const IfArgs<P>& a, hipStream_t st);
 // upper bound of the workgroups launch_interface uses for s interface rows
 // (`partial` holds this many times k entries)
 template <class P> int interface_blocks(int64_t s);

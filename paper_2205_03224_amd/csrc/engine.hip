@@ -445,6 +445,17 @@ struct EngineT final : Engine {
   // GEMSLR_GROUP_CUS=c: group as if the device had c CUs (tests use it to
   // form groups from a few blocks)
   bool no_group = std::getenv("GEMSLR_NO_GROUP") != nullptr;
+  // GEMSLR_NO_FUSE_SMALL: small levels use the three-launch interface step
+  bool no_fuse_small = std::getenv("GEMSLR_NO_FUSE_SMALL") != nullptr;
+  // GEMSLR_NO_FUSE_PERM: the apply gathers and scatters all n rows in
+  // kernels of their own instead of inside the level-0 sweeps
+  bool no_fuse_perm = std::getenv("GEMSLR_NO_FUSE_PERM") != nullptr;
+  struct FusePerm {
+    bool on = false;
+    const O* x = nullptr;
+    O* y = nullptr;
+    const int32_t* perm = nullptr;
+  } fuse;
   int group_cus = 256;
   // chunk buffers per workgroup: 2 (one copy in flight while a chunk is
   // swept) measures faster than 3 (two in flight, but chunks a third smaller
@@ -721,14 +732,26 @@ struct EngineT final : Engine {
     a.chunk_cap = L.chunk_cap;
     a.x_bytes = L.x_bytes;
     a.nbuf = L.nbuf;
+    a.xin = nullptr;
+    a.yout = nullptr;
+    a.perm = nullptr;
     return a;
   }
+  bool streamed(int l) const { return lv[l].blob && !no_stream; }
   void trisolve(int l, int mode) {
     const Lev& L = lv[l];
-    if (L.blob && !no_stream)
-      launch_trisolve_streamed<P>(tri_args(l), mode, L.maxslot, L.max_block_rows, st);
-    else
+    if (streamed(l)) {
+      TriArgs<P> a = tri_args(l);
+      if (l == 0 && fuse.on) {
+        // the apply's gather (scatter) of B_0 rows happens in this sweep
+        a.perm = fuse.perm;
+        if (mode == TRI_DOWN) a.xin = fuse.x;
+        else a.yout = fuse.y;
+      }
+      launch_trisolve_streamed<P>(a, mode, L.maxslot, L.max_block_rows, st);
+    } else {
       launch_trisolve<P>(tri_args(l), mode, L.maxslot, L.max_block_rows, st);
+    }
   }
 
   hipEvent_t ev_at(size_t i) {
@@ -766,9 +789,18 @@ struct EngineT final : Engine {
 
   // ---- compulsory HBM bytes of each launch (every stored array read once,
   // every vector entry read or written once per touch)
-  double tri_bytes(int l, int mode) const {
+  // the apply reads and writes the B_0 rows of the caller's vectors inside
+  // the level-0 sweeps
+  bool fuse_ok() const {
+    return inner_m == 0 && !no_fuse_perm && !lv.empty() && lv[0].d > 0 && lv[0].start == 0 &&
+           streamed(0);
+  }
+  double tri_bytes(int l, int mode, bool perm_fused = false) const {
     const Lev& L = lv[l];
     const double vb = sizeof(V), xb = sizeof(X), db = sizeof(D);
+    // with the apply's permutation fused into level 0, the right-hand side
+    // (DOWN) or the result (UP) is a caller vector entry plus its index
+    const double fused = perm_fused ? (double)L.d * (4.0 + sizeof(O) - xb) : 0.0;
     double b = (double)(L.nnz_lu - L.d) * (vb + 2)   // factor value + 16-bit column
                + 2.0 * L.d * 4 + L.d * db              // row info (L and U), 1/u_ii
                + 4.0 * L.nstages + 8.0 * (L.nb + 1)    // stage and block tables
@@ -776,7 +808,7 @@ struct EngineT final : Engine {
     if (mode == TRI_UP)
       b += (double)L.nnz_f * (vb + 4) + (double)(L.d + 1) * 4  // F_l
            + (double)L.nnz_f * xb + (double)L.d * xb;           // y2 gathers, z1 read
-    return b;
+    return b + fused;
   }
   double if_bytes(int l, int k) const {
     const Lev& L = lv[l];
@@ -802,6 +834,13 @@ struct EngineT final : Engine {
     a.H = L.H;
     a.partial = L.partial;
     a.tprime = L.tprime;
+    if (L.s <= 4096 && k <= 64 && !no_fuse_small) {
+      // small level: the three steps in one workgroup
+      step("interface+update L" + std::to_string(l), KIND_INTERFACE,
+           if_bytes(l, k) + (k > 0 ? upd_bytes(l, k) : 0.0),
+           [&] { launch_interface_small<P>(a, st); });
+      return;
+    }
     step("interface L" + std::to_string(l), KIND_INTERFACE, if_bytes(l, k),
          [&] { launch_interface<P>(a, st); });
     if (k > 0)
@@ -812,7 +851,7 @@ struct EngineT final : Engine {
   void down(int l) {
     if (lv[l].nb > 0)
       step("trisolve_down L" + std::to_string(l), l == 0 ? KIND_TRI0 : KIND_TRI,
-           tri_bytes(l, TRI_DOWN), [&] {
+           tri_bytes(l, TRI_DOWN, l == 0 && fuse.on), [&] {
              trisolve(l, TRI_DOWN);
            });
     if (l + 1 < (int)lv.size()) interface(l, lv[l].k);
@@ -820,7 +859,7 @@ struct EngineT final : Engine {
   void up(int l) {
     if (lv[l].nb > 0)
       step("trisolve_up L" + std::to_string(l), l == 0 ? KIND_TRI0 : KIND_TRI,
-           tri_bytes(l, TRI_UP), [&] {
+           tri_bytes(l, TRI_UP, l == 0 && fuse.on), [&] {
              trisolve(l, TRI_UP);
            });
   }
@@ -831,12 +870,30 @@ struct EngineT final : Engine {
   }
 
   void apply(const void* x, void* y, bool permuted) override {
+    const int32_t* pm = permuted ? nullptr : perm_d;
+    const int64_t d0 = lv.empty() ? 0 : lv[0].d;
+    if (fuse_ok()) {
+      // B_0 rows are read and written by the level-0 sweeps themselves;
+      // only the C_0 rows go through the gather and scatter kernels
+      const O* xo = (const O*)x;
+      O* yo = (O*)y;
+      step("gather C0", KIND_PERM, perm_bytes(n - d0), [&] {
+        launch_gather<P>(pm ? xo : xo + d0, pm ? pm + d0 : nullptr, t + d0, n - d0, st);
+      });
+      fuse = {true, xo, yo, pm};
+      run_from(0);
+      fuse = {};
+      step("scatter C0", KIND_PERM, perm_bytes(n - d0), [&] {
+        launch_scatter<P>(t + d0, pm ? pm + d0 : nullptr, pm ? yo : yo + d0, n - d0, st);
+      });
+      return;
+    }
     step("gather", KIND_PERM, perm_bytes(n),
-         [&] { launch_gather<P>((const O*)x, permuted ? nullptr : perm_d, t, n, st); });
+         [&] { launch_gather<P>((const O*)x, pm, t, n, st); });
     if (inner_m > 0) inner_root();
     else run_from(0);
     step("scatter", KIND_PERM, perm_bytes(n),
-         [&] { launch_scatter<P>(t, permuted ? nullptr : perm_d, (O*)y, n, st); });
+         [&] { launch_scatter<P>(t, pm, (O*)y, n, st); });
   }
 
   int profile(const void* x, void* y, int reps, std::vector<double>& ms,
@@ -918,6 +975,10 @@ struct EngineT final : Engine {
 
   // Compulsory HBM traffic of one whole apply: the sum over its launches.
   double bytes_per_apply() const override {
+    if (fuse_ok()) {
+      const int64_t d0 = lv[0].d;
+      return 2 * perm_bytes(n - d0) + apply_bytes_from(0, true);
+    }
     double b = 2 * perm_bytes(n);
     if (inner_m > 0) {
       // root level with inner steps: down + interface, per step one product
@@ -936,15 +997,16 @@ struct EngineT final : Engine {
     return b + apply_bytes_from(0);
   }
   // bytes of run_from(l0)
-  double apply_bytes_from(int l0) const {
+  double apply_bytes_from(int l0, bool perm_fused = false) const {
     double b = 0;
     const int L = (int)lv.size() - 1;
     for (int l = l0; l <= L; ++l) {
-      if (lv[l].nb > 0) b += tri_bytes(l, TRI_DOWN);
+      const bool f = perm_fused && l == 0;
+      if (lv[l].nb > 0) b += tri_bytes(l, TRI_DOWN, f);
       if (l < L) {
         b += if_bytes(l, lv[l].k);
         if (lv[l].k > 0) b += upd_bytes(l, lv[l].k);
-        if (lv[l].nb > 0) b += tri_bytes(l, TRI_UP);
+        if (lv[l].nb > 0) b += tri_bytes(l, TRI_UP, f);
       }
     }
     return b;

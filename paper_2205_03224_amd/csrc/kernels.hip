@@ -487,7 +487,16 @@ __device__ __forceinline__ void load_rhs(const TriArgs<P>& a, int r0, int nr, in
   constexpr int U = 256 / (int)sizeof(C) < 32 ? 256 / (int)sizeof(C) : 32;
   for (int i0 = tid; i0 < nr; i0 += NT * U) {
     C r[U];
-    if (MODE == TRI_DOWN) {
+    if (MODE == TRI_DOWN && a.xin) {
+      int src[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int row = r0 + min(i0 + u * NT, nr - 1);
+        src[u] = a.perm ? a.perm[row] : row;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) r[u] = cvt<C>(a.xin[src[u]]);
+    } else if (MODE == TRI_DOWN) {
 #pragma unroll
       for (int u = 0; u < U; ++u) r[u] = cvt<C>(a.t[r0 + min(i0 + u * NT, nr - 1)]);
     } else {
@@ -515,6 +524,21 @@ __device__ __forceinline__ void store_result(const TriArgs<P>& a, int r0, int nr
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * NT;
         if (i < nr) a.t[r0 + i] = cvt<X>(x[i]);
+      }
+    } else if (a.yout) {
+      // y1 = z1 - x straight to the caller's vector
+      C z[U];
+      int dst[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int row = r0 + min(i0 + u * NT, nr - 1);
+        z[u] = cvt<C>(a.t[row]);
+        dst[u] = a.perm ? a.perm[row] : row;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * NT;
+        if (i < nr) a.yout[dst[u]] = cvt<typename P::O>(z[u] - x[i]);
       }
     } else {
       // unconditional clamped loads: all U in flight before the stores
@@ -819,6 +843,78 @@ void launch_interface(const IfArgs<P>& a, hipStream_t st) {
   if (a.k > 0)
     hipLaunchKernelGGL(k_project_finish<P>, dim3(1), dim3(kFinishThreads), (size_t)a.k * sizeof(C),
                        st, a.partial, nblk, a.k, a.H, a.tprime);
+}
+
+// The whole interface step of a small level in one workgroup (s <= 4096,
+// k <= 64): z2 = b2 - E_l z1, t = W^H z2, t' = H t and z2 + W t' written
+// back, with z2 kept in LDS; one launch instead of three, for levels where
+// launch latency, not bandwidth, is the cost.  Sums in fixed order.
+constexpr int kSmallThreads = 1024;
+template <class P>
+__global__ __launch_bounds__(kSmallThreads) void k_interface_small(IfArgs<P> a) {
+  using C = typename P::C;
+  using X = typename P::X;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int s = (int)a.s, k = a.k, tid = threadIdx.x;
+  C* zs = reinterpret_cast<C*>(smem_raw);  // s
+  C* red = zs + s;                          // kSmallThreads
+  C* tv = red + kSmallThreads;              // k: W^H z2
+  C* tp = tv + 64;                          // k: H W^H z2
+  X* tc = a.t + a.d;
+  for (int i = tid; i < s; i += kSmallThreads) {
+    const int rows[1] = {i};
+    C ez[1];
+    csr_rows<C, typename P::V, X, 1, 4>(a.E.rp, a.E.ci, a.E.v, a.t, rows, ez);
+    zs[i] = cvt<C>(tc[i]) - ez[0];
+  }
+  __syncthreads();
+  if (k == 0) {
+    for (int i = tid; i < s; i += kSmallThreads) tc[i] = cvt<X>(zs[i]);
+    return;
+  }
+  // T threads per column, thread (c, g) sums rows g, g + T, ...
+  const int T = kSmallThreads / k;
+  const int c = tid % k, g = tid / k;
+  C acc = zero<C>();
+  if (g < T) {
+#pragma unroll 8
+    for (int i = g; i < s; i += T) acc += conj(cvt<C>(a.W[i + (int64_t)c * a.s])) * zs[i];
+  }
+  red[tid] = acc;
+  __syncthreads();
+  if (tid < k) {
+    C t = zero<C>();
+    for (int q = 0; q < T; ++q) t += red[q * k + tid];
+    tv[tid] = t;
+  }
+  __syncthreads();
+  if (tid < k) {
+    C t = zero<C>();
+    for (int q = 0; q < k; ++q) t += a.H[tid + (int64_t)q * k] * tv[q];
+    tp[tid] = t;
+  }
+  __syncthreads();
+  for (int i = tid; i < s; i += kSmallThreads) {
+    C w = zs[i];
+#pragma unroll 8
+    for (int q = 0; q < k; ++q) w += cvt<C>(a.W[i + (int64_t)q * a.s]) * tp[q];
+    tc[i] = cvt<X>(w);
+  }
+}
+
+template <class P>
+bool launch_interface_small(const IfArgs<P>& a, hipStream_t st) {
+  using C = typename P::C;
+  if (a.s <= 0 || a.s > 4096 || a.k > 64) return false;
+  const size_t lds = ((size_t)a.s + kSmallThreads + 128) * sizeof(C);
+  static size_t attr_set = 65536;
+  if (lds > attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_interface_small<P>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr_set = lds;
+  }
+  hipLaunchKernelGGL(k_interface_small<P>, dim3(1), dim3(kSmallThreads), lds, st, a);
+  return true;
 }
 
 // t_C += W t'
@@ -1201,6 +1297,7 @@ void launch_inner_lsq(const T* h, const double* sub, const double* wn, const dou
   template void launch_trisolve<P>(const TriArgs<P>&, int, int, int, hipStream_t);             \
   template void launch_trisolve_streamed<P>(const TriArgs<P>&, int, int, int, hipStream_t);    \
   template void launch_interface<P>(const IfArgs<P>&, hipStream_t);                            \
+  template bool launch_interface_small<P>(const IfArgs<P>&, hipStream_t);                            \
   template int interface_blocks<P>(int64_t);                                                   \
   template void launch_lowrank_update<P>(P::X*, int64_t, int, const P::V*, const P::C*,        \
                                          hipStream_t);                                         \
