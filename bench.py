@@ -232,6 +232,25 @@ def main():
         log(f"[bench] {key}: median {d['median_us']:.1f} us (p10 {d['p10_us']:.1f}, "
             f"p90 {d['p90_us']:.1f}), {d['GBps_at_median']:.0f} GB/s")
 
+    # two right-hand sides per apply (gs_apply_many): each level's sweep
+    # reads the factor entries once for both vectors
+    B2 = torch.stack([b, torch.flip(b, [0])])
+    Y2 = torch.empty_like(B2)
+    for _ in range(3):
+        ctx.apply_many(2, B2, Y2)
+    torch.cuda.synchronize()
+    kp = max(K // 2, 1)
+    t0 = time.perf_counter()
+    for _ in range(kp):
+        ctx.apply_many(2, B2, Y2)
+    torch.cuda.synchronize()
+    us_pair = (time.perf_counter() - t0) * 1e6 / kp
+    multi = {"nrhs": 2, "us_per_call": us_pair, "applies_per_s": 2e6 / us_pair,
+             "speedup_vs_single": (2e6 / us_pair) / applies_per_s, "calls": kp}
+    log(f"[bench] 2 right-hand sides per apply: {us_pair:.1f} us per call, "
+        f"{multi['applies_per_s']:.0f} applies/s ({multi['speedup_vs_single']:.2f}x single)")
+    del B2, Y2
+
     if args.calibrate_copy:
         nel = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -258,6 +277,7 @@ def main():
                    "n": w.n, "levels": info["nlevels"], "nparts": w.nparts, "rank": w.rank,
                    "ilu": f"ILUT({w.drop_tol},{w.lfil})", "parallelism": "single GPU"},
         "apply_GBps": apply_bytes / (ms_per_apply * 1e-3) / 1e9,
+        "multi_rhs": multi,
         "apply_bytes": apply_bytes,
         "apply_distribution": dist,
         "setup": {"total_s": setup_s, "partition_s": info["t_partition"],

@@ -203,7 +203,13 @@ int gs_set_precision(gs_ctx* ctx, int precision);
 int gs_apply(gs_ctx* ctx, const void* x, void* y);
 
 /* Same as gs_apply for `nrhs` vectors stored one after another
- * (x + j*n, y + j*n).  Errors as gs_apply. */
+ * (x + j*n, y + j*n), device memory, x and y not overlapping.  Vectors go in
+ * pairs: each level's triangular sweep handles both in one launch, reading
+ * the factor entries once for the two (several right-hand sides per factor
+ * pass, named as future work in Sec. 6); an odd last vector, and forms
+ * without the pair sweep (complex128, or with inner GMRES steps), go one at
+ * a time.  Every column equals gs_apply of that column.  Errors as
+ * gs_apply. */
 int gs_apply_many(gs_ctx* ctx, int nrhs, const void* x, void* y);
 
 /* ---------------------------------------------------------------- learned start */

@@ -1245,7 +1245,15 @@ int gs_apply_many(gs_ctx* c, int nrhs, const void* x, void* y) {
     char* yb = (char*)y;
     const size_t bytes = (size_t)n * vb * (size_t)nrhs;
     if (xb < yb + bytes && yb < xb + bytes) throw Error(GS_EINVAL, "x and y alias");
-    for (int j = 0; j < nrhs; ++j) c->eng->apply(xb + (size_t)j * n * vb, yb + (size_t)j * n * vb, false);
+    // pairs share each level's sweep launch (Sec. 6: several right-hand
+    // sides per factor pass); an odd one out, or a form without the pair
+    // path, goes alone
+    int j = 0;
+    for (; j + 1 < nrhs; j += 2) {
+      const size_t o0 = (size_t)j * n * vb, o1 = o0 + (size_t)n * vb;
+      if (!c->eng->apply_pair(xb + o0, xb + o1, yb + o0, yb + o1)) break;
+    }
+    for (; j < nrhs; ++j) c->eng->apply(xb + (size_t)j * n * vb, yb + (size_t)j * n * vb, false);
     hipcheck(hipGetLastError(), "kernel launch");
     return GS_OK;
   });

@@ -149,7 +149,20 @@ struct TriArgs {
   const typename P::O* xin;
   typename P::O* yout;
   const int32_t* perm;
+  // two right-hand sides per sweep (streamed kernel, nrhs = 2): the second
+  // working vector and its F_l y2; in LDS the second block vector starts at
+  // byte pair_offset<C>() (so one instruction gathers both)
+  typename P::X* t2;
+  typename P::C* fy2;
+  int32_t nrhs;
 };
+
+// LDS byte offset of the second block vector in two-right-hand-side sweeps:
+// 65 units of the two-address LDS instructions' stride-64 form (64 elements)
+// covers blocks of up to 4159 rows; defined for 4- and 8-byte elements
+template <class C> __host__ __device__ constexpr int pair_offset() {
+  return sizeof(C) == 8 || sizeof(C) == 4 ? 65 * 64 * (int)sizeof(C) : 0;
+}
 
 template <class P>
 struct IfArgs {

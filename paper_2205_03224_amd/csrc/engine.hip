@@ -407,6 +407,10 @@ struct EngineT final : Engine {
   X* t = nullptr;
   C* xg = nullptr;
   C* fy = nullptr;  // F_l y2 of the streamed up sweep
+  X* t2 = nullptr;  // second working vector of two-right-hand-side applies
+  C* fy2 = nullptr;
+  int64_t fy_len = 0;
+  int max_lds = 65536;
   std::vector<Lev> lv;
 
   template <class U> U* upload(const std::vector<U>& h) {
@@ -472,6 +476,7 @@ struct EngineT final : Engine {
       // up to the device's per-workgroup limit (one group per CU); levels
       // with more groups than CUs share a CU's LDS below
       lds_budget = maxlds;
+      max_lds = maxlds;
       int cus = 256, cu_lds = 163840;
       if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
@@ -566,6 +571,7 @@ struct EngineT final : Engine {
     }
     xg = mem.alloc<C>(maxd);
     fy = mem.alloc<C>(maxd);
+    fy_len = maxd;
     // C_0 (the interface block of P^T A P) for the inner iteration's S_hat_0
     if constexpr (kInnerCapable) {
       if (lv.size() >= 2 && lv[0].s > 0) {
@@ -735,7 +741,39 @@ struct EngineT final : Engine {
     a.xin = nullptr;
     a.yout = nullptr;
     a.perm = nullptr;
+    a.t2 = nullptr;
+    a.fy2 = nullptr;
+    a.nrhs = 1;
     return a;
+  }
+  // level l sweeps both right-hand sides in one launch when its blocks fit
+  // the second vector's LDS offset and the pair kernel still keeps as many
+  // workgroups per CU resident as the single one (measured: at level 0,
+  // 4096-row blocks, the pair kernel at one workgroup per CU takes as long
+  // as two single launches at two per CU)
+  bool pair_ok(int l) const {
+    const Lev& L = lv[l];
+    if (pair_offset<C>() <= 0 || !streamed(l) || L.nb <= 0) return false;
+    if ((int64_t)(L.max_block_rows + 1) * (int64_t)sizeof(C) > pair_offset<C>()) return false;
+    const int per_cu = (L.nb + num_cus - 1) / num_cus;
+    const int need = 2 * pair_offset<C>() + L.nbuf * L.chunk_cap + 1024;
+    return need <= max_lds && need <= lds_per_cu / std::max(1, per_cu);
+  }
+  // the sweep of level l for the working vectors t and t2
+  void trisolve_pair(int l, int mode) {
+    const Lev& L = lv[l];
+    if (pair_ok(l)) {
+      TriArgs<P> a = tri_args(l);
+      a.t2 = t2 + L.start;
+      a.fy2 = fy2;
+      a.nrhs = 2;
+      launch_trisolve_streamed<P>(a, mode, L.maxslot, L.max_block_rows, st);
+      return;
+    }
+    trisolve(l, mode);
+    std::swap(t, t2);
+    trisolve(l, mode);
+    std::swap(t, t2);
   }
   bool streamed(int l) const { return lv[l].blob && !no_stream; }
   void trisolve(int l, int mode) {
@@ -822,11 +860,12 @@ struct EngineT final : Engine {
   }
   double perm_bytes(int64_t m) const { return (double)m * (4 + sizeof(O) + sizeof(X)); }
 
-  void interface(int l, int k) {
+  void interface(int l, int k, X* tv = nullptr) {
     Lev& L = lv[l];
+    if (!tv) tv = t;
     IfArgs<P> a;
     a.E = L.E;
-    a.t = t + L.start;
+    a.t = tv + L.start;
     a.d = L.d;
     a.s = L.s;
     a.k = k;
@@ -845,7 +884,7 @@ struct EngineT final : Engine {
          [&] { launch_interface<P>(a, st); });
     if (k > 0)
       step("lowrank_update L" + std::to_string(l), KIND_LOWRANK, upd_bytes(l, k),
-           [&] { launch_lowrank_update<P>(t + L.start + L.d, L.s, k, L.W, L.tprime, st); });
+           [&] { launch_lowrank_update<P>(tv + L.start + L.d, L.s, k, L.W, L.tprime, st); });
   }
 
   void down(int l) {
@@ -894,6 +933,40 @@ struct EngineT final : Engine {
     else run_from(0);
     step("scatter", KIND_PERM, perm_bytes(n),
          [&] { launch_scatter<P>(t, pm, (O*)y, n, st); });
+  }
+
+  // y0 = M^{-1} x0 and y1 = M^{-1} x1, the triangular sweeps of both in
+  // one launch per level (factor entries read once for two right-hand
+  // sides); false (nothing done) when inner steps are on
+  bool apply_pair(const void* x0, const void* x1, void* y0, void* y1) override {
+    if (inner_m > 0) return false;
+    if (!t2) {
+      t2 = mem.alloc<X>(n);
+      fy2 = mem.alloc<C>(fy_len);
+    }
+    const int L = (int)lv.size() - 1;
+    step("gather x2", KIND_PERM, 2 * perm_bytes(n), [&] {
+      launch_gather<P>((const O*)x0, perm_d, t, n, st);
+      launch_gather<P>((const O*)x1, perm_d, t2, n, st);
+    });
+    for (int l = 0; l <= L; ++l) {
+      if (lv[l].nb > 0)
+        step("trisolve_down x2 L" + std::to_string(l), KIND_TRI, 0.0,
+             [&] { trisolve_pair(l, TRI_DOWN); });
+      if (l < L) {
+        interface(l, lv[l].k, t);
+        interface(l, lv[l].k, t2);
+      }
+    }
+    for (int l = L - 1; l >= 0; --l)
+      if (lv[l].nb > 0)
+        step("trisolve_up x2 L" + std::to_string(l), KIND_TRI, 0.0,
+             [&] { trisolve_pair(l, TRI_UP); });
+    step("scatter x2", KIND_PERM, 2 * perm_bytes(n), [&] {
+      launch_scatter<P>(t, perm_d, (O*)y0, n, st);
+      launch_scatter<P>(t2, perm_d, (O*)y1, n, st);
+    });
+    return true;
   }
 
   int profile(const void* x, void* y, int reps, std::vector<double>& ms,

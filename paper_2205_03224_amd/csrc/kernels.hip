@@ -419,24 +419,39 @@ __device__ __forceinline__ void sweep_load(const typename P::V* val, const typen
 
 // x[row] = (x[row] - sum_j v_j x[c_j]) (* 1/u_ii): all gathers first, two
 // partial sums (padded entries are zero); idle lanes write the dummy slot.
-template <class P, int MS, bool ISU>
+template <class P, int MS, bool ISU, int NB>
 __device__ __forceinline__ void sweep_compute(const SweepRegs<P, MS>& R, typename P::C* x) {
   using C = typename P::C;
   constexpr int kMul = (int)sizeof(C) / ColScale<C>::value;
+  constexpr int kX2 = pair_offset<C>();  // second block vector (NB = 2)
   const unsigned char* xb = reinterpret_cast<const unsigned char*>(x);
-  C xv[MS];
+  C xv[MS], xw[MS];
 #pragma unroll
-  for (int j = 0; j < MS; ++j) xv[j] = *reinterpret_cast<const C*>(xb + R.c[j] * kMul);
+  for (int j = 0; j < MS; ++j) {
+    xv[j] = *reinterpret_cast<const C*>(xb + R.c[j] * kMul);
+    if (NB == 2) xw[j] = *reinterpret_cast<const C*>(xb + R.c[j] * kMul + kX2);
+  }
   const C b = x[R.row];
-  C s0 = zero<C>(), s1 = zero<C>();
+  C bw = zero<C>();
+  if (NB == 2) bw = *reinterpret_cast<const C*>(xb + R.row * sizeof(C) + kX2);
+  C s0 = zero<C>(), s1 = zero<C>(), w0 = zero<C>(), w1 = zero<C>();
 #pragma unroll
   for (int j = 0; j < MS; j += 2) {
     s0 += R.v[j] * xv[j];
     if (j + 1 < MS) s1 += R.v[j + 1] * xv[j + 1];
+    if (NB == 2) {
+      w0 += R.v[j] * xw[j];
+      if (j + 1 < MS) w1 += R.v[j + 1] * xw[j + 1];
+    }
   }
   C acc = b - (s0 + s1);
   if (ISU) acc *= R.dv;
   x[R.row] = acc;
+  if (NB == 2) {
+    C aw = bw - (w0 + w1);
+    if (ISU) aw *= R.dv;
+    *reinterpret_cast<C*>(reinterpret_cast<unsigned char*>(x) + R.row * sizeof(C) + kX2) = aw;
+  }
 }
 
 // Sweep the stages of one chunk held in LDS, two stages per trip with two
@@ -446,7 +461,7 @@ __device__ __forceinline__ void sweep_compute(const SweepRegs<P, MS>& R, typenam
 // before the gathers of stage s, and a stage waits only for its own gathers.
 // LDS executes one wavefront's accesses in order, so a gather issued after
 // the previous stage's store sees the stored value.
-template <class P, int MS, bool ISU>
+template <class P, int MS, bool ISU, int NB>
 __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& cd, int lane,
                                             typename P::C* x, int dummy) {
   using V = typename P::V;
@@ -466,12 +481,12 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
     const int r2 = r1 + B.nr;
     uint32_t i2 = rinfo[min(r2 + lane, (int)cd.nrows)];
     i2 = s + 2 < nst ? i2 : 0u;
-    sweep_compute<P, MS, ISU>(A, x);                                 // stage s
+    sweep_compute<P, MS, ISU, NB>(A, x);                             // stage s
     sweep_load<P, MS, ISU>(val, dinv, col, i2, r2, lane, dummy, A);  // stage s+2
     const int r3 = r2 + A.nr;
     uint32_t i3 = rinfo[min(r3 + lane, (int)cd.nrows)];
     i3 = s + 3 < nst ? i3 : 0u;
-    sweep_compute<P, MS, ISU>(B, x);                                 // stage s+1
+    sweep_compute<P, MS, ISU, NB>(B, x);                             // stage s+1
     r1 = r3;
     i1 = i3;
   }
@@ -481,7 +496,8 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
 // 256 bytes of loads per thread in flight at once (a whole 4096-row float64
 // block in one round trip with 128 threads).
 template <class P, int MODE, int NT>
-__device__ __forceinline__ void load_rhs(const TriArgs<P>& a, int r0, int nr, int tid,
+__device__ __forceinline__ void load_rhs(const TriArgs<P>& a, const typename P::X* tv,
+                                         const typename P::C* fyv, int r0, int nr, int tid,
                                          typename P::C* x) {
   using C = typename P::C;
   constexpr int U = 256 / (int)sizeof(C) < 32 ? 256 / (int)sizeof(C) : 32;
@@ -498,10 +514,10 @@ __device__ __forceinline__ void load_rhs(const TriArgs<P>& a, int r0, int nr, in
       for (int u = 0; u < U; ++u) r[u] = cvt<C>(a.xin[src[u]]);
     } else if (MODE == TRI_DOWN) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) r[u] = cvt<C>(a.t[r0 + min(i0 + u * NT, nr - 1)]);
+      for (int u = 0; u < U; ++u) r[u] = cvt<C>(tv[r0 + min(i0 + u * NT, nr - 1)]);
     } else {
 #pragma unroll
-      for (int u = 0; u < U; ++u) r[u] = a.fy[r0 + min(i0 + u * NT, nr - 1)];
+      for (int u = 0; u < U; ++u) r[u] = fyv[r0 + min(i0 + u * NT, nr - 1)];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -513,8 +529,8 @@ __device__ __forceinline__ void load_rhs(const TriArgs<P>& a, int r0, int nr, in
 
 // Result of a block from LDS: DOWN stores z1, UP stores z1 - (LU)^{-1} F y2.
 template <class P, int MODE, int NT>
-__device__ __forceinline__ void store_result(const TriArgs<P>& a, int r0, int nr, int tid,
-                                             const typename P::C* x) {
+__device__ __forceinline__ void store_result(const TriArgs<P>& a, typename P::X* tv, int r0,
+                                             int nr, int tid, const typename P::C* x) {
   using C = typename P::C;
   using X = typename P::X;
   constexpr int U = 8;
@@ -523,7 +539,7 @@ __device__ __forceinline__ void store_result(const TriArgs<P>& a, int r0, int nr
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * NT;
-        if (i < nr) a.t[r0 + i] = cvt<X>(x[i]);
+        if (i < nr) tv[r0 + i] = cvt<X>(x[i]);
       }
     } else if (a.yout) {
       // y1 = z1 - x straight to the caller's vector
@@ -544,17 +560,17 @@ __device__ __forceinline__ void store_result(const TriArgs<P>& a, int r0, int nr
       // unconditional clamped loads: all U in flight before the stores
       C z[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) z[u] = cvt<C>(a.t[r0 + min(i0 + u * NT, nr - 1)]);
+      for (int u = 0; u < U; ++u) z[u] = cvt<C>(tv[r0 + min(i0 + u * NT, nr - 1)]);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * NT;
-        if (i < nr) a.t[r0 + i] = cvt<X>(z[u] - x[i]);
+        if (i < nr) tv[r0 + i] = cvt<X>(z[u] - x[i]);
       }
     }
   }
 }
 
-template <class P, int MS, int MODE>
+template <class P, int MS, int MODE, int NB>
 __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
   using C = typename P::C;
   using X = typename P::X;
@@ -566,7 +582,9 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
   const int r0 = a.blk_row[b];
   const int nr = a.blk_row[b + 1] - r0;
   C* x = reinterpret_cast<C*>(smem_raw);
-  uint8_t* bufs = smem_raw + a.x_bytes;  // nbuf buffers of chunk_cap bytes
+  // NB = 2: the second block vector at pair_offset, the buffers after it
+  C* x2 = reinterpret_cast<C*>(smem_raw + pair_offset<C>());
+  uint8_t* bufs = smem_raw + (NB == 2 ? 2 * pair_offset<C>() : a.x_bytes);
   const int nbuf = a.nbuf;
   const int full = a.chunk_cap >> 10;    // copy iterations of a full buffer
   const int c0 = a.blk_chunk[b], c1 = a.blk_chunk[b + 1];
@@ -585,7 +603,8 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
     if (nbuf == 3 && c0 + 1 < c1)
       copy_chunk<P>(a, desc_get<P>(a, c0 + 1, c1, lane, dc), bufs + a.chunk_cap, lane, full);
   }
-  load_rhs<P, MODE, 2 * kWave>(a, r0, nr, tid, x);
+  load_rhs<P, MODE, 2 * kWave>(a, a.t, a.fy, r0, nr, tid, x);
+  if (NB == 2) load_rhs<P, MODE, 2 * kWave>(a, a.t2, a.fy2, r0, nr, tid, x2);
   __syncthreads();
   for (int c = c0; c < c1; ++c) {
     const int k = c - c0;
@@ -603,8 +622,8 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
     } else {
       const ChunkDesc cd = desc_get<P>(a, c, c1, lane, dc);
       uint8_t* cur = bufs + (k % nbuf) * a.chunk_cap;
-      if (cd.nst & 0x8000) chunk_sweep<P, MS, true>(cur, cd, lane, x, nr);
-      else chunk_sweep<P, MS, false>(cur, cd, lane, x, nr);
+      if (cd.nst & 0x8000) chunk_sweep<P, MS, true, NB>(cur, cd, lane, x, nr);
+      else chunk_sweep<P, MS, false, NB>(cur, cd, lane, x, nr);
       // every read of the buffer done before the producer may refill it
       __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);
     }
@@ -612,15 +631,18 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
     __builtin_amdgcn_s_barrier();
   }
   __syncthreads();
-  store_result<P, MODE, 2 * kWave>(a, r0, nr, tid, x);
+  store_result<P, MODE, 2 * kWave>(a, a.t, r0, nr, tid, x);
+  if (NB == 2) store_result<P, MODE, 2 * kWave>(a, a.t2, r0, nr, tid, x2);
 }
 
-template <class P, int MS, int MODE>
+template <class P, int MS, int MODE, int NB>
 static void launch_stream_ms(const TriArgs<P>& a, hipStream_t st) {
   // 1 KiB of slack after the second buffer: lanes past the end of a stage
   // read (and then discard) up to 63 elements beyond a section
-  const size_t lds = (size_t)a.x_bytes + (size_t)a.nbuf * (size_t)a.chunk_cap + 1024;
-  auto kern = k_trisolve_streamed<P, MS, MODE>;
+  using C = typename P::C;
+  const size_t xreg = NB == 2 ? 2 * (size_t)pair_offset<C>() : (size_t)a.x_bytes;
+  const size_t lds = xreg + (size_t)a.nbuf * (size_t)a.chunk_cap + 1024;
+  auto kern = k_trisolve_streamed<P, MS, MODE, NB>;
   static size_t attr_set = 65536;
   if (lds > attr_set) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -630,15 +652,25 @@ static void launch_stream_ms(const TriArgs<P>& a, hipStream_t st) {
   hipLaunchKernelGGL(kern, dim3(a.nb), dim3(2 * kWave), lds, st, a);
 }
 
-template <class P, int MODE>
-static void launch_stream_mode(const TriArgs<P>& a, int maxslot, hipStream_t st) {
+template <class P, int MODE, int NB>
+static void launch_stream_nb(const TriArgs<P>& a, int maxslot, hipStream_t st) {
   // the layout was padded to stream_slots(maxslot) slots per stage
   const int ms = stream_slots(maxslot);
-  if (ms == 4) launch_stream_ms<P, 4, MODE>(a, st);
-  else if (ms == 8) launch_stream_ms<P, 8, MODE>(a, st);
-  else if (ms == 10) launch_stream_ms<P, 10, MODE>(a, st);
-  else if (ms == 12) launch_stream_ms<P, 12, MODE>(a, st);
-  else launch_stream_ms<P, 16, MODE>(a, st);
+  if (ms == 4) launch_stream_ms<P, 4, MODE, NB>(a, st);
+  else if (ms == 8) launch_stream_ms<P, 8, MODE, NB>(a, st);
+  else if (ms == 10) launch_stream_ms<P, 10, MODE, NB>(a, st);
+  else if (ms == 12) launch_stream_ms<P, 12, MODE, NB>(a, st);
+  else launch_stream_ms<P, 16, MODE, NB>(a, st);
+}
+template <class P, int MODE>
+static void launch_stream_mode(const TriArgs<P>& a, int maxslot, hipStream_t st) {
+  if constexpr (pair_offset<typename P::C>() > 0) {
+    if (a.nrhs == 2) {
+      launch_stream_nb<P, MODE, 2>(a, maxslot, st);
+      return;
+    }
+  }
+  launch_stream_nb<P, MODE, 1>(a, maxslot, st);
 }
 
 // fy = F_l y2 (most rows of B_l have no entry), so the up sweep's
@@ -672,8 +704,10 @@ void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot, int ma
   if (mode == TRI_DOWN) {
     launch_stream_mode<P, TRI_DOWN>(a, maxslot, st);
   } else {
-    hipLaunchKernelGGL(k_fy<P>, dim3((unsigned)((a.d + 256 * kFyRows - 1) / (256 * kFyRows))),
-                       dim3(256), 0, st, a.F, a.t + a.d, a.fy, a.d);
+    const dim3 gfy((unsigned)((a.d + 256 * kFyRows - 1) / (256 * kFyRows)));
+    hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t + a.d, a.fy, a.d);
+    if (a.nrhs == 2)
+      hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t2 + a.d, a.fy2, a.d);
     launch_stream_mode<P, TRI_UP>(a, maxslot, st);
   }
 }

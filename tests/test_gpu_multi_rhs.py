@@ -1,0 +1,102 @@
+"""Several right-hand sides per apply (gs_apply_many): pairs of vectors share
+each level's triangular-sweep launch (the factor entries are read once for
+both).  Every column must equal the oracle's apply of that column to the
+float64 apply tolerance, and, since each right-hand side goes through the
+same operations in the same order as in a single apply, equal the single
+apply of the same column bit for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_2205_03224_amd import workloads as wl
+from oracle import gemslr as og
+from oracle import partition as opart
+from tests.abi_helpers import oracle_levels, relerr
+
+pytestmark = pytest.mark.gpu
+
+APPLY_TOL_F64 = 1e-11
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_03224_amd import gemslr  # noqa: F401  (fails loudly if unbuilt)
+    return torch
+
+
+def _case(name):
+    if name == "laplace2d_32":
+        w = wl.laplace2d_32()
+        kw = dict(ilu="ilu0", rank=8)
+    elif name == "convdiff3d_20_p27":
+        w = wl.convdiff3d_64(N=20, nparts=27)
+        kw = dict(ilu="ilut", drop_tol=1e-3, lfil=10, rank=8, dense_max=100)
+    elif name == "helmholtz3d_16_p8":
+        w = wl.helmholtz3d_128(N=16, nparts=8, levels=5)
+        kw = dict(ilu="ilut", drop_tol=1e-4, lfil=10, rank=8, dense_max=100)
+    else:
+        raise KeyError(name)
+    part = opart.wirebasket(w.dims, w.nparts, w.levels, w.rowptr, w.col)
+    return w, og.setup(w.rowptr, w.col, w.val, part, **kw)
+
+
+def _block(w, nrhs, seed):
+    rs = np.random.default_rng(seed)
+    X = rs.standard_normal((nrhs, w.n))
+    if w.is_complex:
+        X = X + 1j * rs.standard_normal((nrhs, w.n))
+    return X
+
+
+@pytest.mark.parametrize("env", [{}, {"GEMSLR_GROUP_CUS": "4"}, {"GEMSLR_NO_STREAM": "1"}])
+@pytest.mark.parametrize("name", ["laplace2d_32", "convdiff3d_20_p27", "helmholtz3d_16_p8"])
+@pytest.mark.parametrize("nrhs", [2, 3, 4])
+def test_apply_many_matches_oracle_and_single(torch_dev, name, nrhs, env, monkeypatch):
+    torch = torch_dev
+    from paper_2205_03224_amd import gemslr
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    w, st = _case(name)
+    print(f"[multi-rhs] {name} nrhs={nrhs} {env}", flush=True)
+    ctx = gemslr.Context(0)
+    ctx.setup_explicit(w.rowptr, w.col, w.val, st.perm, oracle_levels(st))
+    X = _block(w, nrhs, 40 + nrhs)
+    xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    yd = torch.empty_like(xd)
+    ctx.apply_many(nrhs, xd, yd)
+    ys = torch.empty_like(xd)
+    for j in range(nrhs):
+        ctx.apply(xd[j], ys[j])
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy()
+    for j in range(nrhs):
+        err = relerr(Y[j], og.apply(st, X[j]))
+        print(f"  column {j}: rel err vs oracle {err:.3e}", flush=True)
+        assert err <= APPLY_TOL_F64
+    assert torch.equal(yd, ys), "apply_many differs from single applies"
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_apply_many_mixed_forms_equal_single(torch_dev, prec):
+    """The float32-sweep forms pair their right-hand sides as well; each
+    column equals the single apply of the same form bit for bit."""
+    torch = torch_dev
+    from paper_2205_03224_amd import gemslr
+    w, st = _case("convdiff3d_20_p27")
+    ctx = gemslr.Context(0)
+    ctx.setup_explicit(w.rowptr, w.col, w.val, st.perm, oracle_levels(st))
+    ctx.set_precision(prec)
+    X = _block(w, 2, 77)
+    xd = torch.from_numpy(X).cuda()
+    yd = torch.empty_like(xd)
+    ys = torch.empty_like(xd)
+    ctx.apply_many(2, xd, yd)
+    ctx.apply(xd[0], ys[0])
+    ctx.apply(xd[1], ys[1])
+    torch.cuda.synchronize()
+    assert torch.equal(yd, ys)
+    ctx.close()
