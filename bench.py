@@ -176,7 +176,9 @@ def main():
     log(f"[bench] setup {time.perf_counter() - t0:.1f} s: partition {info['t_partition']:.2f} "
         f"factor {info['t_factor']:.2f} layout {info['t_layout']:.2f} lowrank "
         f"{info['t_lowrank']:.2f}; d={info['d']} s={info['s']} k={info['k']} "
-        f"depth L/U={info['depth_l']}/{info['depth_u']} fill={info['fill']:.3f}")
+        f"depth L/U={info['depth_l']}/{info['depth_u']} fill={info['fill']:.3f}; Arnoldi "
+        f"cycles {info['arnoldi_cycles'][:info['nlevels']]} products "
+        f"{info['arnoldi_matvecs'][:info['nlevels']]}")
 
     b = torch.from_numpy(w.b).cuda()
     y = torch.empty_like(b)
@@ -285,6 +287,8 @@ def main():
                   "lowrank_s": info["t_lowrank"], "fill": info["fill"],
                   "depth_L": list(info["depth_l"][:info["nlevels"] + 1]),
                   "depth_U": list(info["depth_u"][:info["nlevels"] + 1]),
+                  "arnoldi_cycles": list(info["arnoldi_cycles"][:info["nlevels"]]),
+                  "arnoldi_matvecs": list(info["arnoldi_matvecs"][:info["nlevels"]]),
                   "host_threads": os.cpu_count()},
         "roofline": {"bound": "hbm", "kernel": "k_trisolve level 0 (down + up)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",

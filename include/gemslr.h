@@ -112,7 +112,9 @@ typedef struct {
   int64_t nnz_a;            /* nnz(A)                                         */
   double fill;              /* nnz_lu / nnz_a (Sec. 5 "fill")                 */
   double fill_lowrank;      /* (nnz_lu + sum s_l k_l + k_l^2) / nnz_a         */
-  double apply_bytes;       /* compulsory HBM bytes of one apply (see DESIGN) */
+  double apply_bytes;       /* compulsory HBM bytes of one apply: every
+                               factor, E/F/W entry and index read once, every
+                               vector entry read or written once per launch */
   double t_partition, t_factor, t_layout, t_lowrank, t_solve; /* seconds     */
 } gs_info;
 

@@ -221,10 +221,47 @@ static void lowrank_level(gs_ctx* c, int l, int kreq) {
   std::vector<cplx> Sm((size_t)(m + 1) * m, cplx(0));  // Krylov decomposition G V = V S
   auto Sat = [&](int i, int j) -> cplx& { return Sm[(size_t)j * (m + 1) + i]; };
   const size_t stage_bytes = (m + 1) * sizeof(DT) + 2 * sizeof(double);
+  // device copy of the cycle's Hessenberg columns and norms, read once per
+  // cycle instead of once per step
+  DT* Sd = mem.alloc<DT>((size_t)(m + 1) * m);
+  double* nd = mem.alloc<double>((size_t)2 * m + 1);  // + breakdown flag
+  std::vector<DT> Sh((size_t)(m + 1) * m);
+  std::vector<double> nh((size_t)2 * m + 1);
   int j0 = 0, nmv = 0;
   const int maxcyc = std::max(1, c->opts.arnoldi_max_cycles);
   for (int cycle = 0; cycle < maxcyc; ++cycle) {
-    for (int j = j0; j < m; ++j) {
+    // steps j0..m-1 without host round trips; a breakdown (flagged by the
+    // device) sends the cycle through the step-by-step path below
+    bool stepwise = false;
+    {
+      launch_fill<double>(nd + 2 * m, 0.0, 1, st);
+      for (int j = j0; j < m; ++j) {
+        c->eng->ghat(l, V + (size_t)j * s, w);
+        launch_norm<DT>(w, s, npart, nrm + 1, st);
+        cgs2<DT>(V, s, j + 1, w, s, part, hd, hacc, st);
+        launch_norm<DT>(w, s, npart, nrm, st);
+        launch_arnoldi_step<DT>(hacc, j + 1, nrm, Sd + (size_t)j * (m + 1), nd + 2 * j, nd + 2 * m,
+                                w, V + (size_t)(j + 1) * s, s, st);
+      }
+      HIPCHK(hipMemcpyAsync(Sh.data(), Sd, Sh.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(nh.data(), nd, nh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (nh[2 * m] != 0.0) {
+        stepwise = true;  // redo from j0: column j0 of V is untouched
+      } else {
+        nmv += m - j0;
+        for (int j = j0; j < m; ++j) {
+          for (int i = 0; i <= j; ++i) {
+            cplx v;
+            if (real) v = cplx(((const double*)Sh.data())[(size_t)j * (m + 1) + i], 0.0);
+            else std::memcpy((void*)&v, &Sh[(size_t)j * (m + 1) + i], sizeof(DT));
+            Sat(i, j) = v;
+          }
+          Sat(j + 1, j) = nh[2 * j];
+        }
+      }
+    }
+    for (int j = j0; stepwise && j < m; ++j) {
       c->eng->ghat(l, V + (size_t)j * s, w);
       ++nmv;
       launch_norm<DT>(w, s, npart, nrm + 1, st);

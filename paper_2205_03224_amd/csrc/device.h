@@ -216,6 +216,10 @@ template <class T> void launch_gemv_sub(const T* V, int64_t ld, int ncol, const 
 template <class T> void launch_norm(const T* w, int64_t n, double* partial, double* out,
                                    hipStream_t st);
 // y = x / (*nrm)  (or zero when *nrm == 0)
+// one Arnoldi step's bookkeeping on the device (see kernels.hip)
+template <class T> void launch_arnoldi_step(const T* h, int cnt, const double* nrm, T* Scol,
+                                            double* nd, double* flag, const T* w, T* y, int64_t n,
+                                            hipStream_t st);
 template <class T> void launch_scale_inv(const T* x, const double* nrm, T* y, int64_t n,
                                          hipStream_t st);
 // x += Z y (ncol columns)

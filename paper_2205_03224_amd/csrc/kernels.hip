@@ -1145,6 +1145,35 @@ void launch_scale_inv(const T* x, const double* nrm, T* y, int64_t n, hipStream_
                      y, n);
 }
 
+// One Arnoldi step recorded on the device: the new Hessenberg column h
+// (cnt entries) and the norms (nrm[0] = ||w|| after orthogonalisation,
+// nrm[1] = before) go to Scol and nd; y = w / nrm[0], or zero with *flag
+// set when nrm[0] <= 1e-12 nrm[1] (breakdown: the host then redoes the
+// cycle step by step).
+template <class T>
+__global__ void k_arnoldi_step(const T* h, int cnt, const double* nrm, T* Scol, double* nd,
+                               double* flag, const T* w, T* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double beta = nrm[0], wn = nrm[1];
+  const bool ok = beta > 1e-12 * wn;
+  if (blockIdx.x == 0) {
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) Scol[q] = h[q];
+    if (threadIdx.x == 0) {
+      nd[0] = beta;
+      nd[1] = wn;
+      if (!ok) flag[0] = 1.0;
+    }
+  }
+  if (i >= n) return;
+  y[i] = ok ? w[i] * (1.0 / beta) : zero<T>();
+}
+template <class T>
+void launch_arnoldi_step(const T* h, int cnt, const double* nrm, T* Scol, double* nd, double* flag,
+                         const T* w, T* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_arnoldi_step<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, h,
+                     cnt, nrm, Scol, nd, flag, w, y, n);
+}
+
 template <class T>
 __global__ void k_gemv_add(const T* Z, int64_t ld, int ncol, const T* y, T* x, int64_t n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1353,6 +1382,8 @@ GS_PREC_INSTANCES(PBF16)
                                    hipStream_t);                                               \
   template void launch_norm<T>(const T*, int64_t, double*, double*, hipStream_t);              \
   template void launch_scale_inv<T>(const T*, const double*, T*, int64_t, hipStream_t);        \
+  template void launch_arnoldi_step<T>(const T*, int, const double*, T*, double*, double*,     \
+                                       const T*, T*, int64_t, hipStream_t);                    \
   template void launch_gemv_add<T>(const T*, int64_t, int, const T*, T*, int64_t,              \
                                    hipStream_t);                                               \
   template void launch_gemm_small<T>(const T*, int64_t, int, const T*, int, T*, int64_t,       \
