@@ -120,6 +120,9 @@ __host__ __device__ constexpr int stream_slots(int maxslot) {
 }
 __host__ __device__ constexpr int stream_vstride(int ms) { return ms + 1; }
 __host__ __device__ constexpr int stream_cstride(int ms) { return ms <= 4 ? 4 : ms <= 12 ? 12 : 20; }
+// half-row U stages: a row's slots ms/2 .. ms-1 start at this 16-bit
+// position of its column row (the next 4-byte boundary)
+__host__ __device__ constexpr int stream_half_coff(int ms) { return ((ms / 2) + 1) & ~1; }
 // byte scale of the stored column: the element size, so the stored value is
 // the element's LDS byte offset (16-bit: blocks of up to 65536 / sizeof(C)
 // rows use the streamed layout)
@@ -142,6 +145,7 @@ struct TriArgs {
   int32_t chunk_cap;         // max chunk bytes (multiple of 1 KiB)
   int32_t x_bytes;           // LDS bytes reserved for the block's vector (16-aligned)
   int32_t nbuf;              // chunk buffers in LDS: 2 (one chunk in flight) or 3 (two)
+  int32_t half_u;            // U chunks in half-row form: lanes l and l+32 share row l
   // level 0 of an apply (streamed kernel only): DOWN reads its right-hand
   // side from the caller's vector, xin[perm[row]], instead of t; UP writes
   // its result to yout[perm[row]] instead of t.  null: use t.  perm null:

@@ -33,6 +33,7 @@ struct TriHost {
   std::vector<T> dinv, val;
   std::vector<uint16_t> col;
   int maxslot = 0, depth = 0;
+  int maxwidth = 0;  // most rows in one wavefront level of one block
 };
 template <class T>
 TriHost<T> build_tri(const CSR<T>& M, const std::vector<int64_t>& blocks, bool upper);

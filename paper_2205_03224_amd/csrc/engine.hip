@@ -96,6 +96,7 @@ TriHost<T> build_tri(const CSR<T>& M, const std::vector<int64_t>& blocks, bool u
     h.depth = std::max(h.depth, depth);
     bylev.assign(depth, {});
     for (int64_t i = r0; i < r1; ++i) bylev[lev[i - r0]].push_back(i);
+    for (const auto& rl : bylev) h.maxwidth = std::max(h.maxwidth, (int)rl.size());
     auto offd_count = [&](int64_t i) {
       int c = 0;
       for (int64_t p = M.rp[i]; p < M.rp[i + 1]; ++p)
@@ -152,7 +153,7 @@ TriHost<T> build_tri(const CSR<T>& M, const std::vector<int64_t>& blocks, bool u
 // single stage does not fit.
 template <class V, class D, class T>
 bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, int cap, int ms,
-                  int col_scale, int max_rows, std::vector<uint8_t>& blob,
+                  int col_scale, int max_rows, bool half_u, std::vector<uint8_t>& blob,
                   std::vector<ChunkDesc>& desc, std::vector<int32_t>& blk_chunk) {
   auto pad = [](size_t x) { return (x + 15) & ~(size_t)15; };
   // block-vector byte offsets of the columns (rows 0 .. max_rows - 1) must
@@ -214,7 +215,10 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, in
               const V v = to_store<V, T>(h.val[src]);
               const uint16_t cb = (uint16_t)((uint32_t)h.col[src] * (uint32_t)col_scale);
               std::memcpy(p + o_val + (row * VS + j) * sizeof(V), &v, sizeof(V));
-              std::memcpy(p + o_col + (row * CS + j) * 2, &cb, 2);
+              // half-row U stages: slots ms/2.. start at the next 4-byte
+              // boundary of the column row (two lanes per row)
+              const int hs = ms / 2, jc = (isU && half_u && j >= hs) ? j - hs + stream_half_coff(ms) : j;
+              std::memcpy(p + o_col + (row * CS + jc) * 2, &cb, 2);
               ++src;
             }
           }
@@ -311,13 +315,14 @@ TriHost<T> build_tri_par(const CSR<T>& M, const std::vector<int64_t>& blocks, bo
     h.col.insert(h.col.end(), q.col.begin(), q.col.end());
     h.maxslot = std::max(h.maxslot, q.maxslot);
     h.depth = std::max(h.depth, q.depth);
+    h.maxwidth = std::max(h.maxwidth, q.maxwidth);
   }
   return h;
 }
 
 template <class V, class D, class T>
 bool build_chunks_par(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, int ms,
-                      int col_scale, int max_rows, std::vector<uint8_t>& blob,
+                      int col_scale, int max_rows, bool half_u, std::vector<uint8_t>& blob,
                       std::vector<ChunkDesc>& desc, std::vector<int32_t>& blk_chunk) {
   const int nt = layout_threads((size_t)nb);
   std::vector<std::vector<uint8_t>> pb(nt);
@@ -330,7 +335,7 @@ bool build_chunks_par(const TriHost<T>& lo, const TriHost<T>& up, int nb, int ca
     th.emplace_back([&, t] {
       try {
         const int b0 = (int)((int64_t)nb * t / nt), b1 = (int)((int64_t)nb * (t + 1) / nt);
-        ok[t] = build_chunks<V, D, T>(lo, up, b0, b1, cap, ms, col_scale, max_rows, pb[t], pd[t],
+        ok[t] = build_chunks<V, D, T>(lo, up, b0, b1, cap, ms, col_scale, max_rows, half_u, pb[t], pd[t],
                                       pc[t]);
       } catch (...) {
         err[t] = std::current_exception();
@@ -385,6 +390,7 @@ struct EngineT final : Engine {
     const ChunkDesc* chunk = nullptr;
     const int32_t* blk_chunk = nullptr;
     int chunk_cap = 0, x_bytes = 0, nbuf = 2;
+    bool half_u = false;  // U chunks laid out and swept as half rows
     int64_t nchunks = 0;
     int depth_l = 0, depth_u = 0;
   };
@@ -449,6 +455,9 @@ struct EngineT final : Engine {
   // GEMSLR_GROUP_CUS=c: group as if the device had c CUs (tests use it to
   // form groups from a few blocks)
   bool no_group = std::getenv("GEMSLR_NO_GROUP") != nullptr;
+  // GEMSLR_NO_HALF_U: U stages swept one lane per row even when no
+  // wavefront level is wider than 32 rows
+  bool no_half_u = std::getenv("GEMSLR_NO_HALF_U") != nullptr;
   // GEMSLR_NO_FUSE_SMALL: small levels use the three-launch interface step
   bool no_fuse_small = std::getenv("GEMSLR_NO_FUSE_SMALL") != nullptr;
   // GEMSLR_NO_FUSE_PERM: the apply gathers and scatters all n rows in
@@ -536,8 +545,12 @@ struct EngineT final : Engine {
           std::vector<uint8_t> blob;
           std::vector<ChunkDesc> desc;
           std::vector<int32_t> bc;
+          // U stages of at most 32 rows (no wavefront level wider): two lanes
+          // per row, each with half of the row's slots
+          const bool half_u = !no_half_u && tu.maxwidth <= 32;
           if (build_chunks_par<V, D, T>(tl, tu, L.nb, cap, ms, ColScale<C>::value,
-                                        L.max_block_rows, blob, desc, bc)) {
+                                        L.max_block_rows, half_u, blob, desc, bc)) {
+            L.half_u = half_u;
             L.blob = upload(blob);
             std::vector<uint8_t> draw(desc.size() * sizeof(ChunkDesc));
             if (!desc.empty()) std::memcpy(draw.data(), desc.data(), draw.size());
@@ -738,6 +751,7 @@ struct EngineT final : Engine {
     a.chunk_cap = L.chunk_cap;
     a.x_bytes = L.x_bytes;
     a.nbuf = L.nbuf;
+    a.half_u = L.half_u ? 1 : 0;
     a.xin = nullptr;
     a.yout = nullptr;
     a.perm = nullptr;

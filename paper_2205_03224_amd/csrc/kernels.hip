@@ -492,6 +492,135 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
   }
 }
 
+// Half-row U stages (stages of at most 32 rows): lanes l and l + 32 share
+// row l of the stage, each with MS/2 of its slots (the column row holds the
+// second half from 16-bit position stream_half_coff(MS)).  Each lane forms
+// the partial sum of its half; v_permlane32_swap hands it to the partner,
+// and both lanes add the two halves in the same order (low half first), so
+// they compute identical values and store the same result.  Half the
+// entry, column and gather LDS operations of a full-row stage.
+template <class P, int MS>
+struct HalfRegs {
+  typename P::C v[MS / 2];
+  uint32_t c[(MS / 2 + 1) / 2];
+  typename P::C dv;
+  int row;
+  int nr;
+};
+
+template <class P, int MS>
+__device__ __forceinline__ void half_load(const typename P::V* val, const typename P::D* dinv,
+                                          const uint16_t* col, uint32_t info, int r0, int ql,
+                                          int half, int dummy, HalfRegs<P, MS>& R) {
+  using C = typename P::C;
+  constexpr int VS = stream_vstride(MS), CS = stream_cstride(MS), HS = MS / 2;
+  constexpr int CO = stream_half_coff(MS);
+  static_assert(CO + HS <= CS, "column row holds both halves");
+  R.nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
+  const bool act = ql < R.nr;
+  R.row = act ? (int)(info & 0xffffu) : dummy;
+  const int q = act ? r0 + ql : r0;
+  const typename P::V* vr = val + q * VS + half * HS;
+  const uint32_t* cr = reinterpret_cast<const uint32_t*>(col + q * CS + half * CO);
+#pragma unroll
+  for (int j = 0; j < HS; ++j) R.v[j] = cvt<C>(vr[j]);
+#pragma unroll
+  for (int j = 0; j < (HS + 1) / 2; ++j) R.c[j] = cr[j];
+  R.dv = cvt<C>(dinv[q]);
+}
+
+// the partner lane's (lane +- 32) value of x
+__device__ __forceinline__ double swap32(double x, bool low) {
+  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double((int)(low ? b[1] : b[0]), (int)(low ? a[1] : a[0]));
+}
+__device__ __forceinline__ float swap32(float x, bool low) {
+  const unsigned u = __float_as_uint(x);
+  const auto a = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  return __uint_as_float(low ? a[1] : a[0]);
+}
+__device__ __forceinline__ dcplx swap32(dcplx x, bool low) {
+  return mk(swap32(x.x, low), swap32(x.y, low));
+}
+
+template <class P, int MS, int NB>
+__device__ __forceinline__ void half_compute(const HalfRegs<P, MS>& R, typename P::C* x,
+                                             bool low) {
+  using C = typename P::C;
+  constexpr int kMul = (int)sizeof(C) / ColScale<C>::value;
+  constexpr int kX2 = pair_offset<C>();
+  constexpr int HS = MS / 2;
+  const unsigned char* xb = reinterpret_cast<const unsigned char*>(x);
+  C xv[HS], xw[HS];
+#pragma unroll
+  for (int j = 0; j < HS; ++j) {
+    const uint32_t cj = j % 2 ? R.c[j / 2] >> 16 : R.c[j / 2] & 0xffffu;
+    xv[j] = *reinterpret_cast<const C*>(xb + cj * kMul);
+    if (NB == 2) xw[j] = *reinterpret_cast<const C*>(xb + cj * kMul + kX2);
+  }
+  const C b = x[R.row];
+  C bw = zero<C>();
+  if (NB == 2) bw = *reinterpret_cast<const C*>(xb + R.row * sizeof(C) + kX2);
+  C s0 = zero<C>(), s1 = zero<C>(), w0 = zero<C>(), w1 = zero<C>();
+#pragma unroll
+  for (int j = 0; j < HS; j += 2) {
+    s0 += R.v[j] * xv[j];
+    if (j + 1 < HS) s1 += R.v[j + 1] * xv[j + 1];
+    if (NB == 2) {
+      w0 += R.v[j] * xw[j];
+      if (j + 1 < HS) w1 += R.v[j + 1] * xw[j + 1];
+    }
+  }
+  const C p = s0 + s1;
+  const C o = swap32(p, low);
+  C acc = b - (low ? p + o : o + p);
+  acc *= R.dv;
+  x[R.row] = acc;
+  if (NB == 2) {
+    const C pw = w0 + w1;
+    const C ow = swap32(pw, low);
+    C aw = bw - (low ? pw + ow : ow + pw);
+    aw *= R.dv;
+    *reinterpret_cast<C*>(reinterpret_cast<unsigned char*>(x) + R.row * sizeof(C) + kX2) = aw;
+  }
+}
+
+// chunk_sweep for a half-row U chunk (same two-register-set pipeline)
+template <class P, int MS, int NB>
+__device__ __forceinline__ void chunk_sweep_half(const uint8_t* cb, const ChunkDesc& cd,
+                                                 int lane, typename P::C* x, int dummy) {
+  using V = typename P::V;
+  using D = typename P::D;
+  const V* val = reinterpret_cast<const V*>(cb);
+  const D* dinv = reinterpret_cast<const D*>(cb + 16 * (int)cd.dinv16);
+  const uint32_t* rinfo = reinterpret_cast<const uint32_t*>(cb + 16 * (int)cd.info16);
+  const uint16_t* col = reinterpret_cast<const uint16_t*>(cb + 16 * (int)cd.col16);
+  const int nst = cd.nst & 0x7fff;
+  const int ql = lane & 31, half = lane >> 5;
+  const bool low = half == 0;
+  HalfRegs<P, MS> A, B;
+  half_load<P, MS>(val, dinv, col, rinfo[ql], 0, ql, half, dummy, A);
+  int r1 = A.nr;
+  uint32_t i1 = rinfo[min(r1 + ql, (int)cd.nrows)];
+  i1 = nst > 1 ? i1 : 0u;
+  for (int s = 0; s < nst; s += 2) {
+    half_load<P, MS>(val, dinv, col, i1, r1, ql, half, dummy, B);  // stage s+1
+    const int r2 = r1 + B.nr;
+    uint32_t i2 = rinfo[min(r2 + ql, (int)cd.nrows)];
+    i2 = s + 2 < nst ? i2 : 0u;
+    half_compute<P, MS, NB>(A, x, low);                            // stage s
+    half_load<P, MS>(val, dinv, col, i2, r2, ql, half, dummy, A);  // stage s+2
+    const int r3 = r2 + A.nr;
+    uint32_t i3 = rinfo[min(r3 + ql, (int)cd.nrows)];
+    i3 = s + 3 < nst ? i3 : 0u;
+    half_compute<P, MS, NB>(B, x, low);                            // stage s+1
+    r1 = r3;
+    i1 = i3;
+  }
+}
+
 // Right-hand side of a block into LDS: DOWN reads b1, UP reads F_l y2.
 // 256 bytes of loads per thread in flight at once (a whole 4096-row float64
 // block in one round trip with 128 threads).
@@ -622,7 +751,8 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
     } else {
       const ChunkDesc cd = desc_get<P>(a, c, c1, lane, dc);
       uint8_t* cur = bufs + (k % nbuf) * a.chunk_cap;
-      if (cd.nst & 0x8000) chunk_sweep<P, MS, true, NB>(cur, cd, lane, x, nr);
+      if ((cd.nst & 0x8000) && a.half_u) chunk_sweep_half<P, MS, NB>(cur, cd, lane, x, nr);
+      else if (cd.nst & 0x8000) chunk_sweep<P, MS, true, NB>(cur, cd, lane, x, nr);
       else chunk_sweep<P, MS, false, NB>(cur, cd, lane, x, nr);
       // every read of the buffer done before the producer may refill it
       __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);

@@ -155,7 +155,8 @@ def test_native_setup_solves(torch_dev):
                                  {"GEMSLR_CHUNK_BUFS": "3", "GEMSLR_LDS_BUDGET": "16384"},
                                  {"GEMSLR_NO_GROUP": "1"}, {"GEMSLR_GROUP_CUS": "4"},
                                  {"GEMSLR_GROUP_CUS": "2", "GEMSLR_NO_STREAM": "1"},
-                                 {"GEMSLR_NO_FUSE_SMALL": "1"}, {"GEMSLR_NO_FUSE_PERM": "1"}])
+                                 {"GEMSLR_NO_FUSE_SMALL": "1"}, {"GEMSLR_NO_FUSE_PERM": "1"},
+                                 {"GEMSLR_NO_HALF_U": "1"}])
 @pytest.mark.parametrize("name", ["convdiff3d_20_p27", "helmholtz3d_16_p8"])
 def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
     """Both block-trisolve kernels (register prefetch; LDS-streamed with small
@@ -163,8 +164,8 @@ def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
     two or three chunk buffers; consecutive diagonal blocks swept by one
     workgroup or one each), both interface paths (one fused launch for
     small levels, three launches) and both ways of applying the permutation
-    (inside the level-0 sweeps, or separate kernels) give the oracle's
-    apply."""
+    (inside the level-0 sweeps, or separate kernels), and U stages swept
+    with one lane per row or two lanes per row, give the oracle's apply."""
     torch = torch_dev
     for k, v in env.items():
         monkeypatch.setenv(k, v)
