@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "device.h"
 
@@ -974,6 +975,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typenam
 template <class P>
 static int interface_rows(int64_t s, int k) {
   using C = typename P::C;
+  // (measured at level 0, k = 33: two rows 28 us, one row 31 us)
   return sizeof(C) < 16 && k <= 40 && s >= (int64_t)kIfThreads * 2 * 512 ? 2 : 1;
 }
 
