@@ -22,102 +22,173 @@ const double kEps = std::numeric_limits<double>::epsilon();
 }  // namespace
 
 void schur_complex(int m, std::vector<cplx>& a, std::vector<cplx>& q) {
-  q.assign((size_t)m * m, cplx(0));
-  for (int i = 0; i < m; ++i) at(q, m, i, i) = 1.0;
-  if (m <= 1) return;
-  // --- Householder reduction to Hessenberg form: A <- P A P, Q <- Q P
-  std::vector<cplx> v(m);
-  for (int k = 0; k + 2 < m; ++k) {
-    double xn = 0;
-    for (int i = k + 1; i < m; ++i) xn += std::norm(at(a, m, i, k));
-    xn = std::sqrt(xn);
-    if (xn == 0) continue;
-    cplx x0 = at(a, m, k + 1, k);
-    cplx ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : cplx(1);
-    for (int i = 0; i < m; ++i) v[i] = 0;
-    for (int i = k + 1; i < m; ++i) v[i] = at(a, m, i, k);
-    v[k + 1] += ph * xn;
-    double vn = 0;
-    for (int i = k + 1; i < m; ++i) vn += std::norm(v[i]);
-    if (vn == 0) continue;
-    // A <- (I - 2 v v^H / vn) A
-    for (int j = 0; j < m; ++j) {
-      cplx s = 0;
-      for (int i = k + 1; i < m; ++i) s += std::conj(v[i]) * at(a, m, i, j);
-      s *= 2.0 / vn;
-      for (int i = k + 1; i < m; ++i) at(a, m, i, j) -= v[i] * s;
-    }
-    // A <- A (I - 2 v v^H / vn), Q likewise
-    for (std::vector<cplx>* M : {&a, &q}) {
-      for (int i = 0; i < m; ++i) {
-        cplx s = 0;
-        for (int j = k + 1; j < m; ++j) s += at(*M, m, i, j) * v[j];
-        s *= 2.0 / vn;
-        for (int j = k + 1; j < m; ++j) at(*M, m, i, j) -= s * std::conj(v[j]);
-      }
-    }
-    for (int i = k + 2; i < m; ++i) at(a, m, i, k) = 0;
+  // Real and imaginary parts in separate column-major arrays, so that the
+  // column and Schur-vector updates below are contiguous loops the compiler
+  // vectorises; the arithmetic is the same as with std::complex.
+  const size_t mm = (size_t)m * m;
+  std::vector<double> Ar(mm), Ai(mm), Qr(mm, 0.0), Qi(mm, 0.0);
+  for (size_t e = 0; e < mm; ++e) {
+    Ar[e] = a[e].real();
+    Ai[e] = a[e].imag();
   }
-  // --- shifted QR on the Hessenberg matrix
-  int hi = m - 1;
-  int iter = 0, total = 0;
-  while (hi > 0) {
-    // find the start of the active unreduced block
-    int lo = hi;
-    while (lo > 0) {
-      double sub = std::abs(at(a, m, lo, lo - 1));
-      double dd = std::abs(at(a, m, lo - 1, lo - 1)) + std::abs(at(a, m, lo, lo));
-      if (dd == 0) dd = 1.0;
-      if (sub <= kEps * dd) { at(a, m, lo, lo - 1) = 0; break; }
-      --lo;
+  for (int i = 0; i < m; ++i) Qr[(size_t)i * m + i] = 1.0;
+  auto ix = [m](int i, int j) { return (size_t)j * m + i; };
+  if (m > 1) {
+    // --- Householder reduction to Hessenberg form: A <- P A P, Q <- Q P,
+    // P = I - 2 v v^H / |v|^2
+    std::vector<double> vr(m), vi(m), wr(m), wi(m);
+    for (int k = 0; k + 2 < m; ++k) {
+      double xn = 0;
+      for (int i = k + 1; i < m; ++i) xn += Ar[ix(i, k)] * Ar[ix(i, k)] + Ai[ix(i, k)] * Ai[ix(i, k)];
+      xn = std::sqrt(xn);
+      if (xn == 0) continue;
+      const double x0r = Ar[ix(k + 1, k)], x0i = Ai[ix(k + 1, k)];
+      const double x0a = std::hypot(x0r, x0i);
+      const double phr = x0a > 0 ? x0r / x0a : 1.0, phi = x0a > 0 ? x0i / x0a : 0.0;
+      for (int i = k + 1; i < m; ++i) {
+        vr[i] = Ar[ix(i, k)];
+        vi[i] = Ai[ix(i, k)];
+      }
+      vr[k + 1] += phr * xn;
+      vi[k + 1] += phi * xn;
+      double vn = 0;
+      for (int i = k + 1; i < m; ++i) vn += vr[i] * vr[i] + vi[i] * vi[i];
+      if (vn == 0) continue;
+      const double f = 2.0 / vn;
+      // A <- P A: column j -= v (v^H A_j) f
+      for (int j = 0; j < m; ++j) {
+        const double* cr = &Ar[ix(0, j)];
+        const double* ci = &Ai[ix(0, j)];
+        double sr = 0, si = 0;
+        for (int i = k + 1; i < m; ++i) {  // conj(v) * a
+          sr += vr[i] * cr[i] + vi[i] * ci[i];
+          si += vr[i] * ci[i] - vi[i] * cr[i];
+        }
+        sr *= f;
+        si *= f;
+        double* dr = &Ar[ix(0, j)];
+        double* di = &Ai[ix(0, j)];
+        for (int i = k + 1; i < m; ++i) {
+          dr[i] -= vr[i] * sr - vi[i] * si;
+          di[i] -= vr[i] * si + vi[i] * sr;
+        }
+      }
+      // M <- M P for M = A, Q: w = M v, then column j -= w conj(v_j) f
+      for (int which = 0; which < 2; ++which) {
+        std::vector<double>& Mr = which ? Qr : Ar;
+        std::vector<double>& Mi = which ? Qi : Ai;
+        std::fill(wr.begin(), wr.end(), 0.0);
+        std::fill(wi.begin(), wi.end(), 0.0);
+        for (int j = k + 1; j < m; ++j) {
+          const double* cr = &Mr[ix(0, j)];
+          const double* ci = &Mi[ix(0, j)];
+          const double br = vr[j], bi = vi[j];
+          for (int i = 0; i < m; ++i) {
+            wr[i] += cr[i] * br - ci[i] * bi;
+            wi[i] += cr[i] * bi + ci[i] * br;
+          }
+        }
+        for (int j = k + 1; j < m; ++j) {
+          const double br = vr[j] * f, bi = -vi[j] * f;  // conj(v_j) f
+          double* dr = &Mr[ix(0, j)];
+          double* di = &Mi[ix(0, j)];
+          for (int i = 0; i < m; ++i) {
+            dr[i] -= wr[i] * br - wi[i] * bi;
+            di[i] -= wr[i] * bi + wi[i] * br;
+          }
+        }
+      }
+      for (int i = k + 2; i < m; ++i) Ar[ix(i, k)] = Ai[ix(i, k)] = 0.0;
     }
-    if (lo == hi) { --hi; iter = 0; continue; }
-    if (++total > 100 * m) throw Error(GS_EINVAL, "Schur QR iteration did not converge");
-    ++iter;
-    // Wilkinson shift from the trailing 2x2 of the active block
-    cplx sigma;
-    if (iter % 11 == 10) {
-      sigma = at(a, m, hi, hi) + 0.75 * std::abs(at(a, m, hi, hi - 1));
-    } else {
-      cplx aa = at(a, m, hi - 1, hi - 1), bb = at(a, m, hi - 1, hi);
-      cplx cc = at(a, m, hi, hi - 1), dd = at(a, m, hi, hi);
-      cplx tr2 = (aa + dd) * 0.5;
-      cplx disc = std::sqrt((aa - dd) * (aa - dd) * 0.25 + bb * cc);
-      cplx e1 = tr2 + disc, e2 = tr2 - disc;
-      sigma = (std::abs(e1 - dd) < std::abs(e2 - dd)) ? e1 : e2;
+    // --- shifted QR on the Hessenberg matrix
+    auto absA = [&](int i, int j) { return std::hypot(Ar[ix(i, j)], Ai[ix(i, j)]); };
+    int hi = m - 1;
+    int iter = 0, total = 0;
+    while (hi > 0) {
+      // find the start of the active unreduced block
+      int lo = hi;
+      while (lo > 0) {
+        const double sub = absA(lo, lo - 1);
+        double dd = absA(lo - 1, lo - 1) + absA(lo, lo);
+        if (dd == 0) dd = 1.0;
+        if (sub <= kEps * dd) {
+          Ar[ix(lo, lo - 1)] = Ai[ix(lo, lo - 1)] = 0.0;
+          break;
+        }
+        --lo;
+      }
+      if (lo == hi) {
+        --hi;
+        iter = 0;
+        continue;
+      }
+      if (++total > 100 * m) throw Error(GS_EINVAL, "Schur QR iteration did not converge");
+      ++iter;
+      // Wilkinson shift from the trailing 2x2 of the active block
+      cplx sigma;
+      if (iter % 11 == 10) {
+        sigma = cplx(Ar[ix(hi, hi)], Ai[ix(hi, hi)]) + 0.75 * absA(hi, hi - 1);
+      } else {
+        const cplx aa(Ar[ix(hi - 1, hi - 1)], Ai[ix(hi - 1, hi - 1)]);
+        const cplx bb(Ar[ix(hi - 1, hi)], Ai[ix(hi - 1, hi)]);
+        const cplx cc(Ar[ix(hi, hi - 1)], Ai[ix(hi, hi - 1)]);
+        const cplx dd(Ar[ix(hi, hi)], Ai[ix(hi, hi)]);
+        const cplx tr2 = (aa + dd) * 0.5;
+        const cplx disc = std::sqrt((aa - dd) * (aa - dd) * 0.25 + bb * cc);
+        const cplx e1 = tr2 + disc, e2 = tr2 - disc;
+        sigma = (std::abs(e1 - dd) < std::abs(e2 - dd)) ? e1 : e2;
+      }
+      // implicit single-shift bulge chase on rows/cols lo..hi
+      double xr = Ar[ix(lo, lo)] - sigma.real(), xi = Ai[ix(lo, lo)] - sigma.imag();
+      double yr = Ar[ix(lo + 1, lo)], yi = Ai[ix(lo + 1, lo)];
+      for (int k = lo; k < hi; ++k) {
+        const double r = std::sqrt(xr * xr + xi * xi + yr * yr + yi * yi);
+        double cr = 1, ci = 0, sr = 0, si = 0;
+        if (r != 0) {
+          cr = xr / r;
+          ci = xi / r;
+          sr = yr / r;
+          si = yi / r;
+        }
+        // rows k, k+1 <- G^H rows, G^H = [[conj c, conj s], [-s, c]]
+        for (int j = std::max(lo, k - 1); j < m; ++j) {
+          const size_t p0 = ix(k, j), p1 = p0 + 1;
+          const double pr = Ar[p0], pi = Ai[p0], tr = Ar[p1], ti = Ai[p1];
+          Ar[p0] = (cr * pr + ci * pi) + (sr * tr + si * ti);
+          Ai[p0] = (cr * pi - ci * pr) + (sr * ti - si * tr);
+          Ar[p1] = -(sr * pr - si * pi) + (cr * tr - ci * ti);
+          Ai[p1] = -(sr * pi + si * pr) + (cr * ti + ci * tr);
+        }
+        if (k > lo) Ar[ix(k + 1, k - 1)] = Ai[ix(k + 1, k - 1)] = 0.0;  // the bulge just annihilated
+        // cols k, k+1 <- cols G, G = [[c, -conj s], [s, conj c]]
+        const int imax = std::min(k + 2, hi);
+        for (int which = 0; which < 2; ++which) {
+          double* Pr = which ? &Qr[ix(0, k)] : &Ar[ix(0, k)];
+          double* Pi = which ? &Qi[ix(0, k)] : &Ai[ix(0, k)];
+          double* Tr = Pr + m;
+          double* Ti = Pi + m;
+          const int n = which ? m : imax + 1;
+          for (int i = 0; i < n; ++i) {
+            const double pr = Pr[i], pi = Pi[i], tr = Tr[i], ti = Ti[i];
+            Pr[i] = (pr * cr - pi * ci) + (tr * sr - ti * si);
+            Pi[i] = (pr * ci + pi * cr) + (tr * si + ti * sr);
+            Tr[i] = -(pr * sr + pi * si) + (tr * cr + ti * ci);
+            Ti[i] = -(pi * sr - pr * si) + (ti * cr - tr * ci);
+          }
+        }
+        if (k + 1 < hi) {
+          xr = Ar[ix(k + 1, k)];
+          xi = Ai[ix(k + 1, k)];
+          yr = Ar[ix(k + 2, k)];
+          yi = Ai[ix(k + 2, k)];
+        }
+      }
     }
-    // implicit single-shift bulge chase on rows/cols lo..hi
-    cplx x = at(a, m, lo, lo) - sigma;
-    cplx y = at(a, m, lo + 1, lo);
-    for (int k = lo; k < hi; ++k) {
-      double r = std::sqrt(std::norm(x) + std::norm(y));
-      cplx c, s;
-      if (r == 0) { c = 1; s = 0; }
-      else { c = x / r; s = y / r; }
-      // rows k, k+1 <- G^H rows, G^H = [[conj c, conj s], [-s, c]]
-      for (int j = std::max(lo, k - 1); j < m; ++j) {
-        cplx p = at(a, m, k, j), t = at(a, m, k + 1, j);
-        at(a, m, k, j) = std::conj(c) * p + std::conj(s) * t;
-        at(a, m, k + 1, j) = -s * p + c * t;
-      }
-      if (k > lo) at(a, m, k + 1, k - 1) = 0;  // the bulge just annihilated
-      // cols k, k+1 <- cols G, G = [[c, -conj s], [s, conj c]]
-      int imax = std::min(k + 2, hi);
-      for (int i = 0; i <= imax; ++i) {
-        cplx p = at(a, m, i, k), t = at(a, m, i, k + 1);
-        at(a, m, i, k) = p * c + t * s;
-        at(a, m, i, k + 1) = -p * std::conj(s) + t * std::conj(c);
-      }
-      for (int i = 0; i < m; ++i) {
-        cplx p = at(q, m, i, k), t = at(q, m, i, k + 1);
-        at(q, m, i, k) = p * c + t * s;
-        at(q, m, i, k + 1) = -p * std::conj(s) + t * std::conj(c);
-      }
-      if (k + 1 < hi) {
-        x = at(a, m, k + 1, k);
-        y = at(a, m, k + 2, k);
-      }
-    }
+  }
+  q.assign(mm, cplx(0));
+  for (size_t e = 0; e < mm; ++e) {
+    a[e] = cplx(Ar[e], Ai[e]);
+    q[e] = cplx(Qr[e], Qi[e]);
   }
   for (int j = 0; j < m; ++j)
     for (int i = j + 1; i < m; ++i) at(a, m, i, j) = 0;
