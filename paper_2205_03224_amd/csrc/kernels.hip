@@ -1130,12 +1130,14 @@ __global__ void k_scatter(const typename P::X* t, const int32_t* perm, typename 
 template <class P>
 void launch_gather(const typename P::O* x, const int32_t* perm, typename P::X* t, int64_t n,
                    hipStream_t st) {
+  if (n <= 0) return;
   hipLaunchKernelGGL(k_gather<P>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, perm,
                      t, n);
 }
 template <class P>
 void launch_scatter(const typename P::X* t, const int32_t* perm, typename P::O* y, int64_t n,
                     hipStream_t st) {
+  if (n <= 0) return;
   hipLaunchKernelGGL(k_scatter<P>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t,
                      perm, y, n);
 }
@@ -1273,6 +1275,7 @@ __global__ void k_scale_inv(const T* x, const double* nrm, T* y, int64_t n) {
 }
 template <class T>
 void launch_scale_inv(const T* x, const double* nrm, T* y, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
   hipLaunchKernelGGL(k_scale_inv<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, nrm,
                      y, n);
 }
@@ -1302,8 +1305,10 @@ __global__ void k_arnoldi_step(const T* h, int cnt, const double* nrm, T* Scol, 
 template <class T>
 void launch_arnoldi_step(const T* h, int cnt, const double* nrm, T* Scol, double* nd, double* flag,
                          const T* w, T* y, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_arnoldi_step<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, h,
-                     cnt, nrm, Scol, nd, flag, w, y, n);
+  // at least one block: block 0 records h and the norms
+  const int64_t nblk = n > 0 ? (n + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_arnoldi_step<T>, dim3((unsigned)nblk), dim3(256), 0, st, h, cnt, nrm, Scol,
+                     nd, flag, w, y, n);
 }
 
 template <class T>
