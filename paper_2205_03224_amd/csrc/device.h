@@ -178,6 +178,13 @@ struct IfArgs {
   const typename P::C* H;    // k x k column-major, compute type
   typename P::C* partial;    // gridDim x k partial sums of W^H z2
   typename P::C* tprime;     // k: H (W^H z2), written by a second launch
+  // small-level kernel only: when the next (last) level is diagonal, its
+  // solve in the same pass: C-part = w * last_dinv (1/u_ii in row order)
+  const typename P::D* last_dinv = nullptr;
+  // level 0 of an apply: b2 read from the caller's vector, xin[perm[d + i]]
+  // (perm null: identity), instead of t
+  const typename P::O* xin = nullptr;
+  const int32_t* perm = nullptr;
 };
 
 // ------------------------------------------------------------ launchers

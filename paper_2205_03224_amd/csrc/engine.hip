@@ -391,6 +391,7 @@ struct EngineT final : Engine {
     const int32_t* blk_chunk = nullptr;
     int chunk_cap = 0, x_bytes = 0, nbuf = 2;
     bool half_u = false;  // U chunks laid out and swept as half rows
+    D* diag_dinv = nullptr;  // diagonal level (L = I, U diagonal): 1/u_ii in row order
     int64_t nchunks = 0;
     int depth_l = 0, depth_u = 0;
   };
@@ -524,6 +525,19 @@ struct EngineT final : Engine {
       TriHost<T> tl = build_tri_par(h.L, grp, false);
       TriHost<T> tu = build_tri_par(h.U, grp, true);
       L.maxslot = std::max(tl.maxslot, tu.maxslot);
+      if (L.maxslot == 0 && h.d > 0) {
+        // a diagonal level: keep 1/u_ii in row order (computed as the sweep
+        // layout computes it), so a caller may fuse its solve
+        std::vector<D> dv((size_t)h.d);
+        for (int64_t i = 0; i < h.d; ++i) {
+          T diag = T(0);
+          for (int64_t p = h.U.rp[i]; p < h.U.rp[i + 1]; ++p)
+            if (h.U.ci[p] == i) diag = h.U.v[p];
+          if (absval(diag) == 0.0) throw Error(GS_EZEROPIVOT, "U factor has a zero or missing diagonal");
+          dv[(size_t)i] = to_store<D, T>(T(1) / diag);
+        }
+        L.diag_dinv = upload(dv);
+      }
       L.depth_l = tl.depth;
       L.depth_u = tu.depth;
       L.nstages = (int64_t)(tl.stage_row.size() + tu.stage_row.size()) - 2;
@@ -862,11 +876,13 @@ struct EngineT final : Engine {
            + (double)L.nnz_f * xb + (double)L.d * xb;           // y2 gathers, z1 read
     return b + fused;
   }
-  double if_bytes(int l, int k) const {
+  double if_bytes(int l, int k, bool gather_fused = false) const {
     const Lev& L = lv[l];
     const double vb = sizeof(V), xb = sizeof(X);
+    // gather fused: b2 is a caller vector entry plus its index
+    const double b2 = gather_fused ? 4.0 + sizeof(O) : xb;
     return (double)L.nnz_e * (vb + 4) + (double)(L.s + 1) * 4 + (double)L.nnz_e * xb +
-           2.0 * L.s * xb + (double)L.s * k * vb;
+           (double)L.s * (b2 + xb) + (double)L.s * k * vb;
   }
   double upd_bytes(int l, int k) const {
     const Lev& L = lv[l];
@@ -874,7 +890,16 @@ struct EngineT final : Engine {
   }
   double perm_bytes(int64_t m) const { return (double)m * (4 + sizeof(O) + sizeof(X)); }
 
-  void interface(int l, int k, X* tv = nullptr) {
+  // level l's small-level interface step can also do the solve of level
+  // l + 1: the last level, diagonal, exactly level l's C-part
+  bool last_fusable(int l) const {
+    const Lev& L = lv[l];
+    return !no_fuse_small && L.s <= 4096 && l + 2 == (int)lv.size() && lv[l + 1].diag_dinv &&
+           lv[l + 1].start == L.start + L.d && lv[l + 1].d == L.s && lv[l].k <= 64;
+  }
+  // Returns true when the solve of level l + 1 (diagonal, the last level)
+  // was done in the same launch (fuse_last requested and possible).
+  bool interface(int l, int k, X* tv = nullptr, bool fuse_last = false) {
     Lev& L = lv[l];
     if (!tv) tv = t;
     IfArgs<P> a;
@@ -887,27 +912,43 @@ struct EngineT final : Engine {
     a.H = L.H;
     a.partial = L.partial;
     a.tprime = L.tprime;
-    if (L.s <= 4096 && k <= 64 && !no_fuse_small) {
-      // small level: the three steps in one workgroup
-      step("interface+update L" + std::to_string(l), KIND_INTERFACE,
-           if_bytes(l, k) + (k > 0 ? upd_bytes(l, k) : 0.0),
-           [&] { launch_interface_small<P>(a, st); });
-      return;
+    const bool gfused = l == 0 && fuse.on && tv == t;
+    if (gfused) {
+      // the apply's gather of the C_0 rows happens here
+      a.xin = fuse.x;
+      a.perm = fuse.perm;
     }
-    step("interface L" + std::to_string(l), KIND_INTERFACE, if_bytes(l, k),
+    if (L.s <= 4096 && k <= 64 && !no_fuse_small) {
+      // small level: the three steps in one workgroup (and, when the next
+      // level is the last and diagonal, its solve)
+      const bool last = fuse_last && last_fusable(l);
+      if (last) a.last_dinv = lv[l + 1].diag_dinv;
+      step(std::string(last ? "interface+update+solve L" : "interface+update L") +
+               std::to_string(l),
+           KIND_INTERFACE,
+           if_bytes(l, k, gfused) + (k > 0 ? upd_bytes(l, k) : 0.0) +
+               (last ? (double)L.s * sizeof(D) : 0.0),
+           [&] { launch_interface_small<P>(a, st); });
+      return last;
+    }
+    step("interface L" + std::to_string(l), KIND_INTERFACE, if_bytes(l, k, gfused),
          [&] { launch_interface<P>(a, st); });
     if (k > 0)
       step("lowrank_update L" + std::to_string(l), KIND_LOWRANK, upd_bytes(l, k),
            [&] { launch_lowrank_update<P>(tv + L.start + L.d, L.s, k, L.W, L.tprime, st); });
+    return false;
   }
 
-  void down(int l) {
+  // returns true when the last level's solve was fused into this level's
+  // interface step
+  bool down(int l) {
     if (lv[l].nb > 0)
       step("trisolve_down L" + std::to_string(l), l == 0 ? KIND_TRI0 : KIND_TRI,
            tri_bytes(l, TRI_DOWN, l == 0 && fuse.on), [&] {
              trisolve(l, TRI_DOWN);
            });
-    if (l + 1 < (int)lv.size()) interface(l, lv[l].k);
+    if (l + 1 < (int)lv.size()) return interface(l, lv[l].k, nullptr, !no_fuse_small);
+    return false;
   }
   void up(int l) {
     if (lv[l].nb > 0)
@@ -918,7 +959,11 @@ struct EngineT final : Engine {
   }
   void run_from(int l0) {
     const int L = (int)lv.size() - 1;
-    for (int l = l0; l <= L; ++l) down(l);
+    bool last_done = false;
+    for (int l = l0; l <= L; ++l) {
+      if (l == L && last_done) break;
+      last_done = down(l);
+    }
     for (int l = L - 1; l >= l0; --l) up(l);
   }
 
@@ -926,13 +971,11 @@ struct EngineT final : Engine {
     const int32_t* pm = permuted ? nullptr : perm_d;
     const int64_t d0 = lv.empty() ? 0 : lv[0].d;
     if (fuse_ok()) {
-      // B_0 rows are read and written by the level-0 sweeps themselves;
-      // only the C_0 rows go through the gather and scatter kernels
+      // B_0 rows are read and written by the level-0 sweeps themselves and
+      // the C_0 rows read by the level-0 interface step; only the C_0 rows
+      // go through a scatter kernel
       const O* xo = (const O*)x;
       O* yo = (O*)y;
-      step("gather C0", KIND_PERM, perm_bytes(n - d0), [&] {
-        launch_gather<P>(pm ? xo : xo + d0, pm ? pm + d0 : nullptr, t + d0, n - d0, st);
-      });
       fuse = {true, xo, yo, pm};
       run_from(0);
       fuse = {};
@@ -963,13 +1006,16 @@ struct EngineT final : Engine {
       launch_gather<P>((const O*)x0, perm_d, t, n, st);
       launch_gather<P>((const O*)x1, perm_d, t2, n, st);
     });
+    bool last_done = false;
     for (int l = 0; l <= L; ++l) {
+      if (l == L && last_done) break;
       if (lv[l].nb > 0)
         step("trisolve_down x2 L" + std::to_string(l), KIND_TRI, 0.0,
              [&] { trisolve_pair(l, TRI_DOWN); });
       if (l < L) {
-        interface(l, lv[l].k, t);
-        interface(l, lv[l].k, t2);
+        const bool a0 = interface(l, lv[l].k, t, !no_fuse_small);
+        const bool a1 = interface(l, lv[l].k, t2, !no_fuse_small);
+        last_done = a0 && a1;
       }
     }
     for (int l = L - 1; l >= 0; --l)
@@ -1064,7 +1110,7 @@ struct EngineT final : Engine {
   double bytes_per_apply() const override {
     if (fuse_ok()) {
       const int64_t d0 = lv[0].d;
-      return 2 * perm_bytes(n - d0) + apply_bytes_from(0, true);
+      return perm_bytes(n - d0) + apply_bytes_from(0, true);
     }
     double b = 2 * perm_bytes(n);
     if (inner_m > 0) {
@@ -1089,9 +1135,13 @@ struct EngineT final : Engine {
     const int L = (int)lv.size() - 1;
     for (int l = l0; l <= L; ++l) {
       const bool f = perm_fused && l == 0;
+      if (l == L && l > l0 && last_fusable(l - 1)) {
+        b += (double)lv[l].d * sizeof(D);  // 1/u_ii read by the fused solve
+        break;
+      }
       if (lv[l].nb > 0) b += tri_bytes(l, TRI_DOWN, f);
       if (l < L) {
-        b += if_bytes(l, lv[l].k);
+        b += if_bytes(l, lv[l].k, f);
         if (lv[l].k > 0) b += upd_bytes(l, lv[l].k);
         if (lv[l].nb > 0) b += tri_bytes(l, TRI_UP, f);
       }

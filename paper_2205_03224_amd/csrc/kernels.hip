@@ -851,6 +851,18 @@ void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot, int ma
 // ======================================================================
 constexpr int kIfThreads = 256;
 
+// b2 of interface row i: t, or the caller's vector through the permutation
+template <class P>
+__device__ __forceinline__ typename P::C if_b2(const IfArgs<P>& a, int64_t i) {
+  using C = typename P::C;
+  using X = typename P::X;
+  if (a.xin) {
+    const int64_t g = a.d + i;
+    return cvt<C>(cvt<X>(a.xin[a.perm ? a.perm[g] : g]));
+  }
+  return cvt<C>(a.t[a.d + i]);
+}
+
 template <class P, int R, int KG>
 __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
   using C = typename P::C;
@@ -873,7 +885,7 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
     for (int q = 0; q < R; ++q) {
       z[q] = zero<C>();
       if (rows[q] >= 0) {
-        const C acc = cvt<C>(a.t[a.d + rows[q]]) - ez[q];
+        const C acc = if_b2(a, rows[q]) - ez[q];
         a.t[a.d + rows[q]] = cvt<X>(acc);
         z[q] = acc;
       }
@@ -1031,11 +1043,17 @@ __global__ __launch_bounds__(kSmallThreads) void k_interface_small(IfArgs<P> a) 
     const int rows[1] = {i};
     C ez[1];
     csr_rows<C, typename P::V, X, 1, 4>(a.E.rp, a.E.ci, a.E.v, a.t, rows, ez);
-    zs[i] = cvt<C>(tc[i]) - ez[0];
+    zs[i] = if_b2(a, i) - ez[0];
   }
   __syncthreads();
+  // the C-part's final value: w, or the diagonal last level's solve of it
+  // (as that level's sweep computes it: (w - 0) * 1/u_ii)
+  const auto put = [&](int i, const C& w) {
+    if (a.last_dinv) tc[i] = cvt<X>(cvt<C>(cvt<X>(w)) * cvt<C>(a.last_dinv[i]));
+    else tc[i] = cvt<X>(w);
+  };
   if (k == 0) {
-    for (int i = tid; i < s; i += kSmallThreads) tc[i] = cvt<X>(zs[i]);
+    for (int i = tid; i < s; i += kSmallThreads) put(i, zs[i]);
     return;
   }
   // T threads per column, thread (c, g) sums rows g, g + T, ...
@@ -1064,7 +1082,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_interface_small(IfArgs<P> a) 
     C w = zs[i];
 #pragma unroll 8
     for (int q = 0; q < k; ++q) w += cvt<C>(a.W[i + (int64_t)q * a.s]) * tp[q];
-    tc[i] = cvt<X>(w);
+    put(i, w);
   }
 }
 
