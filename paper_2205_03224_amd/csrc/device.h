@@ -159,6 +159,17 @@ struct TriArgs {
   typename P::X* t2;
   typename P::C* fy2;
   int32_t nrhs;
+  // streamed UP mode: F_l y2 formed by the sweep itself, from the rows of
+  // F_l that hold entries (null: read from fy, formed by a launch before).
+  // Record q is unit-local row frow[q] with entries j < fw at
+  // fcol/fval[j * nrec + q] (level-local C columns; padding column 0,
+  // value 0); sweep unit b owns records funit[b] .. funit[b + 1] - 1.
+  const int32_t* frow = nullptr;
+  const int32_t* fcol = nullptr;
+  const typename P::V* fval = nullptr;
+  const int32_t* funit = nullptr;
+  int32_t fw = 0;
+  int64_t nrec = 0;
 };
 
 // LDS byte offset of the second block vector in two-right-hand-side sweeps:

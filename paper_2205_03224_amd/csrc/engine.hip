@@ -394,6 +394,13 @@ struct EngineT final : Engine {
     D* diag_dinv = nullptr;  // diagonal level (L = I, U diagonal): 1/u_ii in row order
     int64_t nchunks = 0;
     int depth_l = 0, depth_u = 0;
+    // F_l records of the streamed up sweep (null: F_l y2 by k_fy)
+    const int32_t* frow = nullptr;
+    const int32_t* fcol = nullptr;
+    const V* fval = nullptr;
+    const int32_t* funit = nullptr;
+    int fw = 0;
+    int64_t nrec = 0;
   };
 
   hipStream_t st;
@@ -464,6 +471,45 @@ struct EngineT final : Engine {
   // GEMSLR_NO_FUSE_PERM: the apply gathers and scatters all n rows in
   // kernels of their own instead of inside the level-0 sweeps
   bool no_fuse_perm = std::getenv("GEMSLR_NO_FUSE_PERM") != nullptr;
+  // GEMSLR_NO_FUSE_FY: F_l y2 of the streamed up sweep in a launch of its own
+  bool no_fuse_fy = std::getenv("GEMSLR_NO_FUSE_FY") != nullptr;
+  // F_l records (see TriArgs::frow) of the sweep units grp: the rows that
+  // hold entries, padded to the longest such row; none if a row is longer
+  // than 16 entries (the sweep's prologue would then loop too long)
+  void build_f_records(Lev& L, const CSR<T>& F, const std::vector<int64_t>& grp) {
+    int64_t nrec = 0;
+    int fw = 0;
+    for (int64_t i = 0; i < L.d; ++i) {
+      const int64_t len = F.rp[i + 1] - F.rp[i];
+      if (len > 0) ++nrec;
+      fw = std::max<int>(fw, (int)std::min<int64_t>(len, 1 << 20));
+    }
+    if (fw > 16) return;
+    std::vector<int32_t> frow((size_t)nrec), funit((size_t)L.nb + 1, 0);
+    std::vector<int32_t> fcol((size_t)(nrec * fw), 0);
+    std::vector<T> fval((size_t)(nrec * fw), T(0));
+    int64_t q = 0;
+    for (int b = 0; b < L.nb; ++b) {
+      funit[(size_t)b] = (int32_t)q;
+      for (int64_t i = grp[b]; i < grp[b + 1]; ++i) {
+        if (F.rp[i + 1] == F.rp[i]) continue;
+        frow[(size_t)q] = (int32_t)(i - grp[b]);
+        for (int64_t p = F.rp[i]; p < F.rp[i + 1]; ++p) {
+          const int64_t j = p - F.rp[i];
+          fcol[(size_t)(j * nrec + q)] = F.ci[p];
+          fval[(size_t)(j * nrec + q)] = F.v[p];
+        }
+        ++q;
+      }
+    }
+    funit[(size_t)L.nb] = (int32_t)q;
+    L.frow = upload(frow);
+    L.fcol = upload(fcol);
+    L.fval = upload(convert<V, T>(fval));
+    L.funit = upload(funit);
+    L.fw = fw;
+    L.nrec = nrec;
+  }
   struct FusePerm {
     bool on = false;
     const O* x = nullptr;
@@ -589,6 +635,7 @@ struct EngineT final : Engine {
         L.F = upload_csr(h.F);
         L.nnz_e = h.E.nnz();
         L.nnz_f = h.F.nnz();
+        if (L.blob && !no_fuse_fy && L.nnz_f > 0) build_f_records(L, h.F, grp);
       } else {
         std::vector<int32_t> zr(h.d + 1, 0);
         L.F.rp = upload(zr);
@@ -772,6 +819,14 @@ struct EngineT final : Engine {
     a.t2 = nullptr;
     a.fy2 = nullptr;
     a.nrhs = 1;
+    if (streamed(l) && L.frow) {
+      a.frow = L.frow;
+      a.fcol = L.fcol;
+      a.fval = L.fval;
+      a.funit = L.funit;
+      a.fw = L.fw;
+      a.nrec = L.nrec;
+    }
     return a;
   }
   // level l sweeps both right-hand sides in one launch when its blocks fit
@@ -871,9 +926,13 @@ struct EngineT final : Engine {
                + 2.0 * L.d * 4 + L.d * db              // row info (L and U), 1/u_ii
                + 4.0 * L.nstages + 8.0 * (L.nb + 1)    // stage and block tables
                + 2.0 * L.d * xb;                       // right-hand side in, result out
+    // F_l: entries, then row pointers, or with the records the row of each
+    // record and the unit table
+    const double frows = streamed(l) && L.frow ? (double)L.nrec * 4 + (double)(L.nb + 1) * 4
+                                               : (double)(L.d + 1) * 4;
     if (mode == TRI_UP)
-      b += (double)L.nnz_f * (vb + 4) + (double)(L.d + 1) * 4  // F_l
-           + (double)L.nnz_f * xb + (double)L.d * xb;           // y2 gathers, z1 read
+      b += (double)L.nnz_f * (vb + 4) + frows                // F_l
+           + (double)L.nnz_f * xb + (double)L.d * xb;        // y2 gathers, z1 read
     return b + fused;
   }
   double if_bytes(int l, int k, bool gather_fused = false) const {

@@ -657,6 +657,66 @@ __device__ __forceinline__ void load_rhs(const TriArgs<P>& a, const typename P::
   }
 }
 
+// Right-hand side of the up sweep, F_l y2, from the unit's F records (rows
+// without entries are zero): every row's entries are added from zero in
+// stored order, the operations of k_fy, so the sums are the same.  Eight
+// records per thread and four entries of each are in flight at once; the
+// zero fill is ordered before the records' stores by a bare barrier, so the
+// producer's first chunk copy stays in flight.
+template <class P, int NB, int NT>
+__device__ __forceinline__ void rhs_from_f(const TriArgs<P>& a, int b, int nr, int tid,
+                                           typename P::C* x, typename P::C* x2) {
+  using C = typename P::C;
+  using X = typename P::X;
+  for (int i = tid; i < nr; i += NT) {
+    x[i] = zero<C>();
+    if (NB == 2) x2[i] = zero<C>();
+  }
+  __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);
+  __builtin_amdgcn_s_barrier();
+  const X* y2 = a.t + a.d;
+  const X* y2b = NB == 2 ? a.t2 + a.d : nullptr;
+  const int q0 = a.funit[b], q1 = a.funit[b + 1];
+  constexpr int U = 8, J = 4;
+  for (int qb = q0 + tid; qb < q1; qb += NT * U) {
+    int q[U], row[U];
+    C r[U], r2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      q[u] = min(qb + u * NT, q1 - 1);
+      row[u] = a.frow[q[u]];
+      r[u] = zero<C>();
+      r2[u] = zero<C>();
+    }
+    for (int j0 = 0; j0 < a.fw; j0 += J) {
+      int cc[U][J];
+      C fv[U][J];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int jj = 0; jj < J; ++jj) {
+          const int j = min(j0 + jj, a.fw - 1);
+          const int64_t e = (int64_t)j * a.nrec + q[u];
+          cc[u][jj] = a.fcol[e];
+          fv[u][jj] = sel(j0 + jj < a.fw, cvt<C>(a.fval[e]), zero<C>());
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int jj = 0; jj < J; ++jj) {
+          r[u] += fv[u][jj] * cvt<C>(y2[cc[u][jj]]);
+          if (NB == 2) r2[u] += fv[u][jj] * cvt<C>(y2b[cc[u][jj]]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (qb + u * NT < q1) {
+        x[row[u]] = r[u];
+        if (NB == 2) x2[row[u]] = r2[u];
+      }
+  }
+}
+
 // Result of a block from LDS: DOWN stores z1, UP stores z1 - (LU)^{-1} F y2.
 template <class P, int MODE, int NT>
 __device__ __forceinline__ void store_result(const TriArgs<P>& a, typename P::X* tv, int r0,
@@ -733,8 +793,12 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
     if (nbuf == 3 && c0 + 1 < c1)
       copy_chunk<P>(a, desc_get<P>(a, c0 + 1, c1, lane, dc), bufs + a.chunk_cap, lane, full);
   }
-  load_rhs<P, MODE, 2 * kWave>(a, a.t, a.fy, r0, nr, tid, x);
-  if (NB == 2) load_rhs<P, MODE, 2 * kWave>(a, a.t2, a.fy2, r0, nr, tid, x2);
+  if (MODE == TRI_UP && a.frow) {
+    rhs_from_f<P, NB, 2 * kWave>(a, b, nr, tid, x, x2);
+  } else {
+    load_rhs<P, MODE, 2 * kWave>(a, a.t, a.fy, r0, nr, tid, x);
+    if (NB == 2) load_rhs<P, MODE, 2 * kWave>(a, a.t2, a.fy2, r0, nr, tid, x2);
+  }
   __syncthreads();
   for (int c = c0; c < c1; ++c) {
     const int k = c - c0;
@@ -835,10 +899,12 @@ void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot, int ma
   if (mode == TRI_DOWN) {
     launch_stream_mode<P, TRI_DOWN>(a, maxslot, st);
   } else {
-    const dim3 gfy((unsigned)((a.d + 256 * kFyRows - 1) / (256 * kFyRows)));
-    hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t + a.d, a.fy, a.d);
-    if (a.nrhs == 2)
-      hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t2 + a.d, a.fy2, a.d);
+    if (!a.frow) {
+      const dim3 gfy((unsigned)((a.d + 256 * kFyRows - 1) / (256 * kFyRows)));
+      hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t + a.d, a.fy, a.d);
+      if (a.nrhs == 2)
+        hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t2 + a.d, a.fy2, a.d);
+    }
     launch_stream_mode<P, TRI_UP>(a, maxslot, st);
   }
 }

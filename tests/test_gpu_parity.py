@@ -156,7 +156,7 @@ def test_native_setup_solves(torch_dev):
                                  {"GEMSLR_NO_GROUP": "1"}, {"GEMSLR_GROUP_CUS": "4"},
                                  {"GEMSLR_GROUP_CUS": "2", "GEMSLR_NO_STREAM": "1"},
                                  {"GEMSLR_NO_FUSE_SMALL": "1"}, {"GEMSLR_NO_FUSE_PERM": "1"},
-                                 {"GEMSLR_NO_HALF_U": "1"}])
+                                 {"GEMSLR_NO_HALF_U": "1"}, {"GEMSLR_NO_FUSE_FY": "1"}])
 @pytest.mark.parametrize("name", ["convdiff3d_20_p27", "helmholtz3d_16_p8"])
 def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
     """Both block-trisolve kernels (register prefetch; LDS-streamed with small
@@ -164,8 +164,9 @@ def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
     two or three chunk buffers; consecutive diagonal blocks swept by one
     workgroup or one each), both interface paths (one fused launch for
     small levels, three launches) and both ways of applying the permutation
-    (inside the level-0 sweeps, or separate kernels), and U stages swept
-    with one lane per row or two lanes per row, give the oracle's apply."""
+    (inside the level-0 sweeps, or separate kernels), U stages swept with
+    one lane per row or two lanes per row, and F_l y2 formed inside the up
+    sweep or by a launch of its own, give the oracle's apply."""
     torch = torch_dev
     for k, v in env.items():
         monkeypatch.setenv(k, v)
@@ -185,6 +186,31 @@ def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
     print(f"  rel err {err:.3e}", flush=True)
     assert err <= APPLY_TOL_F64
     ctx.close()
+
+
+@pytest.mark.parametrize("name", ["convdiff3d_20_p27", "helmholtz3d_16_p8"])
+def test_fused_fy_bit_equal(torch_dev, name, monkeypatch):
+    """F_l y2 formed in the up sweep's prologue adds every row's entries in
+    the same order as the separate launch: the applies agree bit for bit
+    (the 27-point case has F rows longer than one batch of four entries)."""
+    torch = torch_dev
+    w, kw = _case(name)
+    st = _oracle_setup(w, kw)
+    x = np.random.default_rng(9).standard_normal(w.n)
+    if w.is_complex:
+        x = x + 1j * np.random.default_rng(10).standard_normal(w.n)
+    xd = torch.from_numpy(x).cuda()
+    out = []
+    for env in ({}, {"GEMSLR_NO_FUSE_FY": "1"}):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        ctx = _ctx_explicit(torch, w, st)
+        yd = torch.empty_like(xd)
+        ctx.apply(xd, yd)
+        torch.cuda.synchronize()
+        out.append(yd.clone())
+        ctx.close()
+    assert torch.equal(out[0], out[1])
 
 
 @pytest.mark.parametrize("lfil", [2, 6, 12, 16, 24])
