@@ -196,6 +196,10 @@ struct IfArgs {
   // (perm null: identity), instead of t
   const typename P::O* xin = nullptr;
   const int32_t* perm = nullptr;
+  // small-level kernel: copy W_l and H_l to LDS when they fit in max_lds
+  // bytes of the workgroup's LDS (0: read them from global memory)
+  int32_t stage_w = 1;
+  int32_t max_lds = 65536;
 };
 
 // ------------------------------------------------------------ launchers

@@ -473,6 +473,9 @@ struct EngineT final : Engine {
   bool no_fuse_perm = std::getenv("GEMSLR_NO_FUSE_PERM") != nullptr;
   // GEMSLR_NO_FUSE_FY: F_l y2 of the streamed up sweep in a launch of its own
   bool no_fuse_fy = std::getenv("GEMSLR_NO_FUSE_FY") != nullptr;
+  // GEMSLR_NO_SMALL_LDS: the small-level interface step reads W_l and H_l
+  // from global memory instead of copies in LDS
+  bool no_small_lds = std::getenv("GEMSLR_NO_SMALL_LDS") != nullptr;
   // F_l records (see TriArgs::frow) of the sweep units grp: the rows that
   // hold entries, padded to the longest such row; none if a row is longer
   // than 16 entries (the sweep's prologue would then loop too long)
@@ -971,6 +974,8 @@ struct EngineT final : Engine {
     a.H = L.H;
     a.partial = L.partial;
     a.tprime = L.tprime;
+    a.stage_w = no_small_lds ? 0 : 1;
+    a.max_lds = max_lds;
     const bool gfused = l == 0 && fuse.on && tv == t;
     if (gfused) {
       // the apply's gather of the C_0 rows happens here

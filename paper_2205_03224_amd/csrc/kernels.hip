@@ -1093,33 +1093,73 @@ void launch_interface(const IfArgs<P>& a, hipStream_t st) {
 // k <= 64): z2 = b2 - E_l z1, t = W^H z2, t' = H t and z2 + W t' written
 // back, with z2 kept in LDS; one launch instead of three, for levels where
 // launch latency, not bandwidth, is the cost.  Sums in fixed order.
+// WL: W_l (s x k, at most kSmallW values per thread) and H_l are copied to
+// LDS, their loads issued before the E-product's, so the step costs the
+// E-product's dependent loads and not three more rounds of W and H loads.
 constexpr int kSmallThreads = 1024;
-template <class P>
+constexpr int kSmallW = 16;
+template <class P, bool WL>
 __global__ __launch_bounds__(kSmallThreads) void k_interface_small(IfArgs<P> a) {
   using C = typename P::C;
   using X = typename P::X;
+  using V = typename P::V;
+  using D = typename P::D;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int s = (int)a.s, k = a.k, tid = threadIdx.x;
   C* zs = reinterpret_cast<C*>(smem_raw);  // s
   C* red = zs + s;                          // kSmallThreads
   C* tv = red + kSmallThreads;              // k: W^H z2
   C* tp = tv + 64;                          // k: H W^H z2
+  C* hs = tp + 64;                          // WL: H (k x k)
+  V* ws = reinterpret_cast<V*>(hs + (WL ? k * k : 0));  // WL: W (s x k)
   X* tc = a.t + a.d;
+  const int sk = s * k, kk = k * k;
+  V wr[WL ? kSmallW : 1];
+  C hr[WL ? 4 : 1];
+  D dr[WL ? 4 : 1];
+  if (WL && k > 0) {
+#pragma unroll
+    for (int m = 0; m < kSmallW; ++m) wr[m] = a.W[min(tid + m * kSmallThreads, sk - 1)];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) hr[m] = a.H[min(tid + m * kSmallThreads, kk - 1)];
+  }
+  if (WL && a.last_dinv) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dr[m] = a.last_dinv[min(tid + m * kSmallThreads, s - 1)];
+  }
   for (int i = tid; i < s; i += kSmallThreads) {
     const int rows[1] = {i};
     C ez[1];
-    csr_rows<C, typename P::V, X, 1, 4>(a.E.rp, a.E.ci, a.E.v, a.t, rows, ez);
+    csr_rows<C, V, X, 1, 4>(a.E.rp, a.E.ci, a.E.v, a.t, rows, ez);
     zs[i] = if_b2(a, i) - ez[0];
   }
+  if (WL && k > 0) {
+#pragma unroll
+    for (int m = 0; m < kSmallW; ++m)
+      if (tid + m * kSmallThreads < sk) ws[tid + m * kSmallThreads] = wr[m];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (tid + m * kSmallThreads < kk) hs[tid + m * kSmallThreads] = hr[m];
+  }
   __syncthreads();
+  const V* Wv = WL ? ws : a.W;
+  const C* Hv = WL ? hs : a.H;
   // the C-part's final value: w, or the diagonal last level's solve of it
-  // (as that level's sweep computes it: (w - 0) * 1/u_ii)
-  const auto put = [&](int i, const C& w) {
-    if (a.last_dinv) tc[i] = cvt<X>(cvt<C>(cvt<X>(w)) * cvt<C>(a.last_dinv[i]));
-    else tc[i] = cvt<X>(w);
+  // (as that level's sweep computes it: (w - 0) * 1/u_ii); m: i's index
+  // among the thread's rows
+  const auto put = [&](int i, int m, const C& w) {
+    if (a.last_dinv) {
+      const D dv = WL ? dr[m] : a.last_dinv[i];
+      tc[i] = cvt<X>(cvt<C>(cvt<X>(w)) * cvt<C>(dv));
+    } else {
+      tc[i] = cvt<X>(w);
+    }
   };
+  // s <= 4096: at most four rows per thread
   if (k == 0) {
-    for (int i = tid; i < s; i += kSmallThreads) put(i, zs[i]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (tid + m * kSmallThreads < s) put(tid + m * kSmallThreads, m, zs[tid + m * kSmallThreads]);
     return;
   }
   // T threads per column, thread (c, g) sums rows g, g + T, ...
@@ -1128,7 +1168,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_interface_small(IfArgs<P> a) 
   C acc = zero<C>();
   if (g < T) {
 #pragma unroll 8
-    for (int i = g; i < s; i += T) acc += conj(cvt<C>(a.W[i + (int64_t)c * a.s])) * zs[i];
+    for (int i = g; i < s; i += T) acc += conj(cvt<C>(Wv[i + (int64_t)c * s])) * zs[i];
   }
   red[tid] = acc;
   __syncthreads();
@@ -1140,30 +1180,48 @@ __global__ __launch_bounds__(kSmallThreads) void k_interface_small(IfArgs<P> a) 
   __syncthreads();
   if (tid < k) {
     C t = zero<C>();
-    for (int q = 0; q < k; ++q) t += a.H[tid + (int64_t)q * k] * tv[q];
+    for (int q = 0; q < k; ++q) t += Hv[tid + (int64_t)q * k] * tv[q];
     tp[tid] = t;
   }
   __syncthreads();
-  for (int i = tid; i < s; i += kSmallThreads) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int i = tid + m * kSmallThreads;
+    if (i >= s) break;
     C w = zs[i];
 #pragma unroll 8
-    for (int q = 0; q < k; ++q) w += cvt<C>(a.W[i + (int64_t)q * a.s]) * tp[q];
-    put(i, w);
+    for (int q = 0; q < k; ++q) w += cvt<C>(Wv[i + (int64_t)q * s]) * tp[q];
+    put(i, m, w);
   }
+}
+
+template <class P, bool WL>
+static void launch_small_wl(const IfArgs<P>& a, size_t lds, hipStream_t st) {
+  static size_t attr_set = 65536;
+  if (lds > attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_interface_small<P, WL>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr_set = lds;
+  }
+  hipLaunchKernelGGL((k_interface_small<P, WL>), dim3(1), dim3(kSmallThreads), lds, st, a);
 }
 
 template <class P>
 bool launch_interface_small(const IfArgs<P>& a, hipStream_t st) {
   using C = typename P::C;
+  using V = typename P::V;
   if (a.s <= 0 || a.s > 4096 || a.k > 64) return false;
-  const size_t lds = ((size_t)a.s + kSmallThreads + 128) * sizeof(C);
-  static size_t attr_set = 65536;
-  if (lds > attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_interface_small<P>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    attr_set = lds;
+  const size_t base = ((size_t)a.s + kSmallThreads + 128) * sizeof(C);
+  const size_t wl = base + (size_t)a.k * a.k * sizeof(C) + (size_t)a.s * a.k * sizeof(V) + 16;
+  // (real forms only: complex W values would not stay in registers)
+  if constexpr (sizeof(V) <= 8) {
+    if (a.stage_w && a.k > 0 && a.s * a.k <= (int64_t)kSmallW * kSmallThreads &&
+        a.k * a.k <= 4 * kSmallThreads && wl <= (size_t)a.max_lds) {
+      launch_small_wl<P, true>(a, wl, st);
+      return true;
+    }
   }
-  hipLaunchKernelGGL(k_interface_small<P>, dim3(1), dim3(kSmallThreads), lds, st, a);
+  launch_small_wl<P, false>(a, base, st);
   return true;
 }
 

@@ -156,7 +156,8 @@ def test_native_setup_solves(torch_dev):
                                  {"GEMSLR_NO_GROUP": "1"}, {"GEMSLR_GROUP_CUS": "4"},
                                  {"GEMSLR_GROUP_CUS": "2", "GEMSLR_NO_STREAM": "1"},
                                  {"GEMSLR_NO_FUSE_SMALL": "1"}, {"GEMSLR_NO_FUSE_PERM": "1"},
-                                 {"GEMSLR_NO_HALF_U": "1"}, {"GEMSLR_NO_FUSE_FY": "1"}])
+                                 {"GEMSLR_NO_HALF_U": "1"}, {"GEMSLR_NO_FUSE_FY": "1"},
+                                 {"GEMSLR_NO_SMALL_LDS": "1"}])
 @pytest.mark.parametrize("name", ["convdiff3d_20_p27", "helmholtz3d_16_p8"])
 def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
     """Both block-trisolve kernels (register prefetch; LDS-streamed with small
@@ -166,7 +167,9 @@ def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
     small levels, three launches) and both ways of applying the permutation
     (inside the level-0 sweeps, or separate kernels), U stages swept with
     one lane per row or two lanes per row, and F_l y2 formed inside the up
-    sweep or by a launch of its own, give the oracle's apply."""
+    sweep or by a launch of its own, and the small-level interface step with
+    W_l and H_l copied to LDS or read from global memory, give the oracle's
+    apply."""
     torch = torch_dev
     for k, v in env.items():
         monkeypatch.setenv(k, v)
@@ -189,10 +192,13 @@ def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
 
 
 @pytest.mark.parametrize("name", ["convdiff3d_20_p27", "helmholtz3d_16_p8"])
-def test_fused_fy_bit_equal(torch_dev, name, monkeypatch):
+@pytest.mark.parametrize("knob", ["GEMSLR_NO_FUSE_FY", "GEMSLR_NO_SMALL_LDS"])
+def test_fused_paths_bit_equal(torch_dev, name, knob, monkeypatch):
     """F_l y2 formed in the up sweep's prologue adds every row's entries in
-    the same order as the separate launch: the applies agree bit for bit
-    (the 27-point case has F rows longer than one batch of four entries)."""
+    the same order as the separate launch (the 27-point case has F rows
+    longer than one batch of four entries), and the small-level interface
+    step computes the same sums from LDS copies of W_l and H_l as from
+    global memory: the applies agree bit for bit."""
     torch = torch_dev
     w, kw = _case(name)
     st = _oracle_setup(w, kw)
@@ -201,7 +207,7 @@ def test_fused_fy_bit_equal(torch_dev, name, monkeypatch):
         x = x + 1j * np.random.default_rng(10).standard_normal(w.n)
     xd = torch.from_numpy(x).cuda()
     out = []
-    for env in ({}, {"GEMSLR_NO_FUSE_FY": "1"}):
+    for env in ({}, {knob: "1"}):
         for k, v in env.items():
             monkeypatch.setenv(k, v)
         ctx = _ctx_explicit(torch, w, st)
