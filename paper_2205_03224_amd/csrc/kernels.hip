@@ -622,6 +622,195 @@ __device__ __forceinline__ void chunk_sweep_half(const uint8_t* cb, const ChunkD
   }
 }
 
+// Three-stage pipeline over the stages of one chunk (full rows, or half
+// rows: lanes l and l + 32 share row l).  Per stage s: the gathers of s are
+// issued first and waited for alone (every older LDS access has long
+// completed), then the loads of s+2 (entries, columns, 1/u_ii and the row
+// info of s+3) are issued among the sums of s and the gather offsets of
+// s+1, and the result of s is stored.  So a stage's critical path is one
+// LDS round trip plus its arithmetic, the loads of s+2 travel while s+1
+// runs, and no wait ever needs more than the 15 LDS operations the counter
+// can track.  Scheduling barriers keep that order; LDS executes one
+// wavefront's accesses in order, so the gathers of s+1 see the store of s.
+template <class P, int MS, bool HALF>
+struct PipeRegs {
+  static constexpr int SL = HALF ? MS / 2 : MS;  // slots per lane
+  static constexpr int NW = (SL + 1) / 2;        // 32-bit words of packed columns
+  typename P::C v[SL];
+  uint32_t cw[NW];
+  uint32_t ad[SL];  // gather byte offsets into the block vector
+  typename P::C dv;
+  int row;  // the lane's row, or the block's dummy slot for idle lanes
+  int nr;   // rows of the stage (uniform; 0 past the chunk's last stage)
+};
+template <class P, int MS, bool HALF, int NB>
+struct PipeGath {
+  static constexpr int SL = HALF ? MS / 2 : MS;
+  typename P::C xv[SL];
+  typename P::C xw[NB == 2 ? SL : 1];
+  typename P::C b, bw;
+};
+
+template <class P, int MS, bool HALF, bool ISU>
+__device__ __forceinline__ void st_load(const typename P::V* val, const typename P::D* dinv,
+                                        const uint16_t* col, uint32_t info, int r0, int ql,
+                                        int half, int dummy, PipeRegs<P, MS, HALF>& R) {
+  using C = typename P::C;
+  using RG = PipeRegs<P, MS, HALF>;
+  constexpr int VS = stream_vstride(MS), CS = stream_cstride(MS);
+  constexpr int CO = HALF ? stream_half_coff(MS) : 0;
+  static_assert(CO + RG::SL <= CS, "column row holds both halves");
+  R.nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
+  const bool act = ql < R.nr;
+  R.row = act ? (int)(info & 0xffffu) : dummy;
+  const int q = act ? r0 + ql : r0;
+  const typename P::V* vr = val + q * VS + (HALF ? half * RG::SL : 0);
+  const uint32_t* cr = reinterpret_cast<const uint32_t*>(col + q * CS + (HALF ? half * CO : 0));
+#pragma unroll
+  for (int j = 0; j < RG::SL; ++j) R.v[j] = cvt<C>(vr[j]);
+#pragma unroll
+  for (int j = 0; j < RG::NW; ++j) R.cw[j] = cr[j];
+  if (ISU) R.dv = cvt<C>(dinv[q]);
+}
+
+// load of a value at LDS byte address a
+template <class C>
+__device__ __forceinline__ C lds_ld(uint32_t a) {
+  typedef __attribute__((address_space(3))) const C T;
+  return *(T*)(size_t)a;
+}
+template <>
+__device__ __forceinline__ dcplx lds_ld<dcplx>(uint32_t a) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(3))) const d2 T;
+  const d2 v = *(T*)(size_t)a;
+  return mk(v.x, v.y);
+}
+
+// LDS byte address of a block-vector element (x0: LDS address of x[0])
+template <class P, int MS, bool HALF>
+__device__ __forceinline__ void st_addr(PipeRegs<P, MS, HALF>& R, uint32_t x0) {
+  using C = typename P::C;
+  constexpr int kMul = (int)sizeof(C) / ColScale<C>::value;
+#pragma unroll
+  for (int j = 0; j < PipeRegs<P, MS, HALF>::SL; ++j) {
+    R.ad[j] = x0 + (j % 2 ? R.cw[j / 2] >> 16 : R.cw[j / 2] & 0xffffu) * kMul;
+    asm volatile("" : "+v"(R.ad[j]));  // formed here, not again before the gathers
+  }
+}
+
+template <class P, int MS, bool HALF, int NB>
+__device__ __forceinline__ void st_gather(const PipeRegs<P, MS, HALF>& R, const typename P::C* x,
+                                          PipeGath<P, MS, HALF, NB>& G) {
+  using C = typename P::C;
+  constexpr int kX2 = pair_offset<C>();
+#pragma unroll
+  for (int j = 0; j < PipeRegs<P, MS, HALF>::SL; ++j) {
+    G.xv[j] = lds_ld<C>(R.ad[j]);
+    if (NB == 2) G.xw[j] = lds_ld<C>(R.ad[j] + kX2);
+  }
+  G.b = x[R.row];
+  if (NB == 2)
+    G.bw = *reinterpret_cast<const C*>(reinterpret_cast<const unsigned char*>(x) +
+                                       R.row * sizeof(C) + kX2);
+}
+
+// x[row] = (b - sum_j v_j x[c_j]) (* 1/u_ii), two partial sums (padded
+// entries are zero); half rows: the partner's half sum via permlane32, low
+// half first on both lanes, so both store the same value
+template <class P, int MS, bool HALF, bool ISU, int NB>
+__device__ __forceinline__ void st_finish(const PipeRegs<P, MS, HALF>& R,
+                                          const PipeGath<P, MS, HALF, NB>& G,
+                                          typename P::C* x, bool low) {
+  using C = typename P::C;
+  constexpr int kX2 = pair_offset<C>();
+  constexpr int SL = PipeRegs<P, MS, HALF>::SL;
+  C s0 = zero<C>(), s1 = zero<C>(), w0 = zero<C>(), w1 = zero<C>();
+#pragma unroll
+  for (int j = 0; j < SL; j += 2) {
+    s0 += R.v[j] * G.xv[j];
+    if (j + 1 < SL) s1 += R.v[j + 1] * G.xv[j + 1];
+    if (NB == 2) {
+      w0 += R.v[j] * G.xw[j];
+      if (j + 1 < SL) w1 += R.v[j + 1] * G.xw[j + 1];
+    }
+  }
+  C acc, aw = zero<C>();
+  if (HALF) {
+    const C p = s0 + s1;
+    const C o = swap32(p, low);
+    acc = G.b - (low ? p + o : o + p);
+    if (NB == 2) {
+      const C pw = w0 + w1;
+      const C ow = swap32(pw, low);
+      aw = G.bw - (low ? pw + ow : ow + pw);
+    }
+  } else {
+    acc = G.b - (s0 + s1);
+    if (NB == 2) aw = G.bw - (w0 + w1);
+  }
+  if (ISU) {
+    acc *= R.dv;
+    if (NB == 2) aw *= R.dv;
+  }
+  x[R.row] = acc;
+  if (NB == 2)
+    *reinterpret_cast<C*>(reinterpret_cast<unsigned char*>(x) + R.row * sizeof(C) + kX2) = aw;
+}
+
+template <class P, int MS, bool HALF, bool ISU, int NB>
+__device__ __forceinline__ void chunk_sweep3(const uint8_t* cb, const ChunkDesc& cd, int lane,
+                                             typename P::C* x, int dummy) {
+  using V = typename P::V;
+  using D = typename P::D;
+  const V* val = reinterpret_cast<const V*>(cb);
+  const D* dinv = reinterpret_cast<const D*>(cb + 16 * (int)cd.dinv16);
+  const uint32_t* rinfo = reinterpret_cast<const uint32_t*>(cb + 16 * (int)cd.info16);
+  const uint16_t* col = reinterpret_cast<const uint16_t*>(cb + 16 * (int)cd.col16);
+  const int nst = cd.nst & 0x7fff;
+  if (nst == 0) return;
+  const int nrows = (int)cd.nrows;
+  const int ql = HALF ? (lane & 31) : lane, half = HALF ? lane >> 5 : 0;
+  const bool low = half == 0;
+  typedef __attribute__((address_space(3))) typename P::C lds_c;
+  const uint32_t x0 = (uint32_t)(size_t)(lds_c*)x;
+  PipeRegs<P, MS, HALF> A, B, Cr;
+  PipeGath<P, MS, HALF, NB> G;
+  // prologue: stages 0 and 1 loaded, the row info of stage 2 read
+  st_load<P, MS, HALF, ISU>(val, dinv, col, rinfo[ql], 0, ql, half, dummy, A);
+  int r = A.nr;
+  uint32_t info = rinfo[min(r + ql, nrows)];
+  info = nst > 1 ? info : 0u;
+  st_load<P, MS, HALF, ISU>(val, dinv, col, info, r, ql, half, dummy, B);
+  r += B.nr;
+  info = rinfo[min(r + ql, nrows)];
+  info = nst > 2 ? info : 0u;
+  st_addr<P, MS, HALF>(A, x0);
+  // one stage: cur = s, nxt = s+1, far receives s+2
+  const auto step = [&](PipeRegs<P, MS, HALF>& cur, PipeRegs<P, MS, HALF>& nxt,
+                        PipeRegs<P, MS, HALF>& far, int s) {
+    st_gather<P, MS, HALF, NB>(cur, x, G);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);
+    __builtin_amdgcn_sched_barrier(0);
+    st_load<P, MS, HALF, ISU>(val, dinv, col, info, r, ql, half, dummy, far);
+    r += far.nr;
+    const uint32_t i3 = rinfo[min(r + ql, nrows)];
+    info = s + 3 < nst ? i3 : 0u;
+    st_addr<P, MS, HALF>(nxt, x0);
+    st_finish<P, MS, HALF, ISU, NB>(cur, G, x, low);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  for (int s = 0;; s += 3) {
+    step(A, B, Cr, s);
+    if (s + 1 >= nst) break;
+    step(B, Cr, A, s + 1);
+    if (s + 2 >= nst) break;
+    step(Cr, A, B, s + 2);
+    if (s + 3 >= nst) break;
+  }
+}
+
 // Right-hand side of a block into LDS: DOWN reads b1, UP reads F_l y2.
 // 256 bytes of loads per thread in flight at once (a whole 4096-row float64
 // block in one round trip with 128 threads).
@@ -816,9 +1005,9 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
     } else {
       const ChunkDesc cd = desc_get<P>(a, c, c1, lane, dc);
       uint8_t* cur = bufs + (k % nbuf) * a.chunk_cap;
-      if ((cd.nst & 0x8000) && a.half_u) chunk_sweep_half<P, MS, NB>(cur, cd, lane, x, nr);
-      else if (cd.nst & 0x8000) chunk_sweep<P, MS, true, NB>(cur, cd, lane, x, nr);
-      else chunk_sweep<P, MS, false, NB>(cur, cd, lane, x, nr);
+      if ((cd.nst & 0x8000) && a.half_u) chunk_sweep3<P, MS, true, true, NB>(cur, cd, lane, x, nr);
+      else if (cd.nst & 0x8000) chunk_sweep3<P, MS, false, true, NB>(cur, cd, lane, x, nr);
+      else chunk_sweep3<P, MS, false, false, NB>(cur, cd, lane, x, nr);
       // every read of the buffer done before the producer may refill it
       __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);
     }
