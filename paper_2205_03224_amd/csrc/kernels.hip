@@ -377,159 +377,6 @@ __device__ __forceinline__ void wait_vmcnt(int n) {
 // lgkmcnt(0) alone (vmcnt and expcnt at their maxima)
 #define GS_LGKM0_IMM 0xC07F
 
-// One stage of a chunk in registers: the MS padded entries of each lane's
-// row (zeros past the row's length), their block-vector byte offsets, 1/u_ii
-// and the target row.
-template <class P, int MS>
-struct SweepRegs {
-  typename P::C v[MS];
-  uint32_t c[MS];
-  typename P::C dv;
-  int row;  // the lane's row, or the block's dummy slot for idle lanes
-  int nr;   // rows of the stage (uniform; 0 past the chunk's last stage)
-};
-
-// Fill R from the stage's row info (0 past the last stage) for the stage
-// whose first row in the chunk is r0.  Lane l reads row r0 + l of the chunk,
-// idle lanes row r0 (past the last stage that is the zero row closing the
-// column section), so every column read is a valid block-vector offset and
-// an idle lane's values only reach the dummy slot.  All MS slots of a row
-// are immediate offsets from one address.
-template <class P, int MS, bool ISU>
-__device__ __forceinline__ void sweep_load(const typename P::V* val, const typename P::D* dinv,
-                                           const uint16_t* col, uint32_t info, int r0, int lane,
-                                           int dummy, SweepRegs<P, MS>& R) {
-  using C = typename P::C;
-  constexpr int VS = stream_vstride(MS), CS = stream_cstride(MS);
-  R.nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
-  const bool act = lane < R.nr;
-  R.row = act ? (int)(info & 0xffffu) : dummy;
-  const int q = act ? r0 + lane : r0;
-  const typename P::V* vr = val + q * VS;
-  const uint32_t* cr = reinterpret_cast<const uint32_t*>(col + q * CS);
-#pragma unroll
-  for (int j = 0; j < MS; ++j) R.v[j] = cvt<C>(vr[j]);
-#pragma unroll
-  for (int j = 0; j < MS; j += 2) {
-    const uint32_t w = cr[j / 2];
-    R.c[j] = w & 0xffffu;
-    if (j + 1 < MS) R.c[j + 1] = w >> 16;
-  }
-  if (ISU) R.dv = cvt<C>(dinv[q]);
-}
-
-// x[row] = (x[row] - sum_j v_j x[c_j]) (* 1/u_ii): all gathers first, two
-// partial sums (padded entries are zero); idle lanes write the dummy slot.
-template <class P, int MS, bool ISU, int NB>
-__device__ __forceinline__ void sweep_compute(const SweepRegs<P, MS>& R, typename P::C* x) {
-  using C = typename P::C;
-  constexpr int kMul = (int)sizeof(C) / ColScale<C>::value;
-  constexpr int kX2 = pair_offset<C>();  // second block vector (NB = 2)
-  const unsigned char* xb = reinterpret_cast<const unsigned char*>(x);
-  C xv[MS], xw[MS];
-#pragma unroll
-  for (int j = 0; j < MS; ++j) {
-    xv[j] = *reinterpret_cast<const C*>(xb + R.c[j] * kMul);
-    if (NB == 2) xw[j] = *reinterpret_cast<const C*>(xb + R.c[j] * kMul + kX2);
-  }
-  const C b = x[R.row];
-  C bw = zero<C>();
-  if (NB == 2) bw = *reinterpret_cast<const C*>(xb + R.row * sizeof(C) + kX2);
-  C s0 = zero<C>(), s1 = zero<C>(), w0 = zero<C>(), w1 = zero<C>();
-#pragma unroll
-  for (int j = 0; j < MS; j += 2) {
-    s0 += R.v[j] * xv[j];
-    if (j + 1 < MS) s1 += R.v[j + 1] * xv[j + 1];
-    if (NB == 2) {
-      w0 += R.v[j] * xw[j];
-      if (j + 1 < MS) w1 += R.v[j + 1] * xw[j + 1];
-    }
-  }
-  C acc = b - (s0 + s1);
-  if (ISU) acc *= R.dv;
-  x[R.row] = acc;
-  if (NB == 2) {
-    C aw = bw - (w0 + w1);
-    if (ISU) aw *= R.dv;
-    *reinterpret_cast<C*>(reinterpret_cast<unsigned char*>(x) + R.row * sizeof(C) + kX2) = aw;
-  }
-}
-
-// Sweep the stages of one chunk held in LDS, two stages per trip with two
-// register sets and no register copies.  Straight-line code (no branch
-// around an LDS access), so the compiler's waits are exact: the row info of
-// stage s+1 is read one stage ahead, the entries of stage s+1 are fetched
-// before the gathers of stage s, and a stage waits only for its own gathers.
-// LDS executes one wavefront's accesses in order, so a gather issued after
-// the previous stage's store sees the stored value.
-template <class P, int MS, bool ISU, int NB>
-__device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& cd, int lane,
-                                            typename P::C* x, int dummy) {
-  using V = typename P::V;
-  using D = typename P::D;
-  const V* val = reinterpret_cast<const V*>(cb);
-  const D* dinv = reinterpret_cast<const D*>(cb + 16 * (int)cd.dinv16);
-  const uint32_t* rinfo = reinterpret_cast<const uint32_t*>(cb + 16 * (int)cd.info16);
-  const uint16_t* col = reinterpret_cast<const uint16_t*>(cb + 16 * (int)cd.col16);
-  const int nst = cd.nst & 0x7fff;
-  SweepRegs<P, MS> A, B;
-  sweep_load<P, MS, ISU>(val, dinv, col, rinfo[lane], 0, lane, dummy, A);
-  int r1 = A.nr;
-  uint32_t i1 = rinfo[min(r1 + lane, (int)cd.nrows)];
-  i1 = nst > 1 ? i1 : 0u;
-  for (int s = 0; s < nst; s += 2) {
-    sweep_load<P, MS, ISU>(val, dinv, col, i1, r1, lane, dummy, B);  // stage s+1
-    const int r2 = r1 + B.nr;
-    uint32_t i2 = rinfo[min(r2 + lane, (int)cd.nrows)];
-    i2 = s + 2 < nst ? i2 : 0u;
-    sweep_compute<P, MS, ISU, NB>(A, x);                             // stage s
-    sweep_load<P, MS, ISU>(val, dinv, col, i2, r2, lane, dummy, A);  // stage s+2
-    const int r3 = r2 + A.nr;
-    uint32_t i3 = rinfo[min(r3 + lane, (int)cd.nrows)];
-    i3 = s + 3 < nst ? i3 : 0u;
-    sweep_compute<P, MS, ISU, NB>(B, x);                             // stage s+1
-    r1 = r3;
-    i1 = i3;
-  }
-}
-
-// Half-row U stages (stages of at most 32 rows): lanes l and l + 32 share
-// row l of the stage, each with MS/2 of its slots (the column row holds the
-// second half from 16-bit position stream_half_coff(MS)).  Each lane forms
-// the partial sum of its half; v_permlane32_swap hands it to the partner,
-// and both lanes add the two halves in the same order (low half first), so
-// they compute identical values and store the same result.  Half the
-// entry, column and gather LDS operations of a full-row stage.
-template <class P, int MS>
-struct HalfRegs {
-  typename P::C v[MS / 2];
-  uint32_t c[(MS / 2 + 1) / 2];
-  typename P::C dv;
-  int row;
-  int nr;
-};
-
-template <class P, int MS>
-__device__ __forceinline__ void half_load(const typename P::V* val, const typename P::D* dinv,
-                                          const uint16_t* col, uint32_t info, int r0, int ql,
-                                          int half, int dummy, HalfRegs<P, MS>& R) {
-  using C = typename P::C;
-  constexpr int VS = stream_vstride(MS), CS = stream_cstride(MS), HS = MS / 2;
-  constexpr int CO = stream_half_coff(MS);
-  static_assert(CO + HS <= CS, "column row holds both halves");
-  R.nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
-  const bool act = ql < R.nr;
-  R.row = act ? (int)(info & 0xffffu) : dummy;
-  const int q = act ? r0 + ql : r0;
-  const typename P::V* vr = val + q * VS + half * HS;
-  const uint32_t* cr = reinterpret_cast<const uint32_t*>(col + q * CS + half * CO);
-#pragma unroll
-  for (int j = 0; j < HS; ++j) R.v[j] = cvt<C>(vr[j]);
-#pragma unroll
-  for (int j = 0; j < (HS + 1) / 2; ++j) R.c[j] = cr[j];
-  R.dv = cvt<C>(dinv[q]);
-}
-
 // the partner lane's (lane +- 32) value of x
 __device__ __forceinline__ double swap32(double x, bool low) {
   const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
@@ -544,82 +391,6 @@ __device__ __forceinline__ float swap32(float x, bool low) {
 }
 __device__ __forceinline__ dcplx swap32(dcplx x, bool low) {
   return mk(swap32(x.x, low), swap32(x.y, low));
-}
-
-template <class P, int MS, int NB>
-__device__ __forceinline__ void half_compute(const HalfRegs<P, MS>& R, typename P::C* x,
-                                             bool low) {
-  using C = typename P::C;
-  constexpr int kMul = (int)sizeof(C) / ColScale<C>::value;
-  constexpr int kX2 = pair_offset<C>();
-  constexpr int HS = MS / 2;
-  const unsigned char* xb = reinterpret_cast<const unsigned char*>(x);
-  C xv[HS], xw[HS];
-#pragma unroll
-  for (int j = 0; j < HS; ++j) {
-    const uint32_t cj = j % 2 ? R.c[j / 2] >> 16 : R.c[j / 2] & 0xffffu;
-    xv[j] = *reinterpret_cast<const C*>(xb + cj * kMul);
-    if (NB == 2) xw[j] = *reinterpret_cast<const C*>(xb + cj * kMul + kX2);
-  }
-  const C b = x[R.row];
-  C bw = zero<C>();
-  if (NB == 2) bw = *reinterpret_cast<const C*>(xb + R.row * sizeof(C) + kX2);
-  C s0 = zero<C>(), s1 = zero<C>(), w0 = zero<C>(), w1 = zero<C>();
-#pragma unroll
-  for (int j = 0; j < HS; j += 2) {
-    s0 += R.v[j] * xv[j];
-    if (j + 1 < HS) s1 += R.v[j + 1] * xv[j + 1];
-    if (NB == 2) {
-      w0 += R.v[j] * xw[j];
-      if (j + 1 < HS) w1 += R.v[j + 1] * xw[j + 1];
-    }
-  }
-  const C p = s0 + s1;
-  const C o = swap32(p, low);
-  C acc = b - (low ? p + o : o + p);
-  acc *= R.dv;
-  x[R.row] = acc;
-  if (NB == 2) {
-    const C pw = w0 + w1;
-    const C ow = swap32(pw, low);
-    C aw = bw - (low ? pw + ow : ow + pw);
-    aw *= R.dv;
-    *reinterpret_cast<C*>(reinterpret_cast<unsigned char*>(x) + R.row * sizeof(C) + kX2) = aw;
-  }
-}
-
-// chunk_sweep for a half-row U chunk (same two-register-set pipeline)
-template <class P, int MS, int NB>
-__device__ __forceinline__ void chunk_sweep_half(const uint8_t* cb, const ChunkDesc& cd,
-                                                 int lane, typename P::C* x, int dummy) {
-  using V = typename P::V;
-  using D = typename P::D;
-  const V* val = reinterpret_cast<const V*>(cb);
-  const D* dinv = reinterpret_cast<const D*>(cb + 16 * (int)cd.dinv16);
-  const uint32_t* rinfo = reinterpret_cast<const uint32_t*>(cb + 16 * (int)cd.info16);
-  const uint16_t* col = reinterpret_cast<const uint16_t*>(cb + 16 * (int)cd.col16);
-  const int nst = cd.nst & 0x7fff;
-  const int ql = lane & 31, half = lane >> 5;
-  const bool low = half == 0;
-  HalfRegs<P, MS> A, B;
-  half_load<P, MS>(val, dinv, col, rinfo[ql], 0, ql, half, dummy, A);
-  int r1 = A.nr;
-  uint32_t i1 = rinfo[min(r1 + ql, (int)cd.nrows)];
-  i1 = nst > 1 ? i1 : 0u;
-  for (int s = 0; s < nst; s += 2) {
-    half_load<P, MS>(val, dinv, col, i1, r1, ql, half, dummy, B);  // stage s+1
-    const int r2 = r1 + B.nr;
-    uint32_t i2 = rinfo[min(r2 + ql, (int)cd.nrows)];
-    i2 = s + 2 < nst ? i2 : 0u;
-    half_compute<P, MS, NB>(A, x, low);                            // stage s
-    half_load<P, MS>(val, dinv, col, i2, r2, ql, half, dummy, A);  // stage s+2
-    const int r3 = r2 + A.nr;
-    uint32_t i3 = rinfo[min(r3 + ql, (int)cd.nrows)];
-    i3 = s + 3 < nst ? i3 : 0u;
-    half_compute<P, MS, NB>(B, x, low);                            // stage s+1
-    r1 = r3;
-    i1 = i3;
-  }
 }
 
 // Three-stage pipeline over the stages of one chunk (full rows, or half
@@ -651,28 +422,6 @@ struct PipeGath {
   typename P::C b, bw;
 };
 
-template <class P, int MS, bool HALF, bool ISU>
-__device__ __forceinline__ void st_load(const typename P::V* val, const typename P::D* dinv,
-                                        const uint16_t* col, uint32_t info, int r0, int ql,
-                                        int half, int dummy, PipeRegs<P, MS, HALF>& R) {
-  using C = typename P::C;
-  using RG = PipeRegs<P, MS, HALF>;
-  constexpr int VS = stream_vstride(MS), CS = stream_cstride(MS);
-  constexpr int CO = HALF ? stream_half_coff(MS) : 0;
-  static_assert(CO + RG::SL <= CS, "column row holds both halves");
-  R.nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
-  const bool act = ql < R.nr;
-  R.row = act ? (int)(info & 0xffffu) : dummy;
-  const int q = act ? r0 + ql : r0;
-  const typename P::V* vr = val + q * VS + (HALF ? half * RG::SL : 0);
-  const uint32_t* cr = reinterpret_cast<const uint32_t*>(col + q * CS + (HALF ? half * CO : 0));
-#pragma unroll
-  for (int j = 0; j < RG::SL; ++j) R.v[j] = cvt<C>(vr[j]);
-#pragma unroll
-  for (int j = 0; j < RG::NW; ++j) R.cw[j] = cr[j];
-  if (ISU) R.dv = cvt<C>(dinv[q]);
-}
-
 // load of a value at LDS byte address a
 template <class C>
 __device__ __forceinline__ C lds_ld(uint32_t a) {
@@ -687,6 +436,12 @@ __device__ __forceinline__ dcplx lds_ld<dcplx>(uint32_t a) {
   return mk(v.x, v.y);
 }
 
+template <>
+__device__ __forceinline__ bf16 lds_ld<bf16>(uint32_t a) {
+  typedef __attribute__((address_space(3))) const uint16_t T;
+  return bf16{*(T*)(size_t)a};
+}
+
 // LDS byte address of a block-vector element (x0: LDS address of x[0])
 template <class P, int MS, bool HALF>
 __device__ __forceinline__ void st_addr(PipeRegs<P, MS, HALF>& R, uint32_t x0) {
@@ -697,6 +452,33 @@ __device__ __forceinline__ void st_addr(PipeRegs<P, MS, HALF>& R, uint32_t x0) {
     R.ad[j] = x0 + (j % 2 ? R.cw[j / 2] >> 16 : R.cw[j / 2] & 0xffffu) * kMul;
     asm volatile("" : "+v"(R.ad[j]));  // formed here, not again before the gathers
   }
+}
+
+// loads of one stage whose row info is `info` and first chunk row r0; the
+// chunk's sections are given by LDS byte addresses (32-bit arithmetic)
+template <class P, int MS, bool HALF, bool ISU>
+__device__ __forceinline__ void st_load(uint32_t vbase, uint32_t dbase, uint32_t cbase,
+                                        uint32_t info, int r0, int ql, int half, int dummy,
+                                        PipeRegs<P, MS, HALF>& R) {
+  using C = typename P::C;
+  using V = typename P::V;
+  using D = typename P::D;
+  using RG = PipeRegs<P, MS, HALF>;
+  constexpr int VS = stream_vstride(MS), CS = stream_cstride(MS);
+  constexpr int CO = HALF ? stream_half_coff(MS) : 0;
+  static_assert(CO + RG::SL <= CS, "column row holds both halves");
+  R.nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
+  const bool act = ql < R.nr;
+  R.row = act ? (int)(info & 0xffffu) : dummy;
+  const uint32_t q = (uint32_t)(act ? r0 + ql : r0);
+  const uint32_t va = vbase + __umul24(q, (uint32_t)(VS * sizeof(V))) +
+                      (HALF ? (uint32_t)(half * RG::SL * sizeof(V)) : 0u);
+  const uint32_t ca = cbase + __umul24(q, (uint32_t)(CS * 2)) + (HALF ? (uint32_t)(half * CO * 2) : 0u);
+#pragma unroll
+  for (int j = 0; j < RG::SL; ++j) R.v[j] = cvt<C>(lds_ld<V>(va + j * (uint32_t)sizeof(V)));
+#pragma unroll
+  for (int j = 0; j < RG::NW; ++j) R.cw[j] = lds_ld<uint32_t>(ca + 4u * j);
+  if (ISU) R.dv = cvt<C>(lds_ld<D>(dbase + __umul24(q, (uint32_t)sizeof(D))));
 }
 
 template <class P, int MS, bool HALF, int NB>
@@ -761,12 +543,12 @@ __device__ __forceinline__ void st_finish(const PipeRegs<P, MS, HALF>& R,
 template <class P, int MS, bool HALF, bool ISU, int NB>
 __device__ __forceinline__ void chunk_sweep3(const uint8_t* cb, const ChunkDesc& cd, int lane,
                                              typename P::C* x, int dummy) {
-  using V = typename P::V;
-  using D = typename P::D;
-  const V* val = reinterpret_cast<const V*>(cb);
-  const D* dinv = reinterpret_cast<const D*>(cb + 16 * (int)cd.dinv16);
-  const uint32_t* rinfo = reinterpret_cast<const uint32_t*>(cb + 16 * (int)cd.info16);
-  const uint16_t* col = reinterpret_cast<const uint16_t*>(cb + 16 * (int)cd.col16);
+  typedef __attribute__((address_space(3))) const uint8_t lds_u8;
+  const uint32_t vbase = (uint32_t)(size_t)(lds_u8*)cb;
+  const uint32_t dbase = vbase + 16u * cd.dinv16;
+  const uint32_t ibase = vbase + 16u * cd.info16;
+  const uint32_t cbase = vbase + 16u * cd.col16;
+  const auto rinfo = [&](int i) { return lds_ld<uint32_t>(ibase + 4u * (uint32_t)i); };
   const int nst = cd.nst & 0x7fff;
   if (nst == 0) return;
   const int nrows = (int)cd.nrows;
@@ -777,13 +559,13 @@ __device__ __forceinline__ void chunk_sweep3(const uint8_t* cb, const ChunkDesc&
   PipeRegs<P, MS, HALF> A, B, Cr;
   PipeGath<P, MS, HALF, NB> G;
   // prologue: stages 0 and 1 loaded, the row info of stage 2 read
-  st_load<P, MS, HALF, ISU>(val, dinv, col, rinfo[ql], 0, ql, half, dummy, A);
+  st_load<P, MS, HALF, ISU>(vbase, dbase, cbase, rinfo(ql), 0, ql, half, dummy, A);
   int r = A.nr;
-  uint32_t info = rinfo[min(r + ql, nrows)];
+  uint32_t info = rinfo(min(r + ql, nrows));
   info = nst > 1 ? info : 0u;
-  st_load<P, MS, HALF, ISU>(val, dinv, col, info, r, ql, half, dummy, B);
+  st_load<P, MS, HALF, ISU>(vbase, dbase, cbase, info, r, ql, half, dummy, B);
   r += B.nr;
-  info = rinfo[min(r + ql, nrows)];
+  info = rinfo(min(r + ql, nrows));
   info = nst > 2 ? info : 0u;
   st_addr<P, MS, HALF>(A, x0);
   // one stage: cur = s, nxt = s+1, far receives s+2
@@ -793,9 +575,9 @@ __device__ __forceinline__ void chunk_sweep3(const uint8_t* cb, const ChunkDesc&
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);
     __builtin_amdgcn_sched_barrier(0);
-    st_load<P, MS, HALF, ISU>(val, dinv, col, info, r, ql, half, dummy, far);
+    st_load<P, MS, HALF, ISU>(vbase, dbase, cbase, info, r, ql, half, dummy, far);
     r += far.nr;
-    const uint32_t i3 = rinfo[min(r + ql, nrows)];
+    const uint32_t i3 = rinfo(min(r + ql, nrows));
     info = s + 3 < nst ? i3 : 0u;
     st_addr<P, MS, HALF>(nxt, x0);
     st_finish<P, MS, HALF, ISU, NB>(cur, G, x, low);
