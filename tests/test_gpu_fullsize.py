@@ -11,7 +11,9 @@ level (computed in worker processes, see fullsize_helpers), and seeded
 synthetic low-rank terms of the ranks the benchmark's setup yields (33, 33,
 32), since the oracle's Krylov-Schur iteration at this size would exceed a
 test's time.  The apply is then compared element by element with the
-oracle's apply of the same data.
+oracle's apply of the same data, in float64 and in the float32 / bfloat16
+storage forms; the complex128 path is checked the same way on the 128^3
+Helmholtz operator.
 """
 import numpy as np
 import pytest
@@ -25,6 +27,7 @@ from tests.fullsize_helpers import oracle_setup_parallel
 pytestmark = pytest.mark.gpu
 
 APPLY_TOL_F64 = 1e-11
+MIXED_TOL = {"f32": 2e-5, "bf16": 3e-2}  # as in test_gpu_mixed.py
 RANKS = (33, 33, 32)
 
 
@@ -97,4 +100,47 @@ def test_fullsize_apply_matches_oracle(torch_dev, full):
     err1 = relerr(yd[1].cpu().numpy(), og.apply(st, X[1]))
     print(f"  second vector rel err vs oracle {err1:.3e}", flush=True)
     assert err1 <= APPLY_TOL_F64
+    # the float32 and bfloat16 storage forms of the same preconditioner
+    for prec, tol in (("f32", MIXED_TOL["f32"]), ("bf16", MIXED_TOL["bf16"])):
+        ctx.set_precision(prec)
+        ctx.apply(xd[0], yd[0])
+        torch.cuda.synchronize()
+        e = relerr(yd[0].cpu().numpy(), ref)
+        print(f"  {prec} storage: rel err vs oracle {e:.3e}", flush=True)
+        assert e <= tol
+    ctx.close()
+
+
+def test_fullsize_helmholtz_complex_apply_matches_oracle(torch_dev):
+    """The complex128 path at full size: the 128^3 Helmholtz operator
+    (ILUT(1e-4, 10)), the library's own setup for its structure and ranks,
+    then the oracle's factors with synthetic low-rank terms of those ranks
+    handed to the device and the apply compared with the oracle's."""
+    torch = torch_dev
+    from paper_2205_03224_amd import gemslr
+    w = wl.helmholtz3d_128()
+    part = opart.wirebasket(w.dims, w.nparts, w.levels, w.rowptr, w.col)
+    lib = gemslr.Context(0)
+    lib.setup(w.rowptr, w.col, w.val, w.levels, w.nparts, w.rank, w.drop_tol, lfil=w.lfil,
+              grid_dims=w.dims, fgmres_restart=w.restart)
+    assert np.array_equal(lib.perm(), np.asarray(part.perm))
+    sizes = [lib.level_size(l) for l in range(len(part.blocks))]
+    lib.close()
+    ranks = tuple(int(z[7]) for z in sizes)
+    print(f"[fullsize] helmholtz ranks {ranks}; oracle ILU of every level", flush=True)
+    st = oracle_setup_parallel(w.rowptr, w.col, w.val, part, ranks, tau=w.drop_tol, lfil=w.lfil,
+                               seed=5)
+    for lv, z in zip(st.levels, sizes):
+        assert (z[0], z[1], z[3], z[4]) == (lv.d, lv.s, lv.Lf.nnz, lv.Uf.nnz)
+    ctx = gemslr.Context(0)
+    ctx.setup_explicit(w.rowptr, w.col, w.val, st.perm, oracle_levels(st))
+    rs = np.random.default_rng(12)
+    x = rs.standard_normal(w.n) + 1j * rs.standard_normal(w.n)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    ctx.apply(xd, yd)
+    torch.cuda.synchronize()
+    err = relerr(yd.cpu().numpy(), og.apply(st, x))
+    print(f"  rel err vs oracle {err:.3e}", flush=True)
+    assert err <= APPLY_TOL_F64
     ctx.close()
