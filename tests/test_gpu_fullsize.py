@@ -54,7 +54,8 @@ def full(torch_dev):
 def test_fullsize_library_setup_matches_oracle_structure(torch_dev, full):
     """The benchmark's own setup call partitions exactly as the oracle does
     and factors to the oracle's fill: same permutation, and per level the
-    same d, s, number of blocks and L/U/E/F entry counts."""
+    same d, s, number of blocks and L/U/E/F entry counts; the FGMRES solve
+    with that preconditioner meets the requested true residual."""
     from paper_2205_03224_amd import gemslr
     w, st = full
     ctx = gemslr.Context(0)
@@ -67,6 +68,19 @@ def test_fullsize_library_setup_matches_oracle_structure(torch_dev, full):
         assert (d, s, nb) == (lv.d, lv.s, len(lv.blocks) - 1)
         assert (nl, nu) == (lv.Lf.nnz, lv.Uf.nnz)
         assert (ne, nf) == (lv.E.nnz, lv.F.nnz)
+    # and the preconditioned FGMRES solve it serves reaches its tolerance in
+    # the true residual, computed here on the host from A
+    torch = torch_dev
+    import scipy.sparse as sp
+    bd = torch.from_numpy(w.b).cuda()
+    xd = torch.zeros_like(bd)
+    res = ctx.solve(bd, xd, 1e-8)
+    x = xd.cpu().numpy()
+    A = sp.csr_matrix((w.val, w.col, w.rowptr), shape=(w.n, w.n))
+    rel = np.linalg.norm(w.b - A @ x) / np.linalg.norm(w.b)
+    print(f"  FGMRES: {res['its']} its, true relative residual {rel:.3e}", flush=True)
+    assert res["converged"]
+    assert rel <= 1.5e-8
     ctx.close()
 
 
