@@ -152,7 +152,7 @@ def main():
                          "copy kernel of known traffic for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        log("bench.py measures one GPU: this build holds all subdomains on a single "
+        log("bench.py measures one GPU: the library holds all subdomains on a single "
             "MI355X and has no multi-GPU path; run it with --gpus 1.")
         sys.exit(2)
 
