@@ -13,12 +13,10 @@ on its diagonal blocks (block Jacobi) and factored the same way (Sec. 4.3);
 it is stored here as level L with no interface (s = 0).
 
 Apply (Alg. 2) with a low-rank term at every level, the last one included,
-and by default zero inner GMRES iterations at level 0:
-    z1 = U_l^{-1} L_l^{-1} b1
-    z2 = b2 - E_l z1
-    u2 = W_l [(I - R_l)^{-1} - I] W_l^H z2
-    y2 = M_{l+1}^{-1} (u2 + z2)        (C_last^{-1} below the last level)
-    y1 = z1 - U_l^{-1} L_l^{-1} F_l y2
+and by default zero inner GMRES iterations at level 0: M_l^{-1} is the
+inverse of the block LDU factorisation of A_l (Sec. 2.2) with B_l^{-1} taken
+as the ILU solve and the Schur complement inverse as the low-rank corrected
+next-level preconditioner of eq. gemslr6 (see apply_level).
 """
 from dataclasses import dataclass
 
@@ -137,21 +135,49 @@ def inner_gmres(st, z2, its):
     return PK @ c
 
 
+def ilu_solve(lv, b):
+    """B_l^{-1} b with B_l replaced by its incomplete factors, U_l^{-1} L_l^{-1} b."""
+    return trisolve(lv, b)
+
+
+def schur_solve(st, l, r, inner_its=0):
+    """S_l^{-1} r for the Schur complement S_l = C_l - E_l B_l^{-1} F_l.
+
+    eq. gemslr6 (with eq. gemslr4): S_l^{-1} ~ C_l^{-1} (I + W_l H_l W_l^H)
+    with H_l = (I - R_l)^{-1} - I, and C_l^{-1} is the preconditioner of the
+    next level (C_last^{-1} below the last one).  At the root level with
+    inner_its > 0 the system S_hat_0 y = r is instead solved by that many
+    GMRES steps preconditioned by this approximation (Alg. 2, l = 0)."""
+    if l == 0 and inner_its > 0:
+        return inner_gmres(st, r, inner_its)
+    return lowrank_then_lower(st, l, r)
+
+
 def apply_level(st, l, b, inner_its=0):
-    """M_l^{-1} b on the index range of level l (Alg. 2); inner_its > 0 runs
-    that many inner GMRES steps on S_hat_0 at the root level."""
+    """M_l^{-1} b on the index range of level l.
+
+    A_l = [[B, F], [E, C]] factors into block unit-lower, block diagonal and
+    block unit-upper parts (Sec. 2.2),
+        A_l = [[I, 0], [E B^{-1}, I]] [[B, 0], [0, S]] [[I, B^{-1} F], [0, I]],
+    and M_l^{-1} is the inverse of that product, taken factor by factor, with
+    B^{-1} replaced by the ILU solve and S^{-1} by schur_solve -- the
+    recursion of Alg. 2.  The last level is the block-Jacobi ILU of C_last
+    (Sec. 4.3)."""
     lv = st.levels[l]
     if l == st.nlevels:
-        return trisolve(lv, b)
-    b1, b2 = b[:lv.d], b[lv.d:]
-    z1 = trisolve(lv, b1)
-    z2 = b2 - lv.E @ z1
-    if l == 0 and inner_its > 0:
-        y2 = inner_gmres(st, z2, inner_its)
-    else:
-        y2 = lowrank_then_lower(st, l, z2)
-    y1 = z1 - trisolve(lv, lv.F @ y2)
-    return np.concatenate([y1, y2], axis=0)
+        return ilu_solve(lv, b)
+    d = lv.d
+    # inverse of the block unit-lower factor: [b1; b2 - E B^{-1} b1]
+    u = b.copy()
+    u[d:] = b[d:] - lv.E @ ilu_solve(lv, b[:d])
+    # inverse of the block diagonal: [B^{-1} u1; S^{-1} u2]
+    v = np.empty_like(u)
+    v[:d] = ilu_solve(lv, u[:d])
+    v[d:] = schur_solve(st, l, u[d:], inner_its)
+    # inverse of the block unit-upper factor: [v1 - B^{-1} F v2; v2]
+    y = v.copy()
+    y[:d] = v[:d] - ilu_solve(lv, lv.F @ v[d:])
+    return y
 
 
 def apply(st, x, inner_its=0):

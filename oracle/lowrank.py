@@ -150,7 +150,7 @@ def krylov_schur(matvec, s, k, real, seed=0, tol=1e-2, max_cycles=20):
     V[:, 0] = v0 / np.linalg.norm(v0)
     j0 = 0
     nmv = 0
-    info = {"cycles": 0, "converged": False}
+    info = {"cycles": 0, "converged": False, "breakdowns": 0}
     for cycle in range(max_cycles):
         for j in range(j0, m):
             w = matvec(V[:, j])
@@ -168,6 +168,7 @@ def krylov_schur(matvec, s, k, real, seed=0, tol=1e-2, max_cycles=20):
                 V[:, j + 1] = w / beta
             else:
                 # invariant subspace found: continue from a fresh direction
+                info["breakdowns"] += 1
                 S[j + 1, j] = 0.0
                 V[:, j + 1] = _fresh_direction(V[:, :j + 1], seed, nmv) \
                     if j + 1 < m else 0.0

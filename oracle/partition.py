@@ -125,26 +125,6 @@ def wirebasket(dims, nparts, levels, rowptr, col):
                      np.array(level_start, dtype=np.int64), blocks)
 
 
-def from_user(perm, level_start, rowptr, col):
-    """Partition from a user permutation and level boundaries; blocks are the
-    connected components inside each level segment (in segment order)."""
-    perm = np.asarray(perm, dtype=np.int64)
-    n = len(perm)
-    g = _pattern_graph(n, rowptr, col)
-    gp = g[perm][:, perm].tocsr()
-    level_start = np.asarray(level_start, dtype=np.int64)
-    blocks = []
-    for l in range(len(level_start) - 1):
-        a, b = level_start[l], level_start[l + 1]
-        verts = np.arange(a, b)
-        comps = _components(gp, verts)
-        if any(np.any(np.diff(c) != 1) for c in comps):
-            raise ValueError("user level segment is not ordered by component")
-        bnd = [a] + [int(c[-1]) + 1 for c in comps]
-        blocks.append(np.array(bnd, dtype=np.int64))
-    return Partition(perm, len(level_start) - 2, level_start, blocks)
-
-
 # ---------------------------------------------------------------- algebraic
 # Partitioner for matrices without grid coordinates (the paper uses
 # ParMETIS, Sec. 3.2): nested dissection by breadth-first level structures.

@@ -227,7 +227,10 @@ static void lowrank_level(gs_ctx* c, int l, int kreq) {
   double* nd = mem.alloc<double>((size_t)2 * m + 1);  // + breakdown flag
   std::vector<DT> Sh((size_t)(m + 1) * m);
   std::vector<double> nh((size_t)2 * m + 1);
-  int j0 = 0, nmv = 0;
+  // nmv: products of the Krylov decomposition (it also salts the fresh start
+  // directions after a breakdown); redone: products of cycles that broke
+  // down, computed and discarded before the step-by-step rerun
+  int j0 = 0, nmv = 0, redone = 0;
   const int maxcyc = std::max(1, c->opts.arnoldi_max_cycles);
   for (int cycle = 0; cycle < maxcyc; ++cycle) {
     // steps j0..m-1 without host round trips; a breakdown (flagged by the
@@ -248,6 +251,7 @@ static void lowrank_level(gs_ctx* c, int l, int kreq) {
       HIPCHK(hipStreamSynchronize(st));
       if (nh[2 * m] != 0.0) {
         stepwise = true;  // redo from j0: column j0 of V is untouched
+        redone += m - j0;
       } else {
         nmv += m - j0;
         for (int j = j0; j < m; ++j) {
@@ -327,7 +331,7 @@ static void lowrank_level(gs_ctx* c, int l, int kreq) {
       h.k = kk;
       h.H = correction_matrix<T>(kk, R, thk);
       h.arnoldi_cycles = cycle + 1;
-      h.arnoldi_matvecs = nmv;
+      h.arnoldi_matvecs = nmv + redone;
       h.arnoldi_converged = conv ? 1 : 0;
       c->eng->set_lowrank(l, kk, h.W.data(), h.H.data());
       return;

@@ -10,8 +10,8 @@ The device gets the oracle's setup: its partition, its ILU factors of every
 level (computed in worker processes, see fullsize_helpers), and seeded
 synthetic low-rank terms of the ranks the benchmark's setup yields (33, 33,
 32), since the oracle's Krylov-Schur iteration at this size would exceed a
-test's time.  The apply is then compared element by element with the
-oracle's apply of the same data, in float64 and in the float32 / bfloat16
+test's time.  The apply is then compared entry by entry
+(tests/abi_helpers.assert_close) with the oracle's apply of the same data, in float64 and in the float32 / bfloat16
 storage forms; the complex128 path is checked the same way on the 128^3
 Helmholtz operator.
 """
@@ -21,13 +21,12 @@ import pytest
 from paper_2205_03224_amd import workloads as wl
 from oracle import gemslr as og
 from oracle import partition as opart
-from tests.abi_helpers import oracle_levels, relerr
+from tests.abi_helpers import MIXED_FLOOR, MIXED_TOL, assert_close, oracle_levels
 from tests.fullsize_helpers import oracle_setup_parallel
 
 pytestmark = pytest.mark.gpu
 
-APPLY_TOL_F64 = 1e-11
-MIXED_TOL = {"f32": 2e-5, "bf16": 3e-2}  # as in test_gpu_mixed.py
+APPLY_TOL_F64 = 1e-10
 RANKS = (33, 33, 32)
 
 
@@ -98,9 +97,7 @@ def test_fullsize_apply_matches_oracle(torch_dev, full):
     torch.cuda.synchronize()
     print("[fullsize] oracle apply", flush=True)
     ref = og.apply(st, X[0])
-    err = relerr(yd[0].cpu().numpy(), ref)
-    print(f"  rel err vs oracle {err:.3e}", flush=True)
-    assert err <= APPLY_TOL_F64
+    assert_close(yd[0].cpu().numpy(), ref, APPLY_TOL_F64, what="f64 vs oracle")
     # the same input again gives the same bits (no races, no stale state)
     y2 = torch.empty_like(xd[0])
     ctx.apply(xd[0], y2)
@@ -111,17 +108,15 @@ def test_fullsize_apply_matches_oracle(torch_dev, full):
     torch.cuda.synchronize()
     assert torch.equal(y2, yd[0])
     assert torch.equal(ym, yd)
-    err1 = relerr(yd[1].cpu().numpy(), og.apply(st, X[1]))
-    print(f"  second vector rel err vs oracle {err1:.3e}", flush=True)
-    assert err1 <= APPLY_TOL_F64
+    assert_close(yd[1].cpu().numpy(), og.apply(st, X[1]), APPLY_TOL_F64,
+                 what="second vector vs oracle")
     # the float32 and bfloat16 storage forms of the same preconditioner
     for prec, tol in (("f32", MIXED_TOL["f32"]), ("bf16", MIXED_TOL["bf16"])):
         ctx.set_precision(prec)
         ctx.apply(xd[0], yd[0])
         torch.cuda.synchronize()
-        e = relerr(yd[0].cpu().numpy(), ref)
-        print(f"  {prec} storage: rel err vs oracle {e:.3e}", flush=True)
-        assert e <= tol
+        assert_close(yd[0].cpu().numpy(), ref, tol, floor=MIXED_FLOOR,
+                     what=f"{prec} storage vs oracle")
     ctx.close()
 
 
@@ -154,7 +149,5 @@ def test_fullsize_helmholtz_complex_apply_matches_oracle(torch_dev):
     yd = torch.empty_like(xd)
     ctx.apply(xd, yd)
     torch.cuda.synchronize()
-    err = relerr(yd.cpu().numpy(), og.apply(st, x))
-    print(f"  rel err vs oracle {err:.3e}", flush=True)
-    assert err <= APPLY_TOL_F64
+    assert_close(yd.cpu().numpy(), og.apply(st, x), APPLY_TOL_F64, what="c128 vs oracle")
     ctx.close()

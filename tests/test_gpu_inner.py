@@ -4,19 +4,20 @@ with m inner steps on S_hat_0 against the oracle's, on the same setup data.
 The oracle takes the GMRES minimiser from its definition (least squares over
 an orthonormal Krylov basis), the device path from Arnoldi plus plane
 rotations, so the two agree up to rounding amplified by the conditioning of
-the small least-squares problem; 1e-9 relative bounds that with margin for
-m <= 5 on these operators (observed differences are near 1e-13).
+the small least-squares problem; entry by entry (tests/abi_helpers.assert_close)
+1e-8 bounds that with margin for m <= 5 on these operators (observed
+differences in norm are near 1e-13).
 """
 import numpy as np
 import pytest
 
 from oracle import gemslr as og
-from tests.abi_helpers import relerr
+from tests.abi_helpers import assert_close, relerr
 from tests.test_gpu_parity import _case, _ctx_explicit, _oracle_setup
 
 pytestmark = pytest.mark.gpu
 
-INNER_TOL = 1e-9
+INNER_TOL = 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -46,9 +47,7 @@ def test_inner_apply_matches_oracle(torch_dev, name, its):
         yd = torch.empty_like(xd)
         ctx.apply(xd, yd)
         torch.cuda.synchronize()
-        err = relerr(yd.cpu().numpy(), ref)
-        print(f"  trial {trial}: rel err {err:.3e}", flush=True)
-        assert err <= INNER_TOL
+        assert_close(yd.cpu().numpy(), ref, INNER_TOL, what=f"trial {trial}")
     ctx.close()
 
 
@@ -77,7 +76,7 @@ def test_inner_exact_case_breaks_down_cleanly(torch_dev):
     A = sp.csr_matrix((v, c, r)).toarray()
     y = yd.cpu().numpy()
     assert np.all(np.isfinite(y))
-    assert relerr(y, np.linalg.solve(A, x)) <= 1e-9
+    assert_close(y, np.linalg.solve(A, x), 1e-8, what="exact case vs A^-1 x")
     ctx.close()
 
 

@@ -1,10 +1,13 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
 same seeded inputs.
 
-Tolerances (derivation in the design notes): a float64 apply differs from the
-oracle only by the order of additions inside the triangular solves and
-sparse products, so the relative difference is a small multiple of
-depth * eps * cond(L U); 1e-11 bounds it with margin on these operators.
+Tolerances: a float64 apply differs from the oracle only by the order of
+additions inside the triangular solves and sparse products.  Per entry the
+difference is a small multiple of depth * eps times the magnitudes of the
+partial sums, which on these diagonally dominant factors stay within a small
+factor of the result's own entries; applies are compared entry by entry
+(tests/abi_helpers.assert_close: |y_i - ref_i| <= tol (|ref_i| + 1e-3
+||ref||_inf)) with tol = 1e-10.
 The solve compares FGMRES(m) runs with the same M^{-1}: both stop at the same
 true-residual tolerance and their iterates agree to well below 1e-10.
 """
@@ -15,11 +18,11 @@ from paper_2205_03224_amd import workloads as wl
 from oracle import fgmres as ofg
 from oracle import gemslr as og
 from oracle import partition as opart
-from tests.abi_helpers import oracle_levels, relerr
+from tests.abi_helpers import assert_close, oracle_levels, relerr
 
 pytestmark = pytest.mark.gpu
 
-APPLY_TOL_F64 = 1e-11
+APPLY_TOL_F64 = 1e-10
 
 
 @pytest.fixture(scope="module")
@@ -81,10 +84,7 @@ def test_apply_matches_oracle(torch_dev, name):
         yd = torch.empty_like(xd)
         ctx.apply(xd, yd)
         torch.cuda.synchronize()
-        y = yd.cpu().numpy()
-        err = relerr(y, ref)
-        print(f"  trial {trial}: rel err {err:.3e}", flush=True)
-        assert err <= APPLY_TOL_F64
+        assert_close(yd.cpu().numpy(), ref, APPLY_TOL_F64, what=f"trial {trial}")
     ctx.close()
 
 
@@ -101,7 +101,7 @@ def test_apply_full_rank_is_exact_inverse(torch_dev):
     yd = torch.empty_like(xd)
     ctx.apply(xd, yd)
     torch.cuda.synchronize()
-    assert relerr(yd.cpu().numpy(), np.linalg.solve(A, x)) <= 1e-11
+    assert_close(yd.cpu().numpy(), np.linalg.solve(A, x), 1e-10, what="M^-1 x vs A^-1 x")
     ctx.close()
 
 
@@ -185,9 +185,7 @@ def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
     yd = torch.empty_like(xd)
     ctx.apply(xd, yd)
     torch.cuda.synchronize()
-    err = relerr(yd.cpu().numpy(), ref)
-    print(f"  rel err {err:.3e}", flush=True)
-    assert err <= APPLY_TOL_F64
+    assert_close(yd.cpu().numpy(), ref, APPLY_TOL_F64)
     ctx.close()
 
 
@@ -238,7 +236,5 @@ def test_apply_matches_oracle_across_row_lengths(torch_dev, lfil):
     yd = torch.empty_like(xd)
     ctx.apply(xd, yd)
     torch.cuda.synchronize()
-    err = relerr(yd.cpu().numpy(), ref)
-    print(f"  rel err {err:.3e}", flush=True)
-    assert err <= APPLY_TOL_F64
+    assert_close(yd.cpu().numpy(), ref, APPLY_TOL_F64)
     ctx.close()

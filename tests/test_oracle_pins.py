@@ -281,6 +281,31 @@ def test_krylov_schur_complex_spectrum():
     np.testing.assert_allclose(W.T @ G @ W, R, atol=1e-11)
 
 
+def test_krylov_schur_breakdown_invariant_subspace():
+    # G = a I + U diag(lam) U^T with U of rank 3: the Krylov space of any
+    # start vector is span{v0} + range(U) (4-dimensional), so with k = 3
+    # (m = 6) the step on v_3 finds nothing new; the fresh direction v_4 is
+    # orthogonal to range(U), so G v_4 = a v_4 is in the basis again, and so
+    # is G v_5: the breakdown branch runs three times.  The wanted Ritz values
+    # are then exactly a + lam (largest theta/(1 - theta)), W spans range(U),
+    # and the Krylov relation has no remainder.
+    rs = np.random.default_rng(21)
+    s = 40
+    U, _ = np.linalg.qr(rs.standard_normal((s, 3)))
+    a, lam = 0.1, np.array([0.6, 0.4, 0.2])
+    G = a * np.eye(s) + U @ np.diag(lam) @ U.T
+    for real in (True, False):
+        W, R, info = lowrank.krylov_schur(lambda v: G @ v, s, 3, real=real, seed=5)
+        assert info["breakdowns"] == 3
+        assert info["converged"] and info["cycles"] == 1 and info["matvecs"] == 6
+        np.testing.assert_allclose(np.sort(np.linalg.eigvals(R).real)[::-1], a + lam,
+                                   atol=1e-13)
+        np.testing.assert_allclose(W.conj().T @ W, np.eye(3), atol=1e-13)
+        np.testing.assert_allclose(W.conj().T @ G @ W, R, atol=1e-13)
+        # span(W) = range(U): the projector difference vanishes
+        assert np.linalg.norm(W @ W.conj().T - U @ U.T) < 1e-12
+
+
 def test_singular_correction_raises():
     R = np.array([[1.0, 0.3], [0.0, 0.5]])
     with pytest.raises(lowrank.SingularCorrectionError):
