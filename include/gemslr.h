@@ -214,6 +214,22 @@ int gs_apply(gs_ctx* ctx, const void* x, void* y);
  * gs_apply. */
 int gs_apply_many(gs_ctx* ctx, int nrhs, const void* x, void* y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): gs_apply
+ * with every scratch buffer of the apply (the permuted working vector, the
+ * partial sums of W_l^H z_2, staging vectors) cut from a static device
+ * region of 64 MiB (67,108,864 bytes) that the library holds on each GPU
+ * until the process ends.  The call allocates nothing; the preconditioner's
+ * own data stay where the setup put them.  x, y as for gs_apply.  Every call
+ * on one GPU uses the same region: calls that overlap in time on one GPU
+ * (several streams, several host threads) race and must be ordered by the
+ * caller.  No region content has to start at zero (each apply writes every
+ * scratch entry before reading it).
+ * Errors: GS_ESTATE (no setup), GS_EINVAL (NULL or aliasing vectors; scratch
+ * needed above 64 MiB -- e.g. n above ~4.1M float64 unknowns; inner GMRES
+ * steps switched on), GS_EDEVICE. */
+int gs_apply_noalloc(gs_ctx* ctx, const void* x, void* y);
+
 /* ---------------------------------------------------------------- learned start */
 /* Per-node features of the interface unknowns C_l of level l (0 <= l < L), for
  * a network that predicts starting bases of the low-rank terms.  Host only

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 
 #include "device.h"
@@ -41,6 +42,29 @@ struct gs_ctx {
 };
 
 static std::string g_create_error;
+
+// Scratch region of gs_apply_noalloc: static device memory of the code
+// object, one copy per GPU, so that entry point allocates nothing.  Host
+// code never uses the symbol itself (on the host it is only a stand-in);
+// gs_create resolves each device's address once with hipGetSymbolAddress,
+// with that device current, and the apply takes that address.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on `device` (current), resolved on first use.
+static hipError_t resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
 
 namespace gs {
 
@@ -1171,6 +1195,11 @@ int gs_create(gs_ctx** ctx, int device, void* stream) {
       return GS_EDEVICE;
     }
     c->stream = (hipStream_t)stream;
+    e = resolve_scratch(device);
+    if (e != hipSuccess) {
+      g_create_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return GS_EDEVICE;
+    }
   }
   *ctx = c.release();
   return GS_OK;
@@ -1295,6 +1324,34 @@ int gs_apply_many(gs_ctx* c, int nrhs, const void* x, void* y) {
       if (!c->eng->apply_pair(xb + o0, xb + o1, yb + o0, yb + o1)) break;
     }
     for (; j < nrhs; ++j) c->eng->apply(xb + (size_t)j * n * vb, yb + (size_t)j * n * vb, false);
+    hipcheck(hipGetLastError(), "kernel launch");
+    return GS_OK;
+  });
+}
+
+int gs_apply_noalloc(gs_ctx* c, const void* x, void* y) {
+  if (!c) return GS_EINVAL;
+  GS_GUARD(c, {
+    int r = need_device(c);
+    if (r) return r;
+    if (!c->ready) throw Error(GS_ESTATE, "apply before setup");
+    if (!x || !y) throw Error(GS_EINVAL, "NULL vector");
+    const int64_t n = c->dtype == GS_F64 ? c->hd->n : c->hz->n;
+    const size_t vb = c->dtype == GS_F64 ? 8 : 16;
+    const char* xb = (const char*)x;
+    const char* yb = (const char*)y;
+    const size_t bytes = (size_t)n * vb;
+    if (xb < yb + bytes && yb < xb + bytes) throw Error(GS_EINVAL, "x and y alias");
+    const size_t need = c->eng->scratch_bytes();
+    if (need == 0)
+      throw Error(GS_EINVAL, "gs_apply_noalloc: not available with inner GMRES steps");
+    if (need > kStaticScratchBytes)
+      throw Error(GS_EINVAL, "gs_apply_noalloc: this preconditioner needs " + std::to_string(need) +
+                                 " bytes of scratch; the static region holds " +
+                                 std::to_string(kStaticScratchBytes));
+    void* base = c->device < kMaxDevices ? g_scratch_ptr[c->device] : nullptr;
+    if (!base) throw Error(GS_EDEVICE, "static scratch not resolved for this device");
+    c->eng->apply_in(x, y, base);
     hipcheck(hipGetLastError(), "kernel launch");
     return GS_OK;
   });

@@ -63,6 +63,14 @@ struct Engine {
   // m > 0: m inner GMRES steps on S_hat_0 at the root level of every apply
   // (float64 / complex128 forms only); 0 switches them off
   virtual void set_inner(int m) = 0;
+  // Device scratch one apply needs (working vector, partial sums and the
+  // staging vectors of the levels that use them) when every buffer is cut
+  // from one region at 256-byte offsets; 0 when the apply cannot run that
+  // way (inner GMRES steps keep their own work space).
+  virtual size_t scratch_bytes() const = 0;
+  // apply(x, y, false) with every scratch buffer cut from `base`
+  // (scratch_bytes() bytes, device memory, 256-byte aligned): no allocation.
+  virtual void apply_in(const void* x, void* y, void* base) = 0;
 };
 
 // kernel classes for the measurement probe

@@ -1056,6 +1056,78 @@ struct EngineT final : Engine {
          [&] { launch_scatter<P>(t, pm, (O*)y, n, st); });
   }
 
+  // ---- the apply on a caller's scratch region (see Engine::apply_in)
+  static size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+  // rows of the global block-vector staging (blocks too large for LDS in
+  // the register-prefetch sweep) and of F_l y2 staging (up sweeps that take
+  // F_l y2 from a launch of its own)
+  int64_t xg_need() const {
+    int64_t m = 0;
+    for (const Lev& L : lv)
+      if (L.nb > 0 && !streamed((int)(&L - lv.data())) &&
+          (size_t)L.max_block_rows * sizeof(C) > 65536)
+        m = std::max(m, L.d);
+    return m;
+  }
+  int64_t fy_need() const {
+    int64_t m = 0;
+    for (size_t l = 0; l + 1 < lv.size(); ++l)
+      if (lv[l].nb > 0 && streamed((int)l) && !lv[l].frow) m = std::max(m, lv[l].d);
+    return m;
+  }
+  size_t scratch_bytes() const override {
+    if (inner_m > 0) return 0;
+    size_t b = up256((size_t)n * sizeof(X)) + up256((size_t)xg_need() * sizeof(C)) +
+               up256((size_t)fy_need() * sizeof(C));
+    for (const Lev& L : lv)
+      if (L.k > 0)
+        b += up256((size_t)interface_blocks<P>(L.s) * L.k * sizeof(C)) + up256((size_t)L.k * sizeof(C));
+    return std::max<size_t>(b, 256);
+  }
+  void apply_in(const void* x, void* y, void* base) override {
+    if (inner_m > 0) throw Error(GS_EINVAL, "inner GMRES steps keep their own work space");
+    uint8_t* p = (uint8_t*)base;
+    auto take = [&](size_t bytes) {
+      void* q = p;
+      p += up256(bytes);
+      return q;
+    };
+    X* const t0 = t;
+    C* const xg0 = xg;
+    C* const fy0 = fy;
+    C* part0[GS_MAX_LEVELS + 2];
+    C* tp0[GS_MAX_LEVELS + 2];
+    const size_t nl = std::min(lv.size(), (size_t)GS_MAX_LEVELS + 2);
+    t = (X*)take((size_t)n * sizeof(X));
+    xg = (C*)take((size_t)xg_need() * sizeof(C));
+    fy = (C*)take((size_t)fy_need() * sizeof(C));
+    for (size_t l = 0; l < nl; ++l) {
+      Lev& L = lv[l];
+      part0[l] = L.partial;
+      tp0[l] = L.tprime;
+      if (L.k > 0) {
+        L.partial = (C*)take((size_t)interface_blocks<P>(L.s) * L.k * sizeof(C));
+        L.tprime = (C*)take((size_t)L.k * sizeof(C));
+      }
+    }
+    auto restore = [&] {
+      t = t0;
+      xg = xg0;
+      fy = fy0;
+      for (size_t l = 0; l < nl; ++l) {
+        lv[l].partial = part0[l];
+        lv[l].tprime = tp0[l];
+      }
+    };
+    try {
+      apply(x, y, false);
+    } catch (...) {
+      restore();
+      throw;
+    }
+    restore();
+  }
+
   // y0 = M^{-1} x0 and y1 = M^{-1} x1, the triangular sweeps of both in
   // one launch per level (factor entries read once for two right-hand
   // sides); false (nothing done) when inner steps are on

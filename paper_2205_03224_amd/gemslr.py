@@ -100,6 +100,7 @@ SIGNATURES = [
     ("gs_set_precision", ct.c_int, [_p, ct.c_int]),
     ("gs_apply", ct.c_int, [_p, _p, _p]),
     ("gs_apply_many", ct.c_int, [_p, ct.c_int, _p, _p]),
+    ("gs_apply_noalloc", ct.c_int, [_p, _p, _p]),
     ("gs_apply_profile", ct.c_int, [_p, _p, _p, ct.c_int, _p, _p, ct.c_int,
                                     ct.POINTER(ct.c_int)]),
     ("gs_apply_step_label", ct.c_char_p, [_p, ct.c_int]),
@@ -300,6 +301,11 @@ class Context:
 
     def apply(self, x, y):
         self._check(lib().gs_apply(self._h, self._vec(x), self._vec(y)))
+
+    def apply_noalloc(self, x, y):
+        """gs_apply_noalloc: the apply with its scratch in the library's static
+        device region (no allocation in the call)."""
+        self._check(lib().gs_apply_noalloc(self._h, self._vec(x), self._vec(y)))
 
     def apply_many(self, nrhs, x, y):
         self._check(lib().gs_apply_many(self._h, nrhs, self._vec(x, nrhs), self._vec(y, nrhs)))
