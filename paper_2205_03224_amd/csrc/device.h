@@ -97,7 +97,10 @@ enum { TRI_DOWN = 0, TRI_UP = 1 };
 //   columns      (rows + 1) x CS x uint16 (the last row all zero)
 // Each row of the chunk (rows of consecutive stages follow each other) holds
 // its MS slots contiguously (MS = stream_slots(level's longest row)): the
-// row's entries, then zero values with column 0.  The row strides VS =
+// row's entries, with the near ones (see near_slots) in the last slots of
+// each lane's share, and zero values with column 0 in the slots left over.
+// In half-row stages lanes l and l + 32 share row l, lane l taking slots
+// 0 .. MS/2 - 1 and lane l + 32 the rest.  The row strides VS =
 // MS + 1 values and CS column entries make the per-lane accesses of a wave
 // free of LDS bank conflicts, and let every slot be an immediate offset from
 // one address per stage.  Columns are stored as LDS byte offsets of the
@@ -120,9 +123,19 @@ __host__ __device__ constexpr int stream_slots(int maxslot) {
 }
 __host__ __device__ constexpr int stream_vstride(int ms) { return ms + 1; }
 __host__ __device__ constexpr int stream_cstride(int ms) { return ms <= 4 ? 4 : ms <= 12 ? 12 : 20; }
-// half-row U stages: a row's slots ms/2 .. ms-1 start at this 16-bit
+// half-row stages: a row's slots ms/2 .. ms-1 start at this 16-bit
 // position of its column row (the next 4-byte boundary)
 __host__ __device__ constexpr int stream_half_coff(int ms) { return ((ms / 2) + 1) & ~1; }
+// Near slots per lane: the last near_slots(ms, half) slots of each lane's
+// share of a row hold the entries whose column was computed by the stage
+// just before (plus, if the row has fewer such entries, any others).  The
+// sweep gathers them after that stage's store; every other slot refers to a
+// stage at least two back and is gathered a stage ahead.  The layout keeps
+// at most this many near entries per lane (a stage that would hold more is
+// split).
+__host__ __device__ constexpr int near_slots(int ms, bool half) {
+  return half ? (ms / 2 < 2 ? ms / 2 : 2) : (ms < 3 ? ms : 3);
+}
 // byte scale of the stored column: the element size, so the stored value is
 // the element's LDS byte offset (16-bit: blocks of up to 65536 / sizeof(C)
 // rows use the streamed layout)
@@ -146,6 +159,7 @@ struct TriArgs {
   int32_t x_bytes;           // LDS bytes reserved for the block's vector (16-aligned)
   int32_t nbuf;              // chunk buffers in LDS: 2 (one chunk in flight) or 3 (two)
   int32_t half_u;            // U chunks in half-row form: lanes l and l+32 share row l
+  int32_t half_l;            // L chunks likewise
   // level 0 of an apply (streamed kernel only): DOWN reads its right-hand
   // side from the caller's vector, xin[perm[row]], instead of t; UP writes
   // its result to yout[perm[row]] instead of t.  null: use t.  perm null:

@@ -33,10 +33,16 @@ struct TriHost {
   std::vector<T> dinv, val;
   std::vector<uint16_t> col;
   int maxslot = 0, depth = 0;
-  int maxwidth = 0;  // most rows in one wavefront level of one block
+  int maxwidth = 0;  // most rows in one wavefront level (stage) of one block
+  // streamed layout only: per row slot, how many of its stored entries (the
+  // last ones) refer to rows of the stage just before
+  std::vector<uint8_t> nnear;
 };
 template <class T>
 TriHost<T> build_tri(const CSR<T>& M, const std::vector<int64_t>& blocks, bool upper);
+template <class T>
+TriHost<T> build_tri_sched(const CSR<T>& M, const std::vector<int64_t>& blocks, bool upper,
+                           int width, int near_cap);
 
 // The preconditioner on the device in one storage precision.  Vectors at
 // this interface hold float64 (real) or complex128 values.

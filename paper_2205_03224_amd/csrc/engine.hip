@@ -148,14 +148,191 @@ TriHost<T> build_tri(const CSR<T>& M, const std::vector<int64_t>& blocks, bool u
 }
 
 
+// Stages of the streamed sweep, by list scheduling per block: stage t takes
+// up to `width` rows whose in-block dependencies all lie in earlier stages,
+// longest remaining dependency chain first (ties: lower row), and passes
+// over a row with more than `near_cap` entries in stage t - 1 (a stage
+// later all of them are two back).  Every valid stage order gives the same
+// solution; this one keeps the stage count near the dependency depth while
+// bounding the stage width and the entries the sweep must gather after the
+// previous stage's store.  Each row's entries are stored with those in
+// stage t - 1 ("near") last, in column order otherwise; nnear records how
+// many.  A stage for which every ready row is passed over holds one dummy
+// row (index = block rows, no entries: the slot idle lanes store to).
+template <class T>
+TriHost<T> build_tri_sched(const CSR<T>& M, const std::vector<int64_t>& blocks, bool upper,
+                           int width, int near_cap) {
+  TriHost<T> h;
+  std::vector<int32_t> dp, dc, sp, sc, height, rem, stage_of, cnt;
+  std::vector<T> dval, diag;
+  for (size_t b = 0; b + 1 < blocks.size(); ++b) {
+    const int64_t r0 = blocks[b], r1 = blocks[b + 1];
+    const int nr = (int)(r1 - r0);
+    if (r1 - r0 > 65535) throw Error(GS_EINVAL, "diagonal block larger than 65535 rows");
+    // in-block dependencies (off-diagonal entries of the triangle) and
+    // their reverse
+    dp.assign(nr + 1, 0);
+    dc.clear();
+    dval.clear();
+    diag.assign(nr, T(0));
+    std::vector<char> hasdiag(nr, 0);
+    for (int i = 0; i < nr; ++i) {
+      const int64_t gi = r0 + i;
+      for (int64_t p = M.rp[gi]; p < M.rp[gi + 1]; ++p) {
+        const int64_t c = M.ci[p];
+        if (c < r0 || c >= r1) throw Error(GS_EINVAL, "factor entry outside its diagonal block");
+        if (c == gi) {
+          diag[i] = M.v[p];
+          hasdiag[i] = 1;
+        } else if (upper ? c > gi : c < gi) {
+          dc.push_back((int32_t)(c - r0));
+          dval.push_back(M.v[p]);
+        }
+      }
+      dp[i + 1] = (int32_t)dc.size();
+      if (dp[i + 1] - dp[i] > 65535) throw Error(GS_EINVAL, "row too long");
+      h.maxslot = std::max(h.maxslot, dp[i + 1] - dp[i]);
+    }
+    sp.assign(nr + 1, 0);
+    for (int32_t c : dc) ++sp[c + 1];
+    for (int i = 0; i < nr; ++i) sp[i + 1] += sp[i];
+    sc.assign(dc.size(), 0);
+    {
+      std::vector<int32_t> fill(sp.begin(), sp.end() - 1);
+      for (int i = 0; i < nr; ++i)
+        for (int32_t p = dp[i]; p < dp[i + 1]; ++p) sc[fill[dc[p]]++] = i;
+    }
+    // longest chain of dependents below each row (dependents come after it
+    // in the sweep order: higher rows for L, lower for U)
+    height.assign(nr, 1);
+    int depth = 0;
+    for (int k = 0; k < nr; ++k) {
+      const int i = upper ? k : nr - 1 - k;
+      for (int32_t p = sp[i]; p < sp[i + 1]; ++p) height[i] = std::max(height[i], height[sc[p]] + 1);
+      depth = std::max(depth, height[i]);
+    }
+    h.depth = std::max(h.depth, depth);
+    rem.assign(nr, 0);
+    for (int i = 0; i < nr; ++i) rem[i] = dp[i + 1] - dp[i];
+    stage_of.assign(nr, -1);
+    // ready rows, best first: longest chain, then lower row
+    auto worse = [&](int x, int y) { return height[x] != height[y] ? height[x] < height[y] : x > y; };
+    std::vector<int> ready;
+    for (int i = 0; i < nr; ++i)
+      if (rem[i] == 0) ready.push_back(i);
+    std::make_heap(ready.begin(), ready.end(), worse);
+    std::vector<int> take, skip, fresh;
+    int done = 0;
+    for (int t = 0; done < nr; ++t) {
+      take.clear();
+      skip.clear();
+      while (!ready.empty() && (int)take.size() < width) {
+        std::pop_heap(ready.begin(), ready.end(), worse);
+        const int i = ready.back();
+        ready.pop_back();
+        int near = 0;
+        for (int32_t p = dp[i]; p < dp[i + 1]; ++p) near += stage_of[dc[p]] == t - 1;
+        if (near > near_cap) skip.push_back(i);
+        else take.push_back(i);
+      }
+      for (int i : skip) {
+        ready.push_back(i);
+        std::push_heap(ready.begin(), ready.end(), worse);
+      }
+      if (take.empty()) {
+        // every ready row waits a stage: a stage of one dummy row
+        h.rowinfo.push_back((uint32_t)nr);
+        h.nnear.push_back(0);
+        if (upper) h.dinv.push_back(T(1));
+        h.stage_row.push_back((int32_t)h.rowinfo.size());
+        h.stage_ent.push_back((int32_t)h.val.size());
+        h.maxwidth = std::max(h.maxwidth, 1);
+        continue;
+      }
+      for (int i : take) stage_of[i] = t;
+      done += (int)take.size();
+      h.maxwidth = std::max(h.maxwidth, (int)take.size());
+      // rows with more entries first (slot-major storage below)
+      std::stable_sort(take.begin(), take.end(), [&](int x, int y) {
+        return dp[x + 1] - dp[x] > dp[y + 1] - dp[y];
+      });
+      std::vector<std::vector<std::pair<int32_t, T>>> ent(take.size());
+      int maxnz = 0;
+      for (size_t q = 0; q < take.size(); ++q) {
+        const int i = take[q];
+        int nn = 0;
+        for (int pass = 0; pass < 2; ++pass)
+          for (int32_t p = dp[i]; p < dp[i + 1]; ++p) {
+            const bool nearp = stage_of[dc[p]] == t - 1;
+            if (nearp != (pass == 1)) continue;
+            ent[q].push_back({dc[p], dval[p]});
+            nn += nearp;
+          }
+        const int nz = (int)ent[q].size();
+        maxnz = std::max(maxnz, nz);
+        h.rowinfo.push_back((uint32_t)i | ((uint32_t)nz << 16));
+        h.nnear.push_back((uint8_t)nn);
+        if (upper) {
+          if (!hasdiag[i] || absval(diag[i]) == 0.0)
+            throw Error(GS_EZEROPIVOT, "U factor has a zero or missing diagonal");
+          h.dinv.push_back(T(1) / diag[i]);
+        }
+      }
+      for (int j = 0; j < maxnz; ++j)
+        for (size_t q = 0; q < ent.size(); ++q)
+          if ((int)ent[q].size() > j) {
+            h.val.push_back(ent[q][j].second);
+            h.col.push_back((uint16_t)ent[q][j].first);
+          }
+      if (h.val.size() > (size_t)INT32_MAX) throw Error(GS_EINVAL, "factor too large");
+      h.stage_row.push_back((int32_t)h.rowinfo.size());
+      h.stage_ent.push_back((int32_t)h.val.size());
+      // rows whose last dependency was scheduled become ready next stage
+      fresh.clear();
+      for (int i : take)
+        for (int32_t p = sp[i]; p < sp[i + 1]; ++p)
+          if (--rem[sc[p]] == 0) fresh.push_back(sc[p]);
+      for (int i : fresh) {
+        ready.push_back(i);
+        std::push_heap(ready.begin(), ready.end(), worse);
+      }
+    }
+    h.blk_stage.push_back((int32_t)h.stage_row.size() - 1);
+  }
+  return h;
+}
+
 // Pack the stages of every block (L stages, then U stages) into chunks of
 // whole stages of at most `cap` bytes (see ChunkDesc).  Returns false if a
 // single stage does not fit.
+// Entry j of a row with cnt entries, the last nn of them near, goes to
+// value slot slot_of(...) of the row (see near_slots): near entries fill the
+// last slots of each lane's share (the low half first), far entries the
+// remaining slots in order.  -1 if the row does not fit.
+static int slot_of(int j, int cnt, int nn, int ms, bool half) {
+  const int nfar = cnt - nn;
+  if (cnt > ms || nn < 0 || nfar < 0) return -1;
+  if (!half) {
+    if (nn > near_slots(ms, false)) return -1;
+    return j < nfar ? j : ms - cnt + j;
+  }
+  const int sl = ms / 2, nnh = near_slots(ms, true);
+  const int klo = std::min(nn, nnh), khi = nn - klo;
+  if (khi > nnh) return -1;
+  if (j >= nfar) {
+    const int u = j - nfar;
+    return u < klo ? sl - klo + u : 2 * sl - khi + (u - klo);
+  }
+  const int flo = sl - klo;
+  return j < flo ? j : sl + (j - flo);
+}
+
 template <class V, class D, class T>
 bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, int cap, int ms,
-                  int col_scale, int max_rows, bool half_u, std::vector<uint8_t>& blob,
+                  int col_scale, int max_rows, bool half_l, bool half_u, std::vector<uint8_t>& blob,
                   std::vector<ChunkDesc>& desc, std::vector<int32_t>& blk_chunk) {
   auto pad = [](size_t x) { return (x + 15) & ~(size_t)15; };
+  if (lo.nnear.size() != lo.rowinfo.size() || up.nnear.size() != up.rowinfo.size()) return false;
   // block-vector byte offsets of the columns (rows 0 .. max_rows - 1) must
   // fit the 16-bit column field
   if (max_rows > 0 && (size_t)(max_rows - 1) * (size_t)col_scale > 65535) return false;
@@ -166,6 +343,7 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, in
     for (int tri = 0; tri < 2; ++tri) {
       const TriHost<T>& h = tri == 0 ? lo : up;
       const bool isU = tri == 1;
+      const bool half = isU ? half_u : half_l;
       const int sb = h.blk_stage[b], se = h.blk_stage[b + 1];
       const int VS = stream_vstride(ms), CS = stream_cstride(ms);
       auto size_of = [&](int s0, int s1) {
@@ -214,10 +392,12 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, in
               const size_t row = (size_t)(q - rb);
               const V v = to_store<V, T>(h.val[src]);
               const uint16_t cb = (uint16_t)((uint32_t)h.col[src] * (uint32_t)col_scale);
-              std::memcpy(p + o_val + (row * VS + j) * sizeof(V), &v, sizeof(V));
-              // half-row U stages: slots ms/2.. start at the next 4-byte
+              const int js = slot_of(j, (int)cnt, (int)h.nnear[q], ms, half);
+              if (js < 0) return false;
+              std::memcpy(p + o_val + (row * VS + js) * sizeof(V), &v, sizeof(V));
+              // half-row stages: slots ms/2.. start at the next 4-byte
               // boundary of the column row (two lanes per row)
-              const int hs = ms / 2, jc = (isU && half_u && j >= hs) ? j - hs + stream_half_coff(ms) : j;
+              const int hs = ms / 2, jc = (half && js >= hs) ? js - hs + stream_half_coff(ms) : js;
               std::memcpy(p + o_col + (row * CS + jc) * 2, &cb, 2);
               ++src;
             }
@@ -241,6 +421,18 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, in
     blk_chunk.push_back((int32_t)desc.size());
   }
   return true;
+}
+
+// most entries besides the diagonal in one row of a triangle
+template <class T>
+static int max_offdiag(const CSR<T>& M, bool upper) {
+  int m = 0;
+  for (int64_t i = 0; i + 1 < (int64_t)M.rp.size(); ++i) {
+    int c = 0;
+    for (int64_t p = M.rp[i]; p < M.rp[i + 1]; ++p) c += upper ? M.ci[p] > i : M.ci[p] < i;
+    m = std::max(m, c);
+  }
+  return m;
 }
 
 // Diagonal blocks of a level swept by one workgroup.  Consecutive blocks are
@@ -280,11 +472,13 @@ static int layout_threads(size_t nb) {
   return (int)std::max<size_t>(1, std::min<size_t>({(size_t)hw, (size_t)16, nb / 8 + 1}));
 }
 
-template <class T>
-TriHost<T> build_tri_par(const CSR<T>& M, const std::vector<int64_t>& blocks, bool upper) {
+// fn(sub-block list) builds the layout of those blocks (build_tri or
+// build_tri_sched)
+template <class T, class Fn>
+TriHost<T> build_tri_par(const std::vector<int64_t>& blocks, Fn fn) {
   const size_t nb = blocks.size() - 1;
   const int nt = layout_threads(nb);
-  if (nt <= 1) return build_tri(M, blocks, upper);
+  if (nt <= 1) return fn(blocks);
   std::vector<TriHost<T>> part(nt);
   std::vector<std::exception_ptr> err(nt);
   std::vector<std::thread> th;
@@ -293,7 +487,7 @@ TriHost<T> build_tri_par(const CSR<T>& M, const std::vector<int64_t>& blocks, bo
       try {
         const size_t b0 = nb * t / nt, b1 = nb * (t + 1) / nt;
         std::vector<int64_t> sub(blocks.begin() + b0, blocks.begin() + b1 + 1);
-        part[t] = build_tri(M, sub, upper);
+        part[t] = fn(sub);
       } catch (...) {
         err[t] = std::current_exception();
       }
@@ -313,6 +507,7 @@ TriHost<T> build_tri_par(const CSR<T>& M, const std::vector<int64_t>& blocks, bo
     h.dinv.insert(h.dinv.end(), q.dinv.begin(), q.dinv.end());
     h.val.insert(h.val.end(), q.val.begin(), q.val.end());
     h.col.insert(h.col.end(), q.col.begin(), q.col.end());
+    h.nnear.insert(h.nnear.end(), q.nnear.begin(), q.nnear.end());
     h.maxslot = std::max(h.maxslot, q.maxslot);
     h.depth = std::max(h.depth, q.depth);
     h.maxwidth = std::max(h.maxwidth, q.maxwidth);
@@ -322,7 +517,7 @@ TriHost<T> build_tri_par(const CSR<T>& M, const std::vector<int64_t>& blocks, bo
 
 template <class V, class D, class T>
 bool build_chunks_par(const TriHost<T>& lo, const TriHost<T>& up, int nb, int cap, int ms,
-                      int col_scale, int max_rows, bool half_u, std::vector<uint8_t>& blob,
+                      int col_scale, int max_rows, bool half_l, bool half_u, std::vector<uint8_t>& blob,
                       std::vector<ChunkDesc>& desc, std::vector<int32_t>& blk_chunk) {
   const int nt = layout_threads((size_t)nb);
   std::vector<std::vector<uint8_t>> pb(nt);
@@ -335,8 +530,8 @@ bool build_chunks_par(const TriHost<T>& lo, const TriHost<T>& up, int nb, int ca
     th.emplace_back([&, t] {
       try {
         const int b0 = (int)((int64_t)nb * t / nt), b1 = (int)((int64_t)nb * (t + 1) / nt);
-        ok[t] = build_chunks<V, D, T>(lo, up, b0, b1, cap, ms, col_scale, max_rows, half_u, pb[t], pd[t],
-                                      pc[t]);
+        ok[t] = build_chunks<V, D, T>(lo, up, b0, b1, cap, ms, col_scale, max_rows, half_l, half_u,
+                                      pb[t], pd[t], pc[t]);
       } catch (...) {
         err[t] = std::current_exception();
       }
@@ -390,7 +585,7 @@ struct EngineT final : Engine {
     const ChunkDesc* chunk = nullptr;
     const int32_t* blk_chunk = nullptr;
     int chunk_cap = 0, x_bytes = 0, nbuf = 2;
-    bool half_u = false;  // U chunks laid out and swept as half rows
+    bool half_l = false, half_u = false;  // L / U chunks laid out and swept as half rows
     D* diag_dinv = nullptr;  // diagonal level (L = I, U diagonal): 1/u_ii in row order
     int64_t nchunks = 0;
     int depth_l = 0, depth_u = 0;
@@ -463,9 +658,9 @@ struct EngineT final : Engine {
   // GEMSLR_GROUP_CUS=c: group as if the device had c CUs (tests use it to
   // form groups from a few blocks)
   bool no_group = std::getenv("GEMSLR_NO_GROUP") != nullptr;
-  // GEMSLR_NO_HALF_U: U stages swept one lane per row even when no
-  // wavefront level is wider than 32 rows
-  bool no_half_u = std::getenv("GEMSLR_NO_HALF_U") != nullptr;
+  // GEMSLR_NO_HALF: stages swept one lane per row even where two lanes per
+  // row would pay
+  bool no_half = std::getenv("GEMSLR_NO_HALF") != nullptr;
   // GEMSLR_NO_FUSE_SMALL: small levels use the three-launch interface step
   bool no_fuse_small = std::getenv("GEMSLR_NO_FUSE_SMALL") != nullptr;
   // GEMSLR_NO_FUSE_PERM: the apply gathers and scatters all n rows in
@@ -571,9 +766,8 @@ struct EngineT final : Engine {
       for (int b = 0; b < L.nb; ++b)
         L.max_block_rows = std::max<int>(L.max_block_rows, (int)(grp[b + 1] - grp[b]));
       L.blk_row = upload(br);
-      TriHost<T> tl = build_tri_par(h.L, grp, false);
-      TriHost<T> tu = build_tri_par(h.U, grp, true);
-      L.maxslot = std::max(tl.maxslot, tu.maxslot);
+      // longest row of either triangle (entries besides the diagonal)
+      L.maxslot = std::max(max_offdiag(h.L, false), max_offdiag(h.U, true));
       if (L.maxslot == 0 && h.d > 0) {
         // a diagonal level: keep 1/u_ii in row order (computed as the sweep
         // layout computes it), so a caller may fuse its solve
@@ -587,9 +781,6 @@ struct EngineT final : Engine {
         }
         L.diag_dinv = upload(dv);
       }
-      L.depth_l = tl.depth;
-      L.depth_u = tu.depth;
-      L.nstages = (int64_t)(tl.stage_row.size() + tu.stage_row.size()) - 2;
       {
         // streamed layout: block vector and two chunk buffers in LDS, sized so
         // that two workgroups share one CU
@@ -604,16 +795,36 @@ struct EngineT final : Engine {
         }
         int cap = std::min(kChunkCapMax, ((budget - xb - 1024) / chunk_bufs) & ~1023);
         const int ms = stream_slots(L.maxslot);
-        if (L.nb > 0 && ms > 0 && cap >= 4096) {
+        if (!no_stream && L.nb > 0 && ms > 0 && cap >= 4096) {
+          // per triangle: half-row stages (at most 32 rows, two lanes per
+          // row, each with half of the row's slots) unless they take more
+          // than 8% more stages than full-row ones (at most 64 rows)
+          auto sched = [&](const CSR<T>& M, bool upper, bool& half) {
+            const int nf = near_slots(ms, false), nh = 2 * near_slots(ms, true);
+            TriHost<T> full = build_tri_par<T>(grp, [&](const std::vector<int64_t>& sub) {
+              return build_tri_sched(M, sub, upper, 64, nf);
+            });
+            half = false;
+            if (no_half) return full;
+            TriHost<T> hr = build_tri_par<T>(grp, [&](const std::vector<int64_t>& sub) {
+              return build_tri_sched(M, sub, upper, 32, nh);
+            });
+            if ((hr.stage_row.size() - 1) * 100 <= (full.stage_row.size() - 1) * 108) {
+              half = true;
+              return hr;
+            }
+            return full;
+          };
+          bool hl = false, hu = false;
+          TriHost<T> sl = sched(h.L, false, hl);
+          TriHost<T> su = sched(h.U, true, hu);
           std::vector<uint8_t> blob;
           std::vector<ChunkDesc> desc;
           std::vector<int32_t> bc;
-          // U stages of at most 32 rows (no wavefront level wider): two lanes
-          // per row, each with half of the row's slots
-          const bool half_u = !no_half_u && tu.maxwidth <= 32;
-          if (build_chunks_par<V, D, T>(tl, tu, L.nb, cap, ms, ColScale<C>::value,
-                                        L.max_block_rows, half_u, blob, desc, bc)) {
-            L.half_u = half_u;
+          if (build_chunks_par<V, D, T>(sl, su, L.nb, cap, ms, ColScale<C>::value,
+                                        L.max_block_rows, hl, hu, blob, desc, bc)) {
+            L.half_l = hl;
+            L.half_u = hu;
             L.blob = upload(blob);
             std::vector<uint8_t> draw(desc.size() * sizeof(ChunkDesc));
             if (!desc.empty()) std::memcpy(draw.data(), desc.data(), draw.size());
@@ -623,14 +834,26 @@ struct EngineT final : Engine {
             L.x_bytes = xb;
             L.nbuf = chunk_bufs;
             L.nchunks = (int64_t)desc.size();
+            L.depth_l = sl.depth;
+            L.depth_u = su.depth;
+            L.nstages = (int64_t)(sl.stage_row.size() + su.stage_row.size()) - 2;
           }
         }
       }
-      // the per-stage layout only feeds the register-prefetch kernel, used
-      // when the streamed layout is unavailable or switched off
-      if (!L.blob || no_stream) {
+      // the per-stage layout feeds the register-prefetch kernel, used when
+      // the streamed layout is unavailable or switched off
+      if (!L.blob) {
+        TriHost<T> tl = build_tri_par<T>(grp, [&](const std::vector<int64_t>& sub) {
+          return build_tri(h.L, sub, false);
+        });
+        TriHost<T> tu = build_tri_par<T>(grp, [&](const std::vector<int64_t>& sub) {
+          return build_tri(h.U, sub, true);
+        });
         L.lo = upload_tri(tl, false);
         L.up = upload_tri(tu, true);
+        L.depth_l = tl.depth;
+        L.depth_u = tu.depth;
+        L.nstages = (int64_t)(tl.stage_row.size() + tu.stage_row.size()) - 2;
       }
       L.nnz_lu = h.L.nnz() + h.U.nnz();
       if (h.s > 0) {
@@ -816,6 +1039,7 @@ struct EngineT final : Engine {
     a.x_bytes = L.x_bytes;
     a.nbuf = L.nbuf;
     a.half_u = L.half_u ? 1 : 0;
+    a.half_l = L.half_l ? 1 : 0;
     a.xin = nullptr;
     a.yout = nullptr;
     a.perm = nullptr;

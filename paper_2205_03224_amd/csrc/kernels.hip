@@ -393,33 +393,40 @@ __device__ __forceinline__ dcplx swap32(dcplx x, bool low) {
   return mk(swap32(x.x, low), swap32(x.y, low));
 }
 
-// Three-stage pipeline over the stages of one chunk (full rows, or half
-// rows: lanes l and l + 32 share row l).  Per stage s: the gathers of s are
-// issued first and waited for alone (every older LDS access has long
-// completed), then the loads of s+2 (entries, columns, 1/u_ii and the row
-// info of s+3) are issued among the sums of s and the gather offsets of
-// s+1, and the result of s is stored.  So a stage's critical path is one
-// LDS round trip plus its arithmetic, the loads of s+2 travel while s+1
-// runs, and no wait ever needs more than the 15 LDS operations the counter
-// can track.  Scheduling barriers keep that order; LDS executes one
-// wavefront's accesses in order, so the gathers of s+1 see the store of s.
-template <class P, int MS, bool HALF>
+// Pipeline over the stages of one chunk (full rows, or half rows: lanes l
+// and l + 32 share row l).  A lane's SL slots split into NF far slots, whose
+// columns were computed two or more stages back, and the NN near slots after
+// them, which may refer to the stage just before (near_slots; the layout
+// guarantees the split).  Per stage s:
+//   1. gather the near slots of s -- LDS executes one wavefront's accesses
+//      in order, so these see the store of s - 1 that precedes them;
+//   2. form the gather addresses of s + 1 and gather its far slots and the
+//      current value of its rows (nothing of stage s is involved);
+//   3. issue the loads of s + 2 (entries, columns, 1/u_ii, the row info of
+//      s + 3), ahead of the near wait when the LDS counter can still tell the
+//      near gathers apart (at most 15 operations younger), else after it;
+//   4. add the far products of s (gathered during stage s - 1);
+//   5. add the near products, finish and store the result of s.
+// So the critical path of a stage is the store -> near-gather round trip plus
+// NN products and the finish, and the far gathers and loads travel while the
+// previous stage completes.  Scheduling barriers keep the order; the compiler
+// places the waits at the first use of each gathered value.
+template <class P, int MS, bool HALF, int NB>
 struct PipeRegs {
+  using C = typename P::C;
   static constexpr int SL = HALF ? MS / 2 : MS;  // slots per lane
+  static constexpr int NN = near_slots(MS, HALF);
+  static constexpr int NF = SL - NN;
   static constexpr int NW = (SL + 1) / 2;        // 32-bit words of packed columns
-  typename P::C v[SL];
+  C v[SL];
   uint32_t cw[NW];
   uint32_t ad[SL];  // gather byte offsets into the block vector
-  typename P::C dv;
+  C dv;
   int row;  // the lane's row, or the block's dummy slot for idle lanes
   int nr;   // rows of the stage (uniform; 0 past the chunk's last stage)
-};
-template <class P, int MS, bool HALF, int NB>
-struct PipeGath {
-  static constexpr int SL = HALF ? MS / 2 : MS;
-  typename P::C xv[SL];
-  typename P::C xw[NB == 2 ? SL : 1];
-  typename P::C b, bw;
+  C xv[SL];                     // gathered block-vector values
+  C xw[NB == 2 ? SL : 1];       // the second right-hand side's
+  C b, bw;                      // current value of the row (right-hand side)
 };
 
 // load of a value at LDS byte address a
@@ -443,12 +450,12 @@ __device__ __forceinline__ bf16 lds_ld<bf16>(uint32_t a) {
 }
 
 // LDS byte address of a block-vector element (x0: LDS address of x[0])
-template <class P, int MS, bool HALF>
-__device__ __forceinline__ void st_addr(PipeRegs<P, MS, HALF>& R, uint32_t x0) {
+template <class P, int MS, bool HALF, int NB>
+__device__ __forceinline__ void st_addr(PipeRegs<P, MS, HALF, NB>& R, uint32_t x0) {
   using C = typename P::C;
   constexpr int kMul = (int)sizeof(C) / ColScale<C>::value;
 #pragma unroll
-  for (int j = 0; j < PipeRegs<P, MS, HALF>::SL; ++j) {
+  for (int j = 0; j < PipeRegs<P, MS, HALF, NB>::SL; ++j) {
     R.ad[j] = x0 + (j % 2 ? R.cw[j / 2] >> 16 : R.cw[j / 2] & 0xffffu) * kMul;
     asm volatile("" : "+v"(R.ad[j]));  // formed here, not again before the gathers
   }
@@ -456,14 +463,14 @@ __device__ __forceinline__ void st_addr(PipeRegs<P, MS, HALF>& R, uint32_t x0) {
 
 // loads of one stage whose row info is `info` and first chunk row r0; the
 // chunk's sections are given by LDS byte addresses (32-bit arithmetic)
-template <class P, int MS, bool HALF, bool ISU>
+template <class P, int MS, bool HALF, bool ISU, int NB>
 __device__ __forceinline__ void st_load(uint32_t vbase, uint32_t dbase, uint32_t cbase,
                                         uint32_t info, int r0, int ql, int half, int dummy,
-                                        PipeRegs<P, MS, HALF>& R) {
+                                        PipeRegs<P, MS, HALF, NB>& R) {
   using C = typename P::C;
   using V = typename P::V;
   using D = typename P::D;
-  using RG = PipeRegs<P, MS, HALF>;
+  using RG = PipeRegs<P, MS, HALF, NB>;
   constexpr int VS = stream_vstride(MS), CS = stream_cstride(MS);
   constexpr int CO = HALF ? stream_half_coff(MS) : 0;
   static_assert(CO + RG::SL <= CS, "column row holds both halves");
@@ -481,55 +488,71 @@ __device__ __forceinline__ void st_load(uint32_t vbase, uint32_t dbase, uint32_t
   if (ISU) R.dv = cvt<C>(lds_ld<D>(dbase + __umul24(q, (uint32_t)sizeof(D))));
 }
 
-template <class P, int MS, bool HALF, int NB>
-__device__ __forceinline__ void st_gather(const PipeRegs<P, MS, HALF>& R, const typename P::C* x,
-                                          PipeGath<P, MS, HALF, NB>& G) {
+// gathers of slots J0 .. J1 - 1 (both right-hand sides with NB = 2: one
+// two-address instruction per slot)
+template <int J0, int J1, class P, int MS, bool HALF, int NB>
+__device__ __forceinline__ void st_gather(PipeRegs<P, MS, HALF, NB>& R) {
   using C = typename P::C;
   constexpr int kX2 = pair_offset<C>();
 #pragma unroll
-  for (int j = 0; j < PipeRegs<P, MS, HALF>::SL; ++j) {
-    G.xv[j] = lds_ld<C>(R.ad[j]);
-    if (NB == 2) G.xw[j] = lds_ld<C>(R.ad[j] + kX2);
+  for (int j = J0; j < J1; ++j) {
+    R.xv[j] = lds_ld<C>(R.ad[j]);
+    if (NB == 2) R.xw[j] = lds_ld<C>(R.ad[j] + kX2);
   }
-  G.b = x[R.row];
+}
+// current value of the lane's row
+template <class P, int MS, bool HALF, int NB>
+__device__ __forceinline__ void st_gather_b(PipeRegs<P, MS, HALF, NB>& R, const typename P::C* x) {
+  using C = typename P::C;
+  constexpr int kX2 = pair_offset<C>();
+  R.b = x[R.row];
   if (NB == 2)
-    G.bw = *reinterpret_cast<const C*>(reinterpret_cast<const unsigned char*>(x) +
+    R.bw = *reinterpret_cast<const C*>(reinterpret_cast<const unsigned char*>(x) +
                                        R.row * sizeof(C) + kX2);
 }
 
-// x[row] = (b - sum_j v_j x[c_j]) (* 1/u_ii), two partial sums (padded
-// entries are zero); half rows: the partner's half sum via permlane32, low
-// half first on both lanes, so both store the same value
+// the two partial sums of each right-hand side (even and odd slots; padded
+// entries are zero)
+template <class C>
+struct PipeAcc {
+  C s0, s1, w0, w1;
+};
+template <int J0, int J1, class P, int MS, bool HALF, int NB>
+__device__ __forceinline__ void st_sum(const PipeRegs<P, MS, HALF, NB>& R, PipeAcc<typename P::C>& a) {
+#pragma unroll
+  for (int j = J0; j < J1; ++j) {
+    if (j % 2 == 0) {
+      a.s0 += R.v[j] * R.xv[j];
+      if (NB == 2) a.w0 += R.v[j] * R.xw[j];
+    } else {
+      a.s1 += R.v[j] * R.xv[j];
+      if (NB == 2) a.w1 += R.v[j] * R.xw[j];
+    }
+  }
+}
+
+// x[row] = (b - sum_j v_j x[c_j]) (* 1/u_ii); half rows: the partner's half
+// sum via permlane32, low half first on both lanes, so both store the same
+// value
 template <class P, int MS, bool HALF, bool ISU, int NB>
-__device__ __forceinline__ void st_finish(const PipeRegs<P, MS, HALF>& R,
-                                          const PipeGath<P, MS, HALF, NB>& G,
+__device__ __forceinline__ void st_finish(const PipeRegs<P, MS, HALF, NB>& R,
+                                          const PipeAcc<typename P::C>& a,
                                           typename P::C* x, bool low) {
   using C = typename P::C;
   constexpr int kX2 = pair_offset<C>();
-  constexpr int SL = PipeRegs<P, MS, HALF>::SL;
-  C s0 = zero<C>(), s1 = zero<C>(), w0 = zero<C>(), w1 = zero<C>();
-#pragma unroll
-  for (int j = 0; j < SL; j += 2) {
-    s0 += R.v[j] * G.xv[j];
-    if (j + 1 < SL) s1 += R.v[j + 1] * G.xv[j + 1];
-    if (NB == 2) {
-      w0 += R.v[j] * G.xw[j];
-      if (j + 1 < SL) w1 += R.v[j + 1] * G.xw[j + 1];
-    }
-  }
   C acc, aw = zero<C>();
   if (HALF) {
-    const C p = s0 + s1;
+    const C p = a.s0 + a.s1;
     const C o = swap32(p, low);
-    acc = G.b - (low ? p + o : o + p);
+    acc = R.b - (low ? p + o : o + p);
     if (NB == 2) {
-      const C pw = w0 + w1;
+      const C pw = a.w0 + a.w1;
       const C ow = swap32(pw, low);
-      aw = G.bw - (low ? pw + ow : ow + pw);
+      aw = R.bw - (low ? pw + ow : ow + pw);
     }
   } else {
-    acc = G.b - (s0 + s1);
-    if (NB == 2) aw = G.bw - (w0 + w1);
+    acc = R.b - (a.s0 + a.s1);
+    if (NB == 2) aw = R.bw - (a.w0 + a.w1);
   }
   if (ISU) {
     acc *= R.dv;
@@ -541,8 +564,17 @@ __device__ __forceinline__ void st_finish(const PipeRegs<P, MS, HALF>& R,
 }
 
 template <class P, int MS, bool HALF, bool ISU, int NB>
-__device__ __forceinline__ void chunk_sweep3(const uint8_t* cb, const ChunkDesc& cd, int lane,
-                                             typename P::C* x, int dummy) {
+__device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& cd, int lane,
+                                            typename P::C* x, int dummy) {
+  using C = typename P::C;
+  using V = typename P::V;
+  using RG = PipeRegs<P, MS, HALF, NB>;
+  constexpr int SL = RG::SL, NF = RG::NF, NW = RG::NW;
+  // LDS operations of one stage's loads (paired where adjacent) and of the
+  // far gathers; the loads go ahead of the near wait when the near gathers
+  // stay within the 15 operations the counter tells apart
+  constexpr int kLoadOps = (SL * (int)sizeof(V) + 15) / 16 + (NW + 1) / 2 + (ISU ? 2 : 1);
+  constexpr bool kEarly = NF + 1 + kLoadOps <= 15;
   typedef __attribute__((address_space(3))) const uint8_t lds_u8;
   const uint32_t vbase = (uint32_t)(size_t)(lds_u8*)cb;
   const uint32_t dbase = vbase + 16u * cd.dinv16;
@@ -554,33 +586,49 @@ __device__ __forceinline__ void chunk_sweep3(const uint8_t* cb, const ChunkDesc&
   const int nrows = (int)cd.nrows;
   const int ql = HALF ? (lane & 31) : lane, half = HALF ? lane >> 5 : 0;
   const bool low = half == 0;
-  typedef __attribute__((address_space(3))) typename P::C lds_c;
+  typedef __attribute__((address_space(3))) C lds_c;
   const uint32_t x0 = (uint32_t)(size_t)(lds_c*)x;
-  PipeRegs<P, MS, HALF> A, B, Cr;
-  PipeGath<P, MS, HALF, NB> G;
-  // prologue: stages 0 and 1 loaded, the row info of stage 2 read
-  st_load<P, MS, HALF, ISU>(vbase, dbase, cbase, rinfo(ql), 0, ql, half, dummy, A);
+  RG A, B, Cr;
+  // prologue: stages 0 and 1 loaded, the row info of stage 2 read, the far
+  // slots of stage 0 gathered (everything before the chunk is complete).
+  // Row info read past the chunk's last stage is the closing zero word: a
+  // stage of no rows.
+  st_load<P, MS, HALF, ISU, NB>(vbase, dbase, cbase, rinfo(ql), 0, ql, half, dummy, A);
   int r = A.nr;
   uint32_t info = rinfo(min(r + ql, nrows));
-  info = nst > 1 ? info : 0u;
-  st_load<P, MS, HALF, ISU>(vbase, dbase, cbase, info, r, ql, half, dummy, B);
+  st_load<P, MS, HALF, ISU, NB>(vbase, dbase, cbase, info, r, ql, half, dummy, B);
   r += B.nr;
   info = rinfo(min(r + ql, nrows));
-  info = nst > 2 ? info : 0u;
-  st_addr<P, MS, HALF>(A, x0);
+  st_addr<P, MS, HALF, NB>(A, x0);
+  st_gather<0, NF>(A);
+  st_gather_b(A, x);
   // one stage: cur = s, nxt = s+1, far receives s+2
-  const auto step = [&](PipeRegs<P, MS, HALF>& cur, PipeRegs<P, MS, HALF>& nxt,
-                        PipeRegs<P, MS, HALF>& far, int s) {
-    st_gather<P, MS, HALF, NB>(cur, x, G);
+  const auto step = [&](RG& cur, RG& nxt, RG& far, int s) {
+    st_gather<NF, SL>(cur);
     __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);
+    st_addr<P, MS, HALF, NB>(nxt, x0);
+    st_gather<0, NF>(nxt);
+    st_gather_b(nxt, x);
     __builtin_amdgcn_sched_barrier(0);
-    st_load<P, MS, HALF, ISU>(vbase, dbase, cbase, info, r, ql, half, dummy, far);
-    r += far.nr;
-    const uint32_t i3 = rinfo(min(r + ql, nrows));
-    info = s + 3 < nst ? i3 : 0u;
-    st_addr<P, MS, HALF>(nxt, x0);
-    st_finish<P, MS, HALF, ISU, NB>(cur, G, x, low);
+    const auto loads = [&] {
+      st_load<P, MS, HALF, ISU, NB>(vbase, dbase, cbase, info, r, ql, half, dummy, far);
+      r += far.nr;
+      info = rinfo(min(r + ql, nrows));
+    };
+    if (kEarly) loads();
+    __builtin_amdgcn_sched_barrier(0);
+    PipeAcc<C> acc{zero<C>(), zero<C>(), zero<C>(), zero<C>()};
+    st_sum<0, NF>(cur, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    if (!kEarly) {
+      st_sum<NF, SL>(cur, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      loads();
+      __builtin_amdgcn_sched_barrier(0);
+    } else {
+      st_sum<NF, SL>(cur, acc);
+    }
+    st_finish<P, MS, HALF, ISU, NB>(cur, acc, x, low);
     __builtin_amdgcn_sched_barrier(0);
   };
   for (int s = 0;; s += 3) {
@@ -785,11 +833,21 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
         wait_vmcnt(0);
       }
     } else {
+      // Nothing of this wave is in flight here (its last chunk ended with a
+      // full LDS wait), so this wait costs nothing; it tells the compiler
+      // that the producer's LDS-DMA copies, which it cannot place on the
+      // other wave, are not pending either -- otherwise it turns every LDS
+      // wait of the sweep below into a full one.
+      __builtin_amdgcn_s_waitcnt(0);
       const ChunkDesc cd = desc_get<P>(a, c, c1, lane, dc);
       uint8_t* cur = bufs + (k % nbuf) * a.chunk_cap;
-      if ((cd.nst & 0x8000) && a.half_u) chunk_sweep3<P, MS, true, true, NB>(cur, cd, lane, x, nr);
-      else if (cd.nst & 0x8000) chunk_sweep3<P, MS, false, true, NB>(cur, cd, lane, x, nr);
-      else chunk_sweep3<P, MS, false, false, NB>(cur, cd, lane, x, nr);
+      if (cd.nst & 0x8000) {
+        if (a.half_u) chunk_sweep<P, MS, true, true, NB>(cur, cd, lane, x, nr);
+        else chunk_sweep<P, MS, false, true, NB>(cur, cd, lane, x, nr);
+      } else {
+        if (a.half_l) chunk_sweep<P, MS, true, false, NB>(cur, cd, lane, x, nr);
+        else chunk_sweep<P, MS, false, false, NB>(cur, cd, lane, x, nr);
+      }
       // every read of the buffer done before the producer may refill it
       __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);
     }

@@ -156,7 +156,7 @@ def test_native_setup_solves(torch_dev):
                                  {"GEMSLR_NO_GROUP": "1"}, {"GEMSLR_GROUP_CUS": "4"},
                                  {"GEMSLR_GROUP_CUS": "2", "GEMSLR_NO_STREAM": "1"},
                                  {"GEMSLR_NO_FUSE_SMALL": "1"}, {"GEMSLR_NO_FUSE_PERM": "1"},
-                                 {"GEMSLR_NO_HALF_U": "1"}, {"GEMSLR_NO_FUSE_FY": "1"},
+                                 {"GEMSLR_NO_HALF": "1"}, {"GEMSLR_NO_FUSE_FY": "1"},
                                  {"GEMSLR_NO_SMALL_LDS": "1"}])
 @pytest.mark.parametrize("name", ["convdiff3d_20_p27", "helmholtz3d_16_p8"])
 def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
