@@ -92,7 +92,8 @@ enum { TRI_DOWN = 0, TRI_UP = 1 };
 // 16-byte aligned byte range:
 //   values       rows x VS x V          (offset 0)
 //   inverse diag rows x D               (U chunks only)
-//   row info     (rows + 1) x uint32: block-local row | count << 16 | stage rows << 24
+//   row info     (rows + 1) x uint32: LDS byte offset of the row in the block
+//                vector (row * sizeof(C), 24 bits) | stage rows << 24
 //                (the last word zero: reading past the last stage gives 0 rows)
 //   columns      (rows + 1) x CS x uint16 (the last row all zero)
 // Each row of the chunk (rows of consecutive stages follow each other) holds

@@ -404,9 +404,11 @@ bool build_chunks(const TriHost<T>& lo, const TriHost<T>& up, int b0, int b1, in
           }
           if (src != h.stage_ent[k + 1]) return false;
           for (int32_t q = r0; q < r1; ++q) {
-            const uint32_t inf = h.rowinfo[q];
-            if ((inf >> 16) > 255) return false;
-            const uint32_t w = (inf & 0x00ffffffu) | (nrs << 24);
+            // the row's LDS byte offset in the block vector (24 bits) and
+            // the stage's row count
+            const uint32_t off = (h.rowinfo[q] & 0xffffu) * (uint32_t)col_scale;
+            if (off > 0xffffffu || nrs > 255) return false;
+            const uint32_t w = off | (nrs << 24);
             std::memcpy(p + o_info + (size_t)(q - rb) * 4, &w, 4);
             if (isU) {
               const D dv = to_store<D, T>(h.dinv[q]);

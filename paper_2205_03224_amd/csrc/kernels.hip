@@ -393,6 +393,29 @@ __device__ __forceinline__ dcplx swap32(dcplx x, bool low) {
   return mk(swap32(x.x, low), swap32(x.y, low));
 }
 
+// Lanes 0..31 receive the value of x in lane + 32 (returned in `hi`) while
+// keeping their own (returned in `lo`); `dead` is a value the caller no
+// longer needs (the swap overwrites its register), so no copies are made.
+// Lanes 32..63 get unspecified values.
+__device__ __forceinline__ void from_high(double x, double dead, double& lo, double& hi) {
+  const auto a = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(x),
+                                                  (unsigned)__double2loint(dead), false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(x),
+                                                  (unsigned)__double2hiint(dead), false, false);
+  lo = __hiloint2double((int)b[0], (int)a[0]);
+  hi = __hiloint2double((int)b[1], (int)a[1]);
+}
+__device__ __forceinline__ void from_high(float x, float dead, float& lo, float& hi) {
+  const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(dead), false,
+                                                  false);
+  lo = __uint_as_float(a[0]);
+  hi = __uint_as_float(a[1]);
+}
+__device__ __forceinline__ void from_high(dcplx x, dcplx dead, dcplx& lo, dcplx& hi) {
+  from_high(x.x, dead.x, lo.x, hi.x);
+  from_high(x.y, dead.y, lo.y, hi.y);
+}
+
 // Pipeline over the stages of one chunk (full rows, or half rows: lanes l
 // and l + 32 share row l).  A lane's SL slots split into NF far slots, whose
 // columns were computed two or more stages back, and the NN near slots after
@@ -422,7 +445,8 @@ struct PipeRegs {
   uint32_t cw[NW];
   uint32_t ad[SL];  // gather byte offsets into the block vector
   C dv;
-  int row;  // the lane's row, or the block's dummy slot for idle lanes
+  uint32_t row;  // LDS byte offset of the lane's row in the block vector, or
+                 // of the dummy slot (idle lanes; in half rows the high lane)
   int nr;   // rows of the stage (uniform; 0 past the chunk's last stage)
   C xv[SL];                     // gathered block-vector values
   C xw[NB == 2 ? SL : 1];       // the second right-hand side's
@@ -447,6 +471,22 @@ template <>
 __device__ __forceinline__ bf16 lds_ld<bf16>(uint32_t a) {
   typedef __attribute__((address_space(3))) const uint16_t T;
   return bf16{*(T*)(size_t)a};
+}
+
+// store of a value at LDS byte address a
+template <class C>
+__device__ __forceinline__ void lds_st(uint32_t a, C v) {
+  typedef __attribute__((address_space(3))) C T;
+  *(T*)(size_t)a = v;
+}
+template <>
+__device__ __forceinline__ void lds_st<dcplx>(uint32_t a, dcplx v) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(3))) d2 T;
+  d2 w;
+  w.x = v.x;
+  w.y = v.y;
+  *(T*)(size_t)a = w;
 }
 
 // LDS byte address of a block-vector element (x0: LDS address of x[0])
@@ -476,7 +516,7 @@ __device__ __forceinline__ void st_load(uint32_t vbase, uint32_t dbase, uint32_t
   static_assert(CO + RG::SL <= CS, "column row holds both halves");
   R.nr = (int)__builtin_amdgcn_readfirstlane(info >> 24);
   const bool act = ql < R.nr;
-  R.row = act ? (int)(info & 0xffffu) : dummy;
+  R.row = (act && (!HALF || half == 0)) ? (info & 0xffffffu) : (uint32_t)dummy;
   const uint32_t q = (uint32_t)(act ? r0 + ql : r0);
   const uint32_t va = vbase + __umul24(q, (uint32_t)(VS * sizeof(V))) +
                       (HALF ? (uint32_t)(half * RG::SL * sizeof(V)) : 0u);
@@ -485,7 +525,7 @@ __device__ __forceinline__ void st_load(uint32_t vbase, uint32_t dbase, uint32_t
   for (int j = 0; j < RG::SL; ++j) R.v[j] = cvt<C>(lds_ld<V>(va + j * (uint32_t)sizeof(V)));
 #pragma unroll
   for (int j = 0; j < RG::NW; ++j) R.cw[j] = lds_ld<uint32_t>(ca + 4u * j);
-  if (ISU) R.dv = cvt<C>(lds_ld<D>(dbase + __umul24(q, (uint32_t)sizeof(D))));
+  if (ISU) R.dv = cvt<C>(lds_ld<D>(dbase + q * (uint32_t)sizeof(D)));
 }
 
 // gathers of slots J0 .. J1 - 1 (both right-hand sides with NB = 2: one
@@ -502,13 +542,11 @@ __device__ __forceinline__ void st_gather(PipeRegs<P, MS, HALF, NB>& R) {
 }
 // current value of the lane's row
 template <class P, int MS, bool HALF, int NB>
-__device__ __forceinline__ void st_gather_b(PipeRegs<P, MS, HALF, NB>& R, const typename P::C* x) {
+__device__ __forceinline__ void st_gather_b(PipeRegs<P, MS, HALF, NB>& R, uint32_t x0) {
   using C = typename P::C;
   constexpr int kX2 = pair_offset<C>();
-  R.b = x[R.row];
-  if (NB == 2)
-    R.bw = *reinterpret_cast<const C*>(reinterpret_cast<const unsigned char*>(x) +
-                                       R.row * sizeof(C) + kX2);
+  R.b = lds_ld<C>(x0 + R.row);
+  if (NB == 2) R.bw = lds_ld<C>(x0 + R.row + kX2);
 }
 
 // the two partial sums of each right-hand side (even and odd slots; padded
@@ -531,24 +569,23 @@ __device__ __forceinline__ void st_sum(const PipeRegs<P, MS, HALF, NB>& R, PipeA
   }
 }
 
-// x[row] = (b - sum_j v_j x[c_j]) (* 1/u_ii); half rows: the partner's half
-// sum via permlane32, low half first on both lanes, so both store the same
-// value
+// x[row] = (b - sum_j v_j x[c_j]) (* 1/u_ii); half rows: the low lane adds
+// its half sum and the high lane's, in that order (the high lane stores to
+// the dummy slot)
 template <class P, int MS, bool HALF, bool ISU, int NB>
 __device__ __forceinline__ void st_finish(const PipeRegs<P, MS, HALF, NB>& R,
-                                          const PipeAcc<typename P::C>& a,
-                                          typename P::C* x, bool low) {
+                                          const PipeAcc<typename P::C>& a, uint32_t x0) {
   using C = typename P::C;
   constexpr int kX2 = pair_offset<C>();
   C acc, aw = zero<C>();
   if (HALF) {
-    const C p = a.s0 + a.s1;
-    const C o = swap32(p, low);
-    acc = R.b - (low ? p + o : o + p);
+    C p, o;
+    from_high(a.s0 + a.s1, a.s1, p, o);
+    acc = R.b - (p + o);
     if (NB == 2) {
-      const C pw = a.w0 + a.w1;
-      const C ow = swap32(pw, low);
-      aw = R.bw - (low ? pw + ow : ow + pw);
+      C pw, ow;
+      from_high(a.w0 + a.w1, a.w1, pw, ow);
+      aw = R.bw - (pw + ow);
     }
   } else {
     acc = R.b - (a.s0 + a.s1);
@@ -558,9 +595,8 @@ __device__ __forceinline__ void st_finish(const PipeRegs<P, MS, HALF, NB>& R,
     acc *= R.dv;
     if (NB == 2) aw *= R.dv;
   }
-  x[R.row] = acc;
-  if (NB == 2)
-    *reinterpret_cast<C*>(reinterpret_cast<unsigned char*>(x) + R.row * sizeof(C) + kX2) = aw;
+  lds_st<C>(x0 + R.row, acc);
+  if (NB == 2) lds_st<C>(x0 + R.row + kX2, aw);
 }
 
 template <class P, int MS, bool HALF, bool ISU, int NB>
@@ -585,7 +621,6 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
   if (nst == 0) return;
   const int nrows = (int)cd.nrows;
   const int ql = HALF ? (lane & 31) : lane, half = HALF ? lane >> 5 : 0;
-  const bool low = half == 0;
   typedef __attribute__((address_space(3))) C lds_c;
   const uint32_t x0 = (uint32_t)(size_t)(lds_c*)x;
   RG A, B, Cr;
@@ -601,14 +636,14 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
   info = rinfo(min(r + ql, nrows));
   st_addr<P, MS, HALF, NB>(A, x0);
   st_gather<0, NF>(A);
-  st_gather_b(A, x);
+  st_gather_b(A, x0);
   // one stage: cur = s, nxt = s+1, far receives s+2
   const auto step = [&](RG& cur, RG& nxt, RG& far, int s) {
     st_gather<NF, SL>(cur);
     __builtin_amdgcn_sched_barrier(0);
     st_addr<P, MS, HALF, NB>(nxt, x0);
     st_gather<0, NF>(nxt);
-    st_gather_b(nxt, x);
+    st_gather_b(nxt, x0);
     __builtin_amdgcn_sched_barrier(0);
     const auto loads = [&] {
       st_load<P, MS, HALF, ISU, NB>(vbase, dbase, cbase, info, r, ql, half, dummy, far);
@@ -628,7 +663,7 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
     } else {
       st_sum<NF, SL>(cur, acc);
     }
-    st_finish<P, MS, HALF, ISU, NB>(cur, acc, x, low);
+    st_finish<P, MS, HALF, ISU, NB>(cur, acc, x0);
     __builtin_amdgcn_sched_barrier(0);
   };
   for (int s = 0;; s += 3) {
@@ -841,12 +876,14 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
       __builtin_amdgcn_s_waitcnt(0);
       const ChunkDesc cd = desc_get<P>(a, c, c1, lane, dc);
       uint8_t* cur = bufs + (k % nbuf) * a.chunk_cap;
+      // idle lanes store to the slot after the block's rows
+      const int dummy = nr * (int)sizeof(C);
       if (cd.nst & 0x8000) {
-        if (a.half_u) chunk_sweep<P, MS, true, true, NB>(cur, cd, lane, x, nr);
-        else chunk_sweep<P, MS, false, true, NB>(cur, cd, lane, x, nr);
+        if (a.half_u) chunk_sweep<P, MS, true, true, NB>(cur, cd, lane, x, dummy);
+        else chunk_sweep<P, MS, false, true, NB>(cur, cd, lane, x, dummy);
       } else {
-        if (a.half_l) chunk_sweep<P, MS, true, false, NB>(cur, cd, lane, x, nr);
-        else chunk_sweep<P, MS, false, false, NB>(cur, cd, lane, x, nr);
+        if (a.half_l) chunk_sweep<P, MS, true, false, NB>(cur, cd, lane, x, dummy);
+        else chunk_sweep<P, MS, false, false, NB>(cur, cd, lane, x, dummy);
       }
       // every read of the buffer done before the producer may refill it
       __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);
