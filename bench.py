@@ -57,36 +57,150 @@ def measured_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(seconds=12.0):
-    """Oracle apply timed on the host, one thread, on a bounded sample: the
-    32^3 member of the same operator family with 8 subdomains of the same
-    ~16^3 box size (ILUT(1e-3, 10), rank 32); scaled to the 128^3 workload by
-    the unknown count (1/64)."""
+def oracle_setup_like(ctx, seed=7):
+    """An oracle Setup with the structure of the installed preconditioner:
+    permutation, per-level blocks, ILU factors, E_l and F_l as the library's
+    host stages produced them (gs_get_level; the host ILU equals the oracle's
+    bit for bit), and seeded synthetic W_l, H_l of the same ranks (W_l with
+    orthonormal columns), so that no value computed on the GPU enters the
+    oracle.  Only the time of the oracle's apply on it is used."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
+    import scipy.sparse as sp
 
-    from paper_2205_03224_amd import workloads as wl
-    from oracle import gemslr as og, partition as opart
+    from oracle import gemslr as og
+    info = ctx.info()
+    L = info["nlevels"]
+    rng = np.random.default_rng(seed)
+    levels, start = [], 0
+    for l in range(L + 1):
+        lv = ctx.level(l)
+        d, s, k = lv["d"], lv["s"], lv["k"]
+        mk = lambda m, r, c: sp.csr_matrix((m[2], m[1], m[0]), shape=(r, c))
+        Lf, Uf = mk(lv["L"], d, d), mk(lv["U"], d, d)
+        E, F = mk(lv["E"], s, d), mk(lv["F"], d, s)
+        W = H = None
+        if l < L and k > 0:
+            W, _ = np.linalg.qr(rng.standard_normal((s, k)))
+            H = 0.1 * rng.standard_normal((k, k))
+        levels.append(og.Level(start, d, s, lv["block_ptr"],
+                               Lf, Uf, E, F, W=W, H=H))
+        start += d
+    return og.Setup(ctx.n, ctx.perm(), levels, None, True)
 
-    with threadpool_limits(limits=1):
-        w = wl.convdiff3d_64(N=32, nparts=8)
-        part = opart.wirebasket(w.dims, w.nparts, w.levels, w.rowptr, w.col)
-        st = og.setup(w.rowptr, w.col, w.val, part, ilu="ilut", drop_tol=1e-3, lfil=10,
-                      rank=32)
-        x = w.b
-        og.apply(st, x)
-        n_done = 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < seconds:
-            og.apply(st, x)
-            n_done += 1
-        dt = time.perf_counter() - t0
-    rate = n_done / dt
-    scale = w.n / float(128 ** 3)
-    return {"value": rate * scale, "unit": "applies/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle apply on the 32^3 convection-diffusion grid, 8 subdomains "
-                       f"(same ~16^3 box size), ILUT(1e-3,10), rank 32: {n_done} applies in "
-                       f"{dt:.1f} s on 1 thread = {rate:.2f}/s, scaled by n ratio {scale:.6f}")}
+
+def cpu_baseline(ctx, x, reps=2):
+    """The oracle's apply (oracle.gemslr.apply, unmodified) timed on the host
+    on the benchmark's own preconditioner structure (oracle_setup_like): a
+    bounded sample of `reps` full applies, once on one thread and once with
+    every host thread available to NumPy/SciPy."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import gemslr as og
+    st = oracle_setup_like(ctx)
+    res = {}
+    for label, limit in (("1", 1), ("all", None)):
+        with threadpool_limits(limits=limit):
+            used = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                og.apply(st, x)
+                ts.append(time.perf_counter() - t0)
+        res[label] = {"s_per_apply": float(np.median(ts)), "threads": int(used)}
+    try:
+        import subprocess
+        model = [ln.split(":", 1)[1].strip() for ln in subprocess.run(
+            ["lscpu"], capture_output=True, text=True).stdout.splitlines()
+            if ln.startswith("Model name")][0]
+    except Exception:
+        model = "unknown"
+    one, allc = res["1"], res["all"]
+    return {"value": 1.0 / one["s_per_apply"], "unit": "applies/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{reps} full oracle applies (oracle.gemslr.apply) on the benchmark's "
+                       f"128^3 preconditioner structure (library host-stage factors, E, F; "
+                       f"seeded W, H of the same ranks), median {one['s_per_apply']:.2f} s on 1 "
+                       f"thread; host {model}, os.cpu_count() {os.cpu_count()}"),
+            "all_threads": {"value": 1.0 / allc["s_per_apply"], "threads": allc["threads"],
+                            "s_per_apply": allc["s_per_apply"]},
+            "host_cpu": model, "host_cpu_count": os.cpu_count()}
+
+
+def copy_bandwidth(mib=1024, reps=10):
+    """Device-to-device copy of `mib` MiB with torch (read + write bytes / time)."""
+    import torch
+    src = torch.ones((mib << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2.0 * (mib << 20) / s / 1e9
+
+
+def timed_applies(ctx, b, K, warmup=10):
+    """K applies after `warmup`: us per apply and the level-0 trisolve launch
+    time and compulsory bytes from the library's probe (HIP events on its
+    stream)."""
+    import torch
+    y = torch.empty_like(b)
+    for _ in range(warmup):
+        ctx.apply(b, y)
+    torch.cuda.synchronize()
+    ctx.probe_enable(0, 2 * K + 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        ctx.apply(b, y)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, kms, kbytes = ctx.probe_read()
+    ctx.probe_enable(-1, 0)
+    k_ms = kms / max(launches, 1)
+    k_bytes = kbytes / max(launches, 1)
+    return dt * 1e6 / K, k_ms * 1e3, k_bytes
+
+
+def convdiff64(K, log):
+    """The 64^3 convection-diffusion configuration (n = 262,144, 64
+    subdomains of ~16^3, 3 levels, ILUT(1e-3, 10), rank 32): apply rate,
+    level-0 roofline and time to 1e-8 (low-rank setup + FGMRES(50))."""
+    import numpy as np
+    import torch
+
+    from paper_2205_03224_amd import gemslr, workloads as wl
+    w = wl.convdiff3d_64()
+    ctx = gemslr.Context(0)
+    ctx.setup(w.rowptr, w.col, w.val, w.levels, w.nparts, w.rank, w.drop_tol, lfil=w.lfil,
+              grid_dims=w.dims, fgmres_restart=w.restart)
+    info = ctx.info()
+    b = torch.from_numpy(w.b).cuda()
+    us, k_us, k_b = timed_applies(ctx, b, K)
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.solve(b, x, 1e-8)
+    ts = time.perf_counter() - t0
+    xh = x.cpu().numpy()
+    out = {"workload": "convdiff3d_64 (beta=0.1/h, 64 subdomains)", "n": w.n,
+           "us_per_apply": us, "applies_per_s": 1e6 / us, "apply_bytes": info["apply_bytes"],
+           "apply_GBps": info["apply_bytes"] / (us * 1e-6) / 1e9,
+           "level0_us_per_launch": k_us, "level0_GBps": k_b / (k_us * 1e-6) / 1e9,
+           "level0_frac": k_b / (k_us * 1e-6) / 1e9 / HBM_PEAK_GBPS,
+           "its": res["its"], "relres": res["relres"], "t_lowrank_s": info["t_lowrank"],
+           "t_solve_s": ts, "time_to_tol_s": info["t_lowrank"] + ts,
+           "err_vs_x_true": float(np.linalg.norm(xh - w.x_true) / np.linalg.norm(w.x_true))}
+    log(f"[bench] 64^3: {us:.1f} us/apply, level-0 {k_us:.1f} us ({out['level0_GBps']:.0f} GB/s); "
+        f"time to 1e-8 {out['time_to_tol_s']:.3f} s ({res['its']} its)")
+    ctx.close()
+    return out
 
 
 def helmholtz(N, K, log, ilu_shift=0.0):
@@ -253,6 +367,24 @@ def main():
         f"{multi['applies_per_s']:.0f} applies/s ({multi['speedup_vs_single']:.2f}x single)")
     del B2, Y2
 
+    # the float32 and bfloat16 storage forms of the same preconditioner:
+    # apply rate and level-0 trisolve roofline (factors, E, F, W stored in
+    # the narrow type, sweeps in float32)
+    mixed = {}
+    for prec in ("f32", "bf16"):
+        ctx.set_precision(prec)
+        us_m, k_us, k_b = timed_applies(ctx, b, K)
+        mixed[prec] = {"us_per_apply": us_m, "applies_per_s": 1e6 / us_m,
+                       "apply_bytes": ctx.info()["apply_bytes"],
+                       "level0_us_per_launch": k_us, "level0_bytes_per_launch": k_b,
+                       "level0_GBps": k_b / (k_us * 1e-6) / 1e9,
+                       "level0_frac": k_b / (k_us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
+        log(f"[bench] {prec} storage: {us_m:.1f} us/apply ({1e6 / us_m:.0f} applies/s); level-0 "
+            f"trisolve {k_us:.1f} us/launch, {mixed[prec]['level0_GBps']:.0f} GB/s")
+    ctx.set_precision("f64")
+    copy_gbps = copy_bandwidth()
+    log(f"[bench] device copy (torch, 1 GiB): {copy_gbps:.0f} GB/s read + write")
+
     if args.calibrate_copy:
         nel = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -280,6 +412,8 @@ def main():
                    "ilu": f"ILUT({w.drop_tol},{w.lfil})", "parallelism": "single GPU"},
         "apply_GBps": apply_bytes / (ms_per_apply * 1e-3) / 1e9,
         "multi_rhs": multi,
+        "mixed_storage": mixed,
+        "copy_GBps_measured": copy_gbps,
         "apply_bytes": apply_bytes,
         "apply_distribution": dist,
         "setup": {"total_s": setup_s, "partition_s": info["t_partition"],
@@ -325,7 +459,15 @@ def main():
             del x
         out["time_to_tol"] = forms
 
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on its bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(ctx, w.b)
+        log(f"[bench] cpu baseline: {out['cpu_baseline']['value']:.3f} applies/s on 1 thread, "
+            f"{out['cpu_baseline']['all_threads']['value']:.3f} on "
+            f"{out['cpu_baseline']['all_threads']['threads']} threads")
     ctx.close()
+    if not args.no_forms:
+        out["cfg2"] = convdiff64(args.steps, log)
     if not args.no_forms and not args.no_c128:
         out["c128"] = helmholtz(args.N, args.steps // 2, log)
         out["c128_shifted"] = helmholtz(args.N, args.steps // 2, log, ilu_shift=0.05)
@@ -344,10 +486,6 @@ def main():
         out["learned"]["workload"] = "lognormal_convdiff3d_64, held-out members 100000-100003"
         log(f"[bench] learned: {json.dumps(out['learned'])}")
         mlp.close()
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on its bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline()
-        log(f"[bench] cpu baseline {out['cpu_baseline']['value']:.4f} applies/s (scaled)")
     if breakdown is not None:
         out["breakdown"] = [{"label": s["label"], "us": round(s["ms"] * 1e3, 2),
                              "MB": round(s["bytes"] / 1e6, 3)} for s in breakdown]

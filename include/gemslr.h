@@ -189,6 +189,36 @@ int gs_setup_explicit(gs_ctx* ctx, int64_t n, const int64_t* rowptr,
                       const int32_t* col, const void* val, int dtype,
                       const int64_t* perm, int nlevels,
                       const gs_level_data* levels, const gs_opts* opts);
+/* On a host-only context (gs_create with device < 0) gs_setup_explicit keeps
+ * the host copy only: gs_export, gs_get_level*, gs_get_perm and gs_get_info
+ * work; apply, solve and precision changes return GS_ESTATE. */
+
+/* Write the installed preconditioner -- the setup product of Alg. 1: A, the
+ * permutation and, per level, the block partition, the ILU factors L_l and
+ * U_l, E_l, F_l, W_l and H_l -- to the host file `path` (created or
+ * truncated).  Layout, little endian ("value": 8 bytes for GS_F64, 16 for
+ * GS_C128 as interleaved re, im; a CSR block is int64 nnz, int64
+ * rowptr[rows + 1], int32 col[nnz], value val[nnz]; all numbering as in
+ * gs_level_data):
+ *   char[8] "GEMSLR01", int32 dtype, int32 nlevels L, int64 n,
+ *   CSR A (n rows, original numbering), int64 perm[n],
+ *   for l = 0 .. L: int64 d, int64 nblocks, int64 block_ptr[nblocks + 1],
+ *     CSR L_l (d rows), CSR U_l (d rows), then for l < L (s = n - start_l
+ *     - d): CSR E_l (s rows), CSR F_l (d rows), int32 k, int32 0,
+ *     value W_l[s*k], value H_l[k*k] (both column-major),
+ *   char[8] "GEMSLREN".
+ * Works on device and host-only contexts.  Errors: GS_ESTATE (no setup),
+ * GS_EINVAL (NULL path, file not writable or a write failed). */
+int gs_export(const gs_ctx* ctx, const char* path);
+
+/* Install the preconditioner of a file written by gs_export, exactly as
+ * gs_setup_explicit of its contents (so applies equal those of the exporting
+ * context bit for bit in the same storage precision); opts as for
+ * gs_setup_explicit (NULL: keep the context's options).  A previous setup is
+ * released.  Errors: GS_EINVAL (unreadable file, bad magic or end marker,
+ * truncated or inconsistent contents -- every array is validated as in
+ * gs_setup_explicit), GS_EDEVICE, GS_ENOMEM. */
+int gs_import(gs_ctx* ctx, const char* path, const gs_opts* opts);
 
 /* Change the storage precision of the installed preconditioner (GS_PREC_*):
  * the factors, E, F and W are re-uploaded from the host copy.  FGMRES,
@@ -206,12 +236,15 @@ int gs_apply(gs_ctx* ctx, const void* x, void* y);
 
 /* Same as gs_apply for `nrhs` vectors stored one after another
  * (x + j*n, y + j*n), device memory, x and y not overlapping.  Vectors go in
- * pairs: each level's triangular sweep handles both in one launch, reading
- * the factor entries once for the two (several right-hand sides per factor
- * pass, named as future work in Sec. 6); an odd last vector, and forms
- * without the pair sweep (complex128, or with inner GMRES steps), go one at
- * a time.  Every column equals gs_apply of that column.  Errors as
- * gs_apply. */
+ * pairs.  On levels where the two block vectors and the chunk buffers still
+ * let every workgroup of the level be resident (the grouped small blocks of
+ * levels >= 1 here), one sweep launch handles both and reads the factor
+ * entries once for the two (several right-hand sides per factor pass, named
+ * as future work in Sec. 6); elsewhere -- in particular the 3,375 - 4,096-row
+ * blocks of level 0 of the 128^3 workloads -- the pair runs as two single
+ * sweeps.  An odd last vector, and forms without the pair sweep
+ * (complex128, or with inner GMRES steps), go one at a time.  Every column
+ * equals gs_apply of that column.  Errors as gs_apply. */
 int gs_apply_many(gs_ctx* ctx, int nrhs, const void* x, void* y);
 
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -769,26 +770,8 @@ static int fgmres(gs_ctx* c, const void* b_user, void* x_user, double tol, gs_in
 
 // ------------------------------------------------------------ setup helpers
 template <class T>
-static void finish_setup(gs_ctx* c) {
+static void host_stats(gs_ctx* c) {
   HostSetup<T>& S = host<T>(c);
-  using DT = typename DevOf<T>::type;
-  // permuted A for the solver
-  c->amem = std::make_unique<DevMem>();
-  const CSR<T>& Ap = S.Ap;
-  std::vector<int32_t> rp(Ap.rp.begin(), Ap.rp.end());
-  std::vector<int32_t> p32(S.perm.begin(), S.perm.end());
-  c->a_rp = c->amem->alloc<int32_t>(rp.size());
-  c->a_ci = c->amem->alloc<int32_t>(Ap.ci.size());
-  c->a_v = c->amem->alloc<DT>(Ap.v.size());
-  c->perm = c->amem->alloc<int32_t>(p32.size());
-  HIPCHK(hipMemcpyAsync(c->a_rp, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(c->a_ci, Ap.ci.data(), Ap.ci.size() * 4, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(c->a_v, Ap.v.data(), Ap.v.size() * sizeof(DT), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(c->perm, p32.data(), p32.size() * 4, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  c->wmem.reset();
-  c->w_m = -1;
-  // statistics
   gs_info& I = c->info;
   I.nlevels = S.L();
   I.nnz_lu = 0;
@@ -810,6 +793,36 @@ static void finish_setup(gs_ctx* c) {
   }
   I.fill = (double)I.nnz_lu / (double)std::max<int64_t>(1, I.nnz_a);
   I.fill_lowrank = ((double)I.nnz_lu + lr) / (double)std::max<int64_t>(1, I.nnz_a);
+}
+
+template <class T>
+static void finish_setup(gs_ctx* c) {
+  HostSetup<T>& S = host<T>(c);
+  using DT = typename DevOf<T>::type;
+  if (c->device < 0) {
+    // host-only context: the host copy only (export, inspection)
+    host_stats<T>(c);
+    c->ready = true;
+    return;
+  }
+  // permuted A for the solver
+  c->amem = std::make_unique<DevMem>();
+  const CSR<T>& Ap = S.Ap;
+  std::vector<int32_t> rp(Ap.rp.begin(), Ap.rp.end());
+  std::vector<int32_t> p32(S.perm.begin(), S.perm.end());
+  c->a_rp = c->amem->alloc<int32_t>(rp.size());
+  c->a_ci = c->amem->alloc<int32_t>(Ap.ci.size());
+  c->a_v = c->amem->alloc<DT>(Ap.v.size());
+  c->perm = c->amem->alloc<int32_t>(p32.size());
+  HIPCHK(hipMemcpyAsync(c->a_rp, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->a_ci, Ap.ci.data(), Ap.ci.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->a_v, Ap.v.data(), Ap.v.size() * sizeof(DT), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->perm, p32.data(), p32.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->wmem.reset();
+  c->w_m = -1;
+  host_stats<T>(c);
+  gs_info& I = c->info;
   c->eng->stats(&I, 0);
   I.apply_bytes = c->eng->bytes_per_apply();
   c->ready = true;
@@ -950,10 +963,175 @@ static void setup_explicit(gs_ctx* c, int64_t n, const int64_t* rp, const int32_
   }
   if (std::is_same<T, double>::value) c->hd.reset((HostSetup<double>*)S.release());
   else c->hz.reset((HostSetup<cplx>*)S.release());
-  c->eng = make_engine(host<T>(c), c->precision, c->stream);
-  c->eng->set_inner(c->opts.inner_gmres_its);
+  if (c->device >= 0) {
+    c->eng = make_engine(host<T>(c), c->precision, c->stream);
+    c->eng->set_inner(c->opts.inner_gmres_its);
+  }
   c->info = gs_info{};
   finish_setup<T>(c);
+}
+
+// ------------------------------------------------------------ export / import
+// File layout (little endian; "value" is 8 bytes for GS_F64, 16 for GS_C128
+// as interleaved re, im; a CSR block is int64 nnz, int64 rowptr[rows + 1],
+// int32 col[nnz], value val[nnz]):
+//   char[8] "GEMSLR01", int32 dtype, int32 nlevels L, int64 n
+//   CSR A (n rows, original numbering), int64 perm[n]
+//   for l = 0 .. L: int64 d, int64 nblocks, int64 block_ptr[nblocks + 1],
+//     CSR L_l (d rows), CSR U_l (d rows), and for l < L with
+//     s = n - start_l - d: CSR E_l (s rows), CSR F_l (d rows), int32 k,
+//     int32 0, value W_l[s k] (column-major), value H_l[k k] (column-major)
+//   char[8] "GEMSLREN"
+static const char kExportMagic[8] = {'G', 'E', 'M', 'S', 'L', 'R', '0', '1'};
+static const char kExportEnd[8] = {'G', 'E', 'M', 'S', 'L', 'R', 'E', 'N'};
+
+struct FileW {
+  FILE* f;
+  void put(const void* p, size_t n) {
+    if (n && std::fwrite(p, 1, n, f) != n) throw Error(GS_EINVAL, "export: write failed");
+  }
+  template <class U> void put1(U v) { put(&v, sizeof(U)); }
+};
+struct FileR {
+  FILE* f;
+  void get(void* p, size_t n) {
+    if (n && std::fread(p, 1, n, f) != n) throw Error(GS_EINVAL, "import: file truncated");
+  }
+  template <class U> U get1() {
+    U v;
+    get(&v, sizeof(U));
+    return v;
+  }
+};
+
+template <class T>
+static void put_csr(FileW& w, const CSR<T>& m, int64_t rows) {
+  if ((int64_t)m.rp.size() != rows + 1) throw Error(GS_EINVAL, "export: inconsistent CSR");
+  w.put1<int64_t>(m.nnz());
+  w.put(m.rp.data(), m.rp.size() * sizeof(int64_t));
+  w.put(m.ci.data(), m.ci.size() * sizeof(int32_t));
+  w.put((const void*)m.v.data(), m.v.size() * sizeof(T));
+}
+
+template <class T>
+static void export_setup(const HostSetup<T>& S, int dtype, const char* path) {
+  FILE* f = std::fopen(path, "wb");
+  if (!f) throw Error(GS_EINVAL, std::string("export: cannot open ") + path);
+  std::unique_ptr<FILE, int (*)(FILE*)> guard(f, std::fclose);
+  FileW w{f};
+  w.put(kExportMagic, 8);
+  w.put1<int32_t>(dtype);
+  w.put1<int32_t>(S.L());
+  w.put1<int64_t>(S.n);
+  put_csr(w, S.A, S.n);
+  w.put(S.perm.data(), S.perm.size() * sizeof(int64_t));
+  for (int l = 0; l <= S.L(); ++l) {
+    const HostLevel<T>& h = S.lv[l];
+    w.put1<int64_t>(h.d);
+    w.put1<int64_t>((int64_t)h.blocks.size() - 1);
+    w.put(h.blocks.data(), h.blocks.size() * sizeof(int64_t));
+    put_csr(w, h.L, h.d);
+    put_csr(w, h.U, h.d);
+    if (l < S.L()) {
+      put_csr(w, h.E, h.s);
+      put_csr(w, h.F, h.d);
+      w.put1<int32_t>(h.k);
+      w.put1<int32_t>(0);
+      w.put((const void*)h.W.data(), h.W.size() * sizeof(T));
+      w.put((const void*)h.H.data(), h.H.size() * sizeof(T));
+    }
+  }
+  w.put(kExportEnd, 8);
+  // fclose flushes: report a failure there as well
+  if (std::fclose(guard.release()) != 0) throw Error(GS_EINVAL, "export: write failed");
+}
+
+// Arrays of one CSR block read from a file (validated by setup_explicit).
+template <class T>
+struct CsrBuf {
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<T> v;
+  void read(FileR& r, int64_t rows, int64_t limit) {
+    const int64_t nnz = r.get1<int64_t>();
+    if (rows < 0 || nnz < 0 || nnz > limit) throw Error(GS_EINVAL, "import: bad CSR size");
+    rp.resize((size_t)rows + 1);
+    r.get(rp.data(), rp.size() * sizeof(int64_t));
+    if (rp[0] != 0 || rp[(size_t)rows] != nnz) throw Error(GS_EINVAL, "import: bad row pointers");
+    for (int64_t i = 0; i < rows; ++i)
+      if (rp[i + 1] < rp[i]) throw Error(GS_EINVAL, "import: bad row pointers");
+    ci.resize((size_t)nnz);
+    r.get(ci.data(), ci.size() * sizeof(int32_t));
+    v.resize((size_t)nnz);
+    r.get((void*)v.data(), v.size() * sizeof(T));
+  }
+};
+
+template <class T>
+static void import_setup(gs_ctx* c, const char* path) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) throw Error(GS_EINVAL, std::string("import: cannot open ") + path);
+  std::unique_ptr<FILE, int (*)(FILE*)> guard(f, std::fclose);
+  FileR r{f};
+  char magic[8];
+  r.get(magic, 8);
+  if (std::memcmp(magic, kExportMagic, 8) != 0) throw Error(GS_EINVAL, "import: not a gs_export file");
+  (void)r.get1<int32_t>();  // dtype, checked by the caller
+  const int32_t L = r.get1<int32_t>();
+  const int64_t n = r.get1<int64_t>();
+  if (n <= 0 || L < 0 || L > GS_MAX_LEVELS) throw Error(GS_EINVAL, "import: bad header");
+  // no array can hold more entries than the file has bytes
+  std::fseek(f, 0, SEEK_END);
+  const int64_t fsize = (int64_t)std::ftell(f);
+  std::fseek(f, 24, SEEK_SET);
+  if (n > fsize) throw Error(GS_EINVAL, "import: bad header");
+  CsrBuf<T> A;
+  A.read(r, n, fsize);
+  std::vector<int64_t> perm((size_t)n);
+  r.get(perm.data(), perm.size() * sizeof(int64_t));
+  std::vector<std::vector<int64_t>> bp(L + 1);
+  std::vector<CsrBuf<T>> Lf(L + 1), Uf(L + 1), Ef(L + 1), Ff(L + 1);
+  std::vector<std::vector<T>> W(L + 1), H(L + 1);
+  std::vector<gs_level_data> lv(L + 1);
+  int64_t start = 0;
+  for (int l = 0; l <= L; ++l) {
+    gs_level_data& a = lv[l];
+    std::memset(&a, 0, sizeof(a));
+    a.d = r.get1<int64_t>();
+    a.nblocks = r.get1<int64_t>();
+    if (a.d < 0 || a.d > n - start || a.nblocks < 0 || a.nblocks > fsize)
+      throw Error(GS_EINVAL, "import: bad level sizes");
+    bp[l].resize((size_t)a.nblocks + 1);
+    r.get(bp[l].data(), bp[l].size() * sizeof(int64_t));
+    a.block_ptr = bp[l].data();
+    Lf[l].read(r, a.d, fsize);
+    Uf[l].read(r, a.d, fsize);
+    a.l_rowptr = Lf[l].rp.data(); a.l_col = Lf[l].ci.data(); a.l_val = Lf[l].v.data();
+    a.u_rowptr = Uf[l].rp.data(); a.u_col = Uf[l].ci.data(); a.u_val = Uf[l].v.data();
+    const int64_t sl = n - start - a.d;
+    if (l < L) {
+      Ef[l].read(r, sl, fsize);
+      Ff[l].read(r, a.d, fsize);
+      a.e_rowptr = Ef[l].rp.data(); a.e_col = Ef[l].ci.data(); a.e_val = Ef[l].v.data();
+      a.f_rowptr = Ff[l].rp.data(); a.f_col = Ff[l].ci.data(); a.f_val = Ff[l].v.data();
+      a.k = r.get1<int32_t>();
+      (void)r.get1<int32_t>();
+      if (a.k < 0 || a.k > sl || (int64_t)a.k * sl > fsize) throw Error(GS_EINVAL, "import: bad rank");
+      W[l].resize((size_t)sl * a.k);
+      H[l].resize((size_t)a.k * a.k);
+      r.get((void*)W[l].data(), W[l].size() * sizeof(T));
+      r.get((void*)H[l].data(), H[l].size() * sizeof(T));
+      a.w = W[l].data();
+      a.h = H[l].data();
+    }
+    start += a.d;
+  }
+  char end[8];
+  r.get(end, 8);
+  if (std::memcmp(end, kExportEnd, 8) != 0) throw Error(GS_EINVAL, "import: bad end marker");
+  guard.reset();
+  validate_csr(n, A.rp.data(), A.ci.data(), false);
+  setup_explicit<T>(c, n, A.rp.data(), A.ci.data(), A.v.data(), perm.data(), L, lv.data());
 }
 
 
@@ -1263,8 +1441,8 @@ int gs_setup_explicit(gs_ctx* c, int64_t n, const int64_t* rowptr, const int32_t
                       const gs_level_data* levels, const gs_opts* opts) {
   if (!c) return GS_EINVAL;
   GS_GUARD(c, {
-    int r = need_device(c);
-    if (r) return r;
+    // a host-only context keeps the host copy (export and inspection only)
+    if (c->device >= 0) hipcheck(hipSetDevice(c->device), "hipSetDevice");
     if (opts) c->opts = *opts;
     if (dtype != GS_F64 && dtype != GS_C128) throw Error(GS_EINVAL, "dtype must be GS_F64 or GS_C128");
     if (!perm || !levels || !val) throw Error(GS_EINVAL, "NULL argument");
@@ -1559,6 +1737,47 @@ int gs_get_perm(const gs_ctx* c, int64_t* perm) {
   const std::vector<int64_t>& p = c->dtype == GS_F64 ? c->hd->perm : c->hz->perm;
   std::copy(p.begin(), p.end(), perm);
   return GS_OK;
+}
+
+int gs_export(const gs_ctx* c, const char* path) {
+  if (!c) return GS_EINVAL;
+  gs_ctx* cc = const_cast<gs_ctx*>(c);
+  GS_GUARD(cc, {
+    if (!c->ready) throw Error(GS_ESTATE, "export before setup");
+    if (!path) throw Error(GS_EINVAL, "NULL path");
+    if (c->dtype == GS_F64) export_setup(*c->hd, GS_F64, path);
+    else export_setup(*c->hz, GS_C128, path);
+    return GS_OK;
+  });
+}
+
+int gs_import(gs_ctx* c, const char* path, const gs_opts* opts) {
+  if (!c) return GS_EINVAL;
+  GS_GUARD(c, {
+    if (!path) throw Error(GS_EINVAL, "NULL path");
+    if (c->device >= 0) hipcheck(hipSetDevice(c->device), "hipSetDevice");
+    int32_t dtype = -1;
+    {
+      FILE* f = std::fopen(path, "rb");
+      if (!f) throw Error(GS_EINVAL, std::string("import: cannot open ") + path);
+      char magic[8];
+      const bool ok = std::fread(magic, 1, 8, f) == 8 && std::fread(&dtype, 4, 1, f) == 1;
+      std::fclose(f);
+      if (!ok || std::memcmp(magic, kExportMagic, 8) != 0)
+        throw Error(GS_EINVAL, "import: not a gs_export file");
+    }
+    if (dtype != GS_F64 && dtype != GS_C128) throw Error(GS_EINVAL, "import: bad dtype");
+    if (opts) c->opts = *opts;
+    c->ready = false;
+    c->eng.reset();
+    c->hd.reset();
+    c->hz.reset();
+    c->dtype = dtype;
+    c->precision = c->opts.precision;
+    if (dtype == GS_F64) import_setup<double>(c, path);
+    else import_setup<cplx>(c, path);
+    return GS_OK;
+  });
 }
 
 }  // extern "C"

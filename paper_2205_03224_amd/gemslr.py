@@ -127,6 +127,8 @@ SIGNATURES = [
     ("gs_mlp_set_params", ct.c_int, [_p, _p]),
     ("gs_mlp_get_params", ct.c_int, [_p, _p]),
     ("gs_mlp_get_grads", ct.c_int, [_p, _p]),
+    ("gs_export", ct.c_int, [_p, ct.c_char_p]),
+    ("gs_import", ct.c_int, [_p, ct.c_char_p, _p]),
     ("gs_mlp_zero_grad", ct.c_int, [_p]),
     ("gs_mlp_forward", ct.c_int, [_p, _p, ct.c_int64, _p]),
     ("gs_mlp_loss_backward", ct.c_int, [_p, _p, _p, ct.c_int64, ct.c_int,
@@ -279,6 +281,21 @@ class Context:
         self._check(lib().gs_setup_explicit(self._h, self.n, _ptr(rp), _ptr(ci), _ptr(v),
                                             self.dtype, _ptr(p), len(levels) - 1, arr,
                                             ct.byref(o)))
+        return self
+
+    def export(self, path):
+        """gs_export: write the installed preconditioner to `path`."""
+        self._check(lib().gs_export(self._h, os.fsencode(path)))
+
+    def import_setup(self, path, **kw):
+        """gs_import: install the preconditioner of a gs_export file."""
+        o = opts(**kw)
+        self._check(lib().gs_import(self._h, os.fsencode(path), ct.byref(o)))
+        with open(path, "rb") as f:
+            head = f.read(24)
+        dtype = int(np.frombuffer(head[8:12], dtype="<i4")[0])
+        self.n = int(np.frombuffer(head[16:24], dtype="<i8")[0])
+        self.dtype = dtype
         return self
 
     def set_precision(self, precision):
@@ -552,38 +569,11 @@ def unpack_params(flat, dims):
 
 
 # ---------------------------------------------------------------- checkpoint
-def save_setup(ctx, path, rowptr, col, val):
-    """Write the installed preconditioner (permutation, per-level factors,
-    E, F, W, H) and A to an .npz file; load_setup restores it bit for bit."""
-    info = ctx.info()
-    L = info["nlevels"]
-    arrs = {"n": ctx.n, "nlevels": L, "perm": ctx.perm(), "rowptr": np.asarray(rowptr),
-            "col": np.asarray(col), "val": np.asarray(val)}
-    for l in range(L + 1):
-        lv = ctx.level(l)
-        arrs[f"l{l}_d"] = lv["d"]
-        arrs[f"l{l}_block_ptr"] = lv["block_ptr"]
-        for name in ("L", "U", "E", "F"):
-            for j, part in enumerate(("rowptr", "col", "val")):
-                arrs[f"l{l}_{name}_{part}"] = lv[name][j]
-        arrs[f"l{l}_W"] = lv["W"]
-        arrs[f"l{l}_H"] = lv["H"]
-    np.savez(path, **arrs)
+def save_setup(ctx, path):
+    """Write the installed preconditioner to `path` (gs_export)."""
+    ctx.export(path)
 
 
 def load_setup(path, device=0, **opts_kw):
-    z = np.load(path)
-    L = int(z["nlevels"])
-    levels = []
-    for l in range(L + 1):
-        d = {"d": int(z[f"l{l}_d"]), "block_ptr": z[f"l{l}_block_ptr"]}
-        for name in ("L", "U"):
-            d[name] = tuple(z[f"l{l}_{name}_{p}"] for p in ("rowptr", "col", "val"))
-        if l < L:
-            for name in ("E", "F"):
-                d[name] = tuple(z[f"l{l}_{name}_{p}"] for p in ("rowptr", "col", "val"))
-            d["W"], d["H"] = z[f"l{l}_W"], z[f"l{l}_H"]
-        levels.append(d)
-    ctx = Context(device)
-    ctx.setup_explicit(z["rowptr"], z["col"], z["val"], z["perm"], levels, **opts_kw)
-    return ctx
+    """A context holding the preconditioner of a gs_export file (gs_import)."""
+    return Context(device).import_setup(path, **opts_kw)

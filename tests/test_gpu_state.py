@@ -29,12 +29,38 @@ def test_apply_is_deterministic_and_checkpoint_roundtrips(torch_dev, tmp_path):
     torch.cuda.synchronize()
     # no floating-point atomics anywhere: repeated applies agree bit for bit
     assert torch.equal(y1, y2)
-    path = str(tmp_path / "setup.npz")
-    gemslr.save_setup(ctx, path, w.rowptr, w.col, w.val)
-    ctx2 = gemslr.load_setup(path)
+    # gs_export / gs_import: the imported preconditioner applies bit for bit
+    # like the exporting one, and solves the same way
+    path = str(tmp_path / "setup.gslr")
+    ctx.export(path)
+    ctx2 = gemslr.Context(0).import_setup(path, fgmres_restart=w.restart)
     y3 = torch.empty_like(b)
     ctx2.apply(b, y3)
     torch.cuda.synchronize()
     assert torch.equal(y1, y3)
+    x1, x2 = torch.zeros_like(b), torch.zeros_like(b)
+    i1 = ctx.solve(b, x1, 1e-8)
+    i2 = ctx2.solve(b, x2, 1e-8)
+    assert i1["its"] == i2["its"] and torch.equal(x1, x2)
+    ctx.close()
+    ctx2.close()
+
+
+def test_export_import_complex_bit_equal(torch_dev, tmp_path):
+    torch = torch_dev
+    from paper_2205_03224_amd import gemslr
+    w = wl.helmholtz3d_128(N=12, nparts=8)
+    ctx = gemslr.Context(0)
+    ctx.setup(w.rowptr, w.col, w.val, w.levels, w.nparts, 8, w.drop_tol, lfil=10,
+              grid_dims=w.dims)
+    path = str(tmp_path / "h.gslr")
+    ctx.export(path)
+    ctx2 = gemslr.load_setup(path)
+    b = torch.from_numpy(w.b).cuda()
+    y1, y2 = torch.empty_like(b), torch.empty_like(b)
+    ctx.apply(b, y1)
+    ctx2.apply(b, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
     ctx.close()
     ctx2.close()
