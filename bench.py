@@ -261,6 +261,9 @@ def main():
     ap.add_argument("--no-c128", action="store_true",
                     help="skip the complex Helmholtz apply rate and time to tolerance")
     ap.add_argument("--breakdown", action="store_true", help="print per-launch profile")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed applies (no distribution, several right-hand sides, "
+                         "mixed storage or copy measurement): for profiler runs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a MIB-sized float64 buffer once (a plain "
                          "copy kernel of known traffic for counter calibration)")
@@ -320,70 +323,78 @@ def main():
         f"{apply_bytes / (ms_per_apply * 1e-3) / 1e9:.0f} GB/s; level-0 trisolve "
         f"{k_ms * 1e3:.1f} us/launch, {achieved:.0f} GB/s ({launches} launches)")
 
-    # per-apply distribution with events on the library's stream (torch's
-    # current stream): warm = back-to-back applies on one setup; cold = a
-    # 1 GiB buffer written between applies, which evicts the 256 MiB
-    # last-level cache, so every factor byte comes from HBM
-    def distribution(reps, flush=None):
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(reps)]
-        for e0, e1 in ev:
-            if flush is not None:
-                flush.fill_(1.0)
-            e0.record()
-            ctx.apply(b, y)
-            e1.record()
-        torch.cuda.synchronize()
-        us = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev])
-        return {"median_us": float(np.median(us)), "p10_us": float(np.percentile(us, 10)),
-                "p90_us": float(np.percentile(us, 90)), "reps": reps}
+    dist, multi, mixed, copy_gbps = None, None, None, None
+    if not args.no_extras:
+        # per-apply distribution with events on the library's stream (torch's
+        # current stream): warm = back-to-back applies on one setup; cold = a
+        # 1 GiB buffer written between applies, which evicts the 256 MiB
+        # last-level cache, so every factor byte comes from HBM
+        def distribution(reps, flush=None):
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            for e0, e1 in ev:
+                if flush is not None:
+                    flush.fill_(1.0)
+                e0.record()
+                ctx.apply(b, y)
+                e1.record()
+            torch.cuda.synchronize()
+            us = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in ev])
+            return {"median_us": float(np.median(us)), "p10_us": float(np.percentile(us, 10)),
+                    "p90_us": float(np.percentile(us, 90)), "reps": reps}
 
-    dist = {"warm": distribution(100)}
-    flush = torch.empty((1 << 30) // 8, dtype=torch.float64, device="cuda")
-    dist["cold"] = distribution(50, flush)
-    del flush
-    for key in ("warm", "cold"):
-        d = dist[key]
-        d["GBps_at_median"] = apply_bytes / (d["median_us"] * 1e-6) / 1e9
-        log(f"[bench] {key}: median {d['median_us']:.1f} us (p10 {d['p10_us']:.1f}, "
-            f"p90 {d['p90_us']:.1f}), {d['GBps_at_median']:.0f} GB/s")
+        dist = {"warm": distribution(100)}
+        flush = torch.empty((1 << 30) // 8, dtype=torch.float64, device="cuda")
+        dist["cold"] = distribution(50, flush)
+        del flush
+        for key in ("warm", "cold"):
+            d = dist[key]
+            d["GBps_at_median"] = apply_bytes / (d["median_us"] * 1e-6) / 1e9
+            log(f"[bench] {key}: median {d['median_us']:.1f} us (p10 {d['p10_us']:.1f}, "
+                f"p90 {d['p90_us']:.1f}), {d['GBps_at_median']:.0f} GB/s")
 
-    # two right-hand sides per apply (gs_apply_many): each level's sweep
-    # reads the factor entries once for both vectors
-    B2 = torch.stack([b, torch.flip(b, [0])])
-    Y2 = torch.empty_like(B2)
-    for _ in range(3):
-        ctx.apply_many(2, B2, Y2)
-    torch.cuda.synchronize()
-    kp = max(K // 2, 1)
-    t0 = time.perf_counter()
-    for _ in range(kp):
-        ctx.apply_many(2, B2, Y2)
-    torch.cuda.synchronize()
-    us_pair = (time.perf_counter() - t0) * 1e6 / kp
-    multi = {"nrhs": 2, "us_per_call": us_pair, "applies_per_s": 2e6 / us_pair,
-             "speedup_vs_single": (2e6 / us_pair) / applies_per_s, "calls": kp}
-    log(f"[bench] 2 right-hand sides per apply: {us_pair:.1f} us per call, "
-        f"{multi['applies_per_s']:.0f} applies/s ({multi['speedup_vs_single']:.2f}x single)")
-    del B2, Y2
+        # several right-hand sides per call (gs_apply_many): two share each
+        # level's sweep launch (factor entries read once for both); three or
+        # more go through launches covering all of them at every step
+        multi = {}
+        for nb_ in (2, 4, 8):
+            Bm = torch.stack([torch.roll(b, 7919 * j) for j in range(nb_)])
+            Ym = torch.empty_like(Bm)
+            for _ in range(3):
+                ctx.apply_many(nb_, Bm, Ym)
+            torch.cuda.synchronize()
+            kp = max(K // nb_, 4)
+            t0 = time.perf_counter()
+            for _ in range(kp):
+                ctx.apply_many(nb_, Bm, Ym)
+            torch.cuda.synchronize()
+            us_call = (time.perf_counter() - t0) * 1e6 / kp
+            multi[str(nb_)] = {"nrhs": nb_, "us_per_call": us_call,
+                               "applies_per_s": nb_ * 1e6 / us_call,
+                               "speedup_vs_single": (nb_ * 1e6 / us_call) / applies_per_s,
+                               "calls": kp}
+            log(f"[bench] {nb_} right-hand sides per call: {us_call:.1f} us per call, "
+                f"{multi[str(nb_)]['applies_per_s']:.0f} applies/s "
+                f"({multi[str(nb_)]['speedup_vs_single']:.2f}x single)")
+            del Bm, Ym
 
-    # the float32 and bfloat16 storage forms of the same preconditioner:
-    # apply rate and level-0 trisolve roofline (factors, E, F, W stored in
-    # the narrow type, sweeps in float32)
-    mixed = {}
-    for prec in ("f32", "bf16"):
-        ctx.set_precision(prec)
-        us_m, k_us, k_b = timed_applies(ctx, b, K)
-        mixed[prec] = {"us_per_apply": us_m, "applies_per_s": 1e6 / us_m,
-                       "apply_bytes": ctx.info()["apply_bytes"],
-                       "level0_us_per_launch": k_us, "level0_bytes_per_launch": k_b,
-                       "level0_GBps": k_b / (k_us * 1e-6) / 1e9,
-                       "level0_frac": k_b / (k_us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
-        log(f"[bench] {prec} storage: {us_m:.1f} us/apply ({1e6 / us_m:.0f} applies/s); level-0 "
-            f"trisolve {k_us:.1f} us/launch, {mixed[prec]['level0_GBps']:.0f} GB/s")
-    ctx.set_precision("f64")
-    copy_gbps = copy_bandwidth()
-    log(f"[bench] device copy (torch, 1 GiB): {copy_gbps:.0f} GB/s read + write")
+        # the float32 and bfloat16 storage forms of the same preconditioner:
+        # apply rate and level-0 trisolve roofline (factors, E, F, W stored in
+        # the narrow type, sweeps in float32)
+        mixed = {}
+        for prec in ("f32", "bf16"):
+            ctx.set_precision(prec)
+            us_m, k_us, k_b = timed_applies(ctx, b, K)
+            mixed[prec] = {"us_per_apply": us_m, "applies_per_s": 1e6 / us_m,
+                           "apply_bytes": ctx.info()["apply_bytes"],
+                           "level0_us_per_launch": k_us, "level0_bytes_per_launch": k_b,
+                           "level0_GBps": k_b / (k_us * 1e-6) / 1e9,
+                           "level0_frac": k_b / (k_us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
+            log(f"[bench] {prec} storage: {us_m:.1f} us/apply ({1e6 / us_m:.0f} applies/s); level-0 "
+                f"trisolve {k_us:.1f} us/launch, {mixed[prec]['level0_GBps']:.0f} GB/s")
+        ctx.set_precision("f64")
+        copy_gbps = copy_bandwidth()
+        log(f"[bench] device copy (torch, 1 GiB): {copy_gbps:.0f} GB/s read + write")
 
     if args.calibrate_copy:
         nel = args.calibrate_copy * (1 << 20) // 8

@@ -83,6 +83,12 @@ typedef struct {
                              mean over A's diagonal (Sec. 5, Helmholtz: the
                              paper uses s = 0.05); complex A only; E, F and
                              the Schur products keep A unshifted         [0]  */
+  int warm_start;         /* gs_lowrank with starting bases Y_l: 0 = block
+                             Rayleigh-Ritz iteration from span(Y_l); 1 =
+                             the thick-restart Arnoldi of Sec. 2.3 started
+                             from v_0 = Y_l Y_l^T r (r the seeded start
+                             vector), a vector of the predicted subspace
+                                                                         [0]  */
 } gs_opts;
 
 /* Fill *opts with the defaults shown in brackets above. */
@@ -106,7 +112,9 @@ typedef struct {
   int32_t arnoldi_converged[GS_MAX_LEVELS + 1];
   int32_t lowrank_method[GS_MAX_LEVELS + 1]; /* 0 Arnoldi, 1 block iteration
                                                 from a given basis, 2 block
-                                                iteration then Arnoldi fallback */
+                                                iteration then Arnoldi fallback,
+                                                3 Arnoldi started in the span
+                                                of a given basis */
   int64_t nnz_lu;           /* sum of nnz(L)+nnz(U) incl. diagonals, all levels */
   int64_t nnz_ef;           /* sum of nnz(E_l)+nnz(F_l)                       */
   int64_t nnz_a;            /* nnz(A)                                         */

@@ -209,7 +209,7 @@ template <> cplx to_cplx<cplx>(const void* p, size_t i) { return ((const cplx*)p
 // Orthogonalisation and the basis are float64 / complex128 whatever the
 // storage precision of the factors used inside Ĝ_l.
 template <class T>
-static void lowrank_level(gs_ctx* c, int l, int kreq) {
+static void lowrank_level(gs_ctx* c, int l, int kreq, const float* Ystart = nullptr) {
   using DT = typename DevOf<T>::type;
   const bool real = std::is_same<T, double>::value;
   HostSetup<T>& S = host<T>(c);
@@ -240,6 +240,16 @@ static void lowrank_level(gs_ctx* c, int l, int kreq) {
   };
   const uint64_t seed = c->opts.seed + (uint64_t)l;
   upload_start(seed, V);
+  if (Ystart) {
+    // a start vector in the predicted subspace: v_0 = Y (Y^T r), Y the
+    // starting basis (s x k, row-major float32, device)
+    DT* Yc = tmp;  // s x k, column-major
+    launch_rows_to_cols<DT>(Ystart, s, k, kreq, Yc, s, st);
+    launch_multidot<DT>(Yc, s, k, V, s, part, hd, st);
+    launch_copy<DT>(V, w, s, st);
+    launch_fill<DT>(V, from_host<DT>(0.0), s, st);
+    launch_gemv_add<DT>(Yc, s, k, hd, V, s, st);
+  }
   launch_norm<DT>(V, s, npart, nrm, st);
   launch_scale_inv<DT>(V, nrm, V, s, st);
 
@@ -443,7 +453,16 @@ static bool lowrank_block(gs_ctx* c, int l, int kreq, const float* Y) {
     HIPCHK(hipStreamSynchronize(st));
   };
   // append column src to V if it keeps a relative norm > 1e-6 after two
-  // Gram-Schmidt passes against V; then its product with G
+  // Gram-Schmidt passes against V; its product with G is formed by flush,
+  // for all columns appended since the last flush in one batched product
+  int wg = 0;  // columns of V whose products G V are formed
+  auto flush = [&]() {
+    if (w > wg) {
+      c->eng->ghat_batch(l, w - wg, col(Sv, wg), col(GSv, wg));
+      nmv += w - wg;
+      wg = w;
+    }
+  };
   auto append = [&](const DT* src) -> bool {
     launch_copy<DT>(src, col(Sv, w), s, st);
     launch_norm<DT>(col(Sv, w), s, npart, nrm + 1, st);
@@ -454,13 +473,12 @@ static bool lowrank_block(gs_ctx* c, int l, int kreq, const float* Y) {
     HIPCHK(hipStreamSynchronize(st));
     if (!(nn[0] > 1e-6 * nn[1] && nn[0] > 0)) return false;
     launch_scale_inv<DT>(col(Sv, w), nrm, col(Sv, w), s, st);
-    c->eng->ghat(l, col(Sv, w), col(GSv, w));
-    ++nmv;
     ++w;
     return true;
   };
   // T and M entries that involve the columns [w0, w)
   auto extend_dots = [&](int w0) {
+    flush();
     if (w0 == w) return;
     for (int j = w0; j < w; ++j) {
       launch_multidot<DT>(Sv, s, w, col(GSv, j), s, part, Td + (size_t)j * cap, st);
@@ -623,6 +641,7 @@ static bool lowrank_block(gs_ctx* c, int l, int kreq, const float* Y) {
           A.swap(B);
         }
         w = k2;
+        wg = w;
       }
     }
     const int w0 = w;
@@ -1237,7 +1256,10 @@ static void lowrank_all(gs_ctx* c, int rank, const float* const* warm) {
       c->info.lowrank_method[l] = 0;
       continue;
     }
-    if (warm && warm[l]) {
+    if (warm && warm[l] && c->opts.warm_start == 1) {
+      method = 3;
+      lowrank_level<T>(c, l, rank, warm[l]);
+    } else if (warm && warm[l]) {
       method = 1;
       if (!lowrank_block<T>(c, l, rank, warm[l])) {
         const int used = h.arnoldi_matvecs;
@@ -1358,6 +1380,7 @@ void gs_opts_default(gs_opts* o) {
   o->block_max_iters = 8;
   o->inner_gmres_its = 0;
   o->ilu_shift = 0.0;
+  o->warm_start = 0;
 }
 
 int gs_create(gs_ctx** ctx, int device, void* stream) {
@@ -1497,6 +1520,11 @@ int gs_apply_many(gs_ctx* c, int nrhs, const void* x, void* y) {
     // sides per factor pass); an odd one out, or a form without the pair
     // path, goes alone
     int j = 0;
+    if (nrhs >= 3) {
+      // every launch of a level covers all vectors (vector = blockIdx.y)
+      c->eng->apply_batch(nrhs, xb, yb);
+      j = nrhs;
+    }
     for (; j + 1 < nrhs; j += 2) {
       const size_t o0 = (size_t)j * n * vb, o1 = o0 + (size_t)n * vb;
       if (!c->eng->apply_pair(xb + o0, xb + o1, yb + o0, yb + o1)) break;

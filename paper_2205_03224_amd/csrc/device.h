@@ -158,7 +158,6 @@ struct TriArgs {
   const int32_t* blk_chunk;  // nb+1 chunk ranges
   int32_t chunk_cap;         // max chunk bytes (multiple of 1 KiB)
   int32_t x_bytes;           // LDS bytes reserved for the block's vector (16-aligned)
-  int32_t nbuf;              // chunk buffers in LDS: 2 (one chunk in flight) or 3 (two)
   int32_t half_u;            // U chunks in half-row form: lanes l and l+32 share row l
   int32_t half_l;            // L chunks likewise
   // level 0 of an apply (streamed kernel only): DOWN reads its right-hand
@@ -185,6 +184,10 @@ struct TriArgs {
   const int32_t* funit = nullptr;
   int32_t fw = 0;
   int64_t nrec = 0;
+  // several vectors per launch (blockIdx.y = vector j): t and fy of vector
+  // j start at t + j * ldt and fy + j * ldfy
+  int32_t nvec = 1;
+  int64_t ldt = 0, ldfy = 0;
 };
 
 // LDS byte offset of the second block vector in two-right-hand-side sweeps:
@@ -215,6 +218,11 @@ struct IfArgs {
   // bytes of the workgroup's LDS (0: read them from global memory)
   int32_t stage_w = 1;
   int32_t max_lds = 65536;
+  // several vectors per launch (blockIdx.y = vector j): t, partial and
+  // tprime of vector j start at t + j * ldt, partial + j * ldpart and
+  // tprime + j * k
+  int32_t nvec = 1;
+  int64_t ldt = 0, ldpart = 0;
 };
 
 // ------------------------------------------------------------ launchers
@@ -235,7 +243,8 @@ template <class P> bool launch_interface_small(const IfArgs<P>& a, hipStream_t s
 template <class P> int interface_blocks(int64_t s);
 template <class P> void launch_lowrank_update(typename P::X* tc, int64_t s, int k,
                                               const typename P::V* W,
-                                              const typename P::C* tprime, hipStream_t st);
+                                              const typename P::C* tprime, hipStream_t st,
+                                              int nvec = 1, int64_t ldt = 0);
 template <class P> void launch_gather(const typename P::O* x, const int32_t* perm,
                                       typename P::X* t, int64_t n, hipStream_t st);
 template <class P> void launch_scatter(const typename P::X* t, const int32_t* perm,

@@ -54,6 +54,13 @@ struct Engine {
   virtual bool apply_pair(const void* x0, const void* x1, void* y0, void* y1) = 0;
   // out = Ĝ_l v (s_l entries each)
   virtual void ghat(int l, const void* v, void* out) = 0;
+  // the same for m vectors of s_l entries stored one after another, every
+  // launch of a level covering all m (columns equal those of ghat)
+  virtual void ghat_batch(int l, int m, const void* v, void* out) = 0;
+  // y = M^{-1} x for m vectors of n entries stored one after another
+  // (original ordering), every launch of a level covering all m (columns
+  // equal those of apply)
+  virtual void apply_batch(int m, const void* x, void* y) = 0;
   // install W_l (s_l x k) and H_l (k x k), host arrays of the value type
   virtual void set_lowrank(int l, int k, const void* W, const void* H) = 0;
   virtual void stats(gs_info* info, int vb_vec) = 0;

@@ -586,7 +586,7 @@ struct EngineT final : Engine {
     const uint8_t* blob = nullptr;
     const ChunkDesc* chunk = nullptr;
     const int32_t* blk_chunk = nullptr;
-    int chunk_cap = 0, x_bytes = 0, nbuf = 2;
+    int chunk_cap = 0, x_bytes = 0;
     bool half_l = false, half_u = false;  // L / U chunks laid out and swept as half rows
     D* diag_dinv = nullptr;  // diagonal level (L = I, U diagonal): 1/u_ii in row order
     int64_t nchunks = 0;
@@ -623,6 +623,15 @@ struct EngineT final : Engine {
   int64_t fy_len = 0;
   int max_lds = 65536;
   std::vector<Lev> lv;
+  // several vectors per launch (ghat_batch, apply_batch): while nv > 1 the
+  // working vector t (n rows per vector), fy (fy_len rows per vector) and
+  // every level's partial / tprime are batch buffers of nv columns
+  int nv = 1;
+  std::unique_ptr<DevMem> bmem;
+  int bcap = 0;
+  X* tb = nullptr;
+  C* fyb = nullptr;
+  std::vector<C*> partb, tpb;
 
   template <class U> U* upload(const std::vector<U>& h) {
     U* d = mem.alloc<U>(h.size());
@@ -717,10 +726,10 @@ struct EngineT final : Engine {
     const int32_t* perm = nullptr;
   } fuse;
   int group_cus = 256;
-  // chunk buffers per workgroup: 2 (one copy in flight while a chunk is
-  // swept) measures faster than 3 (two in flight, but chunks a third smaller
-  // and more hand-offs); GEMSLR_CHUNK_BUFS=3 selects the latter
-  int chunk_bufs = 2;
+  // chunk buffers per workgroup: one chunk in flight while one is swept (a
+  // third buffer, two in flight, measured slower: chunks a third smaller,
+  // more hand-offs)
+  static constexpr int chunk_bufs = 2;
 
   EngineT(const HostSetup<T>& S, hipStream_t stream) : st(stream) {
     n = S.n;
@@ -743,7 +752,6 @@ struct EngineT final : Engine {
       group_cus = num_cus;
       if (const char* e = std::getenv("GEMSLR_GROUP_CUS")) group_cus = std::max(1, std::atoi(e));
       lds_per_cu = std::max(cu_lds, lds_budget);
-      if (const char* e = std::getenv("GEMSLR_CHUNK_BUFS")) chunk_bufs = std::atoi(e) == 3 ? 3 : 2;
       if (const char* e = std::getenv("GEMSLR_LDS_BUDGET")) {
         lds_budget = std::atoi(e);
         fixed_budget = true;
@@ -794,6 +802,12 @@ struct EngineT final : Engine {
         if (!fixed_budget && L.nb > 0) {
           const int per_cu = (L.nb + num_cus - 1) / num_cus;
           budget = std::min(lds_budget, lds_per_cu / std::max(1, per_cu));
+          // two per CU when that keeps the largest chunks, so that launches
+          // covering several vectors can double up where one vector leaves
+          // CUs idle
+          const int half = lds_per_cu / 2;
+          if (per_cu == 1 && ((half - xb - 1024) / chunk_bufs) >= kChunkCapMax - 1024)
+            budget = std::min(budget, half);
         }
         int cap = std::min(kChunkCapMax, ((budget - xb - 1024) / chunk_bufs) & ~1023);
         const int ms = stream_slots(L.maxslot);
@@ -834,7 +848,6 @@ struct EngineT final : Engine {
             L.blk_chunk = upload(bc);
             L.chunk_cap = cap;
             L.x_bytes = xb;
-            L.nbuf = chunk_bufs;
             L.nchunks = (int64_t)desc.size();
             L.depth_l = sl.depth;
             L.depth_u = su.depth;
@@ -1039,9 +1052,11 @@ struct EngineT final : Engine {
     a.blk_chunk = L.blk_chunk;
     a.chunk_cap = L.chunk_cap;
     a.x_bytes = L.x_bytes;
-    a.nbuf = L.nbuf;
     a.half_u = L.half_u ? 1 : 0;
     a.half_l = L.half_l ? 1 : 0;
+    a.nvec = nv;
+    a.ldt = nv > 1 ? n : 0;
+    a.ldfy = nv > 1 ? fy_len : 0;
     a.xin = nullptr;
     a.yout = nullptr;
     a.perm = nullptr;
@@ -1068,7 +1083,7 @@ struct EngineT final : Engine {
     if (pair_offset<C>() <= 0 || !streamed(l) || L.nb <= 0) return false;
     if ((int64_t)(L.max_block_rows + 1) * (int64_t)sizeof(C) > pair_offset<C>()) return false;
     const int per_cu = (L.nb + num_cus - 1) / num_cus;
-    const int need = 2 * pair_offset<C>() + L.nbuf * L.chunk_cap + 1024;
+    const int need = 2 * pair_offset<C>() + chunk_bufs * L.chunk_cap + 1024;
     return need <= max_lds && need <= lds_per_cu / std::max(1, per_cu);
   }
   // the sweep of level l for the working vectors t and t2
@@ -1202,6 +1217,9 @@ struct EngineT final : Engine {
     a.tprime = L.tprime;
     a.stage_w = no_small_lds ? 0 : 1;
     a.max_lds = max_lds;
+    a.nvec = nv;
+    a.ldt = nv > 1 ? n : 0;
+    a.ldpart = nv > 1 ? (int64_t)interface_blocks<P>(L.s) * std::max(L.k, 1) : 0;
     const bool gfused = l == 0 && fuse.on && tv == t;
     if (gfused) {
       // the apply's gather of the C_0 rows happens here
@@ -1225,7 +1243,10 @@ struct EngineT final : Engine {
          [&] { launch_interface<P>(a, st); });
     if (k > 0)
       step("lowrank_update L" + std::to_string(l), KIND_LOWRANK, upd_bytes(l, k),
-           [&] { launch_lowrank_update<P>(tv + L.start + L.d, L.s, k, L.W, L.tprime, st); });
+           [&] {
+             launch_lowrank_update<P>(tv + L.start + L.d, L.s, k, L.W, L.tprime, st, nv,
+                                      nv > 1 ? n : 0);
+           });
     return false;
   }
 
@@ -1457,6 +1478,114 @@ struct EngineT final : Engine {
     launch_fill<X>(tc, zero_x(), L.s, st);
     interface(l, 0);
     launch_scatter<P>(tc, nullptr, (O*)out, L.s, st);
+  }
+
+  // ---- several vectors per launch
+  static constexpr int kBatchMax = 64;
+  void batch_reserve(int m) {
+    if (m <= bcap) return;
+    bmem.reset();
+    bmem = std::make_unique<DevMem>();
+    tb = bmem->alloc<X>((size_t)n * m);
+    fyb = bmem->alloc<C>((size_t)std::max<int64_t>(fy_len, 1) * m);
+    partb.assign(lv.size(), nullptr);
+    tpb.assign(lv.size(), nullptr);
+    for (size_t l = 0; l < lv.size(); ++l)
+      if (lv[l].k > 0) {
+        partb[l] = bmem->alloc<C>((size_t)interface_blocks<P>(lv[l].s) * lv[l].k * m);
+        tpb[l] = bmem->alloc<C>((size_t)lv[l].k * m);
+      }
+    bcap = m;
+  }
+  // run f with the batch buffers of m vectors in place of t, fy, partial,
+  // tprime (restored afterwards, also on error)
+  template <class Fn>
+  void with_batch(int m, Fn f) {
+    batch_reserve(m);
+    X* const t0 = t;
+    C* const fy0 = fy;
+    std::vector<C*> p0(lv.size()), q0(lv.size());
+    for (size_t l = 0; l < lv.size(); ++l) {
+      p0[l] = lv[l].partial;
+      q0[l] = lv[l].tprime;
+      if (lv[l].k > 0) {
+        lv[l].partial = partb[l];
+        lv[l].tprime = tpb[l];
+      }
+    }
+    t = tb;
+    fy = fyb;
+    nv = m;
+    auto restore = [&] {
+      t = t0;
+      fy = fy0;
+      nv = 1;
+      for (size_t l = 0; l < lv.size(); ++l) {
+        lv[l].partial = p0[l];
+        lv[l].tprime = q0[l];
+      }
+    };
+    try {
+      f();
+    } catch (...) {
+      restore();
+      throw;
+    }
+    restore();
+  }
+  // out[:, j] = G_hat_l v[:, j] for m vectors of s_l entries each (column
+  // j at v + j * s_l), every launch of a level covering all m vectors;
+  // each column equals ghat of that column
+  void ghat_batch(int l, int m, const void* v, void* out) override {
+    if (m <= 0) return;
+    if (inner_m > 0 || m == 1) {
+      const size_t vb = sizeof(O) * (size_t)lv[l].s;
+      for (int j = 0; j < m; ++j) ghat(l, (const char*)v + j * vb, (char*)out + j * vb);
+      return;
+    }
+    for (int j0 = 0; j0 < m; j0 += kBatchMax) {
+      const int mm = std::min(kBatchMax, m - j0);
+      with_batch(mm, [&] {
+        Lev& L = lv[l];
+        const O* vv = (const O*)v + (size_t)j0 * L.s;
+        O* oo = (O*)out + (size_t)j0 * L.s;
+        for (int j = 0; j < mm; ++j)
+          launch_gather<P>(vv + (size_t)j * L.s, nullptr, t + (size_t)j * n + L.start + L.d, L.s,
+                           st);
+        run_from(l + 1);
+        for (int j = 0; j < mm; ++j) launch_fill<X>(t + (size_t)j * n + L.start, zero_x(), L.d, st);
+        up(l);
+        for (int j = 0; j < mm; ++j)
+          launch_fill<X>(t + (size_t)j * n + L.start + L.d, zero_x(), L.s, st);
+        interface(l, 0);
+        for (int j = 0; j < mm; ++j)
+          launch_scatter<P>(t + (size_t)j * n + L.start + L.d, nullptr, oo + (size_t)j * L.s, L.s,
+                            st);
+      });
+    }
+  }
+  // y[:, j] = M^{-1} x[:, j] for m vectors of n entries (original order),
+  // every launch of a level covering all m vectors; each column equals
+  // apply of that column
+  void apply_batch(int m, const void* x, void* y) override {
+    if (m <= 0) return;
+    if (inner_m > 0) {
+      for (int j = 0; j < m; ++j)
+        apply((const O*)x + (size_t)j * n, (O*)y + (size_t)j * n, false);
+      return;
+    }
+    for (int j0 = 0; j0 < m; j0 += kBatchMax) {
+      const int mm = std::min(kBatchMax, m - j0);
+      with_batch(mm, [&] {
+        const O* xx = (const O*)x + (size_t)j0 * n;
+        O* yy = (O*)y + (size_t)j0 * n;
+        for (int j = 0; j < mm; ++j)
+          launch_gather<P>(xx + (size_t)j * n, perm_d, t + (size_t)j * n, n, st);
+        run_from(0);
+        for (int j = 0; j < mm; ++j)
+          launch_scatter<P>(t + (size_t)j * n, perm_d, yy + (size_t)j * n, n, st);
+      });
+    }
   }
   static X zero_x();
 

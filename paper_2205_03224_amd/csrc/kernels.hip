@@ -286,11 +286,19 @@ static void launch_tri_mode(const TriArgs<P>& a, int maxslot, int mbr, hipStream
 }
 
 template <class P>
-void launch_trisolve(const TriArgs<P>& a, int mode, int maxslot, int max_block_rows,
+void launch_trisolve(const TriArgs<P>& a0, int mode, int maxslot, int max_block_rows,
                      hipStream_t st) {
-  if (a.nb <= 0) return;
-  if (mode == TRI_DOWN) launch_tri_mode<P, TRI_DOWN>(a, maxslot, max_block_rows, st);
-  else launch_tri_mode<P, TRI_UP>(a, maxslot, max_block_rows, st);
+  if (a0.nb <= 0) return;
+  // several vectors: one launch each (they share the global block-vector
+  // staging, in stream order)
+  for (int j = 0; j < a0.nvec; ++j) {
+    TriArgs<P> a = a0;
+    a.t += (int64_t)j * a0.ldt;
+    a.fy += (int64_t)j * a0.ldfy;
+    a.nvec = 1;
+    if (mode == TRI_DOWN) launch_tri_mode<P, TRI_DOWN>(a, maxslot, max_block_rows, st);
+    else launch_tri_mode<P, TRI_UP>(a, maxslot, max_block_rows, st);
+  }
 }
 
 // ======================================================================
@@ -360,20 +368,6 @@ __device__ __forceinline__ ChunkDesc desc_get(const TriArgs<P>& a, int c, int c1
   return cd;
 }
 
-// s_waitcnt with a uniform run-time vector-memory count (the instruction
-// takes an immediate): expcnt and lgkmcnt left at their maxima.
-#define GS_VMCNT_CASE(n) case n: __builtin_amdgcn_s_waitcnt(GS_VMCNT_IMM(n)); break;
-__device__ __forceinline__ void wait_vmcnt(int n) {
-  switch (n) {
-    GS_VMCNT_CASE(1) GS_VMCNT_CASE(2) GS_VMCNT_CASE(3) GS_VMCNT_CASE(4) GS_VMCNT_CASE(5)
-    GS_VMCNT_CASE(6) GS_VMCNT_CASE(7) GS_VMCNT_CASE(8) GS_VMCNT_CASE(9) GS_VMCNT_CASE(10)
-    GS_VMCNT_CASE(11) GS_VMCNT_CASE(12) GS_VMCNT_CASE(13) GS_VMCNT_CASE(14)
-    GS_VMCNT_CASE(15) GS_VMCNT_CASE(16) GS_VMCNT_CASE(17) GS_VMCNT_CASE(18)
-    GS_VMCNT_CASE(19) GS_VMCNT_CASE(20) GS_VMCNT_CASE(21) GS_VMCNT_CASE(22)
-    GS_VMCNT_CASE(23) GS_VMCNT_CASE(24)
-    default: __builtin_amdgcn_s_waitcnt(GS_VMCNT_IMM(0)); break;
-  }
-}
 // lgkmcnt(0) alone (vmcnt and expcnt at their maxima)
 #define GS_LGKM0_IMM 0xC07F
 
@@ -815,9 +809,13 @@ __device__ __forceinline__ void store_result(const TriArgs<P>& a, typename P::X*
 }
 
 template <class P, int MS, int MODE, int NB>
-__global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
+__global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a0) {
   using C = typename P::C;
   using X = typename P::X;
+  // vector blockIdx.y of a batched launch
+  TriArgs<P> a = a0;
+  a.t += (int64_t)blockIdx.y * a0.ldt;
+  a.fy += (int64_t)blockIdx.y * a0.ldfy;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
@@ -829,23 +827,13 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
   // NB = 2: the second block vector at pair_offset, the buffers after it
   C* x2 = reinterpret_cast<C*>(smem_raw + pair_offset<C>());
   uint8_t* bufs = smem_raw + (NB == 2 ? 2 * pair_offset<C>() : a.x_bytes);
-  const int nbuf = a.nbuf;
-  const int full = a.chunk_cap >> 10;    // copy iterations of a full buffer
   const int c0 = a.blk_chunk[b], c1 = a.blk_chunk[b + 1];
   DescCache dc;
   if (c0 < c1) desc_fill<P>(a, c0, c1, lane, dc);
-  // With three buffers every copy issues `full` iterations, so the producer
-  // can wait for the older of two chunks in flight with a fixed count.
-  const auto iters = [&](const ChunkDesc& cd) {
-    return nbuf == 3 ? full : ((int)cd.n16 + kWave - 1) / kWave;
-  };
-  if (wave == 1) {
-    if (c0 < c1) {
-      const ChunkDesc cd = desc_get<P>(a, c0, c1, lane, dc);
-      copy_chunk<P>(a, cd, bufs, lane, iters(cd));
-    }
-    if (nbuf == 3 && c0 + 1 < c1)
-      copy_chunk<P>(a, desc_get<P>(a, c0 + 1, c1, lane, dc), bufs + a.chunk_cap, lane, full);
+  const auto iters = [&](const ChunkDesc& cd) { return ((int)cd.n16 + kWave - 1) / kWave; };
+  if (wave == 1 && c0 < c1) {
+    const ChunkDesc cd = desc_get<P>(a, c0, c1, lane, dc);
+    copy_chunk<P>(a, cd, bufs, lane, iters(cd));
   }
   if (MODE == TRI_UP && a.frow) {
     rhs_from_f<P, NB, 2 * kWave>(a, b, nr, tid, x, x2);
@@ -857,16 +845,13 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
   for (int c = c0; c < c1; ++c) {
     const int k = c - c0;
     if (wave == 1) {
-      // the buffer of chunk c - 1 is free: fill it with the chunk nbuf - 1
-      // ahead, then wait until chunk c + 1 has landed
-      const int cn = c + nbuf - 1;
-      if (cn < c1) {
-        const ChunkDesc cd = desc_get<P>(a, cn, c1, lane, dc);
-        copy_chunk<P>(a, cd, bufs + ((k + nbuf - 1) % nbuf) * a.chunk_cap, lane, iters(cd));
-        wait_vmcnt(nbuf == 3 ? full : 0);
-      } else {
-        wait_vmcnt(0);
+      // the buffer of chunk c - 1 is free: fill it with chunk c + 1, then
+      // wait until that has landed
+      if (c + 1 < c1) {
+        const ChunkDesc cd = desc_get<P>(a, c + 1, c1, lane, dc);
+        copy_chunk<P>(a, cd, bufs + ((k + 1) % 2) * a.chunk_cap, lane, iters(cd));
       }
+      __builtin_amdgcn_s_waitcnt(GS_VMCNT_IMM(0));
     } else {
       // Nothing of this wave is in flight here (its last chunk ended with a
       // full LDS wait), so this wait costs nothing; it tells the compiler
@@ -875,7 +860,7 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a) {
       // wait of the sweep below into a full one.
       __builtin_amdgcn_s_waitcnt(0);
       const ChunkDesc cd = desc_get<P>(a, c, c1, lane, dc);
-      uint8_t* cur = bufs + (k % nbuf) * a.chunk_cap;
+      uint8_t* cur = bufs + (k % 2) * a.chunk_cap;
       // idle lanes store to the slot after the block's rows
       const int dummy = nr * (int)sizeof(C);
       if (cd.nst & 0x8000) {
@@ -902,7 +887,7 @@ static void launch_stream_ms(const TriArgs<P>& a, hipStream_t st) {
   // read (and then discard) up to 63 elements beyond a section
   using C = typename P::C;
   const size_t xreg = NB == 2 ? 2 * (size_t)pair_offset<C>() : (size_t)a.x_bytes;
-  const size_t lds = xreg + (size_t)a.nbuf * (size_t)a.chunk_cap + 1024;
+  const size_t lds = xreg + 2 * (size_t)a.chunk_cap + 1024;
   auto kern = k_trisolve_streamed<P, MS, MODE, NB>;
   static size_t attr_set = 65536;
   if (lds > attr_set) {
@@ -910,7 +895,7 @@ static void launch_stream_ms(const TriArgs<P>& a, hipStream_t st) {
                               (int)lds);
     attr_set = lds;
   }
-  hipLaunchKernelGGL(kern, dim3(a.nb), dim3(2 * kWave), lds, st, a);
+  hipLaunchKernelGGL(kern, dim3(a.nb, a.nvec), dim3(2 * kWave), lds, st, a);
 }
 
 template <class P, int MODE, int NB>
@@ -941,8 +926,11 @@ static void launch_stream_mode(const TriArgs<P>& a, int maxslot, hipStream_t st)
 constexpr int kFyRows = 4;
 template <class P>
 __global__ __launch_bounds__(256) void k_fy(CsrDev<P> F, const typename P::X* y2,
-                                            typename P::C* fy, int64_t d) {
+                                            typename P::C* fy, int64_t d, int64_t ldy,
+                                            int64_t ldfy) {
   using C = typename P::C;
+  y2 += (int64_t)blockIdx.y * ldy;  // vector blockIdx.y of a batched launch
+  fy += (int64_t)blockIdx.y * ldfy;
   const int64_t i0 = (int64_t)blockIdx.x * 256 * kFyRows + threadIdx.x;
   int rows[kFyRows];
 #pragma unroll
@@ -966,10 +954,11 @@ void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot, int ma
     launch_stream_mode<P, TRI_DOWN>(a, maxslot, st);
   } else {
     if (!a.frow) {
-      const dim3 gfy((unsigned)((a.d + 256 * kFyRows - 1) / (256 * kFyRows)));
-      hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t + a.d, a.fy, a.d);
+      const dim3 gfy((unsigned)((a.d + 256 * kFyRows - 1) / (256 * kFyRows)), a.nvec);
+      hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t + a.d, a.fy, a.d, a.ldt, a.ldfy);
       if (a.nrhs == 2)
-        hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t2 + a.d, a.fy2, a.d);
+        hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t2 + a.d, a.fy2, a.d, a.ldt,
+                           a.ldfy);
     }
     launch_stream_mode<P, TRI_UP>(a, maxslot, st);
   }
@@ -996,9 +985,13 @@ __device__ __forceinline__ typename P::C if_b2(const IfArgs<P>& a, int64_t i) {
 }
 
 template <class P, int R, int KG>
-__global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a) {
+__global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a0) {
   using C = typename P::C;
   using X = typename P::X;
+  // vector blockIdx.y of a batched launch
+  IfArgs<P> a = a0;
+  a.t += (int64_t)blockIdx.y * a0.ldt;
+  a.partial += (int64_t)blockIdx.y * a0.ldpart;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* red = reinterpret_cast<C*>(smem_raw);  // 9 x kIfThreads (block_sum8)
   const int tid = threadIdx.x;
@@ -1067,8 +1060,11 @@ template <class P>
 __global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typename P::C* partial,
                                                                    int nb, int k,
                                                                    const typename P::C* H,
-                                                                   typename P::C* tprime) {
+                                                                   typename P::C* tprime,
+                                                                   int64_t ldpart) {
   using C = typename P::C;
+  partial += (int64_t)blockIdx.y * ldpart;  // vector blockIdx.y of a batched launch
+  tprime += (int64_t)blockIdx.y * k;
   __shared__ C red[kFinishThreads];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* tv = reinterpret_cast<C*>(smem_raw);  // k
@@ -1140,7 +1136,7 @@ void launch_interface(const IfArgs<P>& a, hipStream_t st) {
   // columns per load batch: all of k when it is small, else batches sized so
   // that the registers still allow every workgroup to be resident at once
 #define GS_IF_LAUNCH(R_, KG) \
-  hipLaunchKernelGGL((k_interface<P, R_, KG>), dim3(nblk), dim3(kIfThreads), lds, st, a)
+  hipLaunchKernelGGL((k_interface<P, R_, KG>), dim3(nblk, a.nvec), dim3(kIfThreads), lds, st, a)
   if constexpr (sizeof(C) == 16) {
     GS_IF_LAUNCH(1, 16);
   } else {
@@ -1151,8 +1147,8 @@ void launch_interface(const IfArgs<P>& a, hipStream_t st) {
   }
 #undef GS_IF_LAUNCH
   if (a.k > 0)
-    hipLaunchKernelGGL(k_project_finish<P>, dim3(1), dim3(kFinishThreads), (size_t)a.k * sizeof(C),
-                       st, a.partial, nblk, a.k, a.H, a.tprime);
+    hipLaunchKernelGGL(k_project_finish<P>, dim3(1, a.nvec), dim3(kFinishThreads),
+                       (size_t)a.k * sizeof(C), st, a.partial, nblk, a.k, a.H, a.tprime, a.ldpart);
 }
 
 // The whole interface step of a small level in one workgroup (s <= 4096,
@@ -1165,11 +1161,13 @@ void launch_interface(const IfArgs<P>& a, hipStream_t st) {
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallW = 16;
 template <class P, bool WL>
-__global__ __launch_bounds__(kSmallThreads) void k_interface_small(IfArgs<P> a) {
+__global__ __launch_bounds__(kSmallThreads) void k_interface_small(IfArgs<P> a0) {
   using C = typename P::C;
   using X = typename P::X;
   using V = typename P::V;
   using D = typename P::D;
+  IfArgs<P> a = a0;  // vector blockIdx.y of a batched launch
+  a.t += (int64_t)blockIdx.y * a0.ldt;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int s = (int)a.s, k = a.k, tid = threadIdx.x;
   C* zs = reinterpret_cast<C*>(smem_raw);  // s
@@ -1269,7 +1267,7 @@ static void launch_small_wl(const IfArgs<P>& a, size_t lds, hipStream_t st) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     attr_set = lds;
   }
-  hipLaunchKernelGGL((k_interface_small<P, WL>), dim3(1), dim3(kSmallThreads), lds, st, a);
+  hipLaunchKernelGGL((k_interface_small<P, WL>), dim3(1, a.nvec), dim3(kSmallThreads), lds, st, a);
 }
 
 template <class P>
@@ -1295,9 +1293,12 @@ bool launch_interface_small(const IfArgs<P>& a, hipStream_t st) {
 template <class P>
 __global__ __launch_bounds__(256) void k_lowrank_update(typename P::X* tc, int64_t s, int k,
                                                         const typename P::V* W,
-                                                        const typename P::C* tprime) {
+                                                        const typename P::C* tprime,
+                                                        int64_t ldt) {
   using C = typename P::C;
   using X = typename P::X;
+  tc += (int64_t)blockIdx.y * ldt;  // vector blockIdx.y of a batched launch
+  tprime += (int64_t)blockIdx.y * k;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* tp = reinterpret_cast<C*>(smem_raw);
   for (int c = threadIdx.x; c < k; c += blockDim.x) tp[c] = tprime[c];
@@ -1311,11 +1312,11 @@ __global__ __launch_bounds__(256) void k_lowrank_update(typename P::X* tc, int64
 
 template <class P>
 void launch_lowrank_update(typename P::X* tc, int64_t s, int k, const typename P::V* W,
-                           const typename P::C* tprime, hipStream_t st) {
-  if (s <= 0 || k <= 0) return;
+                           const typename P::C* tprime, hipStream_t st, int nvec, int64_t ldt) {
+  if (s <= 0 || k <= 0 || nvec <= 0) return;
   const int nblk = (int)((s + 255) / 256);
-  hipLaunchKernelGGL(k_lowrank_update<P>, dim3(nblk), dim3(256),
-                     (size_t)k * sizeof(typename P::C), st, tc, s, k, W, tprime);
+  hipLaunchKernelGGL(k_lowrank_update<P>, dim3(nblk, nvec), dim3(256),
+                     (size_t)k * sizeof(typename P::C), st, tc, s, k, W, tprime, ldt);
 }
 
 // ---------------------------------------------------------------- perm
@@ -1708,7 +1709,7 @@ void launch_inner_lsq(const T* h, const double* sub, const double* wn, const dou
   template bool launch_interface_small<P>(const IfArgs<P>&, hipStream_t);                            \
   template int interface_blocks<P>(int64_t);                                                   \
   template void launch_lowrank_update<P>(P::X*, int64_t, int, const P::V*, const P::C*,        \
-                                         hipStream_t);                                         \
+                                         hipStream_t, int, int64_t);                           \
   template void launch_gather<P>(const P::O*, const int32_t*, P::X*, int64_t, hipStream_t);    \
   template void launch_scatter<P>(const P::X*, const int32_t*, P::O*, int64_t, hipStream_t);
 GS_PREC_INSTANCES(PF64)

@@ -39,7 +39,8 @@ class GsOpts(ct.Structure):
                 ("grid_ndim", ct.c_int), ("grid_dims", ct.c_int32 * 3),
                 ("seed", ct.c_uint64), ("nthreads", ct.c_int),
                 ("defer_lowrank", ct.c_int), ("block_max_iters", ct.c_int),
-                ("inner_gmres_its", ct.c_int), ("ilu_shift", ct.c_double)]
+                ("inner_gmres_its", ct.c_int), ("ilu_shift", ct.c_double),
+                ("warm_start", ct.c_int)]
 
 
 _L1 = GS_MAX_LEVELS + 1

@@ -121,20 +121,23 @@ def random_bases(ctx, levels, out_dim, seed):
 
 def setup_with(w, rank, mode, mlp=None, levels=(0, 1), seed=0, **extra):
     """Setup with the low-rank stage run by `mode`: "arnoldi" (plain),
-    "learned" (block iteration from the network's bases) or "random" (block
-    iteration from random bases, the control).  Returns (ctx, seconds spent
-    on the low-rank stage incl. the network)."""
+    "learned" (block iteration from the network's bases), "learned_arnoldi"
+    (the thick-restart Arnoldi started from a vector of the network's
+    subspace) or "random" (block iteration from random bases, the control).
+    Returns (ctx, seconds spent on the low-rank stage incl. the network)."""
     import torch
     ctx = gemslr.Context(0)
     kw = setup_kwargs(w)
     kw.update(extra)
+    if mode == "learned_arnoldi":
+        kw["warm_start"] = 1
     ctx.setup(w.rowptr, w.col, w.val, w.levels, w.nparts, rank, w.drop_tol, defer_lowrank=1,
               **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if mode == "arnoldi":
         ctx.lowrank(rank)
-    elif mode == "learned":
+    elif mode in ("learned", "learned_arnoldi"):
         ctx.lowrank(rank, predicted_bases(ctx, mlp, levels, rank))
     elif mode == "random":
         ctx.lowrank(rank, random_bases(ctx, levels, rank, seed))
@@ -151,7 +154,7 @@ def evaluate(instances, mlp, N=64, nparts=64, rank=32, tol=1e-8, levels=(0, 1), 
     rows = []
     for i in instances:
         w = family_member(i, N, nparts)
-        for mode in ("arnoldi", "learned", "random"):
+        for mode in MODES:
             ctx, t_lr = setup_with(w, rank, mode, mlp, levels, seed=1000 + i)
             info = ctx.info()
             b = torch.from_numpy(w.b).cuda()
@@ -174,20 +177,24 @@ def evaluate(instances, mlp, N=64, nparts=64, rank=32, tol=1e-8, levels=(0, 1), 
     return rows
 
 
+MODES = ("arnoldi", "learned", "learned_arnoldi", "random")
+
+
 def summarise(rows):
     out = {}
-    for mode in ("arnoldi", "learned", "random"):
+    for mode in MODES:
         r = [x for x in rows if x["mode"] == mode]
         if not r:
             continue
         out[mode] = {k: float(np.mean([x[k] for x in r]))
                      for k in ("matvecs", "t_lowrank_s", "its", "relres", "time_to_tol_s")}
         out[mode]["median_time_to_tol_s"] = float(np.median([x["time_to_tol_s"] for x in r]))
-    if "learned" in out and "arnoldi" in out:
-        lr = {x["instance"]: x for x in rows if x["mode"] == "learned"}
-        ar = {x["instance"]: x for x in rows if x["mode"] == "arnoldi"}
-        wins = [lr[i]["time_to_tol_s"] < ar[i]["time_to_tol_s"] for i in lr if i in ar]
-        out["learned_win_fraction_vs_arnoldi"] = float(np.mean(wins)) if wins else None
+    ar = {x["instance"]: x for x in rows if x["mode"] == "arnoldi"}
+    for mode in ("learned", "learned_arnoldi"):
+        if mode in out and ar:
+            lr = {x["instance"]: x for x in rows if x["mode"] == mode}
+            wins = [lr[i]["time_to_tol_s"] < ar[i]["time_to_tol_s"] for i in lr if i in ar]
+            out[f"{mode}_win_fraction_vs_arnoldi"] = float(np.mean(wins)) if wins else None
     return out
 
 

@@ -151,9 +151,19 @@ def test_block_setup_from_random_basis(torch_dev):
 @pytest.mark.slow
 def test_learned_gain_small_family(torch_dev):
     """Train on 24 members of the log-normal family (20^3, 8 parts, rank 6)
-    and compare on 6 held-out members: the learned start needs fewer Ĝ
-    products than the block iteration from random bases, and the
-    preconditioner it builds is as good (FGMRES iterations)."""
+    and score on 6 held-out members against the method without the network,
+    plain thick-restart Arnoldi (the judge), with the block iteration from
+    random bases as a second control.  Reported per mode: Ĝ products,
+    low-rank setup time, FGMRES iterations, true residual, time to 1e-8.
+
+    What the network buys on this family: fewer Ĝ products than the same
+    block iteration from random bases, and a preconditioner as good as
+    Arnoldi's (FGMRES iterations within 3).  What it does not buy: time to
+    1e-8 below plain Arnoldi's.  The single-vector Krylov-Schur needs fewer
+    products on these clustered spectra, and the block iteration spends its
+    time in per-iteration host work.  The test states that loss in numbers
+    (learned slower than Arnoldi) instead of asserting a gain that does not
+    hold; it fails if that changes, so that the finding gets re-examined."""
     from paper_2205_03224_amd import learned
     rank = 6
     data = learned.collect(range(24), N=20, nparts=8, rank=rank, levels=(0,))
@@ -163,8 +173,20 @@ def test_learned_gain_small_family(torch_dev):
     rows = learned.evaluate(range(100000, 100006), mlp, N=20, nparts=8, rank=rank,
                             levels=(0,))
     summ = learned.summarise(rows)
-    print("  summary", summ, flush=True)
-    assert all(r["converged"] for r in rows)
+    for mode in learned.MODES:
+        m = summ[mode]
+        print(f"  {mode:16s} products {m['matvecs']:6.1f}  low-rank {m['t_lowrank_s']:.4f} s  "
+              f"its {m['its']:5.1f}  time to 1e-8 {m['time_to_tol_s']:.4f} s", flush=True)
+    assert all(r["converged"] and r["relres"] <= 1.5e-8 for r in rows)
+    # gain over the random-basis control, same preconditioner quality
     assert summ["learned"]["matvecs"] < summ["random"]["matvecs"]
     assert summ["learned"]["its"] <= summ["arnoldi"]["its"] + 3
+    # against the judge: the measured loss on this family
+    ar = summ["arnoldi"]
+    print(f"  learned / Arnoldi time to 1e-8: "
+          f"{summ['learned']['time_to_tol_s'] / ar['time_to_tol_s']:.2f} (block), "
+          f"{summ['learned_arnoldi']['time_to_tol_s'] / ar['time_to_tol_s']:.2f} "
+          f"(Arnoldi from the predicted subspace)", flush=True)
+    assert summ["learned"]["time_to_tol_s"] > ar["time_to_tol_s"]
+    assert summ["learned_win_fraction_vs_arnoldi"] <= 0.5
     mlp.close()

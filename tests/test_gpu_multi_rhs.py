@@ -1,9 +1,10 @@
-"""Several right-hand sides per apply (gs_apply_many): pairs of vectors share
+"""Several right-hand sides per apply (gs_apply_many): two vectors share
 each level's triangular-sweep launch (the factor entries are read once for
-both).  Every column must equal the oracle's apply of that column to the
-float64 apply tolerance, and, since each right-hand side goes through the
-same operations in the same order as in a single apply, equal the single
-apply of the same column bit for bit.
+both); three or more go through launches that cover all of them at every
+step (vector = workgroup row of the grid).  Every column must equal the
+oracle's apply of that column to the float64 apply tolerance, and, since
+each right-hand side goes through the same operations in the same order as
+in a single apply, equal the single apply of the same column bit for bit.
 """
 import numpy as np
 import pytest
@@ -53,7 +54,7 @@ def _block(w, nrhs, seed):
 
 @pytest.mark.parametrize("env", [{}, {"GEMSLR_GROUP_CUS": "4"}, {"GEMSLR_NO_STREAM": "1"}])
 @pytest.mark.parametrize("name", ["laplace2d_32", "convdiff3d_20_p27", "helmholtz3d_16_p8"])
-@pytest.mark.parametrize("nrhs", [2, 3, 4])
+@pytest.mark.parametrize("nrhs", [2, 3, 4, 8])
 def test_apply_many_matches_oracle_and_single(torch_dev, name, nrhs, env, monkeypatch):
     torch = torch_dev
     from paper_2205_03224_amd import gemslr
@@ -78,23 +79,25 @@ def test_apply_many_matches_oracle_and_single(torch_dev, name, nrhs, env, monkey
     ctx.close()
 
 
+@pytest.mark.parametrize("nrhs", [2, 5])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_apply_many_mixed_forms_equal_single(torch_dev, prec):
-    """The float32-sweep forms pair their right-hand sides as well; each
-    column equals the single apply of the same form bit for bit."""
+def test_apply_many_mixed_forms_equal_single(torch_dev, prec, nrhs):
+    """The float32-sweep forms share launches between right-hand sides as
+    well; each column equals the single apply of the same form bit for
+    bit."""
     torch = torch_dev
     from paper_2205_03224_amd import gemslr
     w, st = _case("convdiff3d_20_p27")
     ctx = gemslr.Context(0)
     ctx.setup_explicit(w.rowptr, w.col, w.val, st.perm, oracle_levels(st))
     ctx.set_precision(prec)
-    X = _block(w, 2, 77)
+    X = _block(w, nrhs, 77)
     xd = torch.from_numpy(X).cuda()
     yd = torch.empty_like(xd)
     ys = torch.empty_like(xd)
-    ctx.apply_many(2, xd, yd)
-    ctx.apply(xd[0], ys[0])
-    ctx.apply(xd[1], ys[1])
+    ctx.apply_many(nrhs, xd, yd)
+    for j in range(nrhs):
+        ctx.apply(xd[j], ys[j])
     torch.cuda.synchronize()
     assert torch.equal(yd, ys)
     ctx.close()

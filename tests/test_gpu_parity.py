@@ -151,8 +151,7 @@ def test_native_setup_solves(torch_dev):
 
 
 @pytest.mark.parametrize("env", [{"GEMSLR_NO_STREAM": "1"}, {"GEMSLR_LDS_BUDGET": "16384"},
-                                 {"GEMSLR_LDS_BUDGET": "20480"}, {"GEMSLR_CHUNK_BUFS": "3"},
-                                 {"GEMSLR_CHUNK_BUFS": "3", "GEMSLR_LDS_BUDGET": "16384"},
+                                 {"GEMSLR_LDS_BUDGET": "20480"},
                                  {"GEMSLR_NO_GROUP": "1"}, {"GEMSLR_GROUP_CUS": "4"},
                                  {"GEMSLR_GROUP_CUS": "2", "GEMSLR_NO_STREAM": "1"},
                                  {"GEMSLR_NO_FUSE_SMALL": "1"}, {"GEMSLR_NO_FUSE_PERM": "1"},
