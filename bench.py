@@ -353,11 +353,12 @@ def main():
             log(f"[bench] {key}: median {d['median_us']:.1f} us (p10 {d['p10_us']:.1f}, "
                 f"p90 {d['p90_us']:.1f}), {d['GBps_at_median']:.0f} GB/s")
 
-        # several right-hand sides per call (gs_apply_many): two share each
-        # level's sweep launch (factor entries read once for both); three or
-        # more go through launches covering all of them at every step
+        # several right-hand sides per call (gs_apply_many): every launch of
+        # a level covers all vectors; in the level-0 sweeps workgroups sweep
+        # groups of vectors over the same staged factor entries, so the
+        # level-0 sweep time per vector falls where groups fit in LDS
         multi = {}
-        for nb_ in (2, 4, 8):
+        for nb_ in (2, 3, 4, 8):
             Bm = torch.stack([torch.roll(b, 7919 * j) for j in range(nb_)])
             Ym = torch.empty_like(Bm)
             for _ in range(3):
@@ -369,13 +370,22 @@ def main():
                 ctx.apply_many(nb_, Bm, Ym)
             torch.cuda.synchronize()
             us_call = (time.perf_counter() - t0) * 1e6 / kp
+            # level-0 sweeps (down and up) of a few calls, per vector
+            ctx.probe_enable(0, 2 * 4 + 8)
+            for _ in range(4):
+                ctx.apply_many(nb_, Bm, Ym)
+            l0_launches, l0_ms, _ = ctx.probe_read()
+            ctx.probe_enable(-1, 0)
+            l0_us_vec = l0_ms * 1e3 / max(l0_launches, 1) / nb_
             multi[str(nb_)] = {"nrhs": nb_, "us_per_call": us_call,
                                "applies_per_s": nb_ * 1e6 / us_call,
                                "speedup_vs_single": (nb_ * 1e6 / us_call) / applies_per_s,
+                               "level0_sweep_us_per_vector": l0_us_vec,
                                "calls": kp}
             log(f"[bench] {nb_} right-hand sides per call: {us_call:.1f} us per call, "
                 f"{multi[str(nb_)]['applies_per_s']:.0f} applies/s "
-                f"({multi[str(nb_)]['speedup_vs_single']:.2f}x single)")
+                f"({multi[str(nb_)]['speedup_vs_single']:.2f}x single); level-0 sweep "
+                f"{l0_us_vec:.1f} us per vector")
             del Bm, Ym
 
         # the float32 and bfloat16 storage forms of the same preconditioner:

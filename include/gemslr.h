@@ -243,16 +243,17 @@ int gs_set_precision(gs_ctx* ctx, int precision);
 int gs_apply(gs_ctx* ctx, const void* x, void* y);
 
 /* Same as gs_apply for `nrhs` vectors stored one after another
- * (x + j*n, y + j*n), device memory, x and y not overlapping.  Vectors go in
- * pairs.  On levels where the two block vectors and the chunk buffers still
- * let every workgroup of the level be resident (the grouped small blocks of
- * levels >= 1 here), one sweep launch handles both and reads the factor
- * entries once for the two (several right-hand sides per factor pass, named
- * as future work in Sec. 6); elsewhere -- in particular the 3,375 - 4,096-row
- * blocks of level 0 of the 128^3 workloads -- the pair runs as two single
- * sweeps.  An odd last vector, and forms without the pair sweep
- * (complex128, or with inner GMRES steps), go one at a time.  Every column
- * equals gs_apply of that column.  Errors as gs_apply. */
+ * (x + j*n, y + j*n), device memory, x and y not overlapping.  With two or
+ * more vectors every launch of a level covers all of them (several
+ * right-hand sides per factor pass, named as future work in Sec. 6).  In a
+ * triangular sweep a workgroup may sweep a group of up to 8 vectors over
+ * the same staged chunks of factor entries, which then cross HBM once for
+ * the group; the group size per level follows from how many workgroups LDS
+ * lets share a CU: groups pay where one vector's workgroups already fill
+ * every CU (level 0: three vectors per workgroup at the 3,375 - 4,096-row
+ * blocks of the 128^3 workloads), single-vector workgroups where one vector
+ * leaves CUs idle.  With inner GMRES steps the vectors go one at a time.
+ * Every column equals gs_apply of that column.  Errors as gs_apply. */
 int gs_apply_many(gs_ctx* ctx, int nrhs, const void* x, void* y);
 
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -1516,20 +1516,11 @@ int gs_apply_many(gs_ctx* c, int nrhs, const void* x, void* y) {
     char* yb = (char*)y;
     const size_t bytes = (size_t)n * vb * (size_t)nrhs;
     if (xb < yb + bytes && yb < xb + bytes) throw Error(GS_EINVAL, "x and y alias");
-    // pairs share each level's sweep launch (Sec. 6: several right-hand
-    // sides per factor pass); an odd one out, or a form without the pair
-    // path, goes alone
-    int j = 0;
-    if (nrhs >= 3) {
-      // every launch of a level covers all vectors (vector = blockIdx.y)
-      c->eng->apply_batch(nrhs, xb, yb);
-      j = nrhs;
-    }
-    for (; j + 1 < nrhs; j += 2) {
-      const size_t o0 = (size_t)j * n * vb, o1 = o0 + (size_t)n * vb;
-      if (!c->eng->apply_pair(xb + o0, xb + o1, yb + o0, yb + o1)) break;
-    }
-    for (; j < nrhs; ++j) c->eng->apply(xb + (size_t)j * n * vb, yb + (size_t)j * n * vb, false);
+    // several right-hand sides per factor pass (Sec. 6): every launch of a
+    // level covers all vectors, and the triangular sweeps let groups of
+    // vectors share each staged chunk of factor entries
+    if (nrhs >= 2) c->eng->apply_batch(nrhs, xb, yb);
+    else if (nrhs == 1) c->eng->apply(xb, yb, false);
     hipcheck(hipGetLastError(), "kernel launch");
     return GS_OK;
   });

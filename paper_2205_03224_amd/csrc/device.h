@@ -167,12 +167,6 @@ struct TriArgs {
   const typename P::O* xin;
   typename P::O* yout;
   const int32_t* perm;
-  // two right-hand sides per sweep (streamed kernel, nrhs = 2): the second
-  // working vector and its F_l y2; in LDS the second block vector starts at
-  // byte pair_offset<C>() (so one instruction gathers both)
-  typename P::X* t2;
-  typename P::C* fy2;
-  int32_t nrhs;
   // streamed UP mode: F_l y2 formed by the sweep itself, from the rows of
   // F_l that hold entries (null: read from fy, formed by a launch before).
   // Record q is unit-local row frow[q] with entries j < fw at
@@ -184,17 +178,32 @@ struct TriArgs {
   const int32_t* funit = nullptr;
   int32_t fw = 0;
   int64_t nrec = 0;
-  // several vectors per launch (blockIdx.y = vector j): t and fy of vector
-  // j start at t + j * ldt and fy + j * ldfy
+  // several vectors per launch: t and fy of vector j start at t + j * ldt
+  // and fy + j * ldfy.  The streamed kernel sweeps vectors
+  // ncons * blockIdx.y + c, c < ncons, in one workgroup: consumer wave c
+  // holds its own block vector in LDS and all of them sweep the same staged
+  // chunks (factor entries read once for ncons vectors); the other kernels
+  // take vector j = blockIdx.y.
   int32_t nvec = 1;
+  int32_t ncons = 1;
   int64_t ldt = 0, ldfy = 0;
 };
 
-// LDS byte offset of the second block vector in two-right-hand-side sweeps:
-// 65 units of the two-address LDS instructions' stride-64 form (64 elements)
-// covers blocks of up to 4159 rows; defined for 4- and 8-byte elements
-template <class C> __host__ __device__ constexpr int pair_offset() {
-  return sizeof(C) == 8 || sizeof(C) == 4 ? 65 * 64 * (int)sizeof(C) : 0;
+// most consumer waves (vectors) per workgroup of the streamed sweep
+constexpr int kMaxCons = 8;
+// ... for elements of csize bytes and rows of ms slots: as many as the
+// sweep's registers allow (a workgroup of c + 1 waves has 512 / ceil((c + 1)
+// / 4) registers per lane: 168 at 8 consumers, 256 at 4, 512 at 3; the
+// 16-slot float64 and the 8-or-more-slot complex128 sweeps need more than
+// 168, the 12- and 16-slot complex128 ones more than 256)
+__host__ __device__ constexpr int stream_max_cons(int csize, int ms) {
+  return csize >= 16 ? (ms <= 4 ? kMaxCons : ms <= 10 ? 4 : 3) : (ms <= 12 ? kMaxCons : 4);
+}
+// LDS bytes of a streamed-sweep workgroup with c consumers: c block vectors,
+// two chunk buffers and 1 KiB of slack after the second (lanes past the end
+// of a stage read, and then discard, up to 63 elements beyond a section)
+inline size_t stream_lds_bytes(int x_bytes, int chunk_cap, int c) {
+  return (size_t)c * (size_t)x_bytes + 2 * (size_t)chunk_cap + 1024;
 }
 
 template <class P>
@@ -228,8 +237,8 @@ struct IfArgs {
 // ------------------------------------------------------------ launchers
 template <class P> void launch_trisolve(const TriArgs<P>& a, int mode, int maxslot,
                                         int max_block_rows, hipStream_t st);
-// streamed variant: one producer wave stages chunks into LDS, one consumer
-// wave sweeps; needs a.blob, x in LDS, and maxslot <= 16
+// streamed variant: one producer wave stages chunks into LDS, a.ncons
+// consumer waves sweep them; needs a.blob, x in LDS, and maxslot <= 16
 template <class P> void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot,
                                                  int max_block_rows, hipStream_t st);
 // maximum chunk size the streamed kernel stages (bytes)

@@ -50,8 +50,6 @@ struct Engine {
   virtual ~Engine() = default;
   // y = M^{-1} x; permuted: x, y already in the reordered numbering
   virtual void apply(const void* x, void* y, bool permuted) = 0;
-  // two applies sharing each level's sweep launch; false if not available
-  virtual bool apply_pair(const void* x0, const void* x1, void* y0, void* y1) = 0;
   // out = Ĝ_l v (s_l entries each)
   virtual void ghat(int l, const void* v, void* out) = 0;
   // the same for m vectors of s_l entries stored one after another, every

@@ -618,8 +618,6 @@ struct EngineT final : Engine {
   X* t = nullptr;
   C* xg = nullptr;
   C* fy = nullptr;  // F_l y2 of the streamed up sweep
-  X* t2 = nullptr;  // second working vector of two-right-hand-side applies
-  C* fy2 = nullptr;
   int64_t fy_len = 0;
   int max_lds = 65536;
   std::vector<Lev> lv;
@@ -1060,9 +1058,7 @@ struct EngineT final : Engine {
     a.xin = nullptr;
     a.yout = nullptr;
     a.perm = nullptr;
-    a.t2 = nullptr;
-    a.fy2 = nullptr;
-    a.nrhs = 1;
+    a.ncons = 1;
     if (streamed(l) && L.frow) {
       a.frow = L.frow;
       a.fcol = L.fcol;
@@ -1073,34 +1069,47 @@ struct EngineT final : Engine {
     }
     return a;
   }
-  // level l sweeps both right-hand sides in one launch when its blocks fit
-  // the second vector's LDS offset and the pair kernel still keeps as many
-  // workgroups per CU resident as the single one (measured: at level 0,
-  // 4096-row blocks, the pair kernel at one workgroup per CU takes as long
-  // as two single launches at two per CU)
-  bool pair_ok(int l) const {
+  // Vectors per workgroup of the streamed sweep of level l for m vectors, as
+  // (consumers, vectors) launches covering all m: each takes the consumer
+  // count that sweeps the most vectors per round of co-resident workgroups
+  // (LDS decides how many share a CU; every workgroup of a level is taken
+  // to need the same time), the fewest consumers on ties.  A group of c
+  // consumers reads the factor entries once for c vectors but holds c block
+  // vectors in LDS, so it pays where the level's workgroups already fill
+  // every CU (level 0) and not where one vector leaves CUs idle.
+  std::vector<std::pair<int, int>> cons_plan(int l, int m) const {
     const Lev& L = lv[l];
-    if (pair_offset<C>() <= 0 || !streamed(l) || L.nb <= 0) return false;
-    if ((int64_t)(L.max_block_rows + 1) * (int64_t)sizeof(C) > pair_offset<C>()) return false;
-    const int per_cu = (L.nb + num_cus - 1) / num_cus;
-    const int need = 2 * pair_offset<C>() + chunk_bufs * L.chunk_cap + 1024;
-    return need <= max_lds && need <= lds_per_cu / std::max(1, per_cu);
-  }
-  // the sweep of level l for the working vectors t and t2
-  void trisolve_pair(int l, int mode) {
-    const Lev& L = lv[l];
-    if (pair_ok(l)) {
-      TriArgs<P> a = tri_args(l);
-      a.t2 = t2 + L.start;
-      a.fy2 = fy2;
-      a.nrhs = 2;
-      launch_trisolve_streamed<P>(a, mode, L.maxslot, L.max_block_rows, st);
-      return;
+    std::vector<std::pair<int, int>> plan;
+    const int cmax = stream_max_cons((int)sizeof(C), stream_slots(L.maxslot));
+    for (int r = m; r > 0;) {
+      int best = 1;
+      double brate = -1.0;
+      for (int c = 1; c <= std::min(r, cmax); ++c) {
+        const size_t lds = stream_lds_bytes(L.x_bytes, L.chunk_cap, c);
+        if (lds > (size_t)max_lds) break;
+        // co-resident workgroups per CU: LDS, and at most 32 waves
+        const int64_t per_cu = std::min<int64_t>((int64_t)lds_per_cu / (int64_t)lds, 32 / (c + 1));
+        if (per_cu < 1) break;
+        const int64_t q = r / c;
+        const int64_t slots = (int64_t)num_cus * per_cu;
+        const int64_t rounds = ((int64_t)L.nb * q + slots - 1) / slots;
+        const double rate = (double)(q * c) / (double)rounds;
+        if (rate > brate * (1.0 + 1e-9)) {
+          brate = rate;
+          best = c;
+        }
+      }
+      // GEMSLR_CONSUMERS=c: groups of c vectors wherever they fit (tests use
+      // it where one vector per workgroup would be chosen)
+      if (const char* e = std::getenv("GEMSLR_CONSUMERS")) {
+        best = std::max(1, std::min({std::atoi(e), r, cmax}));
+        while (best > 1 && stream_lds_bytes(L.x_bytes, L.chunk_cap, best) > (size_t)max_lds) --best;
+      }
+      const int cnt = (r / best) * best;
+      plan.emplace_back(best, cnt);
+      r -= cnt;
     }
-    trisolve(l, mode);
-    std::swap(t, t2);
-    trisolve(l, mode);
-    std::swap(t, t2);
+    return plan;
   }
   bool streamed(int l) const { return lv[l].blob && !no_stream; }
   void trisolve(int l, int mode) {
@@ -1113,7 +1122,20 @@ struct EngineT final : Engine {
         if (mode == TRI_DOWN) a.xin = fuse.x;
         else a.yout = fuse.y;
       }
-      launch_trisolve_streamed<P>(a, mode, L.maxslot, L.max_block_rows, st);
+      if (nv == 1) {
+        launch_trisolve_streamed<P>(a, mode, L.maxslot, L.max_block_rows, st);
+        return;
+      }
+      int j0 = 0;
+      for (const auto& pc : cons_plan(l, nv)) {
+        TriArgs<P> b = a;
+        b.t += (int64_t)j0 * a.ldt;
+        b.fy += (int64_t)j0 * a.ldfy;
+        b.nvec = pc.second;
+        b.ncons = pc.first;
+        launch_trisolve_streamed<P>(b, mode, L.maxslot, L.max_block_rows, st);
+        j0 += pc.second;
+      }
     } else {
       launch_trisolve<P>(tri_args(l), mode, L.maxslot, L.max_block_rows, st);
     }
@@ -1373,43 +1395,6 @@ struct EngineT final : Engine {
       throw;
     }
     restore();
-  }
-
-  // y0 = M^{-1} x0 and y1 = M^{-1} x1, the triangular sweeps of both in
-  // one launch per level (factor entries read once for two right-hand
-  // sides); false (nothing done) when inner steps are on
-  bool apply_pair(const void* x0, const void* x1, void* y0, void* y1) override {
-    if (inner_m > 0) return false;
-    if (!t2) {
-      t2 = mem.alloc<X>(n);
-      fy2 = mem.alloc<C>(fy_len);
-    }
-    const int L = (int)lv.size() - 1;
-    step("gather x2", KIND_PERM, 2 * perm_bytes(n), [&] {
-      launch_gather<P>((const O*)x0, perm_d, t, n, st);
-      launch_gather<P>((const O*)x1, perm_d, t2, n, st);
-    });
-    bool last_done = false;
-    for (int l = 0; l <= L; ++l) {
-      if (l == L && last_done) break;
-      if (lv[l].nb > 0)
-        step("trisolve_down x2 L" + std::to_string(l), KIND_TRI, 0.0,
-             [&] { trisolve_pair(l, TRI_DOWN); });
-      if (l < L) {
-        const bool a0 = interface(l, lv[l].k, t, !no_fuse_small);
-        const bool a1 = interface(l, lv[l].k, t2, !no_fuse_small);
-        last_done = a0 && a1;
-      }
-    }
-    for (int l = L - 1; l >= 0; --l)
-      if (lv[l].nb > 0)
-        step("trisolve_up x2 L" + std::to_string(l), KIND_TRI, 0.0,
-             [&] { trisolve_pair(l, TRI_UP); });
-    step("scatter x2", KIND_PERM, 2 * perm_bytes(n), [&] {
-      launch_scatter<P>(t, perm_d, (O*)y0, n, st);
-      launch_scatter<P>(t2, perm_d, (O*)y1, n, st);
-    });
-    return true;
   }
 
   int profile(const void* x, void* y, int reps, std::vector<double>& ms,

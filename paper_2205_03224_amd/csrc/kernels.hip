@@ -428,7 +428,7 @@ __device__ __forceinline__ void from_high(dcplx x, dcplx dead, dcplx& lo, dcplx&
 // NN products and the finish, and the far gathers and loads travel while the
 // previous stage completes.  Scheduling barriers keep the order; the compiler
 // places the waits at the first use of each gathered value.
-template <class P, int MS, bool HALF, int NB>
+template <class P, int MS, bool HALF>
 struct PipeRegs {
   using C = typename P::C;
   static constexpr int SL = HALF ? MS / 2 : MS;  // slots per lane
@@ -442,9 +442,8 @@ struct PipeRegs {
   uint32_t row;  // LDS byte offset of the lane's row in the block vector, or
                  // of the dummy slot (idle lanes; in half rows the high lane)
   int nr;   // rows of the stage (uniform; 0 past the chunk's last stage)
-  C xv[SL];                     // gathered block-vector values
-  C xw[NB == 2 ? SL : 1];       // the second right-hand side's
-  C b, bw;                      // current value of the row (right-hand side)
+  C xv[SL];  // gathered block-vector values
+  C b;       // current value of the row (right-hand side)
 };
 
 // load of a value at LDS byte address a
@@ -484,12 +483,12 @@ __device__ __forceinline__ void lds_st<dcplx>(uint32_t a, dcplx v) {
 }
 
 // LDS byte address of a block-vector element (x0: LDS address of x[0])
-template <class P, int MS, bool HALF, int NB>
-__device__ __forceinline__ void st_addr(PipeRegs<P, MS, HALF, NB>& R, uint32_t x0) {
+template <class P, int MS, bool HALF>
+__device__ __forceinline__ void st_addr(PipeRegs<P, MS, HALF>& R, uint32_t x0) {
   using C = typename P::C;
   constexpr int kMul = (int)sizeof(C) / ColScale<C>::value;
 #pragma unroll
-  for (int j = 0; j < PipeRegs<P, MS, HALF, NB>::SL; ++j) {
+  for (int j = 0; j < PipeRegs<P, MS, HALF>::SL; ++j) {
     R.ad[j] = x0 + (j % 2 ? R.cw[j / 2] >> 16 : R.cw[j / 2] & 0xffffu) * kMul;
     asm volatile("" : "+v"(R.ad[j]));  // formed here, not again before the gathers
   }
@@ -497,14 +496,14 @@ __device__ __forceinline__ void st_addr(PipeRegs<P, MS, HALF, NB>& R, uint32_t x
 
 // loads of one stage whose row info is `info` and first chunk row r0; the
 // chunk's sections are given by LDS byte addresses (32-bit arithmetic)
-template <class P, int MS, bool HALF, bool ISU, int NB>
+template <class P, int MS, bool HALF, bool ISU>
 __device__ __forceinline__ void st_load(uint32_t vbase, uint32_t dbase, uint32_t cbase,
                                         uint32_t info, int r0, int ql, int half, int dummy,
-                                        PipeRegs<P, MS, HALF, NB>& R) {
+                                        PipeRegs<P, MS, HALF>& R) {
   using C = typename P::C;
   using V = typename P::V;
   using D = typename P::D;
-  using RG = PipeRegs<P, MS, HALF, NB>;
+  using RG = PipeRegs<P, MS, HALF>;
   constexpr int VS = stream_vstride(MS), CS = stream_cstride(MS);
   constexpr int CO = HALF ? stream_half_coff(MS) : 0;
   static_assert(CO + RG::SL <= CS, "column row holds both halves");
@@ -522,83 +521,59 @@ __device__ __forceinline__ void st_load(uint32_t vbase, uint32_t dbase, uint32_t
   if (ISU) R.dv = cvt<C>(lds_ld<D>(dbase + q * (uint32_t)sizeof(D)));
 }
 
-// gathers of slots J0 .. J1 - 1 (both right-hand sides with NB = 2: one
-// two-address instruction per slot)
-template <int J0, int J1, class P, int MS, bool HALF, int NB>
-__device__ __forceinline__ void st_gather(PipeRegs<P, MS, HALF, NB>& R) {
+// gathers of slots J0 .. J1 - 1
+template <int J0, int J1, class P, int MS, bool HALF>
+__device__ __forceinline__ void st_gather(PipeRegs<P, MS, HALF>& R) {
   using C = typename P::C;
-  constexpr int kX2 = pair_offset<C>();
 #pragma unroll
-  for (int j = J0; j < J1; ++j) {
-    R.xv[j] = lds_ld<C>(R.ad[j]);
-    if (NB == 2) R.xw[j] = lds_ld<C>(R.ad[j] + kX2);
-  }
+  for (int j = J0; j < J1; ++j) R.xv[j] = lds_ld<C>(R.ad[j]);
 }
 // current value of the lane's row
-template <class P, int MS, bool HALF, int NB>
-__device__ __forceinline__ void st_gather_b(PipeRegs<P, MS, HALF, NB>& R, uint32_t x0) {
+template <class P, int MS, bool HALF>
+__device__ __forceinline__ void st_gather_b(PipeRegs<P, MS, HALF>& R, uint32_t x0) {
   using C = typename P::C;
-  constexpr int kX2 = pair_offset<C>();
   R.b = lds_ld<C>(x0 + R.row);
-  if (NB == 2) R.bw = lds_ld<C>(x0 + R.row + kX2);
 }
 
-// the two partial sums of each right-hand side (even and odd slots; padded
-// entries are zero)
+// the two partial sums (even and odd slots; padded entries are zero)
 template <class C>
 struct PipeAcc {
-  C s0, s1, w0, w1;
+  C s0, s1;
 };
-template <int J0, int J1, class P, int MS, bool HALF, int NB>
-__device__ __forceinline__ void st_sum(const PipeRegs<P, MS, HALF, NB>& R, PipeAcc<typename P::C>& a) {
+template <int J0, int J1, class P, int MS, bool HALF>
+__device__ __forceinline__ void st_sum(const PipeRegs<P, MS, HALF>& R, PipeAcc<typename P::C>& a) {
 #pragma unroll
   for (int j = J0; j < J1; ++j) {
-    if (j % 2 == 0) {
-      a.s0 += R.v[j] * R.xv[j];
-      if (NB == 2) a.w0 += R.v[j] * R.xw[j];
-    } else {
-      a.s1 += R.v[j] * R.xv[j];
-      if (NB == 2) a.w1 += R.v[j] * R.xw[j];
-    }
+    if (j % 2 == 0) a.s0 += R.v[j] * R.xv[j];
+    else a.s1 += R.v[j] * R.xv[j];
   }
 }
 
 // x[row] = (b - sum_j v_j x[c_j]) (* 1/u_ii); half rows: the low lane adds
 // its half sum and the high lane's, in that order (the high lane stores to
 // the dummy slot)
-template <class P, int MS, bool HALF, bool ISU, int NB>
-__device__ __forceinline__ void st_finish(const PipeRegs<P, MS, HALF, NB>& R,
+template <class P, int MS, bool HALF, bool ISU>
+__device__ __forceinline__ void st_finish(const PipeRegs<P, MS, HALF>& R,
                                           const PipeAcc<typename P::C>& a, uint32_t x0) {
   using C = typename P::C;
-  constexpr int kX2 = pair_offset<C>();
-  C acc, aw = zero<C>();
+  C acc;
   if (HALF) {
     C p, o;
     from_high(a.s0 + a.s1, a.s1, p, o);
     acc = R.b - (p + o);
-    if (NB == 2) {
-      C pw, ow;
-      from_high(a.w0 + a.w1, a.w1, pw, ow);
-      aw = R.bw - (pw + ow);
-    }
   } else {
     acc = R.b - (a.s0 + a.s1);
-    if (NB == 2) aw = R.bw - (a.w0 + a.w1);
   }
-  if (ISU) {
-    acc *= R.dv;
-    if (NB == 2) aw *= R.dv;
-  }
+  if (ISU) acc *= R.dv;
   lds_st<C>(x0 + R.row, acc);
-  if (NB == 2) lds_st<C>(x0 + R.row + kX2, aw);
 }
 
-template <class P, int MS, bool HALF, bool ISU, int NB>
+template <class P, int MS, bool HALF, bool ISU>
 __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& cd, int lane,
                                             typename P::C* x, int dummy) {
   using C = typename P::C;
   using V = typename P::V;
-  using RG = PipeRegs<P, MS, HALF, NB>;
+  using RG = PipeRegs<P, MS, HALF>;
   constexpr int SL = RG::SL, NF = RG::NF, NW = RG::NW;
   // LDS operations of one stage's loads (paired where adjacent) and of the
   // far gathers; the loads go ahead of the near wait when the near gathers
@@ -622,31 +597,31 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
   // slots of stage 0 gathered (everything before the chunk is complete).
   // Row info read past the chunk's last stage is the closing zero word: a
   // stage of no rows.
-  st_load<P, MS, HALF, ISU, NB>(vbase, dbase, cbase, rinfo(ql), 0, ql, half, dummy, A);
+  st_load<P, MS, HALF, ISU>(vbase, dbase, cbase, rinfo(ql), 0, ql, half, dummy, A);
   int r = A.nr;
   uint32_t info = rinfo(min(r + ql, nrows));
-  st_load<P, MS, HALF, ISU, NB>(vbase, dbase, cbase, info, r, ql, half, dummy, B);
+  st_load<P, MS, HALF, ISU>(vbase, dbase, cbase, info, r, ql, half, dummy, B);
   r += B.nr;
   info = rinfo(min(r + ql, nrows));
-  st_addr<P, MS, HALF, NB>(A, x0);
+  st_addr<P, MS, HALF>(A, x0);
   st_gather<0, NF>(A);
   st_gather_b(A, x0);
   // one stage: cur = s, nxt = s+1, far receives s+2
   const auto step = [&](RG& cur, RG& nxt, RG& far, int s) {
     st_gather<NF, SL>(cur);
     __builtin_amdgcn_sched_barrier(0);
-    st_addr<P, MS, HALF, NB>(nxt, x0);
+    st_addr<P, MS, HALF>(nxt, x0);
     st_gather<0, NF>(nxt);
     st_gather_b(nxt, x0);
     __builtin_amdgcn_sched_barrier(0);
     const auto loads = [&] {
-      st_load<P, MS, HALF, ISU, NB>(vbase, dbase, cbase, info, r, ql, half, dummy, far);
+      st_load<P, MS, HALF, ISU>(vbase, dbase, cbase, info, r, ql, half, dummy, far);
       r += far.nr;
       info = rinfo(min(r + ql, nrows));
     };
     if (kEarly) loads();
     __builtin_amdgcn_sched_barrier(0);
-    PipeAcc<C> acc{zero<C>(), zero<C>(), zero<C>(), zero<C>()};
+    PipeAcc<C> acc{zero<C>(), zero<C>()};
     st_sum<0, NF>(cur, acc);
     __builtin_amdgcn_sched_barrier(0);
     if (!kEarly) {
@@ -657,7 +632,7 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
     } else {
       st_sum<NF, SL>(cur, acc);
     }
-    st_finish<P, MS, HALF, ISU, NB>(cur, acc, x0);
+    st_finish<P, MS, HALF, ISU>(cur, acc, x0);
     __builtin_amdgcn_sched_barrier(0);
   };
   for (int s = 0;; s += 3) {
@@ -670,71 +645,102 @@ __device__ __forceinline__ void chunk_sweep(const uint8_t* cb, const ChunkDesc& 
   }
 }
 
-// Right-hand side of a block into LDS: DOWN reads b1, UP reads F_l y2.
-// 256 bytes of loads per thread in flight at once (a whole 4096-row float64
-// block in one round trip with 128 threads).
-template <class P, int MODE, int NT>
-__device__ __forceinline__ void load_rhs(const TriArgs<P>& a, const typename P::X* tv,
-                                         const typename P::C* fyv, int r0, int nr, int tid,
-                                         typename P::C* x) {
-  using C = typename P::C;
-  constexpr int U = 256 / (int)sizeof(C) < 32 ? 256 / (int)sizeof(C) : 32;
-  for (int i0 = tid; i0 < nr; i0 += NT * U) {
-    C r[U];
-    if (MODE == TRI_DOWN && a.xin) {
-      int src[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int row = r0 + min(i0 + u * NT, nr - 1);
-        src[u] = a.perm ? a.perm[row] : row;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) r[u] = cvt<C>(a.xin[src[u]]);
-    } else if (MODE == TRI_DOWN) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) r[u] = cvt<C>(tv[r0 + min(i0 + u * NT, nr - 1)]);
-    } else {
-#pragma unroll
-      for (int u = 0; u < U; ++u) r[u] = fyv[r0 + min(i0 + u * NT, nr - 1)];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * NT;
-      if (i < nr) x[i] = r[u];
-    }
+// Vector c and row i of flat index e = c * nr + i, nv vectors (inv = 1 / nr
+// in float: the quotient is off by at most one for e < 2^22 nr, fixed by one
+// step)
+__device__ __forceinline__ void split_flat(int e, int nr, int nv, float inv, int& c, int& i) {
+  if (nv == 1) {
+    c = 0;
+    i = e;
+    return;
+  }
+  c = (int)((float)e * inv);
+  i = e - c * nr;
+  if (i < 0) {
+    --c;
+    i += nr;
+  } else if (i >= nr) {
+    ++c;
+    i -= nr;
   }
 }
 
-// Right-hand side of the up sweep, F_l y2, from the unit's F records (rows
+// Right-hand sides of a block into LDS, vector c of the workgroup at
+// x + c * xs: DOWN reads b1, UP reads F_l y2.  The nv * nr entries form one
+// flat range with U loads per thread in flight at once (U = 32 float64
+// values: a whole 4096-row block in one round trip with 128 threads).
+template <class P, int MODE, int U>
+__device__ __forceinline__ void load_rhs(const TriArgs<P>& a, int r0, int nr, int nv, int tid,
+                                         int nt, typename P::C* x, int xs) {
+  using C = typename P::C;
+  const int tot = nv * nr;
+  const float inv = 1.0f / (float)max(nr, 1);
+  for (int e0 = tid; e0 < tot; e0 += nt * U) {
+    C r[U];
+    int dst[U];
+    if (MODE == TRI_DOWN && a.xin) {
+      // one vector (the caller's), read through the permutation: all
+      // permutation loads first, then all vector loads (two round trips)
+      int src[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        dst[u] = min(e0 + u * nt, tot - 1);
+        src[u] = r0 + dst[u];
+      }
+      if (a.perm) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) src[u] = a.perm[src[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) r[u] = cvt<C>(a.xin[src[u]]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        int c, i;
+        split_flat(min(e0 + u * nt, tot - 1), nr, nv, inv, c, i);
+        dst[u] = c * xs + i;
+        if (MODE == TRI_DOWN) r[u] = cvt<C>(a.t[(int64_t)c * a.ldt + r0 + i]);
+        else r[u] = a.fy[(int64_t)c * a.ldfy + r0 + i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + u * nt < tot) x[dst[u]] = r[u];
+  }
+}
+
+// Right-hand sides of the up sweep, F_l y2, from the unit's F records (rows
 // without entries are zero): every row's entries are added from zero in
-// stored order, the operations of k_fy, so the sums are the same.  Eight
-// records per thread and four entries of each are in flight at once; the
-// zero fill is ordered before the records' stores by a bare barrier, so the
-// producer's first chunk copy stays in flight.
-template <class P, int NB, int NT>
-__device__ __forceinline__ void rhs_from_f(const TriArgs<P>& a, int b, int nr, int tid,
-                                           typename P::C* x, typename P::C* x2) {
+// stored order, the operations of k_fy, so the sums are the same.  The
+// (vector, record) pairs form one flat range; U pairs per thread and four
+// entries of each are in flight at once.  The zero fill is ordered before
+// the records' stores by a bare barrier, so the producer's first chunk copy
+// stays in flight.
+template <class P, int U>
+__device__ __forceinline__ void rhs_from_f(const TriArgs<P>& a, int b, int nv, int tid, int nt,
+                                           typename P::C* x, int xs) {
   using C = typename P::C;
   using X = typename P::X;
-  for (int i = tid; i < nr; i += NT) {
-    x[i] = zero<C>();
-    if (NB == 2) x2[i] = zero<C>();
-  }
+  for (int e = tid; e < nv * xs; e += nt) x[e] = zero<C>();
   __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);
   __builtin_amdgcn_s_barrier();
   const X* y2 = a.t + a.d;
-  const X* y2b = NB == 2 ? a.t2 + a.d : nullptr;
   const int q0 = a.funit[b], q1 = a.funit[b + 1];
-  constexpr int U = 8, J = 4;
-  for (int qb = q0 + tid; qb < q1; qb += NT * U) {
-    int q[U], row[U];
-    C r[U], r2[U];
+  const int nq = q1 - q0, tot = nv * nq;
+  const float inv = 1.0f / (float)max(nq, 1);
+  constexpr int J = 4;
+  for (int eb = tid; eb < tot; eb += nt * U) {
+    int q[U], dst[U];
+    const X* yv[U];
+    C r[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      q[u] = min(qb + u * NT, q1 - 1);
-      row[u] = a.frow[q[u]];
+      int c, i;
+      split_flat(min(eb + u * nt, tot - 1), nq, nv, inv, c, i);
+      q[u] = q0 + i;
+      dst[u] = c * xs + a.frow[q[u]];
+      yv[u] = y2 + (int64_t)c * a.ldt;
       r[u] = zero<C>();
-      r2[u] = zero<C>();
     }
     for (int j0 = 0; j0 < a.fw; j0 += J) {
       int cc[U][J];
@@ -751,100 +757,113 @@ __device__ __forceinline__ void rhs_from_f(const TriArgs<P>& a, int b, int nr, i
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int jj = 0; jj < J; ++jj) {
-          r[u] += fv[u][jj] * cvt<C>(y2[cc[u][jj]]);
-          if (NB == 2) r2[u] += fv[u][jj] * cvt<C>(y2b[cc[u][jj]]);
-        }
+        for (int jj = 0; jj < J; ++jj) r[u] += fv[u][jj] * cvt<C>(yv[u][cc[u][jj]]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (qb + u * NT < q1) {
-        x[row[u]] = r[u];
-        if (NB == 2) x2[row[u]] = r2[u];
-      }
+      if (eb + u * nt < tot) x[dst[u]] = r[u];
   }
 }
 
-// Result of a block from LDS: DOWN stores z1, UP stores z1 - (LU)^{-1} F y2.
-template <class P, int MODE, int NT>
-__device__ __forceinline__ void store_result(const TriArgs<P>& a, typename P::X* tv, int r0,
-                                             int nr, int tid, const typename P::C* x) {
+// Results of a block from LDS: DOWN stores z1, UP stores z1 - (LU)^{-1} F y2.
+template <class P, int MODE>
+__device__ __forceinline__ void store_result(const TriArgs<P>& a, int r0, int nr, int nv, int tid,
+                                             int nt, const typename P::C* x, int xs) {
   using C = typename P::C;
   using X = typename P::X;
   constexpr int U = 8;
-  for (int i0 = tid; i0 < nr; i0 += NT * U) {
+  const int tot = nv * nr;
+  const float inv = 1.0f / (float)max(nr, 1);
+  for (int e0 = tid; e0 < tot; e0 += nt * U) {
     if (MODE == TRI_DOWN) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * NT;
-        if (i < nr) tv[r0 + i] = cvt<X>(x[i]);
+        int c, i;
+        split_flat(min(e0 + u * nt, tot - 1), nr, nv, inv, c, i);
+        if (e0 + u * nt < tot) a.t[(int64_t)c * a.ldt + r0 + i] = cvt<X>(x[c * xs + i]);
       }
     } else if (a.yout) {
-      // y1 = z1 - x straight to the caller's vector
+      // one vector: y1 = z1 - x straight to the caller's vector
       C z[U];
       int dst[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int row = r0 + min(i0 + u * NT, nr - 1);
-        z[u] = cvt<C>(a.t[row]);
-        dst[u] = a.perm ? a.perm[row] : row;
+        dst[u] = r0 + min(e0 + u * nt, tot - 1);
+        z[u] = cvt<C>(a.t[dst[u]]);
+      }
+      if (a.perm) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) dst[u] = a.perm[dst[u]];
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * NT;
-        if (i < nr) a.yout[dst[u]] = cvt<typename P::O>(z[u] - x[i]);
-      }
+      for (int u = 0; u < U; ++u)
+        if (e0 + u * nt < tot) a.yout[dst[u]] = cvt<typename P::O>(z[u] - x[e0 + u * nt]);
     } else {
       // unconditional clamped loads: all U in flight before the stores
       C z[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) z[u] = cvt<C>(tv[r0 + min(i0 + u * NT, nr - 1)]);
+      int64_t g[U];
+      int li[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * NT;
-        if (i < nr) tv[r0 + i] = cvt<X>(z[u] - x[i]);
+        int c, i;
+        split_flat(min(e0 + u * nt, tot - 1), nr, nv, inv, c, i);
+        g[u] = (int64_t)c * a.ldt + r0 + i;
+        li[u] = c * xs + i;
+        z[u] = cvt<C>(a.t[g[u]]);
       }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (e0 + u * nt < tot) a.t[g[u]] = cvt<X>(z[u] - x[li[u]]);
     }
   }
 }
 
-template <class P, int MS, int MODE, int NB>
-__global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a0) {
+// One workgroup per diagonal block (or group of blocks) and group of up to
+// ncons vectors: waves 0 .. ncons - 1 sweep one vector each out of LDS,
+// wave ncons copies the block's chunks.  All consumers sweep the same chunk
+// between two barriers, so the factor entries cross HBM once for all of
+// them.  Consumers without a vector (the launch's last group) only take
+// part in the barriers.  MULTI false: one consumer and one vector per
+// workgroup (vector blockIdx.y), with the register budget of two waves.
+template <class P, int MS, int MODE, bool MULTI>
+__global__ __launch_bounds__(MULTI ? kWave * (stream_max_cons(sizeof(typename P::C), MS) + 1)
+                                   : 2 * kWave) void k_trisolve_streamed(
+    TriArgs<P> a0) {
   using C = typename P::C;
-  using X = typename P::X;
-  // vector blockIdx.y of a batched launch
   TriArgs<P> a = a0;
-  a.t += (int64_t)blockIdx.y * a0.ldt;
-  a.fy += (int64_t)blockIdx.y * a0.ldfy;
+  const int ncons = MULTI ? a0.ncons : 1;
+  const int g0 = (int)blockIdx.y * ncons;
+  const int nv = MULTI ? min(ncons, a0.nvec - g0) : 1;
+  a.t += (int64_t)g0 * a0.ldt;
+  a.fy += (int64_t)g0 * a0.ldfy;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
+  const int nt = kWave * (ncons + 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // uniform: scalar branches
   const int lane = tid % kWave;
   const int r0 = a.blk_row[b];
   const int nr = a.blk_row[b + 1] - r0;
+  // block vector of consumer c at byte c * x_bytes, the two buffers after
   C* x = reinterpret_cast<C*>(smem_raw);
-  // NB = 2: the second block vector at pair_offset, the buffers after it
-  C* x2 = reinterpret_cast<C*>(smem_raw + pair_offset<C>());
-  uint8_t* bufs = smem_raw + (NB == 2 ? 2 * pair_offset<C>() : a.x_bytes);
+  const int xs = a.x_bytes / (int)sizeof(C);
+  uint8_t* bufs = smem_raw + (size_t)ncons * a.x_bytes;
   const int c0 = a.blk_chunk[b], c1 = a.blk_chunk[b + 1];
   DescCache dc;
   if (c0 < c1) desc_fill<P>(a, c0, c1, lane, dc);
   const auto iters = [&](const ChunkDesc& cd) { return ((int)cd.n16 + kWave - 1) / kWave; };
-  if (wave == 1 && c0 < c1) {
+  if (wave == ncons && c0 < c1) {
     const ChunkDesc cd = desc_get<P>(a, c0, c1, lane, dc);
     copy_chunk<P>(a, cd, bufs, lane, iters(cd));
   }
-  if (MODE == TRI_UP && a.frow) {
-    rhs_from_f<P, NB, 2 * kWave>(a, b, nr, tid, x, x2);
-  } else {
-    load_rhs<P, MODE, 2 * kWave>(a, a.t, a.fy, r0, nr, tid, x);
-    if (NB == 2) load_rhs<P, MODE, 2 * kWave>(a, a.t2, a.fy2, r0, nr, tid, x2);
-  }
+  // prologue unrolls within the register budget of the workgroup size
+  constexpr int kU = 256 / (int)sizeof(C) < 32 ? 256 / (int)sizeof(C) : 32;
+  if (MODE == TRI_UP && a.frow) rhs_from_f<P, MULTI ? 4 : 8>(a, b, nv, tid, nt, x, xs);
+  else load_rhs<P, MODE, MULTI ? kU / 2 : kU>(a, r0, nr, nv, tid, nt, x, xs);
   __syncthreads();
   for (int c = c0; c < c1; ++c) {
     const int k = c - c0;
-    if (wave == 1) {
+    if (wave == ncons) {
       // the buffer of chunk c - 1 is free: fill it with chunk c + 1, then
       // wait until that has landed
       if (c + 1 < c1) {
@@ -860,15 +879,20 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a0) {
       // wait of the sweep below into a full one.
       __builtin_amdgcn_s_waitcnt(0);
       const ChunkDesc cd = desc_get<P>(a, c, c1, lane, dc);
-      uint8_t* cur = bufs + (k % 2) * a.chunk_cap;
-      // idle lanes store to the slot after the block's rows
-      const int dummy = nr * (int)sizeof(C);
-      if (cd.nst & 0x8000) {
-        if (a.half_u) chunk_sweep<P, MS, true, true, NB>(cur, cd, lane, x, dummy);
-        else chunk_sweep<P, MS, false, true, NB>(cur, cd, lane, x, dummy);
-      } else {
-        if (a.half_l) chunk_sweep<P, MS, true, false, NB>(cur, cd, lane, x, dummy);
-        else chunk_sweep<P, MS, false, false, NB>(cur, cd, lane, x, dummy);
+      if (wave < nv) {
+        uint8_t* cur = bufs + (k % 2) * a.chunk_cap;
+        // (the single-vector kernel keeps the constant base: every gather
+        // address is then the stored offset itself)
+        C* xv = MULTI ? x + wave * xs : x;
+        // idle lanes store to the slot after the block's rows
+        const int dummy = nr * (int)sizeof(C);
+        if (cd.nst & 0x8000) {
+          if (a.half_u) chunk_sweep<P, MS, true, true>(cur, cd, lane, xv, dummy);
+          else chunk_sweep<P, MS, false, true>(cur, cd, lane, xv, dummy);
+        } else {
+          if (a.half_l) chunk_sweep<P, MS, true, false>(cur, cd, lane, xv, dummy);
+          else chunk_sweep<P, MS, false, false>(cur, cd, lane, xv, dummy);
+        }
       }
       // every read of the buffer done before the producer may refill it
       __builtin_amdgcn_s_waitcnt(GS_LGKM0_IMM);
@@ -877,46 +901,40 @@ __global__ __launch_bounds__(128) void k_trisolve_streamed(TriArgs<P> a0) {
     __builtin_amdgcn_s_barrier();
   }
   __syncthreads();
-  store_result<P, MODE, 2 * kWave>(a, a.t, r0, nr, tid, x);
-  if (NB == 2) store_result<P, MODE, 2 * kWave>(a, a.t2, r0, nr, tid, x2);
+  store_result<P, MODE>(a, r0, nr, nv, tid, nt, x, xs);
 }
 
-template <class P, int MS, int MODE, int NB>
-static void launch_stream_ms(const TriArgs<P>& a, hipStream_t st) {
-  // 1 KiB of slack after the second buffer: lanes past the end of a stage
-  // read (and then discard) up to 63 elements beyond a section
-  using C = typename P::C;
-  const size_t xreg = NB == 2 ? 2 * (size_t)pair_offset<C>() : (size_t)a.x_bytes;
-  const size_t lds = xreg + 2 * (size_t)a.chunk_cap + 1024;
-  auto kern = k_trisolve_streamed<P, MS, MODE, NB>;
+template <class P, int MS, int MODE, bool MULTI>
+static void launch_stream_kern(const TriArgs<P>& a, int nc, hipStream_t st) {
+  const size_t lds = stream_lds_bytes(a.x_bytes, a.chunk_cap, nc);
+  auto kern = k_trisolve_streamed<P, MS, MODE, MULTI>;
   static size_t attr_set = 65536;
   if (lds > attr_set) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     attr_set = lds;
   }
-  hipLaunchKernelGGL(kern, dim3(a.nb, a.nvec), dim3(2 * kWave), lds, st, a);
+  TriArgs<P> b = a;
+  b.ncons = nc;
+  const unsigned groups = (unsigned)((std::max(a.nvec, 1) + nc - 1) / nc);
+  hipLaunchKernelGGL(kern, dim3(a.nb, groups), dim3(kWave * (nc + 1)), lds, st, b);
+}
+template <class P, int MS, int MODE>
+static void launch_stream_ms(const TriArgs<P>& a, hipStream_t st) {
+  const int nc = std::max(1, std::min(a.ncons, stream_max_cons(sizeof(typename P::C), MS)));
+  if (nc == 1) launch_stream_kern<P, MS, MODE, false>(a, 1, st);
+  else launch_stream_kern<P, MS, MODE, true>(a, nc, st);
 }
 
-template <class P, int MODE, int NB>
-static void launch_stream_nb(const TriArgs<P>& a, int maxslot, hipStream_t st) {
-  // the layout was padded to stream_slots(maxslot) slots per stage
-  const int ms = stream_slots(maxslot);
-  if (ms == 4) launch_stream_ms<P, 4, MODE, NB>(a, st);
-  else if (ms == 8) launch_stream_ms<P, 8, MODE, NB>(a, st);
-  else if (ms == 10) launch_stream_ms<P, 10, MODE, NB>(a, st);
-  else if (ms == 12) launch_stream_ms<P, 12, MODE, NB>(a, st);
-  else launch_stream_ms<P, 16, MODE, NB>(a, st);
-}
 template <class P, int MODE>
 static void launch_stream_mode(const TriArgs<P>& a, int maxslot, hipStream_t st) {
-  if constexpr (pair_offset<typename P::C>() > 0) {
-    if (a.nrhs == 2) {
-      launch_stream_nb<P, MODE, 2>(a, maxslot, st);
-      return;
-    }
-  }
-  launch_stream_nb<P, MODE, 1>(a, maxslot, st);
+  // the layout was padded to stream_slots(maxslot) slots per stage
+  const int ms = stream_slots(maxslot);
+  if (ms == 4) launch_stream_ms<P, 4, MODE>(a, st);
+  else if (ms == 8) launch_stream_ms<P, 8, MODE>(a, st);
+  else if (ms == 10) launch_stream_ms<P, 10, MODE>(a, st);
+  else if (ms == 12) launch_stream_ms<P, 12, MODE>(a, st);
+  else launch_stream_ms<P, 16, MODE>(a, st);
 }
 
 // fy = F_l y2 (most rows of B_l have no entry), so the up sweep's
@@ -956,9 +974,6 @@ void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot, int ma
     if (!a.frow) {
       const dim3 gfy((unsigned)((a.d + 256 * kFyRows - 1) / (256 * kFyRows)), a.nvec);
       hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t + a.d, a.fy, a.d, a.ldt, a.ldfy);
-      if (a.nrhs == 2)
-        hipLaunchKernelGGL(k_fy<P>, gfy, dim3(256), 0, st, a.F, a.t2 + a.d, a.fy2, a.d, a.ldt,
-                           a.ldfy);
     }
     launch_stream_mode<P, TRI_UP>(a, maxslot, st);
   }

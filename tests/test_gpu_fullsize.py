@@ -90,7 +90,7 @@ def test_fullsize_apply_matches_oracle(torch_dev, full):
     ctx = gemslr.Context(0)
     ctx.setup_explicit(w.rowptr, w.col, w.val, st.perm, oracle_levels(st))
     rs = np.random.default_rng(11)
-    X = rs.standard_normal((2, w.n))
+    X = rs.standard_normal((3, w.n))
     xd = torch.from_numpy(X).cuda()
     yd = torch.empty_like(xd)
     ctx.apply(xd[0], yd[0])
@@ -101,10 +101,13 @@ def test_fullsize_apply_matches_oracle(torch_dev, full):
     # the same input again gives the same bits (no races, no stale state)
     y2 = torch.empty_like(xd[0])
     ctx.apply(xd[0], y2)
-    # two right-hand sides per call: each column equals its single apply
+    # three right-hand sides per call (at level 0 one workgroup sweeps all
+    # three over the same staged factor entries): each column equals its
+    # single apply
     ym = torch.empty_like(xd)
-    ctx.apply_many(2, xd, ym)
+    ctx.apply_many(3, xd, ym)
     ctx.apply(xd[1], yd[1])
+    ctx.apply(xd[2], yd[2])
     torch.cuda.synchronize()
     assert torch.equal(y2, yd[0])
     assert torch.equal(ym, yd)

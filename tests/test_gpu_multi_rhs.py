@@ -1,7 +1,9 @@
-"""Several right-hand sides per apply (gs_apply_many): two vectors share
-each level's triangular-sweep launch (the factor entries are read once for
-both); three or more go through launches that cover all of them at every
-step (vector = workgroup row of the grid).  Every column must equal the
+"""Several right-hand sides per apply (gs_apply_many): every launch of a
+level covers all vectors, and in the streamed triangular sweeps a workgroup
+may sweep a group of vectors (one consumer wave each) over the same staged
+factor entries.  At these sizes the library would pick one vector per
+workgroup, so GEMSLR_CONSUMERS forces groups of 2, 3 and 8 (with 8 vectors
+and groups of 3: launches of 3 + 3 and 2).  Every column must equal the
 oracle's apply of that column to the float64 apply tolerance, and, since
 each right-hand side goes through the same operations in the same order as
 in a single apply, equal the single apply of the same column bit for bit.
@@ -52,7 +54,9 @@ def _block(w, nrhs, seed):
     return X
 
 
-@pytest.mark.parametrize("env", [{}, {"GEMSLR_GROUP_CUS": "4"}, {"GEMSLR_NO_STREAM": "1"}])
+@pytest.mark.parametrize("env", [{}, {"GEMSLR_GROUP_CUS": "4"}, {"GEMSLR_NO_STREAM": "1"},
+                                 {"GEMSLR_CONSUMERS": "2"}, {"GEMSLR_CONSUMERS": "3"},
+                                 {"GEMSLR_CONSUMERS": "8", "GEMSLR_GROUP_CUS": "4"}])
 @pytest.mark.parametrize("name", ["laplace2d_32", "convdiff3d_20_p27", "helmholtz3d_16_p8"])
 @pytest.mark.parametrize("nrhs", [2, 3, 4, 8])
 def test_apply_many_matches_oracle_and_single(torch_dev, name, nrhs, env, monkeypatch):
@@ -79,14 +83,17 @@ def test_apply_many_matches_oracle_and_single(torch_dev, name, nrhs, env, monkey
     ctx.close()
 
 
+@pytest.mark.parametrize("cons", [None, "3"])
 @pytest.mark.parametrize("nrhs", [2, 5])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_apply_many_mixed_forms_equal_single(torch_dev, prec, nrhs):
+def test_apply_many_mixed_forms_equal_single(torch_dev, prec, nrhs, cons, monkeypatch):
     """The float32-sweep forms share launches between right-hand sides as
     well; each column equals the single apply of the same form bit for
     bit."""
     torch = torch_dev
     from paper_2205_03224_amd import gemslr
+    if cons:
+        monkeypatch.setenv("GEMSLR_CONSUMERS", cons)
     w, st = _case("convdiff3d_20_p27")
     ctx = gemslr.Context(0)
     ctx.setup_explicit(w.rowptr, w.col, w.val, st.perm, oracle_levels(st))
