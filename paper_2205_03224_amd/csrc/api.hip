@@ -37,6 +37,7 @@ struct gs_ctx {
   int w_m = -1;
   void* pin = nullptr;  // pinned staging for small device->host reads
   size_t pin_bytes = 0;
+  hipEvent_t fg_ev[2] = {nullptr, nullptr};  // FGMRES: Hessenberg columns landed
   gs_info info{};
   std::vector<std::string> step_labels;  // of the last gs_apply_profile
   int nparts = 1;                         // of the last gs_setup (feature cut flags)
@@ -121,8 +122,15 @@ template <class T>
 static int schur_basis(int m, const std::vector<cplx>& Sm, int k, std::vector<cplx>& Tm,
                        std::vector<cplx>& Q, std::vector<cplx>& theta_k, std::vector<T>& G,
                        std::vector<T>& R) {
-  Tm = Sm;
-  schur_complex(m, Tm, Q);
+  if (std::is_same<T, double>::value) {
+    // real Rayleigh matrix: real double-shift iteration
+    std::vector<double> Sr((size_t)m * m);
+    for (size_t e = 0; e < Sr.size(); ++e) Sr[e] = Sm[e].real();
+    schur_real(m, Sr, Tm, Q);
+  } else {
+    Tm = Sm;
+    schur_complex(m, Tm, Q);
+  }
   return schur_basis_from<T>(m, Sm, k, Tm, Q, theta_k, G, R);
 }
 
@@ -725,16 +733,34 @@ static int fgmres(gs_ctx* c, const void* b_user, void* x_user, double tol, gs_in
     std::fill(g.begin(), g.end(), T(0));
     g[0] = beta;
     int jend = 0;
-    for (int j = 0; j < m; ++j) {
+    // Step j's device work (apply, product, orthogonalisation, next basis
+    // vector) needs nothing from the host, which only turns the Hessenberg
+    // columns into Givens rotations for the residual estimate and the final
+    // least-squares solve.  So step j + 1 is queued before the host waits
+    // for column j: the device never waits for the host.  A step queued
+    // after the one that ends the cycle is left unused (its columns are
+    // past jend).  Columns land in two pinned slots, step j's in slot j % 2.
+    const size_t slot = ((size_t)(m + 1) * sizeof(DT) + sizeof(double) + 15) & ~(size_t)15;
+    char* pslots = (char*)pinned(c, 2 * slot);
+    auto issue = [&](int j) {
       c->eng->apply(V + (size_t)j * n, Z + (size_t)j * n, true);
       launch_spmv<DT>(c->a_rp, c->a_ci, Av, Z + (size_t)j * n, w, n, st);
       cgs2<DT>(V, n, j + 1, w, n, part, hd, hacc, st);
       launch_norm<DT>(w, n, npart, nrm, st);
       launch_scale_inv<DT>(w, nrm, V + (size_t)(j + 1) * n, n, st);
-      char* pb = (char*)pinned(c, (m + 2) * sizeof(DT) + 16);
+      char* pb = pslots + (size_t)(j % 2) * slot;
       HIPCHK(hipMemcpyAsync(pb, hacc, (j + 1) * sizeof(DT), hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(pb + (m + 1) * sizeof(DT), nrm, sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipEventRecord(c->fg_ev[j % 2], st));
+    };
+    for (hipEvent_t& e : c->fg_ev)
+      if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    issue(0);
+    for (int j = 0; j < m; ++j) {
+      // its counts the steps finished before this one
+      if (j + 1 < m && its + 1 < maxit) issue(j + 1);
+      HIPCHK(hipEventSynchronize(c->fg_ev[j % 2]));
+      const char* pb = pslots + (size_t)(j % 2) * slot;
       for (int i = 0; i <= j; ++i) std::memcpy((void*)&H_(i, j), pb + i * sizeof(DT), sizeof(DT));
       double hn;
       std::memcpy(&hn, pb + (m + 1) * sizeof(DT), sizeof(double));
@@ -1416,6 +1442,8 @@ void gs_destroy(gs_ctx* c) {
     c->amem.reset();
     c->wmem.reset();
     if (c->pin) (void)hipHostFree(c->pin);
+    for (hipEvent_t e : c->fg_ev)
+      if (e) (void)hipEventDestroy(e);
   }
   delete c;
 }

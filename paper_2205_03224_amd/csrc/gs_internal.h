@@ -108,6 +108,11 @@ void factor_levels(HostSetup<T>& S, int kind, double tau, int lfil,
 // Householder reduction to Hessenberg form and shifted QR iteration.
 // On return a holds T (upper triangular) and q holds Q.
 void schur_complex(int m, std::vector<cplx>& a, std::vector<cplx>& q);
+// The same for a real m x m column-major matrix a: the real Schur form by
+// the double-shift QR iteration, its 2x2 blocks (complex-conjugate pairs)
+// then made triangular, so that t (upper triangular) and q (unitary) are a
+// complex Schur form a = q t q^H.
+void schur_real(int m, const std::vector<double>& a, std::vector<cplx>& t, std::vector<cplx>& q);
 // Reorder a complex Schur form so that the positions flagged in `sel` come
 // first (adjacent swaps by plane rotations); sel is permuted along.
 void schur_reorder(int m, std::vector<cplx>& t, std::vector<cplx>& q,

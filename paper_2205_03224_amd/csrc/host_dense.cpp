@@ -7,6 +7,8 @@
 // the bulge with plane rotations (Golub & Van Loan, Matrix Computations,
 // Sec. 7.4-7.5, complex version).  Reordering swaps adjacent diagonal entries
 // with one plane rotation each (Bai & Demmel's swap in the 1x1 case).
+// Real matrices take the real double-shift iteration (schur_real) and are
+// then brought to the same complex triangular form.
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -192,6 +194,258 @@ void schur_complex(int m, std::vector<cplx>& a, std::vector<cplx>& q) {
   }
   for (int j = 0; j < m; ++j)
     for (int i = j + 1; i < m; ++i) at(a, m, i, j) = 0;
+}
+
+void schur_real(int m, const std::vector<double>& a, std::vector<cplx>& t, std::vector<cplx>& q) {
+  // A real matrix: the real Schur form A = Qr Tr Qr^T (Tr quasi-upper
+  // triangular, a 2x2 diagonal block per complex-conjugate pair) by the
+  // Francis double-shift QR algorithm (Golub & Van Loan, Sec. 7.5.5-7.5.6),
+  // in real arithmetic, then each 2x2 block made triangular by a 2x2 unitary
+  // transformation, so that A = Q T Q^H with T upper triangular as from
+  // schur_complex.  About a third of the arithmetic of the complex
+  // single-shift iteration on the same matrix.
+  const size_t mm = (size_t)m * m;
+  std::vector<double> H(a.begin(), a.begin() + mm), Z(mm, 0.0);
+  for (int i = 0; i < m; ++i) Z[(size_t)i * m + i] = 1.0;
+  auto ix = [m](int i, int j) { return (size_t)j * m + i; };
+  // apply the reflector P = I - f v v^T (v of length len at rows r0..) to
+  // rows r0.. of columns c0..c1-1 of H, and to columns r0.. of rows 0..i1-1
+  // of H and of all rows of Z
+  auto refl_rows = [&](const double* v, int len, int r0, int c0, int c1, double f) {
+    for (int j = c0; j < c1; ++j) {
+      double* col = &H[ix(r0, j)];
+      double sdot = 0;
+      for (int u = 0; u < len; ++u) sdot += v[u] * col[u];
+      sdot *= f;
+      for (int u = 0; u < len; ++u) col[u] -= sdot * v[u];
+    }
+  };
+  auto refl_cols = [&](std::vector<double>& M, const double* v, int len, int r0, int i1, double f) {
+    double* cols[3];
+    for (int u = 0; u < len; ++u) cols[u] = &M[ix(0, r0 + u)];
+    for (int i = 0; i < i1; ++i) {
+      double sdot = 0;
+      for (int u = 0; u < len; ++u) sdot += cols[u][i] * v[u];
+      sdot *= f;
+      for (int u = 0; u < len; ++u) cols[u][i] -= sdot * v[u];
+    }
+  };
+  if (m > 2) {
+    // Householder reduction to upper Hessenberg form
+    std::vector<double> v(m), w(m);
+    for (int k = 0; k + 2 < m; ++k) {
+      double xn = 0;
+      for (int i = k + 1; i < m; ++i) xn += H[ix(i, k)] * H[ix(i, k)];
+      xn = std::sqrt(xn);
+      if (xn == 0) continue;
+      const int len = m - k - 1;
+      for (int i = 0; i < len; ++i) v[i] = H[ix(k + 1 + i, k)];
+      v[0] += v[0] >= 0 ? xn : -xn;
+      double vn = 0;
+      for (int i = 0; i < len; ++i) vn += v[i] * v[i];
+      const double f = 2.0 / vn;
+      // rows k+1.. of every column (columns < k are zero there already)
+      for (int j = k; j < m; ++j) {
+        double* col = &H[ix(k + 1, j)];
+        double sdot = 0;
+        for (int i = 0; i < len; ++i) sdot += v[i] * col[i];
+        sdot *= f;
+        for (int i = 0; i < len; ++i) col[i] -= sdot * v[i];
+      }
+      // columns k+1.. of every row of H and Z: w = M v, then M -= f w v^T
+      for (int which = 0; which < 2; ++which) {
+        std::vector<double>& M = which ? Z : H;
+        std::fill(w.begin(), w.end(), 0.0);
+        for (int u = 0; u < len; ++u) {
+          const double* col = &M[ix(0, k + 1 + u)];
+          const double vu = v[u];
+          for (int i = 0; i < m; ++i) w[i] += col[i] * vu;
+        }
+        for (int u = 0; u < len; ++u) {
+          double* col = &M[ix(0, k + 1 + u)];
+          const double vu = v[u] * f;
+          for (int i = 0; i < m; ++i) col[i] -= w[i] * vu;
+        }
+      }
+      for (int i = k + 2; i < m; ++i) H[ix(i, k)] = 0.0;
+    }
+  }
+  // rotation [[c, s], [-s, c]] applied to rows i, i+1 (columns c0..) and its
+  // transpose to columns i, i+1 (rows 0..r1-1 of H, all of Z)
+  auto rot = [&](int i, double c, double sn, int c0, int r1) {
+    for (int j = c0; j < m; ++j) {
+      const double x = H[ix(i, j)], y = H[ix(i + 1, j)];
+      H[ix(i, j)] = c * x + sn * y;
+      H[ix(i + 1, j)] = -sn * x + c * y;
+    }
+    for (int which = 0; which < 2; ++which) {
+      std::vector<double>& M = which ? Z : H;
+      double* p = &M[ix(0, i)];
+      double* q2 = &M[ix(0, i + 1)];
+      const int n = which ? m : r1;
+      for (int r = 0; r < n; ++r) {
+        const double x = p[r], y = q2[r];
+        p[r] = c * x + sn * y;
+        q2[r] = -sn * x + c * y;
+      }
+    }
+  };
+  // a 2x2 diagonal block at (i, i) with real eigenvalues: split it with the
+  // rotation that maps an eigenvector to e_1
+  auto split2 = [&](int i) {
+    const double p = H[ix(i, i)], b = H[ix(i, i + 1)], c = H[ix(i + 1, i)], d = H[ix(i + 1, i + 1)];
+    const double half = 0.5 * (p - d);
+    const double disc = half * half + b * c;
+    if (c == 0.0 || disc < 0.0) return false;
+    // eigenvalue farther from d first (the stable root), eigenvector
+    // (lambda - d, c)
+    const double root = std::sqrt(disc);
+    const double lam = d + half + (half >= 0 ? root : -root);
+    double x = lam - d, y = c;
+    const double r = std::hypot(x, y);
+    if (r == 0.0) return false;
+    x /= r;
+    y /= r;
+    rot(i, x, y, i, std::min(i + 2, m));
+    H[ix(i + 1, i)] = 0.0;
+    return true;
+  };
+  int hi = m - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    int lo = hi;
+    while (lo > 0) {
+      double dd = std::fabs(H[ix(lo - 1, lo - 1)]) + std::fabs(H[ix(lo, lo)]);
+      if (dd == 0) dd = 1.0;
+      if (std::fabs(H[ix(lo, lo - 1)]) <= kEps * dd) {
+        H[ix(lo, lo - 1)] = 0.0;
+        break;
+      }
+      --lo;
+    }
+    if (lo == hi) {
+      --hi;
+      iter = 0;
+      continue;
+    }
+    if (lo == hi - 1) {
+      // a 2x2 block: split when its eigenvalues are real, else keep it
+      split2(hi - 1);
+      hi -= 2;
+      iter = 0;
+      continue;
+    }
+    if (++total > 100 * m) throw Error(GS_EINVAL, "real Schur QR iteration did not converge");
+    ++iter;
+    // shifts s1 = (r1, i1), s2 = (r2, i2): the eigenvalues of the trailing
+    // 2x2 (a real pair replaced by the one nearer H(hi, hi), taken twice),
+    // exceptional ones every 11th iteration without deflation
+    double r1, i1, r2, i2;
+    {
+      double p, b, c, d;
+      if (iter % 11 == 10) {
+        const double e = std::fabs(H[ix(hi, hi - 1)]) + std::fabs(H[ix(hi - 1, hi - 2)]);
+        p = 0.75 * e + H[ix(hi, hi)];
+        b = -0.4375 * e;
+        c = e;
+        d = p;
+      } else {
+        p = H[ix(hi - 1, hi - 1)];
+        b = H[ix(hi - 1, hi)];
+        c = H[ix(hi, hi - 1)];
+        d = H[ix(hi, hi)];
+      }
+      const double half = 0.5 * (p - d);
+      const double disc = half * half + b * c;
+      if (disc >= 0.0) {
+        const double root = std::sqrt(disc);
+        const double e1 = d + half + root, e2 = d + half - root;
+        const double near = std::fabs(e1 - d) <= std::fabs(e2 - d) ? e1 : e2;
+        r1 = r2 = near;
+        i1 = i2 = 0.0;
+      } else {
+        r1 = r2 = d + half;
+        i1 = std::sqrt(-disc);
+        i2 = -i1;
+      }
+    }
+    // first column of (H - s1 I)(H - s2 I) on the active block, scaled by
+    // 1/sc and formed from the differences H(lo, lo) - s, which keeps it
+    // accurate when the shifts lie close to the diagonal (a clustered
+    // spectrum); the expanded polynomial would cancel there
+    const double h00 = H[ix(lo, lo)], h10 = H[ix(lo + 1, lo)];
+    const double sc = std::fabs(h00 - r2) + std::fabs(i2) + std::fabs(h10);
+    const double h10s = sc > 0.0 ? h10 / sc : 0.0;
+    double x = sc > 0.0 ? h10s * H[ix(lo, lo + 1)] + (h00 - r1) * ((h00 - r2) / sc) - i1 * (i2 / sc)
+                        : 0.0;
+    double y = h10s * (h00 + H[ix(lo + 1, lo + 1)] - r1 - r2);
+    double z = h10s * H[ix(lo + 2, lo + 1)];
+    for (int k = lo - 1; k + 3 <= hi; ++k) {
+      // reflector on rows k+1..k+3 taking (x, y, z) to a multiple of e_1
+      const double nrm = std::sqrt(x * x + y * y + z * z);
+      if (nrm != 0.0) {
+        double v[3] = {x + (x >= 0 ? nrm : -nrm), y, z};
+        const double vn = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        const double f = 2.0 / vn;
+        const int r0 = k + 1;
+        refl_rows(v, 3, r0, std::max(lo, k), m, f);
+        refl_cols(H, v, 3, r0, std::min(r0 + 4, hi + 1), f);
+        refl_cols(Z, v, 3, r0, m, f);
+        if (k >= lo) H[ix(k + 2, k)] = H[ix(k + 3, k)] = 0.0;
+      }
+      x = H[ix(k + 2, k + 1)];
+      y = H[ix(k + 3, k + 1)];
+      z = k + 4 <= hi ? H[ix(k + 4, k + 1)] : 0.0;
+    }
+    // last step: a rotation on rows hi-1, hi zeroing (x, y) -> (r, 0)
+    {
+      const double r = std::hypot(x, y);
+      if (r != 0.0) {
+        const int i = hi - 1;
+        rot(i, x / r, y / r, std::max(lo, i - 1), hi + 1);
+        if (i - 1 >= lo) H[ix(i + 1, i - 1)] = 0.0;
+      }
+    }
+  }
+  // complex Schur form: each remaining 2x2 block (a complex pair) made upper
+  // triangular by U = [[x1, -conj x2], [x2, conj x1]], x a unit eigenvector
+  t.assign(mm, cplx(0));
+  q.assign(mm, cplx(0));
+  for (size_t e = 0; e < mm; ++e) {
+    t[e] = cplx(H[e], 0.0);
+    q[e] = cplx(Z[e], 0.0);
+  }
+  for (int i = 0; i + 1 < m; ++i) {
+    if (H[ix(i + 1, i)] == 0.0) continue;
+    const double p = H[ix(i, i)], b = H[ix(i, i + 1)], c = H[ix(i + 1, i)], d = H[ix(i + 1, i + 1)];
+    const double half = 0.5 * (p - d);
+    const double disc = half * half + b * c;
+    // disc < 0 here (real pairs were split); lambda = (p+d)/2 + i sqrt(-disc)
+    const cplx lam(0.5 * (p + d), std::sqrt(std::max(-disc, 0.0)));
+    // (B - lambda I) x = 0: x = (b, lambda - p)
+    cplx x1(b, 0.0), x2 = lam - p;
+    const double xn = std::sqrt(std::norm(x1) + std::norm(x2));
+    x1 /= xn;
+    x2 /= xn;
+    const cplx u11 = x1, u21 = x2, u12 = -std::conj(x2), u22 = std::conj(x1);
+    // rows i, i+1 <- U^H rows (columns i..m-1)
+    for (int j = i; j < m; ++j) {
+      const cplx r0 = t[ix(i, j)], r1 = t[ix(i + 1, j)];
+      t[ix(i, j)] = std::conj(u11) * r0 + std::conj(u21) * r1;
+      t[ix(i + 1, j)] = std::conj(u12) * r0 + std::conj(u22) * r1;
+    }
+    // columns i, i+1 <- columns U (rows 0..i+1 of T, all of Q)
+    for (int which = 0; which < 2; ++which) {
+      std::vector<cplx>& M = which ? q : t;
+      const int n = which ? m : i + 2;
+      for (int r = 0; r < n; ++r) {
+        const cplx c0 = M[ix(r, i)], c1 = M[ix(r, i + 1)];
+        M[ix(r, i)] = c0 * u11 + c1 * u21;
+        M[ix(r, i + 1)] = c0 * u12 + c1 * u22;
+      }
+    }
+    t[ix(i + 1, i)] = 0.0;
+    ++i;  // the pair's second row is done
+  }
 }
 
 void schur_reorder(int m, std::vector<cplx>& t, std::vector<cplx>& q,
