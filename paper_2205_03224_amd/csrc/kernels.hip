@@ -1369,34 +1369,85 @@ void launch_scatter(const typename P::X* t, const int32_t* perm, typename P::O* 
 // ======================================================================
 // float64 / complex128 vector kernels (FGMRES, Arnoldi)
 // ======================================================================
+// One row of a CSR product, y_i = acc0 + sum_p v_p x[ci_p] in stored order
+// (acc0 = 0, or -b_i negated below for the residual).  Up to kRowU entries of
+// the row are loaded at once (columns and values in one round trip, then the
+// x gathers in a second), longer rows continue in further rounds: three
+// dependent round trips per thread for a stencil row instead of two per
+// entry.  Entries past the row end are loaded at its last index and add an
+// exact zero.
+constexpr int kRowU = 8;
 template <class T>
-__global__ void k_spmv(const int32_t* rp, const int32_t* ci, const T* v, const T* x, T* y,
-                       int64_t n) {
+__device__ __forceinline__ T csr_row_dot(const int32_t* rp, const int32_t* ci, const T* v,
+                                         const T* x, int64_t i) {
+  const int p0 = rp[i], p1 = rp[i + 1];
+  T acc = zero<T>();
+  for (int pb = p0; pb < p1; pb += kRowU) {
+    int c[kRowU];
+    T w[kRowU];
+#pragma unroll
+    for (int u = 0; u < kRowU; ++u) {
+      const int p = min(pb + u, p1 - 1);
+      c[u] = ci[p];
+      w[u] = v[p];
+    }
+    T xv[kRowU];
+#pragma unroll
+    for (int u = 0; u < kRowU; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < kRowU; ++u)
+      if (pb + u < p1) acc += w[u] * xv[u];
+  }
+  return acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_spmv(const int32_t* rp, const int32_t* ci, const T* v,
+                                              const T* x, T* y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  T acc = zero<T>();
-  for (int p = rp[i]; p < rp[i + 1]; ++p) acc += v[p] * x[ci[p]];
-  y[i] = acc;
+  y[i] = csr_row_dot(rp, ci, v, x, i);
 }
 template <class T>
 void launch_spmv(const int32_t* rp, const int32_t* ci, const T* v, const T* x, T* y, int64_t n,
                  hipStream_t st) {
+  if (n <= 0) return;
   hipLaunchKernelGGL(k_spmv<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rp, ci, v,
                      x, y, n);
 }
 
+// y = b - A x, the row's products subtracted from b_i one by one in stored
+// order (the operations of the plain loop)
 template <class T>
-__global__ void k_residual(const int32_t* rp, const int32_t* ci, const T* v, const T* x,
-                           const T* b, T* y, int64_t n) {
+__global__ __launch_bounds__(256) void k_residual(const int32_t* rp, const int32_t* ci,
+                                                  const T* v, const T* x, const T* b, T* y,
+                                                  int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int p0 = rp[i], p1 = rp[i + 1];
   T acc = b[i];
-  for (int p = rp[i]; p < rp[i + 1]; ++p) acc -= v[p] * x[ci[p]];
+  for (int pb = p0; pb < p1; pb += kRowU) {
+    int c[kRowU];
+    T w[kRowU];
+#pragma unroll
+    for (int u = 0; u < kRowU; ++u) {
+      const int p = min(pb + u, p1 - 1);
+      c[u] = ci[p];
+      w[u] = v[p];
+    }
+    T xv[kRowU];
+#pragma unroll
+    for (int u = 0; u < kRowU; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < kRowU; ++u)
+      if (pb + u < p1) acc -= w[u] * xv[u];
+  }
   y[i] = acc;
 }
 template <class T>
 void launch_residual(const int32_t* rp, const int32_t* ci, const T* v, const T* x, const T* b,
                      T* y, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
   hipLaunchKernelGGL(k_residual<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rp, ci,
                      v, x, b, y, n);
 }
