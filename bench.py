@@ -473,9 +473,12 @@ def main():
                            "relres": res["relres"], "converged": bool(res["converged"]),
                            "err_vs_x_true": float(np.linalg.norm(xh - w.x_true) /
                                                   np.linalg.norm(w.x_true)),
-                           "diff_vs_f64": float(np.linalg.norm(xh - x64) / np.linalg.norm(x64))}
+                           "diff_vs_f64": float(np.linalg.norm(xh - x64) / np.linalg.norm(x64)),
+                           "arnoldi_cycles": list(i2["arnoldi_cycles"][:i2["nlevels"]]),
+                           "arnoldi_matvecs": list(i2["arnoldi_matvecs"][:i2["nlevels"]])}
             log(f"[bench] form {prec}: lowrank {i2['t_lowrank']:.2f} s + solve {ts:.2f} s, "
-                f"its {res['its']}, relres {res['relres']:.2e}")
+                f"its {res['its']}, relres {res['relres']:.2e}; Arnoldi cycles "
+                f"{forms[prec]['arnoldi_cycles']} products {forms[prec]['arnoldi_matvecs']}")
             c2.close()
             del x
         out["time_to_tol"] = forms

@@ -38,6 +38,9 @@ struct gs_ctx {
   void* pin = nullptr;  // pinned staging for small device->host reads
   size_t pin_bytes = 0;
   hipEvent_t fg_ev[2] = {nullptr, nullptr};  // FGMRES: Hessenberg columns landed
+  // per level: the exact W_l on the device while the engine holds it rounded
+  // (narrower storage) and the host copy has not been fetched
+  std::vector<std::unique_ptr<gs::DevMem>> wkeep;
   gs_info info{};
   std::vector<std::string> step_labels;  // of the last gs_apply_profile
   int nparts = 1;                         // of the last gs_setup (feature cut flags)
@@ -212,6 +215,54 @@ template <> cplx to_cplx<double>(const void* p, size_t i) { return cplx(((const 
 template <> cplx to_cplx<cplx>(const void* p, size_t i) { return ((const cplx*)p)[i]; }
 
 // ------------------------------------------------------------ low-rank setup
+// Install W_l (device, s x k, value type) and the level's H_l in the engine,
+// on the device.  The host copy of W_l is fetched only when the host needs
+// it (fetch_host_w): from the engine when it stores W_l exactly, else from
+// an exact device copy kept here.
+template <class T>
+static void install_lowrank(gs_ctx* c, int l, int k, const void* Wd) {
+  HostLevel<T>& h = host<T>(c).lv[l];
+  if (c->wkeep.size() <= (size_t)l) c->wkeep.resize((size_t)l + 1);
+  c->wkeep[(size_t)l].reset();
+  if (c->eng->set_lowrank_device(l, k, Wd, h.H.data()) == 0) {
+    auto keep = std::make_unique<DevMem>();
+    T* w = keep->alloc<T>((size_t)h.s * k);
+    HIPCHK(hipMemcpyAsync(w, Wd, (size_t)h.s * k * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->wkeep[(size_t)l] = std::move(keep);
+  }
+  h.W.clear();
+  h.W.shrink_to_fit();
+  h.w_on_device = true;
+}
+
+// W_l of every level that only the engine holds, into the host setup
+template <class T>
+static void fetch_host_w(gs_ctx* c) {
+  for (size_t l = 0; l < host<T>(c).lv.size(); ++l) {
+    HostLevel<T>& h = host<T>(c).lv[l];
+    if (!h.w_on_device) continue;
+    h.W.resize((size_t)h.s * h.k);
+    if (l < c->wkeep.size() && c->wkeep[l]) {
+      HIPCHK(hipMemcpyAsync(h.W.data(), c->wkeep[l]->ptrs[0], h.W.size() * sizeof(T),
+                            hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      c->wkeep[l].reset();
+    } else if (!c->eng || !c->eng->get_lowrank_w((int)l, h.W.data())) {
+      throw Error(GS_ESTATE, "W_l is held by no engine");
+    }
+    h.w_on_device = false;
+  }
+}
+static void fetch_host_w_any(gs_ctx* c) {
+  if (c->device >= 0) hipcheck(hipSetDevice(c->device), "hipSetDevice");
+  if (c->dtype == GS_F64) {
+    if (c->hd) fetch_host_w<double>(c);
+  } else if (c->hz) {
+    fetch_host_w<cplx>(c);
+  }
+}
+
 // Thick-restart (Krylov-Schur) Arnoldi on Ĝ_l on the GPU (Sec. 2.3, Sec. 4.2):
 // cycle length m = 2k, Ritz pairs accepted when |b^H y| <= tol |theta|.
 // Orthogonalisation and the basis are float64 / complex128 whatever the
@@ -368,15 +419,12 @@ static void lowrank_level(gs_ctx* c, int l, int kreq, const float* Ystart = null
     const bool last = conv || cycle == maxcyc - 1 || kk >= m;
     if (last) {
       launch_gemm_small<DT>(V, s, m, Gd, kk, tmp, s, s, st);
-      h.W.resize((size_t)s * kk);
-      HIPCHK(hipMemcpyAsync(h.W.data(), tmp, h.W.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
       h.k = kk;
       h.H = correction_matrix<T>(kk, R, thk);
       h.arnoldi_cycles = cycle + 1;
       h.arnoldi_matvecs = nmv + redone;
       h.arnoldi_converged = conv ? 1 : 0;
-      c->eng->set_lowrank(l, kk, h.W.data(), h.H.data());
+      install_lowrank<T>(c, l, kk, tmp);
       return;
     }
     // thick restart: V[:, :kk] = V_m G, V[:, kk] = v_{m+1}
@@ -568,15 +616,12 @@ static bool lowrank_block(gs_ctx* c, int l, int kreq, const float* Y) {
     if (todo.empty()) {
       upload(as_cplx(G), w, kk, Cd);
       launch_gemm_small<DT>(Sv, s, w, Cd, kk, tmp, s, s, st);
-      h.W.resize((size_t)s * kk);
-      HIPCHK(hipMemcpyAsync(h.W.data(), tmp, h.W.size() * sizeof(DT), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
       h.k = kk;
       h.H = correction_matrix<T>(kk, R, thk);
       h.arnoldi_cycles = it + 1;
       h.arnoldi_matvecs = nmv;
       h.arnoldi_converged = 1;
-      c->eng->set_lowrank(l, kk, h.W.data(), h.H.data());
+      install_lowrank<T>(c, l, kk, tmp);
       return true;
     }
     if (nmv >= budget) break;
@@ -1441,6 +1486,7 @@ void gs_destroy(gs_ctx* c) {
     c->eng.reset();
     c->amem.reset();
     c->wmem.reset();
+    c->wkeep.clear();
     if (c->pin) (void)hipHostFree(c->pin);
     for (hipEvent_t e : c->fg_ev)
       if (e) (void)hipEventDestroy(e);
@@ -1517,6 +1563,8 @@ int gs_set_precision(gs_ctx* c, int precision) {
     if (r) return r;
     if (!c->ready) throw Error(GS_ESTATE, "no setup");
     if (precision == c->precision) return GS_OK;
+    // the new engine is built from the host setup
+    fetch_host_w_any(c);
     // build the new engine first: on error the current one stays in place
     std::unique_ptr<Engine> e = c->dtype == GS_F64 ? make_engine(*c->hd, precision, c->stream)
                                                    : make_engine(*c->hz, precision, c->stream);
@@ -1768,6 +1816,7 @@ int gs_get_level(const gs_ctx* c, int l, int64_t* block_ptr, int64_t* l_rowptr, 
   if (!c->ready) return GS_ESTATE;
   gs_ctx* cc = const_cast<gs_ctx*>(c);
   GS_GUARD(cc, {
+    fetch_host_w_any(cc);  // a cache of the engine's W_l: the setup is unchanged
     if (c->dtype == GS_F64)
       level_copy(*c->hd, l, block_ptr, l_rowptr, l_col, l_val, u_rowptr, u_col, u_val, e_rowptr,
                  e_col, e_val, f_rowptr, f_col, f_val, w, h);
@@ -1792,6 +1841,7 @@ int gs_export(const gs_ctx* c, const char* path) {
   GS_GUARD(cc, {
     if (!c->ready) throw Error(GS_ESTATE, "export before setup");
     if (!path) throw Error(GS_EINVAL, "NULL path");
+    fetch_host_w_any(cc);
     if (c->dtype == GS_F64) export_setup(*c->hd, GS_F64, path);
     else export_setup(*c->hz, GS_C128, path);
     return GS_OK;

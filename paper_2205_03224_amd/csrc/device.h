@@ -244,6 +244,10 @@ template <class P> void launch_trisolve_streamed(const TriArgs<P>& a, int mode, 
 // maximum chunk size the streamed kernel stages (bytes)
 constexpr int kChunkCapMax = 24576;
 template <class P> void launch_interface(const IfArgs<P>& a, hipStream_t st);
+// dst[i] = src[i] rounded to V (float or bf16) as the host storage
+// conversion rounds it
+template <class V> void launch_store_from_double(const double* src, V* dst, int64_t n,
+                                                 hipStream_t st);
 // the interface step and the low-rank update of a small level (s <= 4096,
 // k <= 64) in one launch; returns false (launching nothing) otherwise
 template <class P> bool launch_interface_small(const IfArgs<P>& a, hipStream_t st);

@@ -61,6 +61,13 @@ struct Engine {
   virtual void apply_batch(int m, const void* x, void* y) = 0;
   // install W_l (s_l x k) and H_l (k x k), host arrays of the value type
   virtual void set_lowrank(int l, int k, const void* W, const void* H) = 0;
+  // the same with W_l in device memory (value type, s_l x k column-major,
+  // read before the call returns): 1 when the engine now holds W_l exactly,
+  // 0 when it holds it rounded to its storage type
+  virtual int set_lowrank_device(int l, int k, const void* W, const void* H) = 0;
+  // copy the installed W_l to host memory (value type); false when the
+  // engine stores it in another precision
+  virtual bool get_lowrank_w(int l, void* W) = 0;
   virtual void stats(gs_info* info, int vb_vec) = 0;
   virtual double bytes_per_apply() const = 0;
   // One apply per rep with HIP events around every launch; returns the number

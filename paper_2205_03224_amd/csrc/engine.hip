@@ -880,7 +880,10 @@ struct EngineT final : Engine {
         L.F.rp = upload(zr);
       }
       maxd = std::max(maxd, h.d);
-      if (h.k > 0) set_lowrank_host((int)l, h.k, h.W, h.H);
+      if (h.k > 0) {
+        if (h.w_on_device) throw Error(GS_ESTATE, "W_l not fetched to the host before a rebuild");
+        set_lowrank_host((int)l, h.k, h.W.data(), h.H.data());
+      }
     }
     xg = mem.alloc<C>(maxd);
     fy = mem.alloc<C>(maxd);
@@ -1003,7 +1006,25 @@ struct EngineT final : Engine {
   }
 
   // Install W_l, H_l; buffers grow with k and are reused by later calls.
-  void set_lowrank_host(int l, int k, const std::vector<T>& W, const std::vector<T>& H) {
+  void set_lowrank_host(int l, int k, const T* W, const T* H) {
+    lowrank_alloc(l, k);
+    Lev& L = lv[l];
+    std::vector<V> wv((size_t)L.s * k);
+    for (size_t i = 0; i < wv.size(); ++i) wv[i] = to_store<V, T>(W[i]);
+    std::vector<C> hc((size_t)k * k);
+    for (size_t i = 0; i < hc.size(); ++i) hc[i] = to_compute(H[i]);
+    if (!wv.empty())
+      HIPCHK(hipMemcpyAsync(L.W, wv.data(), wv.size() * sizeof(V), hipMemcpyHostToDevice, st));
+    if (!hc.empty())
+      HIPCHK(hipMemcpyAsync(L.H, hc.data(), hc.size() * sizeof(C), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    L.k = k;
+  }
+  static C to_compute(const T& x);
+
+  // W_l in the value type's own layout: float64 and complex128 storage
+  static constexpr bool kExactW = sizeof(V) == sizeof(T);
+  void lowrank_alloc(int l, int k) {
     Lev& L = lv[l];
     if (k > 1024) throw Error(GS_EINVAL, "rank above 1024 per level is not supported");
     if (k > L.kcap) {
@@ -1014,23 +1035,39 @@ struct EngineT final : Engine {
       L.H = mem.alloc<C>((size_t)k * k);
       L.kcap = k;
     }
-    const std::vector<V> wv = convert<V, T>(W);
-    std::vector<C> hc(H.size());
-    for (size_t i = 0; i < H.size(); ++i) hc[i] = to_compute(H[i]);
-    if (!wv.empty())
-      HIPCHK(hipMemcpyAsync(L.W, wv.data(), wv.size() * sizeof(V), hipMemcpyHostToDevice, st));
+  }
+  int set_lowrank_device(int l, int k, const void* W, const void* H) override {
+    lowrank_alloc(l, k);
+    Lev& L = lv[l];
+    const T* h = (const T*)H;
+    std::vector<C> hc((size_t)k * k);
+    for (size_t i = 0; i < hc.size(); ++i) hc[i] = to_compute(h[i]);
+    if (L.s > 0 && k > 0) {
+      if constexpr (kExactW) {
+        HIPCHK(hipMemcpyAsync(L.W, W, (size_t)L.s * k * sizeof(V), hipMemcpyDeviceToDevice, st));
+      } else {
+        // narrower storage of a float64 setup
+        launch_store_from_double<V>((const double*)W, L.W, (int64_t)L.s * k, st);
+      }
+    }
     if (!hc.empty())
       HIPCHK(hipMemcpyAsync(L.H, hc.data(), hc.size() * sizeof(C), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     L.k = k;
+    return kExactW ? 1 : 0;
   }
-  static C to_compute(const T& x);
-
+  bool get_lowrank_w(int l, void* W) override {
+    if (!kExactW) return false;
+    const Lev& L = lv[l];
+    if (L.s > 0 && L.k > 0)
+      HIPCHK(hipMemcpyAsync(W, L.W, (size_t)L.s * L.k * sizeof(V), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return true;
+  }
   void set_lowrank(int l, int k, const void* W, const void* H) override {
     const T* w = (const T*)W;
     const T* h = (const T*)H;
-    set_lowrank_host(l, k, std::vector<T>(w, w + (size_t)lv[l].s * k),
-                     std::vector<T>(h, h + (size_t)k * k));
+    set_lowrank_host(l, k, w, h);
   }
 
   TriArgs<P> tri_args(int l) {

@@ -74,6 +74,9 @@ struct HostLevel {
   CSR<T> L, U, E, F;            // level-local numbering
   int k = 0;
   std::vector<T> W, H;          // s x k and k x k, column-major
+  // W held only by the device engine (in this precision, exactly) and
+  // fetched into W when the host needs it; W is empty meanwhile
+  bool w_on_device = false;
   int arnoldi_cycles = 0, arnoldi_matvecs = 0, arnoldi_converged = 0;
 };
 

@@ -937,6 +937,33 @@ static void launch_stream_mode(const TriArgs<P>& a, int maxslot, hipStream_t st)
   else launch_stream_ms<P, 16, MODE>(a, st);
 }
 
+// float64 values to a narrower storage type on the device, rounded as the
+// host conversion rounds them (to float: nearest even; to bfloat16: the
+// float value, then nearest even on its upper 16 bits)
+template <class V> __device__ inline V store_from_double(double x);
+template <> __device__ inline float store_from_double<float>(double x) { return (float)x; }
+template <> __device__ inline bf16 store_from_double<bf16>(double x) {
+  uint32_t u = __float_as_uint((float)x);
+  if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
+  bf16 b;
+  b.u = (uint16_t)(u >> 16);
+  return b;
+}
+template <class V>
+__global__ __launch_bounds__(256) void k_store_from_double(const double* src, V* dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = store_from_double<V>(src[i]);
+}
+template <class V>
+void launch_store_from_double(const double* src, V* dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_store_from_double<V>, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
+}
+template void launch_store_from_double<float>(const double*, float*, int64_t, hipStream_t);
+template void launch_store_from_double<bf16>(const double*, bf16*, int64_t, hipStream_t);
+
 // fy = F_l y2 (most rows of B_l have no entry), so the up sweep's
 // right-hand side is a plain load like the down sweep's.  Four rows per
 // thread, 256 apart: four independent row-pointer -> entry -> y2 chains in

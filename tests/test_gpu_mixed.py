@@ -110,3 +110,40 @@ def test_native_mixed_setup(torch_dev):
         assert info["converged"], (prec, info)
         assert relerr(xd.cpu().numpy(), w.x_true) <= 1e-5
         ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f64"])
+def test_native_setup_basis_install_matches_host_conversion(torch_dev, prec):
+    """After a native setup the engine receives W_l on the device (float32 /
+    bfloat16 storage: converted there) and the host copy is fetched only when
+    read.  The fetched W_l is the exact float64 basis (orthonormal), and an
+    engine rebuilt from the host setup (host conversion of W_l) gives
+    bit-identical applies, so the device conversion rounds as the host one
+    does."""
+    torch = torch_dev
+    from paper_2205_03224_amd import gemslr
+    w = wl.convdiff3d_64(N=20, nparts=27)
+    ctx = gemslr.Context(0)
+    ctx.setup(w.rowptr, w.col, w.val, w.levels, w.nparts, 8, 1e-3, lfil=10,
+              grid_dims=w.dims, precision=prec)
+    rs = np.random.default_rng(5)
+    xd = torch.from_numpy(rs.standard_normal(w.n)).cuda()
+    y1 = torch.empty_like(xd)
+    ctx.apply(xd, y1)
+    torch.cuda.synchronize()
+    info = ctx.info()
+    assert info["nlevels"] >= 2
+    for l in range(info["nlevels"]):
+        W = ctx.level(l)["W"]
+        if W.size == 0:
+            continue
+        assert W.dtype == np.float64
+        assert np.abs(W.T @ W - np.eye(W.shape[1])).max() <= 1e-12
+    other = "f64" if prec != "f64" else "f32"
+    ctx.set_precision(other)
+    ctx.set_precision(prec)
+    y2 = torch.empty_like(xd)
+    ctx.apply(xd, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    ctx.close()
