@@ -89,6 +89,20 @@ typedef struct {
                              from v_0 = Y_l Y_l^T r (r the seeded start
                              vector), a vector of the predicted subspace
                                                                          [0]  */
+  /* Optional partition given by the caller (host arrays, read during
+   * gs_setup; all NULL: the library partitions A itself, Alg. 3).  Same
+   * format as gs_partition_grid writes: part_perm[new] = old (n entries),
+   * part_level_start (part_nlevels + 2 entries: starts of B_0 .. B_{L-1},
+   * C_last, then n), and optionally part_block_ptr / part_block_count (the
+   * diagonal blocks of every segment).  Without block lists each segment's
+   * blocks are the connected components of its rows in the graph of A,
+   * which must each be contiguous in part_perm.  gs_setup's levels and
+   * nparts are then not used.  Checked as gs_partition_check does.   [NULL] */
+  const int64_t* part_perm;
+  const int64_t* part_level_start;
+  int part_nlevels;
+  const int64_t* part_block_ptr;
+  const int64_t* part_block_count;
 } gs_opts;
 
 /* Fill *opts with the defaults shown in brackets above. */
@@ -140,7 +154,8 @@ int gs_create(gs_ctx** ctx, int device, void* stream);
 void gs_destroy(gs_ctx* ctx);
 
 /* Message of the context's last error ("" if none); valid until the next
- * call on the context.  ctx NULL returns the last gs_create error. */
+ * call on the context.  ctx NULL returns the last error of a call without a
+ * context (gs_create and the host stages gs_partition_*, gs_ilu). */
 const char* gs_last_error(const gs_ctx* ctx);
 
 /* ---------------------------------------------------------------- setup */
@@ -307,7 +322,13 @@ int gs_lowrank(gs_ctx* ctx, int rank, const float* const* warm);
  * Arnoldi.  Parameters are packed W1 (in x hidden, row-major), b1, W2, b2, W3,
  * b3.  Layer widths <= 64.  Errors: GS_EINVAL, GS_EDEVICE. */
 typedef struct gs_mlp gs_mlp;
-int gs_mlp_create(gs_mlp** mlp, int in_dim, int hidden, int out_dim, int device, void* stream);
+/* The weights start Glorot-uniform, biases at zero: packed parameter j (a
+ * weight of the layer a -> b) is sqrt(6 / (a + b)) * v_j with v the SplitMix64
+ * start vector of `seed` (2 u_j - 1, u_j the top 53 bits of its j-th output;
+ * the generator of the Arnoldi start vectors), so a seed fixes the network
+ * before training; gs_mlp_set_params overwrites it. */
+int gs_mlp_create(gs_mlp** mlp, int in_dim, int hidden, int out_dim, uint64_t seed, int device,
+                  void* stream);
 void gs_mlp_destroy(gs_mlp* mlp);
 int gs_mlp_nparams(const gs_mlp* mlp);
 const char* gs_mlp_last_error(const gs_mlp* mlp);
@@ -363,6 +384,26 @@ int gs_solve(gs_ctx* ctx, const void* b, void* x, double tol, gs_info* info);
 int gs_get_info(const gs_ctx* ctx, gs_info* info);
 
 /* ---------------------------------------------------------------- host stages */
+/* Check a partition given by the caller against the pattern of A and
+ * complete its block lists (host only; usable without a device).
+ *  perm, level_start, nlevels: as gs_partition_grid writes them (perm[new] =
+ *              old; level_start: starts of B_0 .. B_{L-1}, C_last, then n)
+ *  block_ptr, block_count: the segments' diagonal blocks in the same format,
+ *              or NULL: each segment's blocks are the connected components
+ *              of its rows in the symmetrised graph of A
+ *  block_ptr_out, block_count_out: out (may be NULL), the blocks used;
+ *              block_cap: capacity of block_ptr_out (n + nlevels + 2 always
+ *              suffices)
+ * Rejected (GS_EINVAL): perm not a permutation of 0..n-1, level_start not
+ * rising from 0 to n, an empty segment, blocks that do not tile their
+ * segment, a component that is not contiguous in perm, and two blocks of one
+ * B_l (l < L) coupled by an entry of A (B_l must be block diagonal, Sec. 2;
+ * C_last's blocks are cut on purpose, Sec. 4.3). */
+int gs_partition_check(int64_t n, const int64_t* rowptr, const int32_t* col, const int64_t* perm,
+                       const int64_t* level_start, int nlevels, const int64_t* block_ptr,
+                       const int64_t* block_count, int64_t* block_ptr_out,
+                       int64_t* block_count_out, int64_t block_cap);
+
 /* Multilevel geometric vertex-separator reordering of a grid operator
  * (Alg. 3, Sec. 3.2).  Host only; usable without a device.
  *  perm:       out, n entries, perm[new] = old

@@ -47,6 +47,9 @@ struct gs_ctx {
 };
 
 static std::string g_create_error;
+// an error's message: on its context, or (calls without one: gs_create and
+// the host stages) where gs_last_error(NULL) reads it
+static void gs_set_err(gs_ctx* c, const char* m);
 
 // Scratch region of gs_apply_noalloc: static device memory of the code
 // object, one copy per GPU, so that entry point allocates nothing.  Host
@@ -950,11 +953,17 @@ static void setup_native(gs_ctx* c, int64_t n, const int64_t* rp, const int32_t*
   auto S = std::make_unique<HostSetup<T>>();
   copy_csr<T>(n, n, rp, ci, val, S->A);
   double t0 = now_s();
-  // geometric separator for grid operators, nested dissection otherwise
-  Partition part = c->opts.grid_ndim > 0
-                       ? partition_grid(c->opts.grid_ndim, c->opts.grid_dims, nparts, levels, n, rp, ci)
-                       : partition_graph(nparts, levels, n, rp, ci);
+  // the caller's partition, else the geometric separator for grid
+  // operators and nested dissection otherwise
+  Partition part =
+      c->opts.part_perm
+          ? user_partition(n, rp, ci, c->opts.part_perm, c->opts.part_level_start,
+                           c->opts.part_nlevels, c->opts.part_block_ptr, c->opts.part_block_count)
+      : c->opts.grid_ndim > 0
+          ? partition_grid(c->opts.grid_ndim, c->opts.grid_dims, nparts, levels, n, rp, ci)
+          : partition_graph(nparts, levels, n, rp, ci);
   if (part.L > GS_MAX_LEVELS) throw Error(GS_EINVAL, "too many levels");
+  if (c->opts.part_perm) c->nparts = (int)part.blocks[0].size() - 1;  // level-0 subdomains
   double t1 = now_s();
   extract_levels<T>(S->A, part, *S);
   check_rank<T>(*S, rank);
@@ -1362,17 +1371,22 @@ static void lowrank_all(gs_ctx* c, int rank, const float* const* warm) {
 // ====================================================================== C ABI
 using namespace gs;
 
+static void gs_set_err(gs_ctx* c, const char* m) {
+  if (c) c->err = m;
+  else g_create_error = m;
+}
+
 #define GS_GUARD(ctx, ...)                                   \
   try {                                                      \
     __VA_ARGS__;                                             \
   } catch (const Error& e) {                                 \
-    if (ctx) (ctx)->err = e.what();                          \
+    gs_set_err((ctx), e.what());                             \
     return e.code;                                           \
   } catch (const std::bad_alloc&) {                          \
-    if (ctx) (ctx)->err = "host allocation failed";          \
+    gs_set_err((ctx), "host allocation failed");             \
     return GS_ENOMEM;                                        \
   } catch (const std::exception& e) {                        \
-    if (ctx) (ctx)->err = e.what();                          \
+    gs_set_err((ctx), e.what());                             \
     return GS_EINVAL;                                        \
   }
 
@@ -1512,12 +1526,27 @@ static int need_device(gs_ctx* c) {
 int gs_setup(gs_ctx* c, int64_t n, const int64_t* rowptr, const int32_t* col, const void* val,
              int dtype, int levels, int nparts, int rank, double drop_tol, const gs_opts* opts) {
   if (!c) return GS_EINVAL;
+  // the partition arrays of opts are the caller's, read during this call
+  // only: the kept options never point at them afterwards
+  struct DropPartition {
+    gs_opts& o;
+    void clear() {
+      o.part_perm = nullptr;
+      o.part_level_start = nullptr;
+      o.part_nlevels = 0;
+      o.part_block_ptr = nullptr;
+      o.part_block_count = nullptr;
+    }
+    ~DropPartition() { clear(); }
+  } drop{c->opts};
   GS_GUARD(c, {
     int r = need_device(c);
     if (r) return r;
     if (opts) c->opts = *opts;
+    else drop.clear();
     if (dtype != GS_F64 && dtype != GS_C128) throw Error(GS_EINVAL, "dtype must be GS_F64 or GS_C128");
-    if (rank < 0 || levels < 1 || nparts < 1) throw Error(GS_EINVAL, "bad levels/nparts/rank");
+    if (rank < 0 || ((levels < 1 || nparts < 1) && !c->opts.part_perm))
+      throw Error(GS_EINVAL, "bad levels/nparts/rank");
     if (!val) throw Error(GS_EINVAL, "NULL values");
     validate_csr(n, rowptr, col, true);
     c->ready = false;
@@ -1744,6 +1773,26 @@ int gs_partition_grid(int ndim, const int32_t* dims, int nparts, int levels, int
     validate_csr(n, rowptr, col, false);
     Partition p = partition_grid(ndim, dims, nparts, levels, n, rowptr, col);
     return export_partition(p, perm, level_start, nlevels, block_ptr, block_count, block_cap);
+  });
+}
+
+int gs_partition_check(int64_t n, const int64_t* rowptr, const int32_t* col, const int64_t* perm,
+                       const int64_t* level_start, int nlevels, const int64_t* block_ptr,
+                       const int64_t* block_count, int64_t* block_ptr_out,
+                       int64_t* block_count_out, int64_t block_cap) {
+  gs_ctx* none = nullptr;
+  GS_GUARD(none, {
+    if (n <= 0) throw Error(GS_EINVAL, "n <= 0");
+    validate_csr(n, rowptr, col, false);
+    Partition p = user_partition(n, rowptr, col, perm, level_start, nlevels, block_ptr, block_count);
+    if (!block_ptr_out || !block_count_out) return GS_OK;
+    int64_t lvl[GS_MAX_LEVELS + 2];
+    int64_t* pbuf = (int64_t*)std::malloc(sizeof(int64_t) * (size_t)n);
+    if (!pbuf) throw std::bad_alloc();
+    int nl = 0;
+    const int rc = export_partition(p, pbuf, lvl, &nl, block_ptr_out, block_count_out, block_cap);
+    std::free(pbuf);
+    return rc;
   });
 }
 

@@ -58,6 +58,15 @@ Partition partition_grid(int ndim, const int32_t* dims, int nparts,
 // needed); nparts a power of two.
 Partition partition_graph(int nparts, int levels, int64_t n, const int64_t* rp,
                           const int32_t* ci);
+// A partition given by the caller (perm[new] = old, L + 2 segment starts),
+// checked against A's pattern: every segment non-empty, and B_l (l < L)
+// block diagonal.  Blocks given as global boundaries per segment (block_ptr,
+// block_count as gs_partition_grid writes them) or, when block_ptr is null,
+// the connected components of each segment's rows in the symmetrised graph
+// of A, which must each be contiguous in perm.  Throws Error(GS_EINVAL).
+Partition user_partition(int64_t n, const int64_t* rp, const int32_t* ci, const int64_t* perm,
+                         const int64_t* level_start, int L, const int64_t* block_ptr,
+                         const int64_t* block_count);
 
 // --------------------------------------------------------------- ILU
 template <class T>

@@ -367,6 +367,112 @@ CSR<T> permute(const CSR<T>& A, const std::vector<int64_t>& perm) {
   return Ap;
 }
 
+Partition user_partition(int64_t n, const int64_t* rp, const int32_t* ci, const int64_t* perm,
+                         const int64_t* level_start, int L, const int64_t* block_ptr,
+                         const int64_t* block_count) {
+  if (!perm || !level_start) throw Error(GS_EINVAL, "user partition: perm and level_start needed");
+  if (L < 0 || L > GS_MAX_LEVELS) throw Error(GS_EINVAL, "user partition: levels out of range");
+  Partition p;
+  p.L = L;
+  p.perm.assign(perm, perm + n);
+  {
+    std::vector<char> seen((size_t)n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t o = perm[i];
+      if (o < 0 || o >= n || seen[(size_t)o]) throw Error(GS_EINVAL, "user partition: perm is not a permutation");
+      seen[(size_t)o] = 1;
+    }
+  }
+  p.level_start.assign(level_start, level_start + L + 2);
+  if (p.level_start[0] != 0 || p.level_start[(size_t)L + 1] != n)
+    throw Error(GS_EINVAL, "user partition: level_start must run from 0 to n");
+  for (int l = 0; l <= L; ++l)
+    if (p.level_start[(size_t)l + 1] <= p.level_start[(size_t)l])
+      throw Error(GS_EINVAL, "user partition: every segment needs at least one row");
+  // new index of every original row
+  std::vector<int64_t> inv((size_t)n);
+  for (int64_t i = 0; i < n; ++i) inv[(size_t)perm[i]] = i;
+  p.blocks.assign((size_t)L + 1, {});
+  if (block_ptr) {
+    if (!block_count) throw Error(GS_EINVAL, "user partition: block_ptr without block_count");
+    int64_t o = 0;
+    for (int l = 0; l <= L; ++l) {
+      const int64_t nb = block_count[l];
+      if (nb < 1) throw Error(GS_EINVAL, "user partition: a segment without blocks");
+      std::vector<int64_t>& b = p.blocks[(size_t)l];
+      b.assign(block_ptr + o, block_ptr + o + nb + 1);
+      o += nb + 1;
+      if (b.front() != p.level_start[(size_t)l] || b.back() != p.level_start[(size_t)l + 1])
+        throw Error(GS_EINVAL, "user partition: blocks must cover their segment");
+      for (int64_t t = 0; t < nb; ++t)
+        if (b[(size_t)t + 1] <= b[(size_t)t]) throw Error(GS_EINVAL, "user partition: empty or unordered block");
+    }
+  } else {
+    // connected components of each segment's rows in the symmetrised graph
+    // of A (union-find over the entries inside the segment)
+    std::vector<int64_t> parent((size_t)n);
+    for (int64_t i = 0; i < n; ++i) parent[(size_t)i] = i;
+    auto find = [&](int64_t x) {
+      while (parent[(size_t)x] != x) {
+        parent[(size_t)x] = parent[(size_t)parent[(size_t)x]];
+        x = parent[(size_t)x];
+      }
+      return x;
+    };
+    auto seg_of = [&](int64_t r) {
+      return (int)(std::upper_bound(p.level_start.begin(), p.level_start.end(), r) -
+                   p.level_start.begin()) - 1;
+    };
+    for (int64_t o = 0; o < n; ++o) {
+      const int64_t i = inv[(size_t)o];
+      const int si = seg_of(i);
+      for (int64_t q = rp[o]; q < rp[o + 1]; ++q) {
+        const int64_t j = inv[(size_t)ci[q]];
+        if (j == i || seg_of(j) != si) continue;
+        const int64_t a = find(i), b = find(j);
+        if (a != b) parent[(size_t)std::max(a, b)] = std::min(a, b);
+      }
+    }
+    for (int l = 0; l <= L; ++l) {
+      const int64_t a = p.level_start[(size_t)l], e = p.level_start[(size_t)l + 1];
+      std::vector<int64_t>& b = p.blocks[(size_t)l];
+      b.push_back(a);
+      std::vector<char> done;  // roots already closed, by offset from a
+      done.assign((size_t)(e - a), 0);
+      int64_t cur = find(a);
+      for (int64_t r = a + 1; r < e; ++r) {
+        const int64_t root = find(r);
+        if (root == cur) continue;
+        done[(size_t)(cur - a)] = 1;
+        if (done[(size_t)(root - a)])
+          throw Error(GS_EINVAL, "user partition: a connected block of level " + std::to_string(l) +
+                                     " is not contiguous in perm");
+        b.push_back(r);
+        cur = root;
+      }
+      b.push_back(e);
+    }
+  }
+  // B_l must be block diagonal (the separator property); C_last's blocks
+  // are cut on purpose (block-Jacobi)
+  for (int l = 0; l < L; ++l) {
+    const std::vector<int64_t>& b = p.blocks[(size_t)l];
+    const int64_t a = p.level_start[(size_t)l], e = p.level_start[(size_t)l + 1];
+    for (int64_t i = a; i < e; ++i) {
+      const int64_t bi = std::upper_bound(b.begin(), b.end(), i) - b.begin();
+      const int64_t o = perm[i];
+      for (int64_t q = rp[o]; q < rp[o + 1]; ++q) {
+        const int64_t j = inv[(size_t)ci[q]];
+        if (j < a || j >= e) continue;
+        if (std::upper_bound(b.begin(), b.end(), j) - b.begin() != bi)
+          throw Error(GS_EINVAL, "user partition: two blocks of level " + std::to_string(l) +
+                                     " are coupled by an entry of A");
+      }
+    }
+  }
+  return p;
+}
+
 template <class T>
 void extract_levels(const CSR<T>& A, const Partition& part, HostSetup<T>& S) {
   const int64_t n = A.nrows;

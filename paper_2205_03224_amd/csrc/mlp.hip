@@ -244,7 +244,8 @@ struct gs_mlp {
 
 extern "C" {
 
-int gs_mlp_create(gs_mlp** out, int in_dim, int hidden, int out_dim, int device, void* stream) {
+int gs_mlp_create(gs_mlp** out, int in_dim, int hidden, int out_dim, uint64_t seed, int device,
+                  void* stream) {
   if (!out) return GS_EINVAL;
   *out = nullptr;
   if (in_dim < 1 || hidden < 1 || out_dim < 1 || in_dim > gs::kMaxDim || hidden > gs::kMaxDim ||
@@ -263,7 +264,26 @@ int gs_mlp_create(gs_mlp** out, int in_dim, int hidden, int out_dim, int device,
     m.grads = m.mem.alloc<float>(m.nparams);
     m.m = m.mem.alloc<float>(m.nparams);
     m.v = m.mem.alloc<float>(m.nparams);
-    gs::launch_fill<float>(m.params, 0.0f, m.nparams, m.st);
+    // Glorot-uniform weights, zero biases: packed parameter j (weights only)
+    // is sqrt(6 / (fan_in + fan_out)) of its layer times v_j, v the
+    // SplitMix64 start vector of `seed` over all nparams positions
+    {
+      std::vector<double> v((size_t)m.nparams);
+      gs::start_vector(seed, m.nparams, v.data());
+      std::vector<float> p((size_t)m.nparams, 0.0f);
+      const int dims[4] = {in_dim, hidden, hidden, out_dim};
+      size_t o = 0;
+      for (int layer = 0; layer < 3; ++layer) {
+        const int a = dims[layer], b = dims[layer + 1];
+        const double lim = std::sqrt(6.0 / (double)(a + b));
+        for (int e = 0; e < a * b; ++e, ++o) p[o] = (float)(lim * v[o]);
+        o += (size_t)b;  // biases stay zero
+      }
+      gs::hipcheck(hipMemcpyAsync(m.params, p.data(), p.size() * sizeof(float),
+                                  hipMemcpyHostToDevice, m.st),
+                   "mlp init");
+      gs::hipcheck(hipStreamSynchronize(m.st), "mlp init");
+    }
     gs::launch_fill<float>(m.grads, 0.0f, m.nparams, m.st);
     gs::launch_fill<float>(m.m, 0.0f, m.nparams, m.st);
     gs::launch_fill<float>(m.v, 0.0f, m.nparams, m.st);

@@ -40,7 +40,10 @@ class GsOpts(ct.Structure):
                 ("seed", ct.c_uint64), ("nthreads", ct.c_int),
                 ("defer_lowrank", ct.c_int), ("block_max_iters", ct.c_int),
                 ("inner_gmres_its", ct.c_int), ("ilu_shift", ct.c_double),
-                ("warm_start", ct.c_int)]
+                ("warm_start", ct.c_int),
+                ("part_perm", ct.c_void_p), ("part_level_start", ct.c_void_p),
+                ("part_nlevels", ct.c_int), ("part_block_ptr", ct.c_void_p),
+                ("part_block_count", ct.c_void_p)]
 
 
 _L1 = GS_MAX_LEVELS + 1
@@ -113,6 +116,8 @@ SIGNATURES = [
                                      _p, _p, ct.POINTER(ct.c_int), _p, _p, ct.c_int64]),
     ("gs_partition_graph", ct.c_int, [ct.c_int, ct.c_int, ct.c_int64, _p, _p, _p, _p,
                                       ct.POINTER(ct.c_int), _p, _p, ct.c_int64]),
+    ("gs_partition_check", ct.c_int, [ct.c_int64, _p, _p, _p, _p, ct.c_int, _p, _p, _p, _p,
+                                      ct.c_int64]),
     ("gs_ilu", ct.c_int, [ct.c_int64, _p, _p, _p, ct.c_int, ct.c_int, ct.c_double, ct.c_int,
                           _p, _p, _p, ct.c_int64, _p, _p, _p, ct.c_int64]),
     ("gs_features", ct.c_int, [_p, ct.c_int, _p, ct.c_int64, ct.c_int,
@@ -121,7 +126,8 @@ SIGNATURES = [
     ("gs_get_level_sizes", ct.c_int, [_p, ct.c_int, _p]),
     ("gs_get_level", ct.c_int, [_p, ct.c_int] + [_p] * 15),
     ("gs_get_perm", ct.c_int, [_p, _p]),
-    ("gs_mlp_create", ct.c_int, [ct.POINTER(_p), ct.c_int, ct.c_int, ct.c_int, ct.c_int, _p]),
+    ("gs_mlp_create", ct.c_int, [ct.POINTER(_p), ct.c_int, ct.c_int, ct.c_int, ct.c_uint64,
+                                 ct.c_int, _p]),
     ("gs_mlp_destroy", None, [_p]),
     ("gs_mlp_nparams", ct.c_int, [_p]),
     ("gs_mlp_last_error", ct.c_char_p, [_p]),
@@ -230,13 +236,18 @@ class Context:
             pass
 
     # ---------------------------------------------------------------- setup
-    def setup(self, rowptr, col, val, levels, nparts, rank, drop_tol, **kw):
+    def setup(self, rowptr, col, val, levels, nparts, rank, drop_tol, partition=None, **kw):
+        """partition: optional (perm, level_start, L[, blocks]) in the format
+        partition_grid returns (blocks None or omitted: the connected
+        components of every segment); levels and nparts are then unused."""
         rp, ci, v = _i64(rowptr), _i32(col), _vals(val)
         self.dtype = GS_C128 if np.iscomplexobj(v) else GS_F64
         self.n = len(rp) - 1
         o = opts(**kw)
+        keep = _partition_opts(o, partition)
         self._check(lib().gs_setup(self._h, self.n, _ptr(rp), _ptr(ci), _ptr(v), self.dtype,
                                    levels, nparts, rank, drop_tol, ct.byref(o)))
+        del keep
         return self
 
     def setup_explicit(self, rowptr, col, val, perm, levels, **kw):
@@ -448,6 +459,54 @@ def partition_grid(dims, nparts, levels, rowptr, col):
     return perm, ls[:L + 2].copy(), L, blocks
 
 
+def _partition_opts(o, partition):
+    """Point the gs_opts partition fields at arrays made from `partition`;
+    returns them (they must live until gs_setup returns)."""
+    if partition is None:
+        return None
+    perm, ls, L = partition[0], partition[1], int(partition[2])
+    blocks = partition[3] if len(partition) > 3 else None
+    keep = [_i64(perm), _i64(ls)]
+    o.part_perm = keep[0].ctypes.data
+    o.part_level_start = keep[1].ctypes.data
+    o.part_nlevels = L
+    if blocks is not None:
+        bp = _i64(np.concatenate([np.asarray(b, np.int64) for b in blocks]))
+        bc = _i64([len(b) - 1 for b in blocks])
+        keep += [bp, bc]
+        o.part_block_ptr = bp.ctypes.data
+        o.part_block_count = bc.ctypes.data
+    return keep
+
+
+def partition_check(rowptr, col, perm, level_start, L, blocks=None):
+    """gs_partition_check: the blocks of a caller's partition (given ones
+    checked, or the connected components of every segment); raises
+    GemslrError for a partition the setup would reject."""
+    rp, ci = _i64(rowptr), _i32(col)
+    n = len(rp) - 1
+    p, ls = _i64(perm), _i64(level_start)
+    cap = n + L + 2
+    out_bp = np.zeros(cap, np.int64)
+    out_bc = np.zeros(L + 1, np.int64)
+    bp = bc = None
+    if blocks is not None:
+        bp = _i64(np.concatenate([np.asarray(b, np.int64) for b in blocks]))
+        bc = _i64([len(b) - 1 for b in blocks])
+    rc = lib().gs_partition_check(n, _ptr(rp), _ptr(ci), _ptr(p), _ptr(ls), int(L),
+                                  _ptr(bp) if bp is not None else None,
+                                  _ptr(bc) if bc is not None else None,
+                                  _ptr(out_bp), _ptr(out_bc), cap)
+    if rc != GS_OK:
+        raise GemslrError(rc, lib().gs_last_error(None).decode())
+    out, pos = [], 0
+    for l in range(L + 1):
+        cnt = int(out_bc[l]) + 1
+        out.append(out_bp[pos:pos + cnt].copy())
+        pos += cnt
+    return out
+
+
 def partition_graph(nparts, levels, rowptr, col):
     """gs_partition_graph: (perm, level_start, L, blocks) for a matrix without
     grid coordinates."""
@@ -494,12 +553,12 @@ def ilu(rowptr, col, val, kind="ilut", tau=0.0, lfil=10):
 class Mlp:
     """The learned-start network on one GPU (gs_mlp_*)."""
 
-    def __init__(self, in_dim, hidden, out_dim, device=0, stream=None):
+    def __init__(self, in_dim, hidden, out_dim, seed=0, device=0, stream=None):
         if stream is None:
             import torch
             stream = torch.cuda.current_stream(device).cuda_stream
         h = ct.c_void_p()
-        rc = lib().gs_mlp_create(ct.byref(h), in_dim, hidden, out_dim, device,
+        rc = lib().gs_mlp_create(ct.byref(h), in_dim, hidden, out_dim, ct.c_uint64(seed), device,
                                  ct.c_void_p(stream or 0))
         if rc != GS_OK:
             raise GemslrError(rc, "gs_mlp_create failed")
