@@ -242,9 +242,12 @@ def helmholtz(N, K, log, ilu_shift=0.0):
            "apply_GBps": info["apply_bytes"] / (us * 1e-6) / 1e9,
            "its": res["its"], "relres": res["relres"], "converged": bool(res["converged"]),
            "t_solve_s": ts, "time_to_tol_s": info["t_lowrank"] + ts,
-           "err_vs_x_true": float(np.linalg.norm(xh - w.x_true) / np.linalg.norm(w.x_true))}
+           "err_vs_x_true": float(np.linalg.norm(xh - w.x_true) / np.linalg.norm(w.x_true)),
+           "arnoldi_cycles": list(info["arnoldi_cycles"][:info["nlevels"]]),
+           "arnoldi_matvecs": list(info["arnoldi_matvecs"][:info["nlevels"]])}
     log(f"[bench] c128 (ilu_shift {ilu_shift}): {us:.1f} us/apply, {out['apply_GBps']:.0f} GB/s; solve its {res['its']} "
-        f"relres {res['relres']:.2e} in {ts:.2f} s (+ lowrank {info['t_lowrank']:.2f} s)")
+        f"relres {res['relres']:.2e} in {ts:.2f} s (+ lowrank {info['t_lowrank']:.2f} s; Arnoldi "
+        f"cycles {out['arnoldi_cycles']} products {out['arnoldi_matvecs']})")
     ctx.close()
     return out
 
