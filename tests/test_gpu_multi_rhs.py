@@ -108,3 +108,32 @@ def test_apply_many_mixed_forms_equal_single(torch_dev, prec, nrhs, cons, monkey
     torch.cuda.synchronize()
     assert torch.equal(yd, ys)
     ctx.close()
+
+
+@pytest.mark.parametrize("cons", [None, "8"])
+def test_apply_many_beyond_one_batch(torch_dev, cons, monkeypatch):
+    """More vectors than one batch holds (64): the library sweeps them in
+    successive batches of its working vectors; every column still equals its
+    single apply bit for bit, and the oracle's apply to the float64 apply
+    tolerance (checked on a few columns)."""
+    torch = torch_dev
+    from paper_2205_03224_amd import gemslr
+    if cons:
+        monkeypatch.setenv("GEMSLR_CONSUMERS", cons)
+    w, st = _case("laplace2d_32")
+    ctx = gemslr.Context(0)
+    ctx.setup_explicit(w.rowptr, w.col, w.val, st.perm, oracle_levels(st))
+    nrhs = 70
+    X = _block(w, nrhs, 1234)
+    xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    yd = torch.empty_like(xd)
+    ctx.apply_many(nrhs, xd, yd)
+    ys = torch.empty_like(xd)
+    for j in range(nrhs):
+        ctx.apply(xd[j], ys[j])
+    torch.cuda.synchronize()
+    assert torch.equal(yd, ys)
+    Y = yd.cpu().numpy()
+    for j in (0, 63, 64, 69):
+        assert_close(Y[j], og.apply(st, X[j]), APPLY_TOL_F64, what=f"column {j}")
+    ctx.close()
