@@ -1216,7 +1216,9 @@ struct EngineT final : Engine {
   // the apply reads and writes the B_0 rows of the caller's vectors inside
   // the level-0 sweeps
   bool fuse_ok() const {
-    return inner_m == 0 && !no_fuse_perm && !lv.empty() && lv[0].d > 0 && lv[0].start == 0 &&
+    // (level 0 must have an up sweep: it writes the B_0 rows of the result;
+    // a one-level preconditioner ends with its down sweep)
+    return inner_m == 0 && !no_fuse_perm && lv.size() > 1 && lv[0].d > 0 && lv[0].start == 0 &&
            streamed(0);
   }
   double tri_bytes(int l, int mode, bool perm_fused = false) const {
