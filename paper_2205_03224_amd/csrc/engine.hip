@@ -807,9 +807,13 @@ struct EngineT final : Engine {
           if (per_cu == 1 && ((half - xb - 1024) / chunk_bufs) >= kChunkCapMax - 1024)
             budget = std::min(budget, half);
         }
-        int cap = std::min(kChunkCapMax, ((budget - xb - 1024) / chunk_bufs) & ~1023);
+        const auto cap_of = [&](int bgt) {
+          return std::min(kChunkCapMax, ((bgt - xb - 1024) / chunk_bufs) & ~1023);
+        };
+        int cap = cap_of(budget);
         const int ms = stream_slots(L.maxslot);
-        if (!no_stream && L.nb > 0 && ms > 0 && cap >= 4096) {
+        if (!no_stream && L.nb > 0 && ms > 0 &&
+            cap_of(std::max(budget, std::min(lds_budget, lds_per_cu))) >= 4096) {
           // per triangle: half-row stages (at most 32 rows, two lanes per
           // row, each with half of the row's slots) unless they take more
           // than 8% more stages than full-row ones (at most 64 rows)
@@ -832,10 +836,30 @@ struct EngineT final : Engine {
           bool hl = false, hu = false;
           TriHost<T> sl = sched(h.L, false, hl);
           TriHost<T> su = sched(h.U, true, hu);
+          // Fewer workgroups per CU when co-residency would leave chunks of
+          // fewer than three average stages: a chunk's copy then outlasts
+          // its sweep and the copy latency shows (measured at level 0 of
+          // the 128^3 workloads: complex128, 7 KB chunks at two workgroups
+          // per CU 310 us per sweep, 24 KB chunks at one 262 us with two
+          // rounds of blocks; float64 holds 3.4 stages in 7 KB chunks and
+          // keeps two per CU)
+          if (!fixed_budget && L.nb > 0) {
+            const int nst = (int)(sl.stage_row.size() + su.stage_row.size()) - 2;
+            const double row_bytes = stream_vstride(ms) * (double)sizeof(V) +
+                                     stream_cstride(ms) * 2.0 + 4.0 + sizeof(D);
+            const double stage_bytes = 2.0 * (double)L.d * row_bytes / std::max(1, nst);
+            int per_cu = std::max(1, lds_per_cu / std::max(1, budget));
+            while (cap < 3.0 * stage_bytes && cap < kChunkCapMax - 1024 && per_cu > 1) {
+              --per_cu;
+              budget = std::min(lds_budget, lds_per_cu / per_cu);
+              cap = cap_of(budget);
+            }
+          }
           std::vector<uint8_t> blob;
           std::vector<ChunkDesc> desc;
           std::vector<int32_t> bc;
-          if (build_chunks_par<V, D, T>(sl, su, L.nb, cap, ms, ColScale<C>::value,
+          if (cap >= 4096 &&
+              build_chunks_par<V, D, T>(sl, su, L.nb, cap, ms, ColScale<C>::value,
                                         L.max_block_rows, hl, hu, blob, desc, bc)) {
             L.half_l = hl;
             L.half_u = hu;
