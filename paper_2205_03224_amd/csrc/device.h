@@ -241,8 +241,12 @@ template <class P> void launch_trisolve(const TriArgs<P>& a, int mode, int maxsl
 // consumer waves sweep them; needs a.blob, x in LDS, and maxslot <= 16
 template <class P> void launch_trisolve_streamed(const TriArgs<P>& a, int mode, int maxslot,
                                                  int max_block_rows, hipStream_t st);
-// maximum chunk size the streamed kernel stages (bytes)
-constexpr int kChunkCapMax = 24576;
+// maximum chunk size the streamed kernel stages (bytes): 48 copy
+// iterations per lane, within the 63 loads a wave can have outstanding
+// (measured: 24 -> 48 KiB took the 64^3 apply from 287 to 269 us and the
+// complex128 128^3 apply from 892 to 835 us, where one workgroup per CU
+// sweeps level 0; at two per CU LDS keeps level 0 at 23 KiB)
+constexpr int kChunkCapMax = 49152;
 template <class P> void launch_interface(const IfArgs<P>& a, hipStream_t st);
 // dst[i] = src[i] rounded to V (float or bf16) as the host storage
 // conversion rounds it
