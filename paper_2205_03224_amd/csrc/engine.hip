@@ -1202,10 +1202,16 @@ struct EngineT final : Engine {
     }
   }
 
+  // Timing events take no system-scope fence: with one, each record writes
+  // the L2s of all XCDs back to memory (measured: 11 us per apply for the
+  // four events around the two level-0 sweeps, 4 us without the fence), time
+  // the bracketed launch and the apply around it would be charged for. The
+  // host reads the events only after a stream synchronisation.
+  static constexpr unsigned kTimingEventFlags = hipEventDisableSystemFence;
   hipEvent_t ev_at(size_t i) {
     while (prof_ev.size() <= i) {
       hipEvent_t e;
-      HIPCHK(hipEventCreate(&e));
+      HIPCHK(hipEventCreateWithFlags(&e, kTimingEventFlags));
       prof_ev.push_back(e);
     }
     return prof_ev[i];
@@ -1491,7 +1497,7 @@ struct EngineT final : Engine {
     probe_bytes_sum = 0;
     for (int i = 0; i < 2 * std::max(0, max_launches) + 1 && kind >= 0; ++i) {
       hipEvent_t e;
-      HIPCHK(hipEventCreate(&e));
+      HIPCHK(hipEventCreateWithFlags(&e, kTimingEventFlags));
       probe_ev.push_back(e);
     }
   }
