@@ -197,7 +197,7 @@ typedef struct {
                                 /* E_l: s x d (rows in C_l, columns in B_l)     */
   const int64_t* f_rowptr; const int32_t* f_col; const void* f_val;
                                 /* F_l: d x s (rows in B_l, columns in C_l)     */
-  int32_t k;                    /* rank of the correction                      */
+  int32_t k;                    /* rank of the correction, 0 <= k <= min(s, 1024) */
   const void* w;                /* W_l: s x k, column-major                     */
   const void* h;                /* H_l = (I - R_l)^{-1} - I: k x k, column-major */
 } gs_level_data;

@@ -1046,7 +1046,9 @@ static void setup_explicit(gs_ctx* c, int64_t n, const int64_t* rp, const int32_
       for (int32_t x : h.E.ci) if (x < 0 || x >= a.d) throw Error(GS_EINVAL, "E column out of range");
       for (int32_t x : h.F.ci) if (x < 0 || x >= h.s) throw Error(GS_EINVAL, "F column out of range");
       h.k = a.k;
-      if (a.k < 0 || a.k > h.s) throw Error(GS_EINVAL, "bad rank");
+      // the low-rank kernels take k <= 1024, as check_rank does for gs_setup
+      if (a.k < 0 || a.k > h.s || a.k > 1024)
+        throw Error(GS_EINVAL, "bad rank on level " + std::to_string(l) + " (0 <= k <= min(s, 1024))");
       if (a.k > 0) {
         h.W.resize((size_t)h.s * a.k);
         h.H.resize((size_t)a.k * a.k);

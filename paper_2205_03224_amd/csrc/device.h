@@ -167,6 +167,12 @@ struct TriArgs {
   const typename P::O* xin;
   typename P::O* yout;
   const int32_t* perm;
+  // UP with yout (single vector, streamed kernel): the sweep also writes the
+  // ccopy rows of C_l, yout[perm[d + i]] = t[d + i] for i < ccopy (the
+  // apply's final scatter); workgroup b takes rows b * ccopy / nb up to
+  // (b + 1) * ccopy / nb, copied by its producer wave while the last chunk
+  // is swept.  0: none.
+  int64_t ccopy = 0;
   // streamed UP mode: F_l y2 formed by the sweep itself, from the rows of
   // F_l that hold entries (null: read from fy, formed by a launch before).
   // Record q is unit-local row frow[q] with entries j < fw at

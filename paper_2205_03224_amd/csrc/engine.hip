@@ -1178,10 +1178,14 @@ struct EngineT final : Engine {
     if (streamed(l)) {
       TriArgs<P> a = tri_args(l);
       if (l == 0 && fuse.on) {
-        // the apply's gather (scatter) of B_0 rows happens in this sweep
+        // the apply's gather (scatter) of B_0 rows happens in this sweep, and
+        // the up sweep also scatters the C_0 rows
         a.perm = fuse.perm;
         if (mode == TRI_DOWN) a.xin = fuse.x;
-        else a.yout = fuse.y;
+        else {
+          a.yout = fuse.y;
+          a.ccopy = nv == 1 ? L.s : 0;  // (fuse is on only for single applies)
+        }
       }
       if (nv == 1) {
         launch_trisolve_streamed<P>(a, mode, L.maxslot, L.max_block_rows, st);
@@ -1268,6 +1272,8 @@ struct EngineT final : Engine {
     if (mode == TRI_UP)
       b += (double)L.nnz_f * (vb + 4) + frows                // F_l
            + (double)L.nnz_f * xb + (double)L.d * xb;        // y2 gathers, z1 read
+    // the level-0 up sweep of an apply also scatters the C_0 rows
+    if (perm_fused && mode == TRI_UP) b += perm_bytes(L.s);
     return b + fused;
   }
   double if_bytes(int l, int k, bool gather_fused = false) const {
@@ -1373,17 +1379,14 @@ struct EngineT final : Engine {
     const int32_t* pm = permuted ? nullptr : perm_d;
     const int64_t d0 = lv.empty() ? 0 : lv[0].d;
     if (fuse_ok()) {
-      // B_0 rows are read and written by the level-0 sweeps themselves and
-      // the C_0 rows read by the level-0 interface step; only the C_0 rows
-      // go through a scatter kernel
+      // B_0 rows are read and written by the level-0 sweeps themselves, the
+      // C_0 rows read by the level-0 interface step and written by the
+      // level-0 up sweep
       const O* xo = (const O*)x;
       O* yo = (O*)y;
       fuse = {true, xo, yo, pm};
       run_from(0);
       fuse = {};
-      step("scatter C0", KIND_PERM, perm_bytes(n - d0), [&] {
-        launch_scatter<P>(t + d0, pm ? pm + d0 : nullptr, pm ? yo : yo + d0, n - d0, st);
-      });
       return;
     }
     step("gather", KIND_PERM, perm_bytes(n),
@@ -1653,10 +1656,7 @@ struct EngineT final : Engine {
 
   // Compulsory HBM traffic of one whole apply: the sum over its launches.
   double bytes_per_apply() const override {
-    if (fuse_ok()) {
-      const int64_t d0 = lv[0].d;
-      return perm_bytes(n - d0) + apply_bytes_from(0, true);
-    }
+    if (fuse_ok()) return apply_bytes_from(0, true);
     double b = 2 * perm_bytes(n);
     if (inner_m > 0) {
       // root level with inner steps: down + interface, per step one product

@@ -838,6 +838,31 @@ __device__ __forceinline__ void store_result(const TriArgs<P>& a, int r0, int nr
 // them.  Consumers without a vector (the launch's last group) only take
 // part in the barriers.  MULTI false: one consumer and one vector per
 // workgroup (vector blockIdx.y), with the register budget of two waves.
+// The C_l rows of TriArgs::ccopy that workgroup b writes to the caller's
+// vector, by one wave (its stores left in flight)
+template <class P>
+__device__ __forceinline__ void copy_c_rows(const TriArgs<P>& a, int b, int lane) {
+  using X = typename P::X;
+  constexpr int U = 8;
+  const int64_t lo = a.ccopy * b / a.nb, hi = a.ccopy * (b + 1) / a.nb;
+  for (int64_t i0 = lo + lane; i0 < hi; i0 += (int64_t)kWave * U) {
+    X v[U];
+    int64_t dst[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      dst[u] = a.d + min(i0 + u * kWave, hi - 1);
+      v[u] = a.t[dst[u]];
+    }
+    if (a.perm) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) dst[u] = a.perm[dst[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * kWave < hi) st_out(&a.yout[dst[u]], cvt<typename P::O>(v[u]));
+  }
+}
+
 template <class P, int MS, int MODE, bool MULTI>
 __global__ __launch_bounds__(MULTI ? kWave * (stream_max_cons(sizeof(typename P::C), MS) + 1)
                                    : 2 * kWave) void k_trisolve_streamed(
@@ -915,6 +940,9 @@ __global__ __launch_bounds__(MULTI ? kWave * (stream_max_cons(sizeof(typename P:
         copy_chunk<P>(a, cd, bufs + ((k + 1) % 2) * a.chunk_cap, lane, iters(cd));
       }
       __builtin_amdgcn_s_waitcnt(GS_VMCNT_IMM(0));
+      // the last chunk is being swept: the C_l rows meanwhile
+      if constexpr (MODE == TRI_UP && !MULTI)
+        if (c + 1 == c1 && a.ccopy > 0) copy_c_rows<P>(a, b, lane);
     } else {
       // Nothing of this wave is in flight here (its last chunk ended with a
       // full LDS wait), so this wait costs nothing; it tells the compiler
@@ -944,6 +972,8 @@ __global__ __launch_bounds__(MULTI ? kWave * (stream_max_cons(sizeof(typename P:
     // hand-over without a memory fence: copies of later chunks stay in flight
     __builtin_amdgcn_s_barrier();
   }
+  if constexpr (MODE == TRI_UP && !MULTI)
+    if (c0 >= c1 && wave == ncons && a.ccopy > 0) copy_c_rows<P>(a, b, lane);
   __syncthreads();
   store_result<P, MODE>(a, r0, nr, nv, tid, nt, x, xs);
 }
@@ -1070,6 +1100,32 @@ __device__ __forceinline__ typename P::C if_b2(const IfArgs<P>& a, int64_t i) {
   return cvt<C>(a.t[a.d + i]);
 }
 
+// z2 = b2 - E_l z1 of R rows per thread, written over t[d + row]; the rows
+// of thread tid of workgroup g are g * 256 R + tid + q * 256
+template <class P, int R>
+__device__ __forceinline__ void if_z2(const IfArgs<P>& a, int64_t base,
+                                      typename P::C (&z)[R]) {
+  using C = typename P::C;
+  using X = typename P::X;
+  int rows[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int64_t j = base + (int64_t)q * kIfThreads;
+    rows[q] = j < a.s ? (int)j : -1;
+  }
+  C ez[R];
+  csr_rows<C, typename P::V, X, R, 4>(a.E.rp, a.E.ci, a.E.v, a.t, rows, ez);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    z[q] = zero<C>();
+    if (rows[q] >= 0) {
+      const C acc = if_b2(a, rows[q]) - ez[q];
+      a.t[a.d + rows[q]] = cvt<X>(acc);
+      z[q] = acc;
+    }
+  }
+}
+
 template <class P, int R, int KG>
 __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a0) {
   using C = typename P::C;
@@ -1083,25 +1139,7 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a0) {
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * kIfThreads * R + tid;
   C z[R];
-  {
-    int rows[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int64_t j = base + (int64_t)q * kIfThreads;
-      rows[q] = j < a.s ? (int)j : -1;
-    }
-    C ez[R];
-    csr_rows<C, typename P::V, X, R, 4>(a.E.rp, a.E.ci, a.E.v, a.t, rows, ez);
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      z[q] = zero<C>();
-      if (rows[q] >= 0) {
-        const C acc = if_b2(a, rows[q]) - ez[q];
-        a.t[a.d + rows[q]] = cvt<X>(acc);
-        z[q] = acc;
-      }
-    }
-  }
+  if_z2<P, R>(a, base, z);
   if (a.k == 0) return;
   // W^H z2 for this workgroup's rows, KG columns at a time: the loads of all
   // KG columns are in flight together (unconditional, at clamped indices:
@@ -1136,11 +1174,48 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a0) {
 
 // t' = H (sum over workgroups of the partials), one workgroup of 1024
 // threads: T = 1024 / k threads per column sum the partials of workgroups
-// g, g+T, ... (coalesced: consecutive threads read consecutive columns, in
-// batches of 8 loads), the T group sums are added in order in LDS; then
-// thread (r, q) forms the part of row r of H t over columns q, q+T, ... and
-// the parts are added in order.  Deterministic; no atomics.
+// g, g+T, ... (coalesced: consecutive threads read consecutive columns; all
+// loads of a thread in flight together, up to kFinishLoads, clamped to the
+// last row), the T group sums are added in order in LDS; then thread (r, q)
+// forms the part of row r of H t over columns q, q+T, ... (its first
+// kFinishH entries of H fetched before the partials) and the parts are
+// added in order.  Deterministic; no atomics.
 constexpr int kFinishThreads = 1024;
+constexpr int kFinishH = 4;
+
+// v[0] + v[ld] + ... + v[(n - 1) ld] from LDS, added in that order, with
+// eight reads in flight at a time (a loop of single reads waits out the
+// LDS latency at every step)
+template <class C>
+__device__ __forceinline__ C lds_sum_ordered(const C* v, int ld, int n) {
+  C t = zero<C>();
+  int q = 0;
+  for (; q + 8 <= n; q += 8) {
+    C r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r[u] = v[(q + u) * ld];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t += r[u];
+  }
+  for (; q < n; ++q) t += v[q * ld];
+  return t;
+}
+
+// sum of partial[b * k + c] over b = g, g + T, ... < nb, in that order,
+// NL loads in flight at a time (clamped to the last row)
+template <class C, int NL>
+__device__ __forceinline__ C finish_part_sum(const C* partial, int nb, int k, int T, int c,
+                                             int g) {
+  C s = zero<C>();
+  for (int b = g; b < nb; b += NL * T) {
+    C v[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) v[u] = partial[(int64_t)min(b + u * T, nb - 1) * k + c];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) s = sel(b + u * T < nb, s + v[u], s);
+  }
+  return s;
+}
 
 template <class P>
 __global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typename P::C* partial,
@@ -1149,6 +1224,9 @@ __global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typenam
                                                                    typename P::C* tprime,
                                                                    int64_t ldpart) {
   using C = typename P::C;
+  // 64 registers of loads per thread (16 wavefronts of 1024 threads leave
+  // 128 per thread)
+  constexpr int kFinishLoads = 256 / (int)sizeof(C);
   partial += (int64_t)blockIdx.y * ldpart;  // vector blockIdx.y of a batched launch
   tprime += (int64_t)blockIdx.y * k;
   __shared__ C red[kFinishThreads];
@@ -1157,27 +1235,28 @@ __global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typenam
   const int tid = threadIdx.x;
   const int T = kFinishThreads / k;
   const int c = tid % k, g = tid / k;
+  C h0[kFinishH];
+#pragma unroll
+  for (int u = 0; u < kFinishH; ++u) h0[u] = H[c + (int64_t)min(g + u * T, k - 1) * k];
   C s = zero<C>();
   if (g < T) {
-    for (int b = g; b < nb; b += 8 * T) {
-      C v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)min(b + u * T, nb - 1) * k + c];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) s = sel(b + u * T < nb, s + v[u], s);
-    }
+    // (few partials per thread: a batch of 8, not kFinishLoads mostly
+    // clamped loads)
+    if (nb <= 8 * T) s = finish_part_sum<C, 8>(partial, nb, k, T, c, g);
+    else s = finish_part_sum<C, kFinishLoads>(partial, nb, k, T, c, g);
   }
   red[tid] = s;
   __syncthreads();
-  if (tid < k) {
-    C t = zero<C>();
-    for (int q = 0; q < T; ++q) t += red[q * k + tid];
-    tv[tid] = t;
-  }
+  if (tid < k) tv[tid] = lds_sum_ordered<C>(red + tid, k, T);
   __syncthreads();
   s = zero<C>();
   if (g < T) {
-    for (int cc = g; cc < k; cc += 8 * T) {
+#pragma unroll
+    for (int u = 0; u < kFinishH; ++u) {
+      const int cc = g + u * T;
+      s = sel(cc < k, s + h0[u] * tv[min(cc, k - 1)], s);
+    }
+    for (int cc = g + kFinishH * T; cc < k; cc += 8 * T) {
       C h[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) h[u] = H[c + (int64_t)min(cc + u * T, k - 1) * k];
@@ -1188,11 +1267,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typenam
   __syncthreads();
   red[tid] = s;
   __syncthreads();
-  if (tid < k) {
-    C t = zero<C>();
-    for (int q = 0; q < T; ++q) t += red[q * k + tid];
-    tprime[tid] = t;
-  }
+  if (tid < k) tprime[tid] = lds_sum_ordered<C>(red + tid, k, T);
 }
 
 // rows per thread of the interface kernel: 2 when that still leaves two
