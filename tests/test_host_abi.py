@@ -103,3 +103,39 @@ def test_host_only_context_refuses_device_work():
         ctx.setup(r, c, v, 2, 4, 4, 0.0, grid_dims=(8, 8))
     assert e.value.code == G.GS_ESTATE
     ctx.close()
+
+
+def _diag_level(d, s, k):
+    """One level of an explicit setup with identity factors and empty E, F;
+    W zero (s x k), H zero (k x k)."""
+    eye = (np.arange(d + 1, dtype=np.int64), np.arange(d, dtype=np.int32), np.ones(d))
+    empty = (np.zeros(d + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    lv = {"d": d, "block_ptr": np.array([0, d], np.int64), "L": empty, "U": eye}
+    if s > 0:
+        lv.update(E=(np.zeros(s + 1, np.int64), np.zeros(0, np.int32), np.zeros(0)),
+                  F=(np.zeros(d + 1, np.int64), np.zeros(0, np.int32), np.zeros(0)),
+                  W=np.zeros((s, k)), H=np.zeros((k, k)))
+    return lv
+
+
+def test_explicit_setup_rejects_rank_above_1024():
+    """The low-rank kernels take k <= 1024 per level (as gs_setup's rank check
+    says); an explicit level with k = 1025 <= s is refused with GS_EINVAL,
+    k = 1024 is accepted (host-only context: validation only)."""
+    d, s = 8, 1100
+    n = d + s
+    A = sp.identity(n, format="csr")
+    perm = np.arange(n, dtype=np.int64)
+    for k, ok in ((1024, True), (1025, False)):
+        ctx = G.Context(-1)
+        try:
+            levels = [_diag_level(d, s, k), _diag_level(s, 0, 0)]
+            if ok:
+                ctx.setup_explicit(A.indptr, A.indices, A.data, perm, levels)
+            else:
+                with pytest.raises(G.GemslrError) as e:
+                    ctx.setup_explicit(A.indptr, A.indices, A.data, perm, levels)
+                assert e.value.code == G.GS_EINVAL
+                assert "1024" in str(e.value)
+        finally:
+            ctx.close()
