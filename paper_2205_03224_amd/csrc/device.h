@@ -173,6 +173,17 @@ struct TriArgs {
   // (b + 1) * ccopy / nb, copied by its producer wave while the last chunk
   // is swept.  0: none.
   int64_t ccopy = 0;
+  // DOWN (streamed kernel): the sweep also files z1 under the entries of
+  // E_l, ez[p] = z1[col] for every entry p of E_l (its index in E_l's CSR
+  // order), so the interface step reads them in that order instead of
+  // gathering z1.  Sweep unit b owns records eunit[b] .. eunit[b + 1] - 1
+  // (an even count: 16-byte aligned), record q = (erec[2q] = p,
+  // erec[2q + 1] = unit-local row), p < 0 for padding; at most chunk_cap
+  // bytes per unit.  Vector j writes ez + j * ldez.  null: none.
+  const int32_t* erec = nullptr;
+  const int32_t* eunit = nullptr;
+  typename P::X* ez = nullptr;
+  int64_t ldez = 0;
   // streamed UP mode: F_l y2 formed by the sweep itself, from the rows of
   // F_l that hold entries (null: read from fy, formed by a launch before).
   // Record q is unit-local row frow[q] with entries j < fw at
@@ -238,6 +249,11 @@ struct IfArgs {
   // tprime + j * k
   int32_t nvec = 1;
   int64_t ldt = 0, ldpart = 0;
+  // z1 filed in E_l's entry order by the level's down sweep (see
+  // TriArgs::erec): the E product reads ez[p] instead of t[col(p)]; vector
+  // j at ez + j * ldez.  null: gather from t.
+  const typename P::X* ez = nullptr;
+  int64_t ldez = 0;
 };
 
 // ------------------------------------------------------------ launchers

@@ -598,6 +598,11 @@ struct EngineT final : Engine {
     const int32_t* funit = nullptr;
     int fw = 0;
     int64_t nrec = 0;
+    // E_l records of the streamed down sweep (null: the interface step
+    // gathers z1)
+    const int32_t* erec = nullptr;
+    const int32_t* eunit = nullptr;
+    int64_t nerec = 0;
   };
 
   hipStream_t st;
@@ -619,6 +624,8 @@ struct EngineT final : Engine {
   C* xg = nullptr;
   C* fy = nullptr;  // F_l y2 of the streamed up sweep
   int64_t fy_len = 0;
+  X* ez = nullptr;  // z1 filed under E_l's entries by a down sweep (one level at a time)
+  int64_t ez_len = 0;
   int max_lds = 65536;
   std::vector<Lev> lv;
   // several vectors per launch (ghat_batch, apply_batch): while nv > 1 the
@@ -629,6 +636,7 @@ struct EngineT final : Engine {
   int bcap = 0;
   X* tb = nullptr;
   C* fyb = nullptr;
+  X* ezb = nullptr;
   std::vector<C*> partb, tpb;
 
   template <class U> U* upload(const std::vector<U>& h) {
@@ -677,6 +685,9 @@ struct EngineT final : Engine {
   bool no_fuse_perm = std::getenv("GEMSLR_NO_FUSE_PERM") != nullptr;
   // GEMSLR_NO_FUSE_FY: F_l y2 of the streamed up sweep in a launch of its own
   bool no_fuse_fy = std::getenv("GEMSLR_NO_FUSE_FY") != nullptr;
+  // GEMSLR_NO_FUSE_E: the interface step gathers z1 for E_l z1 instead of
+  // reading what the down sweep filed under E_l's entries
+  bool no_fuse_e = std::getenv("GEMSLR_NO_FUSE_E") != nullptr;
   // GEMSLR_NO_SMALL_LDS: the small-level interface step reads W_l and H_l
   // from global memory instead of copies in LDS
   bool no_small_lds = std::getenv("GEMSLR_NO_SMALL_LDS") != nullptr;
@@ -716,6 +727,45 @@ struct EngineT final : Engine {
     L.funit = upload(funit);
     L.fw = fw;
     L.nrec = nrec;
+  }
+  // E_l records (see TriArgs::erec) of the sweep units grp: every entry of
+  // E_l, filed under the unit that holds its column, in entry order; none
+  // if one unit's records would not fit a chunk buffer (they are staged
+  // in the free one while the last chunk is swept)
+  void build_e_records(Lev& L, const CSR<T>& E, const std::vector<int64_t>& grp) {
+    const int nb = L.nb;
+    const auto unit_of = [&](int64_t j) {
+      return (int)(std::upper_bound(grp.begin(), grp.end(), j) - grp.begin()) - 1;
+    };
+    std::vector<int64_t> cnt((size_t)nb, 0);
+    for (int32_t j : E.ci) ++cnt[(size_t)unit_of(j)];
+    std::vector<int32_t> eunit((size_t)nb + 1, 0);
+    int64_t tot = 0;
+    for (int b = 0; b < nb; ++b) {
+      const int64_t even = (cnt[(size_t)b] + 1) & ~(int64_t)1;
+      if (even * 8 > L.chunk_cap) return;
+      eunit[(size_t)b] = (int32_t)tot;
+      tot += even;
+    }
+    if (tot >= ((int64_t)1 << 30)) return;
+    eunit[(size_t)nb] = (int32_t)tot;
+    std::vector<int32_t> rec((size_t)(2 * tot), 0);
+    for (size_t q = 0; q < rec.size(); q += 2) rec[q] = -1;  // padding
+    std::vector<int64_t> fill((size_t)nb, 0);
+    for (int64_t p = 0; p < (int64_t)E.ci.size(); ++p) {
+      const int b = unit_of(E.ci[(size_t)p]);
+      const int64_t q = eunit[(size_t)b] + fill[(size_t)b]++;
+      rec[(size_t)(2 * q)] = (int32_t)p;
+      rec[(size_t)(2 * q + 1)] = (int32_t)(E.ci[(size_t)p] - grp[(size_t)b]);
+    }
+    L.erec = upload(rec);
+    L.eunit = upload(eunit);
+    L.nerec = tot;
+  }
+  // the down sweep of level l files z1 under E_l's entries for the
+  // interface step that follows it
+  bool ez_down(int l) const {
+    return lv[l].erec && streamed(l) && lv[l].nb > 0 && l + 1 < (int)lv.size();
   }
   struct FusePerm {
     bool on = false;
@@ -899,6 +949,8 @@ struct EngineT final : Engine {
         L.nnz_e = h.E.nnz();
         L.nnz_f = h.F.nnz();
         if (L.blob && !no_fuse_fy && L.nnz_f > 0) build_f_records(L, h.F, grp);
+        if (L.blob && !no_fuse_e && L.nnz_e > 0 && L.nnz_e < ((int64_t)1 << 30))
+          build_e_records(L, h.E, grp);
       } else {
         std::vector<int32_t> zr(h.d + 1, 0);
         L.F.rp = upload(zr);
@@ -912,6 +964,9 @@ struct EngineT final : Engine {
     xg = mem.alloc<C>(maxd);
     fy = mem.alloc<C>(maxd);
     fy_len = maxd;
+    for (const Lev& L : lv)
+      if (L.erec) ez_len = std::max(ez_len, L.nnz_e);
+    ez = mem.alloc<X>((size_t)std::max<int64_t>(ez_len, 1));
     // C_0 (the interface block of P^T A P) for the inner iteration's S_hat_0
     if constexpr (kInnerCapable) {
       if (lv.size() >= 2 && lv[0].s > 0) {
@@ -1173,10 +1228,16 @@ struct EngineT final : Engine {
     return plan;
   }
   bool streamed(int l) const { return lv[l].blob && !no_stream; }
-  void trisolve(int l, int mode) {
+  void trisolve(int l, int mode, bool ez_out = false) {
     const Lev& L = lv[l];
     if (streamed(l)) {
       TriArgs<P> a = tri_args(l);
+      if (mode == TRI_DOWN && ez_out && L.erec) {
+        a.erec = L.erec;
+        a.eunit = L.eunit;
+        a.ez = ez;
+        a.ldez = nv > 1 ? ez_len : 0;
+      }
       if (l == 0 && fuse.on) {
         // the apply's gather (scatter) of B_0 rows happens in this sweep, and
         // the up sweep also scatters the C_0 rows
@@ -1196,6 +1257,7 @@ struct EngineT final : Engine {
         TriArgs<P> b = a;
         b.t += (int64_t)j0 * a.ldt;
         b.fy += (int64_t)j0 * a.ldfy;
+        if (b.ez) b.ez += (int64_t)j0 * a.ldez;
         b.nvec = pc.second;
         b.ncons = pc.first;
         launch_trisolve_streamed<P>(b, mode, L.maxslot, L.max_block_rows, st);
@@ -1255,7 +1317,7 @@ struct EngineT final : Engine {
     return inner_m == 0 && !no_fuse_perm && lv.size() > 1 && lv[0].d > 0 && lv[0].start == 0 &&
            streamed(0);
   }
-  double tri_bytes(int l, int mode, bool perm_fused = false) const {
+  double tri_bytes(int l, int mode, bool perm_fused = false, bool ez_out = false) const {
     const Lev& L = lv[l];
     const double vb = sizeof(V), xb = sizeof(X), db = sizeof(D);
     // with the apply's permutation fused into level 0, the right-hand side
@@ -1274,14 +1336,18 @@ struct EngineT final : Engine {
            + (double)L.nnz_f * xb + (double)L.d * xb;        // y2 gathers, z1 read
     // the level-0 up sweep of an apply also scatters the C_0 rows
     if (perm_fused && mode == TRI_UP) b += perm_bytes(L.s);
+    // the down sweep filing z1 under E_l's entries: records read, values written
+    if (mode == TRI_DOWN && ez_out) b += 8.0 * L.nerec + 4.0 * (L.nb + 1) + (double)L.nnz_e * xb;
     return b + fused;
   }
-  double if_bytes(int l, int k, bool gather_fused = false) const {
+  double if_bytes(int l, int k, bool gather_fused = false, bool ez_in = false) const {
     const Lev& L = lv[l];
     const double vb = sizeof(V), xb = sizeof(X);
     // gather fused: b2 is a caller vector entry plus its index
     const double b2 = gather_fused ? 4.0 + sizeof(O) : xb;
-    return (double)L.nnz_e * (vb + 4) + (double)(L.s + 1) * 4 + (double)L.nnz_e * xb +
+    // z1 filed in entry order: no column indices read
+    const double ecol = ez_in ? 0.0 : 4.0;
+    return (double)L.nnz_e * (vb + ecol) + (double)(L.s + 1) * 4 + (double)L.nnz_e * xb +
            (double)L.s * (b2 + xb) + (double)L.s * k * vb;
   }
   double upd_bytes(int l, int k) const {
@@ -1299,10 +1365,14 @@ struct EngineT final : Engine {
   }
   // Returns true when the solve of level l + 1 (diagonal, the last level)
   // was done in the same launch (fuse_last requested and possible).
-  bool interface(int l, int k, X* tv = nullptr, bool fuse_last = false) {
+  bool interface(int l, int k, X* tv = nullptr, bool fuse_last = false, bool ez_in = false) {
     Lev& L = lv[l];
     if (!tv) tv = t;
     IfArgs<P> a;
+    if (ez_in) {
+      a.ez = ez;
+      a.ldez = nv > 1 ? ez_len : 0;
+    }
     a.E = L.E;
     a.t = tv + L.start;
     a.d = L.d;
@@ -1331,12 +1401,12 @@ struct EngineT final : Engine {
       step(std::string(last ? "interface+update+solve L" : "interface+update L") +
                std::to_string(l),
            KIND_INTERFACE,
-           if_bytes(l, k, gfused) + (k > 0 ? upd_bytes(l, k) : 0.0) +
+           if_bytes(l, k, gfused, ez_in) + (k > 0 ? upd_bytes(l, k) : 0.0) +
                (last ? (double)L.s * sizeof(D) : 0.0),
            [&] { launch_interface_small<P>(a, st); });
       return last;
     }
-    step("interface L" + std::to_string(l), KIND_INTERFACE, if_bytes(l, k, gfused),
+    step("interface L" + std::to_string(l), KIND_INTERFACE, if_bytes(l, k, gfused, ez_in),
          [&] { launch_interface<P>(a, st); });
     if (k > 0)
       step("lowrank_update L" + std::to_string(l), KIND_LOWRANK, upd_bytes(l, k),
@@ -1350,12 +1420,13 @@ struct EngineT final : Engine {
   // returns true when the last level's solve was fused into this level's
   // interface step
   bool down(int l) {
+    const bool ezl = ez_down(l);
     if (lv[l].nb > 0)
       step("trisolve_down L" + std::to_string(l), l == 0 ? KIND_TRI0 : KIND_TRI,
-           tri_bytes(l, TRI_DOWN, l == 0 && fuse.on), [&] {
-             trisolve(l, TRI_DOWN);
+           tri_bytes(l, TRI_DOWN, l == 0 && fuse.on, ezl), [&] {
+             trisolve(l, TRI_DOWN, ezl);
            });
-    if (l + 1 < (int)lv.size()) return interface(l, lv[l].k, nullptr, !no_fuse_small);
+    if (l + 1 < (int)lv.size()) return interface(l, lv[l].k, nullptr, !no_fuse_small, ezl);
     return false;
   }
   void up(int l) {
@@ -1419,7 +1490,7 @@ struct EngineT final : Engine {
   size_t scratch_bytes() const override {
     if (inner_m > 0) return 0;
     size_t b = up256((size_t)n * sizeof(X)) + up256((size_t)xg_need() * sizeof(C)) +
-               up256((size_t)fy_need() * sizeof(C));
+               up256((size_t)fy_need() * sizeof(C)) + up256((size_t)ez_len * sizeof(X));
     for (const Lev& L : lv)
       if (L.k > 0)
         b += up256((size_t)interface_blocks<P>(L.s) * L.k * sizeof(C)) + up256((size_t)L.k * sizeof(C));
@@ -1436,12 +1507,14 @@ struct EngineT final : Engine {
     X* const t0 = t;
     C* const xg0 = xg;
     C* const fy0 = fy;
+    X* const ez0 = ez;
     C* part0[GS_MAX_LEVELS + 2];
     C* tp0[GS_MAX_LEVELS + 2];
     const size_t nl = std::min(lv.size(), (size_t)GS_MAX_LEVELS + 2);
     t = (X*)take((size_t)n * sizeof(X));
     xg = (C*)take((size_t)xg_need() * sizeof(C));
     fy = (C*)take((size_t)fy_need() * sizeof(C));
+    ez = (X*)take((size_t)ez_len * sizeof(X));
     for (size_t l = 0; l < nl; ++l) {
       Lev& L = lv[l];
       part0[l] = L.partial;
@@ -1455,6 +1528,7 @@ struct EngineT final : Engine {
       t = t0;
       xg = xg0;
       fy = fy0;
+      ez = ez0;
       for (size_t l = 0; l < nl; ++l) {
         lv[l].partial = part0[l];
         lv[l].tprime = tp0[l];
@@ -1545,6 +1619,7 @@ struct EngineT final : Engine {
     bmem = std::make_unique<DevMem>();
     tb = bmem->alloc<X>((size_t)n * m);
     fyb = bmem->alloc<C>((size_t)std::max<int64_t>(fy_len, 1) * m);
+    ezb = bmem->alloc<X>((size_t)std::max<int64_t>(ez_len, 1) * m);
     partb.assign(lv.size(), nullptr);
     tpb.assign(lv.size(), nullptr);
     for (size_t l = 0; l < lv.size(); ++l)
@@ -1561,6 +1636,7 @@ struct EngineT final : Engine {
     batch_reserve(m);
     X* const t0 = t;
     C* const fy0 = fy;
+    X* const ez0 = ez;
     std::vector<C*> p0(lv.size()), q0(lv.size());
     for (size_t l = 0; l < lv.size(); ++l) {
       p0[l] = lv[l].partial;
@@ -1572,10 +1648,12 @@ struct EngineT final : Engine {
     }
     t = tb;
     fy = fyb;
+    ez = ezb;
     nv = m;
     auto restore = [&] {
       t = t0;
       fy = fy0;
+      ez = ez0;
       nv = 1;
       for (size_t l = 0; l < lv.size(); ++l) {
         lv[l].partial = p0[l];
@@ -1684,9 +1762,10 @@ struct EngineT final : Engine {
         b += (double)lv[l].d * sizeof(D);  // 1/u_ii read by the fused solve
         break;
       }
-      if (lv[l].nb > 0) b += tri_bytes(l, TRI_DOWN, f);
+      const bool e = ez_down(l);
+      if (lv[l].nb > 0) b += tri_bytes(l, TRI_DOWN, f, e);
       if (l < L) {
-        b += if_bytes(l, lv[l].k, f);
+        b += if_bytes(l, lv[l].k, f, e);
         if (lv[l].k > 0) b += upd_bytes(l, lv[l].k);
         if (lv[l].nb > 0) b += tri_bytes(l, TRI_UP, f);
       }

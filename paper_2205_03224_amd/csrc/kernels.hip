@@ -77,7 +77,9 @@ __device__ inline T block_sum1(T v, T* red, int tid) {
 // of one thread, with every row's entries fetched together: row pointers,
 // then up to B entries of every row (indices and values), then the gathers.
 // A row of length n costs ceil(n / B) rounds, all rows at once.
-template <class C, class VT, class XT, int U, int B>
+// IDX: x is indexed by the entry itself (x[p], values already gathered in
+// entry order), ci unused.
+template <class C, class VT, class XT, int U, int B, bool IDX = false>
 __device__ __forceinline__ void csr_rows(const int32_t* rp, const int32_t* ci, const VT* val,
                                          const XT* x, const int (&row)[U], C (&r)[U]) {
   int p0[U], p1[U];
@@ -100,7 +102,7 @@ __device__ __forceinline__ void csr_rows(const int32_t* rp, const int32_t* ci, c
         const int q = p0[u] + m + t;
         const bool ok = q < p1[u];
         const int qq = ok ? q : 0;
-        cc[u][t] = ci[qq];
+        cc[u][t] = IDX ? qq : ci[qq];
         fv[u][t] = sel(ok, cvt<C>(val[qq]), zero<C>());
       }
 #pragma unroll
@@ -311,6 +313,16 @@ void launch_trisolve(const TriArgs<P>& a0, int mode, int maxslot, int max_block_
 // latency is paid once per chunk instead of once per wavefront level.
 // ======================================================================
 
+// n16 > 0 units of 16 bytes from src to LDS dst by one wave, as described
+// below for copy_chunk
+__device__ __forceinline__ void copy_to_lds(const uint4* src, int n16, uint8_t* dst, int lane,
+                                            int iters) {
+  const int last = n16 - 1;
+  for (int i = 0; i < iters; ++i)
+    __builtin_amdgcn_global_load_lds(src + min(lane + kWave * i, last),
+                                     (__attribute__((address_space(3))) void*)(dst + 1024 * i),
+                                     16, 0, 0);
+}
 template <class P>
 __device__ __forceinline__ void copy_chunk(const TriArgs<P>& a, const ChunkDesc& cd, uint8_t* dst,
                                            int lane, int iters) {
@@ -320,12 +332,7 @@ __device__ __forceinline__ void copy_chunk(const TriArgs<P>& a, const ChunkDesc&
   // at once.  Lanes past the end re-read the last 16 bytes and land behind
   // the chunk, inside the buffer (iters * 1 KiB <= chunk_cap, a multiple of
   // 1 KiB); a caller may ask for more iterations than the chunk needs.
-  const uint4* src = reinterpret_cast<const uint4*>(a.blob + cd.off);
-  const int last = (int)cd.n16 - 1;
-  for (int i = 0; i < iters; ++i)
-    __builtin_amdgcn_global_load_lds(src + min(lane + kWave * i, last),
-                                     (__attribute__((address_space(3))) void*)(dst + 1024 * i),
-                                     16, 0, 0);
+  copy_to_lds(reinterpret_cast<const uint4*>(a.blob + cd.off), (int)cd.n16, dst, lane, iters);
 }
 
 // s_waitcnt immediates (vmcnt n; expcnt and lgkmcnt at their maxima)
@@ -863,6 +870,31 @@ __device__ __forceinline__ void copy_c_rows(const TriArgs<P>& a, int b, int lane
   }
 }
 
+// z1 of unit b under its E_l entries, ez[p] = x[row], from the records the
+// producer staged in chunk buffer `buf` during the last chunk: eight
+// records per thread in flight (clamped reads, padding p < 0 skipped)
+template <class P>
+__device__ __forceinline__ void file_e(const TriArgs<P>& a, int b, int buf, int nv, int tid, int nt,
+                                       const uint8_t* bufs, const typename P::C* x, int xs) {
+  using X = typename P::X;
+  constexpr int U = 8;
+  const int2* rec = reinterpret_cast<const int2*>(bufs + (size_t)buf * a.chunk_cap);
+  const int nq = a.eunit[b + 1] - a.eunit[b];
+  for (int q0 = tid; q0 < nq; q0 += nt * U) {
+    int2 r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = rec[min(q0 + u * nt, nq - 1)];
+    for (int c = 0; c < nv; ++c) {
+      typename P::C v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = x[c * xs + r[u].y];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (q0 + u * nt < nq && r[u].x >= 0) a.ez[(int64_t)c * a.ldez + r[u].x] = cvt<X>(v[u]);
+    }
+  }
+}
+
 template <class P, int MS, int MODE, bool MULTI>
 __global__ __launch_bounds__(MULTI ? kWave * (stream_max_cons(sizeof(typename P::C), MS) + 1)
                                    : 2 * kWave) void k_trisolve_streamed(
@@ -874,6 +906,7 @@ __global__ __launch_bounds__(MULTI ? kWave * (stream_max_cons(sizeof(typename P:
   const int nv = MULTI ? min(ncons, a0.nvec - g0) : 1;
   a.t += (int64_t)g0 * a0.ldt;
   a.fy += (int64_t)g0 * a0.ldfy;
+  if (MODE == TRI_DOWN && a.ez) a.ez += (int64_t)g0 * a0.ldez;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
@@ -938,6 +971,12 @@ __global__ __launch_bounds__(MULTI ? kWave * (stream_max_cons(sizeof(typename P:
       if (c + 1 < c1) {
         const ChunkDesc cd = desc_get<P>(a, c + 1, c1, lane, dc);
         copy_chunk<P>(a, cd, bufs + ((k + 1) % 2) * a.chunk_cap, lane, iters(cd));
+      } else if (MODE == TRI_DOWN && a.erec) {
+        // the last chunk: stage this unit's E_l records in the free buffer
+        const int q0 = a.eunit[b], nq = a.eunit[b + 1] - q0;
+        if (nq > 0)
+          copy_to_lds(reinterpret_cast<const uint4*>(a.erec + 2 * (int64_t)q0), nq / 2,
+                      bufs + ((k + 1) % 2) * a.chunk_cap, lane, (nq / 2 + kWave - 1) / kWave);
       }
       __builtin_amdgcn_s_waitcnt(GS_VMCNT_IMM(0));
       // the last chunk is being swept: the C_l rows meanwhile
@@ -975,6 +1014,8 @@ __global__ __launch_bounds__(MULTI ? kWave * (stream_max_cons(sizeof(typename P:
   if constexpr (MODE == TRI_UP && !MULTI)
     if (c0 >= c1 && wave == ncons && a.ccopy > 0) copy_c_rows<P>(a, b, lane);
   __syncthreads();
+  if constexpr (MODE == TRI_DOWN)
+    if (a.erec && c0 < c1) file_e<P>(a, b, (c1 - c0) % 2, nv, tid, nt, bufs, x, xs);
   store_result<P, MODE>(a, r0, nr, nv, tid, nt, x, xs);
 }
 
@@ -1100,6 +1141,18 @@ __device__ __forceinline__ typename P::C if_b2(const IfArgs<P>& a, int64_t i) {
   return cvt<C>(a.t[a.d + i]);
 }
 
+// (E_l z1)[row] for R rows per thread: z1 gathered from t, or read in
+// E_l's entry order from ez where the down sweep filed it (same products,
+// same order of summation)
+template <class P, int R>
+__device__ __forceinline__ void e_rows(const IfArgs<P>& a, const int (&rows)[R],
+                                       typename P::C (&r)[R]) {
+  using C = typename P::C;
+  using X = typename P::X;
+  if (a.ez) csr_rows<C, typename P::V, X, R, 4, true>(a.E.rp, a.E.ci, a.E.v, a.ez, rows, r);
+  else csr_rows<C, typename P::V, X, R, 4>(a.E.rp, a.E.ci, a.E.v, a.t, rows, r);
+}
+
 // z2 = b2 - E_l z1 of R rows per thread, written over t[d + row]; the rows
 // of thread tid of workgroup g are g * 256 R + tid + q * 256
 template <class P, int R>
@@ -1114,7 +1167,7 @@ __device__ __forceinline__ void if_z2(const IfArgs<P>& a, int64_t base,
     rows[q] = j < a.s ? (int)j : -1;
   }
   C ez[R];
-  csr_rows<C, typename P::V, X, R, 4>(a.E.rp, a.E.ci, a.E.v, a.t, rows, ez);
+  e_rows<P, R>(a, rows, ez);
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     z[q] = zero<C>();
@@ -1134,6 +1187,7 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a0) {
   IfArgs<P> a = a0;
   a.t += (int64_t)blockIdx.y * a0.ldt;
   a.partial += (int64_t)blockIdx.y * a0.ldpart;
+  if (a.ez) a.ez += (int64_t)blockIdx.y * a0.ldez;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* red = reinterpret_cast<C*>(smem_raw);  // 9 x kIfThreads (block_sum8)
   const int tid = threadIdx.x;
@@ -1174,9 +1228,9 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a0) {
 
 // t' = H (sum over workgroups of the partials), one workgroup of 1024
 // threads: T = 1024 / k threads per column sum the partials of workgroups
-// g, g+T, ... (coalesced: consecutive threads read consecutive columns; all
-// loads of a thread in flight together, up to kFinishLoads, clamped to the
-// last row), the T group sums are added in order in LDS; then thread (r, q)
+// g, g+T, ... (coalesced: consecutive threads read consecutive columns, in
+// batches of 8 loads), the T group sums are added in order in LDS; then
+// thread (r, q)
 // forms the part of row r of H t over columns q, q+T, ... (its first
 // kFinishH entries of H fetched before the partials) and the parts are
 // added in order.  Deterministic; no atomics.
@@ -1224,9 +1278,6 @@ __global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typenam
                                                                    typename P::C* tprime,
                                                                    int64_t ldpart) {
   using C = typename P::C;
-  // 64 registers of loads per thread (16 wavefronts of 1024 threads leave
-  // 128 per thread)
-  constexpr int kFinishLoads = 256 / (int)sizeof(C);
   partial += (int64_t)blockIdx.y * ldpart;  // vector blockIdx.y of a batched launch
   tprime += (int64_t)blockIdx.y * k;
   __shared__ C red[kFinishThreads];
@@ -1238,13 +1289,11 @@ __global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typenam
   C h0[kFinishH];
 #pragma unroll
   for (int u = 0; u < kFinishH; ++u) h0[u] = H[c + (int64_t)min(g + u * T, k - 1) * k];
+  // (batches of 8: at level 0, k = 33, 636 partials, 24 or 32 loads in
+  // flight per thread, mostly clamped repeats, measured no faster or
+  // 1.3 us slower -- one CU's load pipe, not the round trips, bounds it)
   C s = zero<C>();
-  if (g < T) {
-    // (few partials per thread: a batch of 8, not kFinishLoads mostly
-    // clamped loads)
-    if (nb <= 8 * T) s = finish_part_sum<C, 8>(partial, nb, k, T, c, g);
-    else s = finish_part_sum<C, kFinishLoads>(partial, nb, k, T, c, g);
-  }
+  if (g < T) s = finish_part_sum<C, 8>(partial, nb, k, T, c, g);
   red[tid] = s;
   __syncthreads();
   if (tid < k) tv[tid] = lds_sum_ordered<C>(red + tid, k, T);
@@ -1329,6 +1378,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_interface_small(IfArgs<P> a0)
   using D = typename P::D;
   IfArgs<P> a = a0;  // vector blockIdx.y of a batched launch
   a.t += (int64_t)blockIdx.y * a0.ldt;
+  if (a.ez) a.ez += (int64_t)blockIdx.y * a0.ldez;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int s = (int)a.s, k = a.k, tid = threadIdx.x;
   C* zs = reinterpret_cast<C*>(smem_raw);  // s
@@ -1355,7 +1405,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_interface_small(IfArgs<P> a0)
   for (int i = tid; i < s; i += kSmallThreads) {
     const int rows[1] = {i};
     C ez[1];
-    csr_rows<C, V, X, 1, 4>(a.E.rp, a.E.ci, a.E.v, a.t, rows, ez);
+    e_rows<P, 1>(a, rows, ez);
     zs[i] = if_b2(a, i) - ez[0];
   }
   if (WL && k > 0) {

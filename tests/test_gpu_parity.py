@@ -156,7 +156,7 @@ def test_native_setup_solves(torch_dev):
                                  {"GEMSLR_GROUP_CUS": "2", "GEMSLR_NO_STREAM": "1"},
                                  {"GEMSLR_NO_FUSE_SMALL": "1"}, {"GEMSLR_NO_FUSE_PERM": "1"},
                                  {"GEMSLR_NO_HALF": "1"}, {"GEMSLR_NO_FUSE_FY": "1"},
-                                 {"GEMSLR_NO_SMALL_LDS": "1"}])
+                                 {"GEMSLR_NO_FUSE_E": "1"}, {"GEMSLR_NO_SMALL_LDS": "1"}])
 @pytest.mark.parametrize("name", ["convdiff3d_20_p27", "helmholtz3d_16_p8"])
 def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
     """Both block-trisolve kernels (register prefetch; LDS-streamed with small
@@ -165,8 +165,10 @@ def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
     workgroup or one each), both interface paths (one fused launch for
     small levels, three launches) and both ways of applying the permutation
     (inside the level-0 sweeps, or separate kernels), U stages swept with
-    one lane per row or two lanes per row, and F_l y2 formed inside the up
-    sweep or by a launch of its own, and the small-level interface step with
+    one lane per row or two lanes per row, F_l y2 formed inside the up
+    sweep or by a launch of its own, E_l z1 from values the down sweep filed
+    in E_l's entry order or from gathers of z1, and the small-level
+    interface step with
     W_l and H_l copied to LDS or read from global memory, give the oracle's
     apply."""
     torch = torch_dev
@@ -189,11 +191,13 @@ def test_apply_kernel_variants(torch_dev, name, env, monkeypatch):
 
 
 @pytest.mark.parametrize("name", ["convdiff3d_20_p27", "helmholtz3d_16_p8"])
-@pytest.mark.parametrize("knob", ["GEMSLR_NO_FUSE_FY", "GEMSLR_NO_SMALL_LDS"])
+@pytest.mark.parametrize("knob", ["GEMSLR_NO_FUSE_FY", "GEMSLR_NO_FUSE_E", "GEMSLR_NO_SMALL_LDS"])
 def test_fused_paths_bit_equal(torch_dev, name, knob, monkeypatch):
     """F_l y2 formed in the up sweep's prologue adds every row's entries in
     the same order as the separate launch (the 27-point case has F rows
-    longer than one batch of four entries), and the small-level interface
+    longer than one batch of four entries), E_l z1 from the values the down
+    sweep filed in E_l's entry order equals the product over gathers of z1,
+    and the small-level interface
     step computes the same sums from LDS copies of W_l and H_l as from
     global memory: the applies agree bit for bit."""
     torch = torch_dev
