@@ -105,6 +105,34 @@ def test_apply_full_rank_is_exact_inverse(torch_dev):
     ctx.close()
 
 
+@pytest.mark.parametrize("rank", [100, 200])
+def test_apply_matches_oracle_at_ranks_above_64(torch_dev, rank):
+    """Ranks above 64 on the 20^3 / 27-subdomain case (s_l = 2168, 224, 8):
+    levels 0 and 1 take the three-launch interface step (the one-workgroup
+    step stops at k = 64) with three (rank 100) or five (rank 200) batches
+    of 40 columns, and the finish kernel with 10 or 5 threads per column.
+    W_l are seeded orthonormal columns and H_l seeded k x k matrices (the
+    apply does not depend on how they were found), the same on both sides."""
+    torch = torch_dev
+    w = wl.convdiff3d_64(N=20, nparts=27)
+    st = _oracle_setup(w, dict(ilu="ilut", drop_tol=1e-3, lfil=10, rank=0, dense_max=100))
+    rng = np.random.default_rng(rank)
+    for lv in st.levels[:-1]:
+        k = min(rank, lv.s)
+        lv.W = np.linalg.qr(rng.standard_normal((lv.s, k)))[0]
+        lv.H = 0.1 * rng.standard_normal((k, k))
+    print(f"[apply parity] rank {rank}: k = {[lv.W.shape[1] for lv in st.levels[:-1]]}", flush=True)
+    ctx = _ctx_explicit(torch, w, st)
+    x = np.random.default_rng(rank + 1).standard_normal(w.n)
+    ref = og.apply(st, x)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    ctx.apply(xd, yd)
+    torch.cuda.synchronize()
+    assert_close(yd.cpu().numpy(), ref, APPLY_TOL_F64)
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["laplace2d_32", "convdiff3d_20_p27", "helmholtz3d_16_p8"])
 def test_solve_same_setup_matches_oracle(torch_dev, name):
     torch = torch_dev
