@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdlib>
 
 #include "device.h"
@@ -1258,25 +1259,27 @@ __device__ __forceinline__ C lds_sum_ordered(const C* v, int ld, int n) {
 // sum of partial[b * k + c] over b = g, g + T, ... < nb, in that order,
 // NL loads in flight at a time (clamped to the last row)
 template <class C, int NL>
-__device__ __forceinline__ C finish_part_sum(const C* partial, int nb, int k, int T, int c,
-                                             int g) {
+__device__ __forceinline__ C finish_part_sum(const C* partial, int nb, int64_t rs, int64_t cs,
+                                             int T, int c, int g) {
   C s = zero<C>();
   for (int b = g; b < nb; b += NL * T) {
     C v[NL];
 #pragma unroll
-    for (int u = 0; u < NL; ++u) v[u] = partial[(int64_t)min(b + u * T, nb - 1) * k + c];
+    for (int u = 0; u < NL; ++u) v[u] = partial[(int64_t)min(b + u * T, nb - 1) * rs + c * cs];
 #pragma unroll
     for (int u = 0; u < NL; ++u) s = sel(b + u * T < nb, s + v[u], s);
   }
   return s;
 }
 
+// cld > 0: the partials are column-major, partial[c * cld + b] (as
+// k_multidot leaves them), else partial[b * k + c].
 template <class P>
 __global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typename P::C* partial,
                                                                    int nb, int k,
                                                                    const typename P::C* H,
                                                                    typename P::C* tprime,
-                                                                   int64_t ldpart) {
+                                                                   int64_t ldpart, int64_t cld) {
   using C = typename P::C;
   partial += (int64_t)blockIdx.y * ldpart;  // vector blockIdx.y of a batched launch
   tprime += (int64_t)blockIdx.y * k;
@@ -1293,7 +1296,9 @@ __global__ __launch_bounds__(kFinishThreads) void k_project_finish(const typenam
   // flight per thread, mostly clamped repeats, measured no faster or
   // 1.3 us slower -- one CU's load pipe, not the round trips, bounds it)
   C s = zero<C>();
-  if (g < T) s = finish_part_sum<C, 8>(partial, nb, k, T, c, g);
+  if (g < T)
+    s = cld > 0 ? finish_part_sum<C, 8>(partial, nb, 1, cld, T, c, g)
+                : finish_part_sum<C, 8>(partial, nb, k, 1, T, c, g);
   red[tid] = s;
   __syncthreads();
   if (tid < k) tv[tid] = lds_sum_ordered<C>(red + tid, k, T);
@@ -1336,11 +1341,57 @@ int interface_blocks(int64_t s) {
   return (int)((s + kIfThreads - 1) / kIfThreads);
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void k_multidot(const T* V, int64_t ld, int ncol, const T* w,
+                                                  int64_t n, T* partial);
+constexpr int kDotChunk = 8;     // columns per workgroup row of the grid
+constexpr int kDotBlocks = 256;  // workgroups along the rows
+
+// Ranks above two 40-column batches (real types, where W_l, z2 and the sums
+// share one type): the E product alone first (k_interface with k = 0), then
+// W^H z2 as a column-chunked multidot that streams W_l once over the whole
+// chip, and the finish on its column-major partials.  One launch and one z2
+// round trip more than the fused step, but no serial batches of block sums
+// per workgroup (measured at 128^3, level 0: k = 256 212 -> 181 us, k = 129
+// 113 -> 96 us; k = 65 even, level 1 at k = 64 1.7 us slower).
+constexpr int kIfFusedMaxK = 80;
+template <class P>
+static bool interface_by_multidot(const IfArgs<P>& a, int R, hipStream_t st) {
+  using C = typename P::C;
+  if constexpr (!std::is_same<typename P::V, C>::value || !std::is_same<typename P::X, C>::value ||
+                sizeof(C) != 8) {
+    (void)a, (void)R, (void)st;
+    return false;
+  } else {
+    if (a.k <= kIfFusedMaxK) return false;
+    IfArgs<P> e = a;
+    e.k = 0;
+    const int nblk = (int)((a.s + (int64_t)kIfThreads * R - 1) / ((int64_t)kIfThreads * R));
+    const size_t lds = (size_t)9 * kRedThreads * sizeof(C);
+    if (R == 2)
+      hipLaunchKernelGGL((k_interface<P, 2, 16>), dim3(nblk, a.nvec), dim3(kIfThreads), lds, st, e);
+    else
+      hipLaunchKernelGGL((k_interface<P, 1, 16>), dim3(nblk, a.nvec), dim3(kIfThreads), lds, st, e);
+    const int nbm = (int)std::min<int64_t>(kDotBlocks, (a.s + 255) / 256);
+    const dim3 grid(nbm, (a.k + kDotChunk - 1) / kDotChunk);
+    for (int j = 0; j < a.nvec; ++j) {
+      const C* z2 = a.t + (int64_t)j * a.ldt + a.d;
+      C* part = a.partial + (int64_t)j * a.ldpart;
+      hipLaunchKernelGGL(k_multidot<C>, grid, dim3(256), 0, st, a.W, a.s, a.k, z2, a.s, part);
+      hipLaunchKernelGGL(k_project_finish<P>, dim3(1, 1), dim3(kFinishThreads),
+                         (size_t)a.k * sizeof(C), st, part, nbm, a.k, a.H,
+                         a.tprime + (int64_t)j * a.k, (int64_t)0, (int64_t)nbm);
+    }
+    return true;
+  }
+}
+
 template <class P>
 void launch_interface(const IfArgs<P>& a, hipStream_t st) {
   if (a.s <= 0) return;
   using C = typename P::C;
   const int R = interface_rows<P>(a.s, a.k);
+  if (interface_by_multidot<P>(a, R, st)) return;
   const int nblk = (int)((a.s + (int64_t)kIfThreads * R - 1) / ((int64_t)kIfThreads * R));
   const size_t lds = (size_t)9 * kRedThreads * sizeof(C);
   // columns per load batch: all of k when it is small, else batches sized so
@@ -1358,7 +1409,8 @@ void launch_interface(const IfArgs<P>& a, hipStream_t st) {
 #undef GS_IF_LAUNCH
   if (a.k > 0)
     hipLaunchKernelGGL(k_project_finish<P>, dim3(1, a.nvec), dim3(kFinishThreads),
-                       (size_t)a.k * sizeof(C), st, a.partial, nblk, a.k, a.H, a.tprime, a.ldpart);
+                       (size_t)a.k * sizeof(C), st, a.partial, nblk, a.k, a.H, a.tprime, a.ldpart,
+                       (int64_t)0);
 }
 
 // The whole interface step of a small level in one workgroup (s <= 4096,
@@ -1647,9 +1699,6 @@ void launch_residual(const int32_t* rp, const int32_t* ci, const T* v, const T* 
   hipLaunchKernelGGL(k_residual<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rp, ci,
                      v, x, b, y, n);
 }
-
-constexpr int kDotChunk = 8;     // columns per workgroup row of the grid
-constexpr int kDotBlocks = 256;  // workgroups along the rows
 
 template <class T>
 __global__ __launch_bounds__(256) void k_multidot(const T* V, int64_t ld, int ncol,

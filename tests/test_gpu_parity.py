@@ -108,9 +108,10 @@ def test_apply_full_rank_is_exact_inverse(torch_dev):
 @pytest.mark.parametrize("rank", [100, 200])
 def test_apply_matches_oracle_at_ranks_above_64(torch_dev, rank):
     """Ranks above 64 on the 20^3 / 27-subdomain case (s_l = 2168, 224, 8):
-    levels 0 and 1 take the three-launch interface step (the one-workgroup
-    step stops at k = 64) with three (rank 100) or five (rank 200) batches
-    of 40 columns, and the finish kernel with 10 or 5 threads per column.
+    levels 0 and 1 take the interface step of large ranks (the one-workgroup
+    step stops at k = 64; above k = 80 the E product in a launch of its own,
+    W^H z2 as a column-chunked multidot, the finish on its column-major
+    partials with 10 or 5 threads per column).
     W_l are seeded orthonormal columns and H_l seeded k x k matrices (the
     apply does not depend on how they were found), the same on both sides."""
     torch = torch_dev
@@ -130,6 +131,16 @@ def test_apply_matches_oracle_at_ranks_above_64(torch_dev, rank):
     ctx.apply(xd, yd)
     torch.cuda.synchronize()
     assert_close(yd.cpu().numpy(), ref, APPLY_TOL_F64)
+    # three vectors per call: every launch of a level covers all three, each
+    # column equal to its single apply bit for bit
+    X = torch.from_numpy(np.random.default_rng(rank + 2).standard_normal((3, w.n))).cuda()
+    Y = torch.empty_like(X)
+    ctx.apply_many(3, X, Y)
+    torch.cuda.synchronize()
+    for j in range(3):
+        ctx.apply(X[j].contiguous(), yd)
+        torch.cuda.synchronize()
+        assert torch.equal(Y[j], yd), f"column {j}"
     ctx.close()
 
 
