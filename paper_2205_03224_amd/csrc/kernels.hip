@@ -1347,23 +1347,24 @@ __global__ __launch_bounds__(256) void k_multidot(const T* V, int64_t ld, int nc
 constexpr int kDotChunk = 8;     // columns per workgroup row of the grid
 constexpr int kDotBlocks = 256;  // workgroups along the rows
 
-// Ranks above two 40-column batches (real types, where W_l, z2 and the sums
-// share one type): the E product alone first (k_interface with k = 0), then
+// Ranks above two column batches (40 columns for float64, 16 for
+// complex128; forms where W_l, z2 and the sums share one type): the E
+// product alone first (k_interface with k = 0), then
 // W^H z2 as a column-chunked multidot that streams W_l once over the whole
 // chip, and the finish on its column-major partials.  One launch and one z2
 // round trip more than the fused step, but no serial batches of block sums
 // per workgroup (measured at 128^3, level 0: k = 256 212 -> 181 us, k = 129
-// 113 -> 96 us; k = 65 even, level 1 at k = 64 1.7 us slower).
-constexpr int kIfFusedMaxK = 80;
+// 113 -> 96 us; k = 65 even, level 1 at k = 64 1.7 us slower; complex128,
+// k = 65: 97.9 -> 91.6 us).
+template <class C> constexpr int if_fused_max_k() { return sizeof(C) == 16 ? 32 : 80; }
 template <class P>
 static bool interface_by_multidot(const IfArgs<P>& a, int R, hipStream_t st) {
   using C = typename P::C;
-  if constexpr (!std::is_same<typename P::V, C>::value || !std::is_same<typename P::X, C>::value ||
-                sizeof(C) != 8) {
+  if constexpr (!std::is_same<typename P::V, C>::value || !std::is_same<typename P::X, C>::value) {
     (void)a, (void)R, (void)st;
     return false;
   } else {
-    if (a.k <= kIfFusedMaxK) return false;
+    if (a.k <= if_fused_max_k<C>()) return false;
     IfArgs<P> e = a;
     e.k = 0;
     const int nblk = (int)((a.s + (int64_t)kIfThreads * R - 1) / ((int64_t)kIfThreads * R));

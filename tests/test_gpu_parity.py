@@ -105,26 +105,38 @@ def test_apply_full_rank_is_exact_inverse(torch_dev):
     ctx.close()
 
 
-@pytest.mark.parametrize("rank", [100, 200])
-def test_apply_matches_oracle_at_ranks_above_64(torch_dev, rank):
-    """Ranks above 64 on the 20^3 / 27-subdomain case (s_l = 2168, 224, 8):
-    levels 0 and 1 take the interface step of large ranks (the one-workgroup
-    step stops at k = 64; above k = 80 the E product in a launch of its own,
-    W^H z2 as a column-chunked multidot, the finish on its column-major
-    partials with 10 or 5 threads per column).
+@pytest.mark.parametrize("name,rank", [("convdiff3d_20_p27", 100), ("convdiff3d_20_p27", 200),
+                                       ("helmholtz3d_16_p8", 40)])
+def test_apply_matches_oracle_at_large_ranks(torch_dev, name, rank):
+    """The interface step of large ranks.  Float64, 20^3 / 27 subdomains
+    (s_l = 2168, 224, 8), ranks 100 and 200: levels 0 and 1 above the
+    one-workgroup step's k = 64 and above k = 80, where the E product runs
+    alone, W^H z2 as a column-chunked multidot and the finish on its
+    column-major partials (10 or 5 threads per column).  Complex128
+    Helmholtz 16^3 / 8 subdomains (s_0 = 721), rank 40: level 0 above two
+    16-column batches, the same three launches in complex arithmetic.
     W_l are seeded orthonormal columns and H_l seeded k x k matrices (the
     apply does not depend on how they were found), the same on both sides."""
     torch = torch_dev
-    w = wl.convdiff3d_64(N=20, nparts=27)
-    st = _oracle_setup(w, dict(ilu="ilut", drop_tol=1e-3, lfil=10, rank=0, dense_max=100))
+    w, kw = _case(name)
+    kw = dict(kw, rank=0)
+    st = _oracle_setup(w, kw)
     rng = np.random.default_rng(rank)
     for lv in st.levels[:-1]:
         k = min(rank, lv.s)
-        lv.W = np.linalg.qr(rng.standard_normal((lv.s, k)))[0]
-        lv.H = 0.1 * rng.standard_normal((k, k))
-    print(f"[apply parity] rank {rank}: k = {[lv.W.shape[1] for lv in st.levels[:-1]]}", flush=True)
+        G = rng.standard_normal((lv.s, k))
+        H = 0.1 * rng.standard_normal((k, k))
+        if w.is_complex:
+            G = G + 1j * rng.standard_normal((lv.s, k))
+            H = H + 0.1j * rng.standard_normal((k, k))
+        lv.W = np.linalg.qr(G)[0]
+        lv.H = H
+    print(f"[apply parity] {name} rank {rank}: k = {[lv.W.shape[1] for lv in st.levels[:-1]]}",
+          flush=True)
     ctx = _ctx_explicit(torch, w, st)
     x = np.random.default_rng(rank + 1).standard_normal(w.n)
+    if w.is_complex:
+        x = x + 1j * np.random.default_rng(rank + 3).standard_normal(w.n)
     ref = og.apply(st, x)
     xd = torch.from_numpy(x).cuda()
     yd = torch.empty_like(xd)
@@ -133,7 +145,10 @@ def test_apply_matches_oracle_at_ranks_above_64(torch_dev, rank):
     assert_close(yd.cpu().numpy(), ref, APPLY_TOL_F64)
     # three vectors per call: every launch of a level covers all three, each
     # column equal to its single apply bit for bit
-    X = torch.from_numpy(np.random.default_rng(rank + 2).standard_normal((3, w.n))).cuda()
+    Xh = np.random.default_rng(rank + 2).standard_normal((3, w.n))
+    if w.is_complex:
+        Xh = Xh + 1j * np.random.default_rng(rank + 4).standard_normal((3, w.n))
+    X = torch.from_numpy(Xh).cuda()
     Y = torch.empty_like(X)
     ctx.apply_many(3, X, Y)
     torch.cuda.synchronize()
