@@ -839,13 +839,6 @@ __device__ __forceinline__ void store_result(const TriArgs<P>& a, int r0, int nr
   }
 }
 
-// One workgroup per diagonal block (or group of blocks) and group of up to
-// ncons vectors: waves 0 .. ncons - 1 sweep one vector each out of LDS,
-// wave ncons copies the block's chunks.  All consumers sweep the same chunk
-// between two barriers, so the factor entries cross HBM once for all of
-// them.  Consumers without a vector (the launch's last group) only take
-// part in the barriers.  MULTI false: one consumer and one vector per
-// workgroup (vector blockIdx.y), with the register budget of two waves.
 // The C_l rows of TriArgs::ccopy that workgroup b writes to the caller's
 // vector, by one wave (its stores left in flight)
 template <class P>
@@ -896,6 +889,13 @@ __device__ __forceinline__ void file_e(const TriArgs<P>& a, int b, int buf, int 
   }
 }
 
+// One workgroup per diagonal block (or group of blocks) and group of up to
+// ncons vectors: waves 0 .. ncons - 1 sweep one vector each out of LDS,
+// wave ncons copies the block's chunks.  All consumers sweep the same chunk
+// between two barriers, so the factor entries cross HBM once for all of
+// them.  Consumers without a vector (the launch's last group) only take
+// part in the barriers.  MULTI false: one consumer and one vector per
+// workgroup (vector blockIdx.y), with the register budget of two waves.
 template <class P, int MS, int MODE, bool MULTI>
 __global__ __launch_bounds__(MULTI ? kWave * (stream_max_cons(sizeof(typename P::C), MS) + 1)
                                    : 2 * kWave) void k_trisolve_streamed(
@@ -1231,10 +1231,9 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(IfArgs<P> a0) {
 // threads: T = 1024 / k threads per column sum the partials of workgroups
 // g, g+T, ... (coalesced: consecutive threads read consecutive columns, in
 // batches of 8 loads), the T group sums are added in order in LDS; then
-// thread (r, q)
-// forms the part of row r of H t over columns q, q+T, ... (its first
-// kFinishH entries of H fetched before the partials) and the parts are
-// added in order.  Deterministic; no atomics.
+// thread (r, q) forms the part of row r of H t over columns q, q+T, ...
+// (its first kFinishH entries of H fetched before the partials) and the
+// parts are added in order.  Deterministic; no atomics.
 constexpr int kFinishThreads = 1024;
 constexpr int kFinishH = 4;
 
@@ -1256,8 +1255,8 @@ __device__ __forceinline__ C lds_sum_ordered(const C* v, int ld, int n) {
   return t;
 }
 
-// sum of partial[b * k + c] over b = g, g + T, ... < nb, in that order,
-// NL loads in flight at a time (clamped to the last row)
+// sum of partial[b * rs + c * cs] over b = g, g + T, ... < nb, in that
+// order, NL loads in flight at a time (clamped to the last row)
 template <class C, int NL>
 __device__ __forceinline__ C finish_part_sum(const C* partial, int nb, int64_t rs, int64_t cs,
                                              int T, int c, int g) {
