@@ -18,7 +18,7 @@ from paper_2205_03224_amd import workloads as wl
 from oracle import fgmres as ofg
 from oracle import gemslr as og
 from oracle import partition as opart
-from tests.abi_helpers import assert_close, oracle_levels, relerr
+from tests.abi_helpers import MIXED_FLOOR, MIXED_TOL, assert_close, oracle_levels, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -105,14 +105,18 @@ def test_apply_full_rank_is_exact_inverse(torch_dev):
     ctx.close()
 
 
-@pytest.mark.parametrize("name,rank", [("convdiff3d_20_p27", 100), ("convdiff3d_20_p27", 200),
-                                       ("helmholtz3d_16_p8", 40)])
-def test_apply_matches_oracle_at_large_ranks(torch_dev, name, rank):
+@pytest.mark.parametrize("name,rank,prec", [("convdiff3d_20_p27", 100, None),
+                                            ("convdiff3d_20_p27", 200, None),
+                                            ("convdiff3d_20_p27", 100, "f32"),
+                                            ("helmholtz3d_16_p8", 40, None)])
+def test_apply_matches_oracle_at_large_ranks(torch_dev, name, rank, prec):
     """The interface step of large ranks.  Float64, 20^3 / 27 subdomains
     (s_l = 2168, 224, 8), ranks 100 and 200: levels 0 and 1 above the
     one-workgroup step's k = 64 and above k = 80, where the E product runs
     alone, W^H z2 as a column-chunked multidot and the finish on its
-    column-major partials (10 or 5 threads per column).  Complex128
+    column-major partials (10 or 5 threads per column); also with float32
+    storage (the same three launches in float32, against the float64 oracle
+    to the mixed form's tolerance).  Complex128
     Helmholtz 16^3 / 8 subdomains (s_0 = 721), rank 40: level 0 above two
     16-column batches, the same three launches in complex arithmetic.
     W_l are seeded orthonormal columns and H_l seeded k x k matrices (the
@@ -134,6 +138,8 @@ def test_apply_matches_oracle_at_large_ranks(torch_dev, name, rank):
     print(f"[apply parity] {name} rank {rank}: k = {[lv.W.shape[1] for lv in st.levels[:-1]]}",
           flush=True)
     ctx = _ctx_explicit(torch, w, st)
+    if prec:
+        ctx.set_precision(prec)
     x = np.random.default_rng(rank + 1).standard_normal(w.n)
     if w.is_complex:
         x = x + 1j * np.random.default_rng(rank + 3).standard_normal(w.n)
@@ -142,7 +148,10 @@ def test_apply_matches_oracle_at_large_ranks(torch_dev, name, rank):
     yd = torch.empty_like(xd)
     ctx.apply(xd, yd)
     torch.cuda.synchronize()
-    assert_close(yd.cpu().numpy(), ref, APPLY_TOL_F64)
+    if prec:
+        assert_close(yd.cpu().numpy(), ref, MIXED_TOL[prec], floor=MIXED_FLOOR)
+    else:
+        assert_close(yd.cpu().numpy(), ref, APPLY_TOL_F64)
     # three vectors per call: every launch of a level covers all three, each
     # column equal to its single apply bit for bit
     Xh = np.random.default_rng(rank + 2).standard_normal((3, w.n))
