@@ -180,16 +180,26 @@ def apply_level(st, l, b, inner_its=0):
     return y
 
 
+def _promote(st, x):
+    """x in the type of x and of the setup's scalars together: apply_level's
+    work vectors copy the input's type, so a real vector on a complex setup
+    must be made complex first (and a complex one on a real setup stays
+    complex, M^{-1} being real and linear there)."""
+    x = np.asarray(x)
+    return x.astype(np.result_type(x.dtype, np.float64 if st.real else np.complex128),
+                    copy=False)
+
+
 def apply(st, x, inner_its=0):
     """y = M^{-1} x in the original ordering."""
-    q = apply_level(st, 0, x[st.perm], inner_its)
+    q = apply_level(st, 0, _promote(st, x)[st.perm], inner_its)
     y = np.empty_like(q)
     y[st.perm] = q
     return y
 
 
 def apply_permuted(st, xp, inner_its=0):
-    return apply_level(st, 0, xp, inner_its)
+    return apply_level(st, 0, _promote(st, xp), inner_its)
 
 
 def ghat_matvec(st, l, v):

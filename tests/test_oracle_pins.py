@@ -342,6 +342,15 @@ def test_full_rank_apply_is_exact_inverse(case):
     y = gemslr.apply(st, x)
     ref = sla.lu_solve(sla.lu_factor(A), x)
     assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
+    # a vector of the other kind: real on a complex setup (its result is
+    # complex, not the real part of one), complex on a real setup
+    x2 = rs.standard_normal(n)
+    if not np.iscomplexobj(v):
+        x2 = x2 + 1j * rs.standard_normal(n)
+    y2 = gemslr.apply(st, x2)
+    ref2 = np.linalg.solve(A, x2)
+    assert np.iscomplexobj(y2)
+    assert np.linalg.norm(y2 - ref2) <= 1e-12 * np.linalg.norm(ref2)
 
 
 def test_full_rank_via_krylov_schur_is_exact():
