@@ -268,7 +268,9 @@ int gs_apply(gs_ctx* ctx, const void* x, void* y);
  * every CU (level 0: three vectors per workgroup at the 3,375 - 4,096-row
  * blocks of the 128^3 workloads), single-vector workgroups where one vector
  * leaves CUs idle.  With inner GMRES steps the vectors go one at a time.
- * Every column equals gs_apply of that column.  Errors as gs_apply. */
+ * Every column equals gs_apply of that column.  nrhs = 0 is an empty batch:
+ * nothing is read or written, and x and y may be NULL.  Errors as gs_apply,
+ * and GS_EINVAL for nrhs < 0. */
 int gs_apply_many(gs_ctx* ctx, int nrhs, const void* x, void* y);
 
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -1616,7 +1616,9 @@ int gs_apply_many(gs_ctx* c, int nrhs, const void* x, void* y) {
     int r = need_device(c);
     if (r) return r;
     if (!c->ready) throw Error(GS_ESTATE, "apply before setup");
-    if (!x || !y || nrhs < 0) throw Error(GS_EINVAL, "NULL vector");
+    if (nrhs < 0) throw Error(GS_EINVAL, "negative nrhs");
+    if (nrhs == 0) return GS_OK;  // an empty batch: nothing read or written
+    if (!x || !y) throw Error(GS_EINVAL, "NULL vector");
     const int64_t n = c->dtype == GS_F64 ? c->hd->n : c->hz->n;
     const size_t vb = c->dtype == GS_F64 ? 8 : 16;
     const char* xb = (const char*)x;

@@ -169,6 +169,75 @@ def test_apply_matches_oracle_at_large_ranks(torch_dev, name, rank, prec):
 
 
 @pytest.mark.parametrize("name", ["laplace2d_32", "convdiff3d_20_p27", "helmholtz3d_16_p8"])
+def test_apply_rank_zero_matches_oracle(torch_dev, name):
+    """Rank 0 on every level: without the low-rank correction the Schur
+    complement solve is the C_l solve alone, so M^{-1} is the multilevel
+    block LDU of Sec. 2.2 built from the ILU factors (the oracle's rank-0
+    form, pinned against dense inverses).  The interface kernels take their
+    k = 0 branch: z2 written, no projection and no update launch.  Two
+    vectors per call are bit-equal to single applies."""
+    torch = torch_dev
+    w, kw = _case(name)
+    st = _oracle_setup(w, dict(kw, rank=0))
+    assert all(lv.W.shape[1] == 0 for lv in st.levels[:-1])
+    print(f"[apply parity] {name} rank 0", flush=True)
+    ctx = _ctx_explicit(torch, w, st)
+    rs = np.random.default_rng(21)
+    X = rs.standard_normal((2, w.n))
+    if w.is_complex:
+        X = X + 1j * rs.standard_normal((2, w.n))
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty_like(Xd)
+    ctx.apply_many(2, Xd, Yd)
+    yd = torch.empty_like(Xd[0])
+    for j in range(2):
+        ctx.apply(Xd[j].contiguous(), yd)
+        torch.cuda.synchronize()
+        assert_close(yd.cpu().numpy(), og.apply(st, X[j]), APPLY_TOL_F64, what=f"vector {j}")
+        assert torch.equal(Yd[j], yd), f"column {j}"
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["convdiff3d_20_p27", "helmholtz3d_16_p8"])
+def test_apply_degenerate_inputs(torch_dev, name):
+    """x = 0 gives y = 0 in every entry (without inner GMRES steps M^{-1} is
+    a fixed linear operator and every kernel forms sums of products with
+    x's entries), written over an output filled with NaN, so every entry of
+    y, the C_0 rows' scatter included, is written.  An empty batch
+    (nrhs = 0) succeeds and writes nothing, with empty tensors (NULL
+    pointers) and with live buffers."""
+    import ctypes as ct
+
+    from paper_2205_03224_amd import gemslr
+    torch = torch_dev
+    w, kw = _case(name)
+    print(f"[degenerate inputs] {name}", flush=True)
+    st = _oracle_setup(w, kw)
+    ctx = _ctx_explicit(torch, w, st)
+    dt = torch.complex128 if w.is_complex else torch.float64
+    x = torch.zeros(w.n, dtype=dt, device="cuda")
+    y = torch.full((w.n,), float("nan"), dtype=dt, device="cuda")
+    ctx.apply(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(y, torch.zeros_like(y))
+    y.fill_(float("nan"))
+    ctx.apply_many(1, x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(y, torch.zeros_like(y))
+    empty = torch.empty(0, dtype=dt, device="cuda")
+    ctx.apply_many(0, empty, torch.empty_like(empty))
+    y.fill_(float("nan"))
+    rc = gemslr.lib().gs_apply_many(ctx._h, 0, ct.c_void_p(x.data_ptr()),
+                                    ct.c_void_p(y.data_ptr()))
+    torch.cuda.synchronize()
+    assert rc == 0
+    assert torch.isnan(y.real).all()
+    assert gemslr.lib().gs_apply_many(ctx._h, -1, ct.c_void_p(x.data_ptr()),
+                                      ct.c_void_p(y.data_ptr())) != 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["laplace2d_32", "convdiff3d_20_p27", "helmholtz3d_16_p8"])
 def test_solve_same_setup_matches_oracle(torch_dev, name):
     torch = torch_dev
     w, kw = _case(name)
