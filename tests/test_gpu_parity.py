@@ -108,7 +108,9 @@ def test_apply_full_rank_is_exact_inverse(torch_dev):
 @pytest.mark.parametrize("name,rank,prec", [("convdiff3d_20_p27", 100, None),
                                             ("convdiff3d_20_p27", 200, None),
                                             ("convdiff3d_20_p27", 100, "f32"),
-                                            ("helmholtz3d_16_p8", 40, None)])
+                                            ("convdiff3d_20_p27", 1024, None),
+                                            ("helmholtz3d_16_p8", 40, None),
+                                            ("helmholtz3d_16_p8", 1024, None)])
 def test_apply_matches_oracle_at_large_ranks(torch_dev, name, rank, prec):
     """The interface step of large ranks.  Float64, 20^3 / 27 subdomains
     (s_l = 2168, 224, 8), ranks 100 and 200: levels 0 and 1 above the
@@ -119,6 +121,9 @@ def test_apply_matches_oracle_at_large_ranks(torch_dev, name, rank, prec):
     to the mixed form's tolerance).  Complex128
     Helmholtz 16^3 / 8 subdomains (s_0 = 721), rank 40: level 0 above two
     16-column batches, the same three launches in complex arithmetic.
+    Rank 1024, the largest the library takes: k = 1024 / 224 / 8 on the
+    float64 case (one thread per column in the finish), k = 721 / 46 / 1 on
+    the complex one (every level at full rank, k = s_l).
     W_l are seeded orthonormal columns and H_l seeded k x k matrices (the
     apply does not depend on how they were found), the same on both sides."""
     torch = torch_dev
