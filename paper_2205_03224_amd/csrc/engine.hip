@@ -634,6 +634,7 @@ struct EngineT final : Engine {
   int nv = 1;
   std::unique_ptr<DevMem> bmem;
   int bcap = 0;
+  std::vector<int> bk;  // the rank each level's batch partial / tprime were sized for
   X* tb = nullptr;
   C* fyb = nullptr;
   X* ezb = nullptr;
@@ -1614,7 +1615,13 @@ struct EngineT final : Engine {
   // ---- several vectors per launch
   static constexpr int kBatchMax = 64;
   void batch_reserve(int m) {
-    if (m <= bcap) return;
+    // a level's rank can grow after the buffers were made (a low-rank term
+    // installed after a batched product, as the block iteration does level
+    // by level): then they are made again, for the ranks now in place
+    bool fits = m <= bcap && bk.size() == lv.size();
+    for (size_t l = 0; fits && l < lv.size(); ++l) fits = lv[l].k <= bk[l];
+    if (fits) return;
+    m = std::max(m, bcap);
     bmem.reset();
     bmem = std::make_unique<DevMem>();
     tb = bmem->alloc<X>((size_t)n * m);
@@ -1622,10 +1629,12 @@ struct EngineT final : Engine {
     ezb = bmem->alloc<X>((size_t)std::max<int64_t>(ez_len, 1) * m);
     partb.assign(lv.size(), nullptr);
     tpb.assign(lv.size(), nullptr);
+    bk.assign(lv.size(), 0);
     for (size_t l = 0; l < lv.size(); ++l)
       if (lv[l].k > 0) {
         partb[l] = bmem->alloc<C>((size_t)interface_blocks<P>(lv[l].s) * lv[l].k * m);
         tpb[l] = bmem->alloc<C>((size_t)lv[l].k * m);
+        bk[l] = lv[l].k;
       }
     bcap = m;
   }

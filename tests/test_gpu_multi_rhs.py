@@ -137,3 +137,44 @@ def test_apply_many_beyond_one_batch(torch_dev, cons, monkeypatch):
     for j in (0, 63, 64, 69):
         assert_close(Y[j], og.apply(st, X[j]), APPLY_TOL_F64, what=f"column {j}")
     ctx.close()
+
+
+def test_batch_buffers_follow_rank_changes(torch_dev):
+    """The batch buffers (each level's per-vector partial sums and t') are
+    sized for the ranks in place when they are made, and made again when a
+    rank has grown since.  20^3 / 27 subdomains, native setup with the
+    low-rank stage deferred (rank 0 everywhere): a batched apply at rank 0;
+    then ranks 100 / 100 / 8 from the block iteration started from random
+    bases, whose batched G_hat products on level 0 run level 1's interface
+    step at k = 100 (the E product, the multidot and the finish, all through
+    the batch buffers) after level 1's own batched products made the
+    buffers at rank 0 there; then ranks 8 from Arnoldi (smaller: the buffers
+    stay).  After each, a batched apply of three vectors equals the single
+    applies bit for bit."""
+    torch = torch_dev
+    from paper_2205_03224_amd import gemslr, learned
+    w = wl.convdiff3d_64(N=20, nparts=27)
+    ctx = gemslr.Context(0)
+    ctx.setup(w.rowptr, w.col, w.val, w.levels, w.nparts, 100, w.drop_tol, defer_lowrank=1,
+              block_max_iters=2, **learned.setup_kwargs(w))
+    X = torch.from_numpy(np.random.default_rng(77).standard_normal((3, w.n))).cuda()
+
+    def check(what):
+        Y = torch.empty_like(X)
+        ctx.apply_many(3, X, Y)
+        y = torch.empty_like(X[0])
+        for j in range(3):
+            ctx.apply(X[j].contiguous(), y)
+            torch.cuda.synchronize()
+            assert torch.isfinite(y).all(), what
+            assert torch.equal(Y[j], y), f"{what}: column {j}"
+
+    check("rank 0")
+    info = ctx.lowrank(100, learned.random_bases(ctx, (0, 1), 100, seed=9))
+    ks = [ctx.level_size(l)[7] for l in range(info["nlevels"])]
+    print(f"  block iteration: methods {info['lowrank_method']}, k = {ks}", flush=True)
+    assert ks[0] == 100 and ks[1] == 100
+    check("ranks 100")
+    ctx.lowrank(8)
+    check("ranks 8")
+    ctx.close()
