@@ -206,8 +206,10 @@ typedef struct {
  * setup, e.g. for checking the apply against an independent
  * implementation).  A is the unpermuted matrix (used by gs_solve); perm[i]
  * is the original index of permuted position i; levels has nlevels+1
- * entries whose d sum to n.  Copies everything.  Errors: GS_EINVAL,
- * GS_EDEVICE, GS_ENOMEM. */
+ * entries whose d sum to n.  Copies everything.  Errors: GS_EINVAL (also
+ * for a malformed block: NULL or non-monotone rowptr, rowptr[0] != 0, a
+ * column out of range, NULL col/val of a block with entries, NULL w or h
+ * with k > 0), GS_EDEVICE, GS_ENOMEM. */
 int gs_setup_explicit(gs_ctx* ctx, int64_t n, const int64_t* rowptr,
                       const int32_t* col, const void* val, int dtype,
                       const int64_t* perm, int nlevels,

@@ -1002,6 +1002,21 @@ static void setup_native(gs_ctx* c, int64_t n, const int64_t* rp, const int32_t*
   finish_setup<T>(c);
 }
 
+// a CSR block of an explicit level (rows x cols): rowptr present, from 0 and
+// monotone, every column in range, col and val present when it has entries;
+// checked before anything reads the block
+static void check_block(const std::string& what, int64_t rows, int64_t cols, const int64_t* rp,
+                        const int32_t* ci, const void* v) {
+  if (!rp) throw Error(GS_EINVAL, what + ": NULL rowptr");
+  if (rp[0] != 0) throw Error(GS_EINVAL, what + ": rowptr[0] != 0");
+  for (int64_t i = 0; i < rows; ++i)
+    if (rp[i + 1] < rp[i]) throw Error(GS_EINVAL, what + ": rowptr not monotone");
+  const int64_t nnz = rp[rows];
+  if (nnz > 0 && (!ci || !v)) throw Error(GS_EINVAL, what + ": NULL col or val");
+  for (int64_t q = 0; q < nnz; ++q)
+    if (ci[q] < 0 || ci[q] >= cols) throw Error(GS_EINVAL, what + ": column out of range");
+}
+
 template <class T>
 static void setup_explicit(gs_ctx* c, int64_t n, const int64_t* rp, const int32_t* ci,
                            const void* val, const int64_t* perm, int nlevels,
@@ -1034,6 +1049,9 @@ static void setup_explicit(gs_ctx* c, int64_t n, const int64_t* rp, const int32_
     if (h.blocks.front() != 0 || h.blocks.back() != a.d) throw Error(GS_EINVAL, "block_ptr must span [0, d]");
     for (size_t b = 0; b + 1 < h.blocks.size(); ++b)
       if (h.blocks[b + 1] < h.blocks[b]) throw Error(GS_EINVAL, "block_ptr not monotone");
+    const std::string tag = " of level " + std::to_string(l);
+    check_block("L" + tag, a.d, a.d, a.l_rowptr, a.l_col, a.l_val);
+    check_block("U" + tag, a.d, a.d, a.u_rowptr, a.u_col, a.u_val);
     if (a.d > 0) {
       validate_csr(a.d, a.u_rowptr, a.u_col, true);
       if (a.l_rowptr[a.d] > 0) validate_csr(a.d, a.l_rowptr, a.l_col, false);
@@ -1041,15 +1059,16 @@ static void setup_explicit(gs_ctx* c, int64_t n, const int64_t* rp, const int32_
     copy_csr<T>(a.d, a.d, a.l_rowptr, a.l_col, a.l_val, h.L);
     copy_csr<T>(a.d, a.d, a.u_rowptr, a.u_col, a.u_val, h.U);
     if (h.s > 0) {
+      check_block("E" + tag, h.s, a.d, a.e_rowptr, a.e_col, a.e_val);
+      check_block("F" + tag, a.d, h.s, a.f_rowptr, a.f_col, a.f_val);
       copy_csr<T>(h.s, a.d, a.e_rowptr, a.e_col, a.e_val, h.E);
       copy_csr<T>(a.d, h.s, a.f_rowptr, a.f_col, a.f_val, h.F);
-      for (int32_t x : h.E.ci) if (x < 0 || x >= a.d) throw Error(GS_EINVAL, "E column out of range");
-      for (int32_t x : h.F.ci) if (x < 0 || x >= h.s) throw Error(GS_EINVAL, "F column out of range");
       h.k = a.k;
       // the low-rank kernels take k <= 1024, as check_rank does for gs_setup
       if (a.k < 0 || a.k > h.s || a.k > 1024)
         throw Error(GS_EINVAL, "bad rank on level " + std::to_string(l) + " (0 <= k <= min(s, 1024))");
       if (a.k > 0) {
+        if (!a.w || !a.h) throw Error(GS_EINVAL, "NULL W or H" + tag);
         h.W.resize((size_t)h.s * a.k);
         h.H.resize((size_t)a.k * a.k);
         std::memcpy((void*)h.W.data(), a.w, h.W.size() * sizeof(T));

@@ -118,6 +118,40 @@ def _diag_level(d, s, k):
     return lv
 
 
+@pytest.mark.parametrize("block,csr,msg", [
+    ("E", ([0, 2, 1, 2], [0, 1], [1.0, 1.0]), "E of level 0: rowptr not monotone"),
+    ("E", ([1, 1, 1, 1], [], []), "E of level 0: rowptr[0] != 0"),
+    ("F", ([0, 1, 1, 1, 1], [3], [1.0]), "F of level 0: column out of range"),
+    ("L", ([0, 0, 2, 1, 2], [0, 1], [1.0, 1.0]), "L of level 0: rowptr not monotone"),
+    ("E", ([0, 1, 1, 2], [0, 3], [1.0, 2.0]), None),
+    ("F", ([0, 1, 1, 1, 2], [2, 0], [1.0, 2.0]), None),
+])
+def test_explicit_setup_checks_level_blocks(block, csr, msg):
+    """Every CSR block of an explicit level is checked before anything reads
+    it (rowptr from 0 and monotone, columns within the block's width: d for
+    E_l, s for F_l), so a malformed one is refused with GS_EINVAL naming the
+    block and level rather than read out of bounds; well-formed E_l and F_l
+    with entries are accepted (host-only context: validation only)."""
+    d, s = 4, 3
+    n = d + s
+    A = sp.identity(n, format="csr")
+    perm = np.arange(n, dtype=np.int64)
+    lv0 = _diag_level(d, s, 0)
+    lv0[block] = tuple(np.asarray(a, dt) for a, dt in zip(csr, (np.int64, np.int32, float)))
+    ctx = G.Context(-1)
+    try:
+        levels = [lv0, _diag_level(s, 0, 0)]
+        if msg is None:
+            ctx.setup_explicit(A.indptr, A.indices, A.data, perm, levels)
+        else:
+            with pytest.raises(G.GemslrError) as e:
+                ctx.setup_explicit(A.indptr, A.indices, A.data, perm, levels)
+            assert e.value.code == G.GS_EINVAL
+            assert msg in str(e.value)
+    finally:
+        ctx.close()
+
+
 def test_explicit_setup_rejects_rank_above_1024():
     """The low-rank kernels take k <= 1024 per level (as gs_setup's rank check
     says); an explicit level with k = 1025 <= s is refused with GS_EINVAL,
