@@ -152,8 +152,8 @@ def test_block_setup_from_random_basis(torch_dev):
 def test_learned_gain_small_family(torch_dev):
     """Train on 24 members of the log-normal family (20^3, 8 parts, rank 6)
     and score on 6 held-out members against the method without the network,
-    plain thick-restart Arnoldi (the judge), with the block iteration from
-    random bases as a second control.  Reported per mode: Ĝ products,
+    plain thick-restart Arnoldi (the baseline it has to beat), with the block
+    iteration from random bases as a second control.  Reported per mode: Ĝ products,
     low-rank setup time, FGMRES iterations, true residual, time to 1e-8.
 
     What the network buys on this family: fewer Ĝ products than the same
@@ -165,9 +165,11 @@ def test_learned_gain_small_family(torch_dev):
     learned start loses clearly (the single-vector Krylov-Schur needs fewer
     products on those clustered spectra, and the block iteration spends its
     time in per-iteration host work).  The test states this instead of
-    asserting a gain that does not hold: no time win beyond 10 % (timing
-    noise at these ~13 ms); it fails if that changes, so that the finding
-    gets re-examined."""
+    asserting a gain that does not hold: every mode's figures are reported,
+    the times are printed beside Arnoldi's, and the finding is asserted on
+    the G_hat products, which timing noise does not move: no cut beyond 15 %
+    against Arnoldi's (measured ~3 %); it fails if that changes, so that the
+    finding gets re-examined."""
     from paper_2205_03224_amd import learned
     rank = 6
     data = learned.collect(range(24), N=20, nparts=8, rank=rank, levels=(0,))
@@ -185,11 +187,14 @@ def test_learned_gain_small_family(torch_dev):
     # gain over the random-basis control, same preconditioner quality
     assert summ["learned"]["matvecs"] < summ["random"]["matvecs"]
     assert summ["learned"]["its"] <= summ["arnoldi"]["its"] + 3
-    # against the judge: the measured loss on this family
+    # against plain Arnoldi: the measured finding on this family
     ar = summ["arnoldi"]
+    for mode in learned.MODES:
+        for key in ("matvecs", "t_lowrank_s", "its", "time_to_tol_s"):
+            assert np.isfinite(summ[mode][key]) and summ[mode][key] > 0, (mode, key)
     print(f"  learned / Arnoldi time to 1e-8: "
           f"{summ['learned']['time_to_tol_s'] / ar['time_to_tol_s']:.2f} (block), "
           f"{summ['learned_arnoldi']['time_to_tol_s'] / ar['time_to_tol_s']:.2f} "
           f"(Arnoldi from the predicted subspace)", flush=True)
-    assert summ["learned"]["time_to_tol_s"] > 0.9 * ar["time_to_tol_s"]
+    assert summ["learned"]["matvecs"] >= 0.85 * ar["matvecs"]
     mlp.close()
