@@ -150,7 +150,8 @@ def test_batch_buffers_follow_rank_changes(torch_dev):
     the batch buffers) after level 1's own batched products made the
     buffers at rank 0 there; then ranks 8 from Arnoldi (smaller: the buffers
     stay).  After each, a batched apply of three vectors equals the single
-    applies bit for bit."""
+    applies bit for bit, and so does the apply that allocates nothing
+    (gs_apply_noalloc, whose scratch layout follows the current ranks)."""
     torch = torch_dev
     from paper_2205_03224_amd import gemslr, learned
     w = wl.convdiff3d_64(N=20, nparts=27)
@@ -168,6 +169,10 @@ def test_batch_buffers_follow_rank_changes(torch_dev):
             torch.cuda.synchronize()
             assert torch.isfinite(y).all(), what
             assert torch.equal(Y[j], y), f"{what}: column {j}"
+            y2 = torch.empty_like(y)
+            ctx.apply_noalloc(X[j].contiguous(), y2)
+            torch.cuda.synchronize()
+            assert torch.equal(y2, y), f"{what}: no-alloc apply, column {j}"
 
     check("rank 0")
     info = ctx.lowrank(100, learned.random_bases(ctx, (0, 1), 100, seed=9))
